@@ -1,0 +1,69 @@
+"""Low-storage database stage: sharp cut-off filter, filtered stresses, SGS tensor (oracle).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Section 3.1 of the paper: the velocities are truncated in Fourier space in the
+two wall-parallel directions only (no filtering in y); the database also keeps
+the truncated products u_i u_j, from which the sub-grid stress
+tau_ij = F(u_i u_j) - F(u_i) F(u_j) follows.  Readings:
+
+* the retained set is K_c = {0 <= kx <= kcx, |kz| <= kcz} in index units (the
+  printed filter has garbled arguments and uses strict "<" without absolute
+  values; the inclusive form is used here),
+* the products u_i u_j of the full fields are formed on the 3/2 padded grid,
+  which represents every retained product mode exactly,
+* tau_ij is evaluated pointwise on a (q3, q1) grid of the periodic plane,
+  from the zero-padded inverse transforms of F(u_i) and F(u_i u_j),
+* the SGS definition's typo (a repeated index j) is read as tau_ij = F(u_i u_j) - F(u_i) F(u_j).
+
+Output layouts: retained modes ``[n2][kcx+1][2kcz+1]`` with kz in FFT slot
+order (0..kcz, then -kcz..-1); tau ``[6][n2][q3][q1]`` for the pairs
+(11, 12, 13, 22, 23, 33).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import fourier
+
+PAIRS = ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))
+
+
+def kc_slots(n3, kcz):
+    """Stored kz slots (over n3) of the retained kz values, in output order."""
+    kz = list(range(0, kcz + 1)) + list(range(-kcz, 0))
+    return np.array([k if k >= 0 else n3 + k for k in kz])
+
+
+def truncate(uh, kcx, kcz):
+    """F(u) on K_c from a full field uh[n2][n1/2][n3]."""
+    n3 = uh.shape[-1]
+    return uh[..., : kcx + 1, :][..., kc_slots(n3, kcz)]
+
+
+def synth_plane(ch, q1, q3):
+    """Real field on the (q3, q1) grid from retained coefficients ch[..., kcx+1, 2kcz+1]."""
+    kcx1, nz = ch.shape[-2], ch.shape[-1]
+    kcz = (nz - 1) // 2
+    F = np.zeros(ch.shape[:-2] + (q3, q1 // 2 + 1), dtype=np.complex128)
+    kz = np.array(list(range(0, kcz + 1)) + list(range(-kcz, 0)))
+    F[..., kz % q3, :kcx1] = np.swapaxes(ch, -1, -2)
+    return np.fft.irfft2(F, s=(q3, q1)) * (q1 * q3)
+
+
+def filter_and_stress(u1, u2, u3, kcx, kcz, q1, q3):
+    """Returns (ubar[3], uubar[6], tau[6]) as described in the module docstring."""
+    n2, n1h, n3 = u1.shape
+    n1 = 2 * n1h
+    p1, p3 = fourier.padded_size(n1), fourier.padded_size(n3)
+    ub = np.stack([truncate(u, kcx, kcz) for u in (u1, u2, u3)])
+    phys = [fourier.to_physical(u, p1, p3) for u in (u1, u2, u3)]
+    uu = []
+    for i, j in PAIRS:
+        full = fourier.to_spectral(phys[i] * phys[j], n1, n3)
+        uu.append(truncate(full, kcx, kcz))
+    uu = np.stack(uu)
+    ubq = synth_plane(ub, q1, q3)
+    uuq = synth_plane(uu, q1, q3)
+    tau = np.stack([uuq[p] - ubq[i] * ubq[j] for p, (i, j) in enumerate(PAIRS)])
+    return ub, uu, tau

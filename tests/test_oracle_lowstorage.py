@@ -1,0 +1,117 @@
+"""Pins of the oracle's low-storage stage (Section 3.1: cut-off filter, F(u_i u_j), tau_ij).
+
+* brute force: the filtered products equal the exact convolution of the
+  Hermitian-complete mode sets, and tau at every Q-grid point equals the direct
+  Fourier sums, with no FFT anywhere;
+* a field band-limited to kc/2 has tau == 0 (the filter acts as the identity on
+  its products);
+* a single mode u1 = A cos(k x) with k > kc has tau_11 = A^2/2;
+* tau is invariant to adding a plane-constant c(y) to the velocity;
+* tau equals the Germano decomposition -(1-G)(ub_i ub_j) + G(ub_i u''_j +
+  u''_i ub_j + u''_i u''_j), u'' = u - ub.
+"""
+import numpy as np
+import pytest
+
+from oracle import brute, fourier, lowstorage
+
+N1, N2, N3 = 16, 5, 12
+LX, LZ = 2 * np.pi, np.pi
+
+
+def _field(rng, n1=N1, n3=N3, kmax=None):
+    uh = rng.standard_normal((N2, n1 // 2, n3)) + 1j * rng.standard_normal((N2, n1 // 2, n3))
+    uh[:, :, n3 // 2] = 0
+    for kz in range(1, n3 // 2):
+        uh[:, 0, n3 - kz] = np.conj(uh[:, 0, kz])
+    uh[:, 0, 0] = uh[:, 0, 0].real
+    if kmax is not None:
+        kx = np.arange(n1 // 2)[:, None]
+        kz = np.abs(np.fft.fftfreq(n3, 1 / n3))[None, :]
+        uh = uh * ((kx <= kmax) & (kz <= kmax))[None]
+    return uh
+
+
+@pytest.mark.parametrize("kcx,kcz", [(2, 2), (3, 2), (2, 3)])
+def test_filtered_stress_brute_force(kcx, kcz):
+    rng = np.random.default_rng(7)
+    u = [_field(rng) for _ in range(3)]
+    q1, q3 = 4 * kcx + 2, 4 * kcz + 2
+    ub, uu, tau = lowstorage.filter_and_stress(*u, kcx, kcz, q1, q3)
+    xq = np.arange(q1) * LX / q1
+    zq = np.arange(q3) * LZ / q3
+    slots = lowstorage.kc_slots(N3, kcz)
+    kzs = [s if s < N3 // 2 else s - N3 for s in slots]
+    for y in range(N2):
+        modes = [brute.full_modes(ui[y]) for ui in u]
+        for p, (i, j) in enumerate(lowstorage.PAIRS):
+            prod = brute.product_modes(modes[i], modes[j])
+            for kx in range(kcx + 1):
+                for c, kz in enumerate(kzs):
+                    ref = prod.get((kx, kz), 0)
+                    assert abs(uu[p, y, kx, c] - ref) < 1e-13 * (1 + abs(ref)), (p, y, kx, kz)
+        # tau by direct Fourier sums on the Q grid
+        fm = [{k: v for k, v in m.items() if abs(k[0]) <= kcx and abs(k[1]) <= kcz} for m in modes]
+        ubq = [brute.synth_points(m, LX, LZ, xq[None, :], zq[:, None]) for m in fm]
+        for p, (i, j) in enumerate(lowstorage.PAIRS):
+            prod = brute.product_modes(modes[i], modes[j])
+            fp = {k: v for k, v in prod.items() if abs(k[0]) <= kcx and abs(k[1]) <= kcz}
+            uuq = brute.synth_points(fp, LX, LZ, xq[None, :], zq[:, None])
+            ref = uuq - ubq[i] * ubq[j]
+            assert np.abs(tau[p, y] - ref).max() < 1e-13 * np.abs(uuq).max()
+
+
+def test_band_limited_field_has_zero_stress():
+    rng = np.random.default_rng(8)
+    u = [_field(rng, kmax=1) for _ in range(3)]
+    ub, _, tau = lowstorage.filter_and_stress(*u, 2, 2, 10, 10)
+    scale = np.abs(lowstorage.synth_plane(ub, 10, 10)).max() ** 2
+    assert np.abs(tau).max() < 1e-14 * scale
+
+
+def test_single_subfilter_mode():
+    """u1 = A cos(k x), k > kc: ub = 0, F(u1 u1) = A^2/2, tau_11 = A^2/2."""
+    A, k = 0.7, 5
+    u1 = np.zeros((N2, N1 // 2, N3), complex)
+    u1[:, k, 0] = A / 2  # stored kx > 0 coefficient; the -kx conjugate is implicit
+    z = np.zeros_like(u1)
+    ub, uu, tau = lowstorage.filter_and_stress(u1, z, z, 2, 2, 10, 10)
+    assert np.abs(ub).max() == 0
+    assert np.abs(tau[0] - A * A / 2).max() < 1e-14
+    assert np.abs(tau[1:]).max() < 1e-14
+
+
+def test_plane_constant_invariance():
+    rng = np.random.default_rng(9)
+    u = [_field(rng) for _ in range(3)]
+    _, _, tau = lowstorage.filter_and_stress(*u, 3, 2, 14, 10)
+    shifted = [x.copy() for x in u]
+    for i, c in enumerate((1.3, -0.4, 0.25)):
+        shifted[i][:, 0, 0] += c * (1 + np.arange(N2))
+    _, _, tau2 = lowstorage.filter_and_stress(*shifted, 3, 2, 14, 10)
+    assert np.abs(tau2 - tau).max() < 1e-12 * np.abs(tau).max() * 10
+
+
+def test_germano_decomposition():
+    rng = np.random.default_rng(10)
+    u = [_field(rng) for _ in range(3)]
+    kcx, kcz, q1, q3 = 3, 2, 14, 10
+    ub, uu, tau = lowstorage.filter_and_stress(*u, kcx, kcz, q1, q3)
+    p1, p3 = fourier.padded_size(N1), fourier.padded_size(N3)
+    full = [fourier.to_physical(x, p1, p3) for x in u]
+    # ub padded back to the full mode set, and the sub-filter part
+    ubf = []
+    for x in u:
+        y = np.zeros_like(x)
+        y[:, : kcx + 1][..., lowstorage.kc_slots(N3, kcz)] = lowstorage.truncate(x, kcx, kcz)
+        ubf.append(fourier.to_physical(y, p1, p3))
+    upp = [f - g for f, g in zip(full, ubf)]
+
+    def G(f):
+        return lowstorage.synth_plane(lowstorage.truncate(fourier.to_spectral(f, N1, N3), kcx, kcz), q1, q3)
+
+    ubq = lowstorage.synth_plane(ub, q1, q3)
+    for p, (i, j) in enumerate(lowstorage.PAIRS):
+        bb = ubf[i] * ubf[j]
+        germ = -(ubq[i] * ubq[j] - G(bb)) + G(ubf[i] * upp[j] + upp[i] * ubf[j] + upp[i] * upp[j])
+        assert np.abs(germ - tau[p]).max() < 1e-13 * np.abs(ubq[i] * ubq[j]).max()
