@@ -1,0 +1,171 @@
+/*
+ * chn.h -- C ABI of the MI355X (gfx950) channel-flow RK3 hot path.
+ *
+ * The library advances the velocity-vorticity formulation of incompressible
+ * channel flow (the paper's Appendix A: evolution equations for
+ * chi = lap(u2) and omega2 = d3 u1 - d1 u3 plus the mean profiles U1, U3, with
+ * a semi-implicit low-storage three-stage Runge-Kutta scheme), using
+ *   - Fourier expansions in x and z with 3/2-rule dealiased products
+ *     (Section 2.1), evaluated by the library's own FFT kernels;
+ *   - seven-point compact finite differences on a non-uniform wall-normal
+ *     mesh and banded Helmholtz/Poisson solves per Fourier mode with
+ *     Dirichlet end rows (Appendix B);
+ *   - constant mass flux through a time-varying mean pressure gradient
+ *     (Section 2.1),
+ * and provides the low-storage stage of Section 3.1: sharp Fourier cut-off
+ * filtering of the velocities, the filtered products F(u_i u_j) and the
+ * sub-grid stress tau_ij = F(u_i u_j) - F(u_i) F(u_j).
+ *
+ * Conventions shared by every entry point
+ *   - All device pointers are caller-owned.  The library never allocates
+ *     device memory: the caller passes one workspace of
+ *     chn_workspace_bytes(cfg) bytes, 256-byte aligned, and keeps it alive
+ *     until chn_destroy.  Host memory used internally is freed by chn_destroy.
+ *   - Every call is ordered on the HIP stream given in the config and returns
+ *     before the GPU work has finished, except where noted ("synchronises").
+ *   - Spectral fields are complex128, interleaved (re, im), in layout
+ *     [n2][n1/2][n3]: wall-normal node y, streamwise mode kx = 0..n1/2-1, and
+ *     spanwise mode kz in FFT slot order over n3 slots; slot n3/2 (the
+ *     Nyquist mode) is ignored on input and zero on output.  The kx = 0 line
+ *     of a real field must be Hermitian in kz.  Physical wavenumbers are
+ *     a = 2 pi kx / lx and b = 2 pi kz / lz; the channel is y in [-1, 1].
+ *   - Errors: CHN_EINVAL for invalid sizes or pointers (the context is left
+ *     unchanged), CHN_EDEVICE for a HIP runtime error (sticky: every later
+ *     call on that context returns it), CHN_ESTATE for a call made before
+ *     chn_set_state, CHN_EUNSTABLE when a step produced NaN/Inf.
+ *     chn_last_error gives a message for the last failing call.
+ *   - A context is bound to one stream and is not thread-safe.
+ */
+#ifndef CHN_H
+#define CHN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chn_ctx chn_ctx;
+
+typedef enum {
+  CHN_OK = 0,
+  CHN_EINVAL = 1,
+  CHN_ENOMEM = 2,
+  CHN_EDEVICE = 3,
+  CHN_ESTATE = 4,
+  CHN_EUNSTABLE = 5,
+  CHN_EUNSUPPORTED = 6
+} chn_status;
+
+/* CHN_FP64: every kernel computes in float64.
+ * CHN_MIXED: Fourier transforms, products and the filter stage compute in
+ * float32 (with float64 accumulation of plane means); the compact
+ * derivatives, banded Helmholtz/Poisson solves, mean-flow modes and
+ * mass-flux correction stay float64. */
+typedef enum { CHN_FP64 = 0, CHN_MIXED = 1 } chn_precision;
+
+typedef struct {
+  int32_t n1, n2, n3;   /* collocation counts in x, y (walls included), z.
+                           n1, n3 even; 3*n1/2 and 3*n3/2 must factor into
+                           2s and 3s; 9 <= n2 <= 2048. */
+  double lx, lz;        /* periods in x and z, in units of the half height */
+  double re_b;          /* bulk Reynolds number; nu = 1 / re_b */
+  double mass_flux;     /* target integral of U1 over y (2 for unit bulk velocity) */
+  int32_t precision;    /* chn_precision */
+  const double *y;      /* HOST pointer to n2 ascending nodes, y[0] = -1,
+                           y[n2-1] = 1; NULL selects y_j = tanh(2 s_j)/tanh(2),
+                           s_j uniform on [-1, 1] */
+  void *stream;         /* hipStream_t the context runs on (NULL = default stream) */
+} chn_config;
+
+/* Per-step diagnostics, filled by chn_step_rk3 for its last step. */
+typedef struct {
+  double f_mean;        /* mean pressure gradient of the last sub-step (Section 2.1) */
+  double mass_flux;     /* integral of U1 over y after the step */
+  double cfl_max;       /* dt * max(|u1|/dx + |u2|/dy_j + |u3|/dz) on the padded grid,
+                           from the velocities of the step's last sub-step */
+  double utau_lo, utau_hi; /* sqrt(nu |dU1/dy|) at the two walls */
+} chn_step_info;
+
+/* Bytes of device workspace needed for cfg (0 if cfg is invalid). */
+size_t chn_workspace_bytes(const chn_config *cfg);
+
+/* Builds the compact operators of Appendix B on the mesh (rows solved in
+ * extended precision, maximum order, stencils truncated at the walls), the
+ * quadrature weights of the mass flux, and the FFT tables, and uploads them
+ * into d_workspace.  Synchronises.  *out receives the context. */
+chn_status chn_create(const chn_config *cfg, void *d_workspace, size_t ws_bytes, chn_ctx **out);
+
+/* Frees host-side state; the workspace stays the caller's. */
+chn_status chn_destroy(chn_ctx *ctx);
+
+/* Copies an initial state in: d_v (= u2) and d_omega2 spectral fields,
+ * d_u1mean and d_u3mean float64[n2] mean profiles (all device pointers).
+ * chi = (D2 - k^2) v is formed inside with the compact D2.  The (0,0) and
+ * Nyquist modes of v and omega2 are ignored. */
+chn_status chn_set_state(chn_ctx *ctx, const double *d_v, const double *d_omega2,
+                         const double *d_u1mean, const double *d_u3mean);
+
+/* Advances nsteps full RK3 steps of size dt (three sub-steps each, the
+ * paper's Appendix A/C sequence: velocities and vorticities, dealiased
+ * u x omega, non-linear forcings, explicit viscous terms, implicit
+ * Helmholtz steps with the influence-matrix treatment of u2, mean modes with
+ * constant mass flux).  If info is not NULL the call synchronises and fills
+ * it for the last step; it returns CHN_EUNSTABLE if that step's CFL number is
+ * not finite. */
+chn_status chn_step_rk3(chn_ctx *ctx, double dt, int32_t nsteps, chn_step_info *info);
+
+/* Field selectors for chn_get_fields. */
+enum {
+  CHN_F_V = 1u << 0,      /* u2 (spectral) */
+  CHN_F_OMEGA2 = 1u << 1, /* omega2 (spectral) */
+  CHN_F_CHI = 1u << 2,    /* chi = lap(u2) (spectral) */
+  CHN_F_U1 = 1u << 3,     /* u1 (spectral; (0,0) mode = U1) */
+  CHN_F_U3 = 1u << 4,     /* u3 (spectral; (0,0) mode = U3) */
+  CHN_F_OMEGA1 = 1u << 5, /* omega1 (spectral) */
+  CHN_F_OMEGA3 = 1u << 6, /* omega3 (spectral) */
+  CHN_F_U1MEAN = 1u << 7, /* U1, float64[n2] */
+  CHN_F_U3MEAN = 1u << 8  /* U3, float64[n2] */
+};
+
+/* Writes the selected fields of the current state, in bit order, to the
+ * device pointers d_out[0], d_out[1], ... (one per set bit).  u1, u3 and the
+ * vorticities are recovered from v and omega2 by continuity and the compact
+ * D1 (the first steps of every sub-step). */
+chn_status chn_get_fields(chn_ctx *ctx, uint32_t mask, double *const *d_out);
+
+/* The dealiased non-linear term on its own: from the six spectral fields
+ * d_in[0..5] = u1, u2, u3, omega1, omega2, omega3 (device pointers, spectral
+ * layout), forms H = u x omega on the 3n1/2 x 3n3/2 grid of every plane and
+ * writes its truncated transforms d_out[0..2] = H1, H2, H3 (spectral layout,
+ * forward transform scaled by 1/(P1 P3)).  Computes in the context's
+ * precision (inputs and outputs stay float64). */
+chn_status chn_nonlinear(chn_ctx *ctx, const double *const *d_in, double *const *d_out);
+
+/* The low-storage stage (Section 3.1) on the current state.  With the
+ * retained set K = {0 <= kx <= kcx, |kz| <= kcz} (kcx < n1/2, kcz < n3/2):
+ *   d_ubar  [3][n2][kcx+1][2kcz+1] complex: F(u_i) for i = 1, 2, 3,
+ *   d_uubar [6][n2][kcx+1][2kcz+1] complex: F(u_i u_j), pairs 11,12,13,22,23,33,
+ *           products formed on the 3/2 padded grid,
+ *   d_tau   [6][n2][q3][q1] float64: tau_ij = F(u_i u_j) - F(u_i) F(u_j)
+ *           evaluated on the uniform q1 x q3 grid of each plane,
+ * kz in FFT slot order (0..kcz, then -kcz..-1).  q1 > 2 kcx, q3 > 2 kcz,
+ * both even and factoring into 2s and 3s.  d_tau may be NULL. */
+chn_status chn_filter_and_stress(chn_ctx *ctx, int32_t kcx, int32_t kcz, int32_t q1, int32_t q3,
+                                 double *d_ubar, double *d_uubar, double *d_tau);
+
+/* Copies the library's compact-difference tables to host arrays (each
+ * n2 x 7, row i holding M[i][i-3..i+3]) and the mass-flux quadrature weights
+ * (n2).  Any pointer may be NULL.  Synchronises. */
+chn_status chn_get_operators(chn_ctx *ctx, double *a1, double *b1, double *a2, double *b2,
+                             double *quad);
+
+/* Message of the last failing call on ctx (or of the last failing
+ * chn_create if ctx is NULL). */
+const char *chn_last_error(const chn_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHN_H */

@@ -1,0 +1,187 @@
+"""Python binding of the C ABI in include/chn.h (argument marshalling only).
+
+Device memory and the HIP stream come from PyTorch; every computation runs in
+the library's HIP kernels.  The library must be built (``build.py``); there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchn.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "chn.h")
+
+FP64, MIXED = 0, 1
+F_V, F_OMEGA2, F_CHI, F_U1, F_U3, F_OMEGA1, F_OMEGA3, F_U1MEAN, F_U3MEAN = (1 << k for k in range(9))
+FIELD_BITS = {"v": F_V, "omega2": F_OMEGA2, "chi": F_CHI, "u1": F_U1, "u3": F_U3,
+              "omega1": F_OMEGA1, "omega3": F_OMEGA3, "u1mean": F_U1MEAN, "u3mean": F_U3MEAN}
+STATUS = {0: "CHN_OK", 1: "CHN_EINVAL", 2: "CHN_ENOMEM", 3: "CHN_EDEVICE", 4: "CHN_ESTATE",
+          5: "CHN_EUNSTABLE", 6: "CHN_EUNSUPPORTED"}
+
+
+class Config(C.Structure):
+    _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n3", C.c_int32), ("lx", C.c_double),
+                ("lz", C.c_double), ("re_b", C.c_double), ("mass_flux", C.c_double),
+                ("precision", C.c_int32), ("y", C.POINTER(C.c_double)), ("stream", C.c_void_p)]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("f_mean", C.c_double), ("mass_flux", C.c_double), ("cfl_max", C.c_double),
+                ("utau_lo", C.c_double), ("utau_hi", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libchn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1808_06461_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.chn_workspace_bytes.argtypes = [C.POINTER(Config)]
+        L.chn_workspace_bytes.restype = C.c_size_t
+        L.chn_create.argtypes = [C.POINTER(Config), P, C.c_size_t, C.POINTER(P)]
+        L.chn_destroy.argtypes = [P]
+        L.chn_set_state.argtypes = [P, P, P, P, P]
+        L.chn_step_rk3.argtypes = [P, C.c_double, C.c_int32, C.POINTER(StepInfo)]
+        L.chn_get_fields.argtypes = [P, C.c_uint32, C.POINTER(P)]
+        L.chn_nonlinear.argtypes = [P, C.POINTER(P), C.POINTER(P)]
+        L.chn_filter_and_stress.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P]
+        L.chn_get_operators.argtypes = [P, P, P, P, P, P]
+        L.chn_last_error.argtypes = [P]
+        L.chn_last_error.restype = C.c_char_p
+        for name in ("chn_create", "chn_destroy", "chn_set_state", "chn_step_rk3", "chn_get_fields",
+                     "chn_nonlinear", "chn_filter_and_stress", "chn_get_operators"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def header_symbols():
+    """Names of the functions declared in include/chn.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(chn_\w+)\s*\(", text, re.M)))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+class ChnError(RuntimeError):
+    pass
+
+
+class Channel:
+    """One channel context on one GPU stream (see include/chn.h)."""
+
+    def __init__(self, n1, n2, n3, lx, lz, re_b, mass_flux=2.0, precision="fp64", y=None,
+                 device="cuda:0"):
+        self.L = lib()
+        self.device = torch.device(device)
+        self.n1, self.n2, self.n3 = n1, n2, n3
+        self.n1h = n1 // 2
+        self.precision = {"fp64": FP64, "mixed": MIXED}[precision]
+        self._y = None
+        yp = C.POINTER(C.c_double)()
+        if y is not None:
+            self._y = (C.c_double * n2)(*[float(v) for v in y])
+            yp = C.cast(self._y, C.POINTER(C.c_double))
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        self.cfg = Config(n1, n2, n3, lx, lz, re_b, mass_flux, self.precision, yp,
+                          C.c_void_p(self.stream.cuda_stream))
+        nbytes = self.L.chn_workspace_bytes(C.byref(self.cfg))
+        if nbytes == 0:
+            raise ChnError("invalid channel configuration")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.ctx = C.c_void_p()
+        s = self.L.chn_create(C.byref(self.cfg), C.c_void_p(base + off), nbytes, C.byref(self.ctx))
+        if s != 0:
+            raise ChnError(f"chn_create: {STATUS.get(s, s)}: {self.L.chn_last_error(None).decode()}")
+
+    # -- helpers
+    def _check(self, s, what):
+        if s != 0:
+            raise ChnError(f"{what}: {STATUS.get(s, s)}: {self.L.chn_last_error(self.ctx).decode()}")
+
+    def spectral_empty(self):
+        return torch.empty((self.n2, self.n1h, self.n3), dtype=torch.complex128, device=self.device)
+
+    def _dev(self, t, dtype):
+        t = torch.as_tensor(t).to(device=self.device, dtype=dtype)
+        return t.contiguous()
+
+    # -- C ABI
+    def set_state(self, v, omega2, u1mean, u3mean):
+        self._keep = [self._dev(v, torch.complex128), self._dev(omega2, torch.complex128),
+                      self._dev(u1mean, torch.float64), self._dev(u3mean, torch.float64)]
+        self._check(self.L.chn_set_state(self.ctx, *[_ptr(t) for t in self._keep]), "chn_set_state")
+
+    def step(self, dt, nsteps=1, info=False):
+        si = StepInfo()
+        self._check(self.L.chn_step_rk3(self.ctx, float(dt), int(nsteps), C.byref(si) if info else None),
+                    "chn_step_rk3")
+        if info:
+            return {k: getattr(si, k) for k, _ in StepInfo._fields_}
+        return None
+
+    def get_fields(self, *names):
+        mask = 0
+        for n in names:
+            mask |= FIELD_BITS[n]
+        outs = {}
+        ptrs = []
+        for n, bit in FIELD_BITS.items():
+            if mask & bit:
+                t = (torch.empty(self.n2, dtype=torch.float64, device=self.device) if n.endswith("mean")
+                     else self.spectral_empty())
+                outs[n] = t
+                ptrs.append(t.data_ptr())
+        arr = (C.c_void_p * max(1, len(ptrs)))(*ptrs)
+        self._check(self.L.chn_get_fields(self.ctx, mask, arr), "chn_get_fields")
+        return outs
+
+    def nonlinear(self, fields):
+        ins = [self._dev(f, torch.complex128) for f in fields]
+        outs = [self.spectral_empty() for _ in range(3)]
+        a = (C.c_void_p * 6)(*[t.data_ptr() for t in ins])
+        b = (C.c_void_p * 3)(*[t.data_ptr() for t in outs])
+        self._check(self.L.chn_nonlinear(self.ctx, a, b), "chn_nonlinear")
+        return outs
+
+    def filter_and_stress(self, kcx, kcz, q1, q3, with_tau=True):
+        nk = (self.n2, kcx + 1, 2 * kcz + 1)
+        ub = torch.empty((3,) + nk, dtype=torch.complex128, device=self.device)
+        uu = torch.empty((6,) + nk, dtype=torch.complex128, device=self.device)
+        tau = torch.empty((6, self.n2, q3, q1), dtype=torch.float64, device=self.device) if with_tau else None
+        self._check(self.L.chn_filter_and_stress(self.ctx, kcx, kcz, q1, q3, _ptr(ub), _ptr(uu), _ptr(tau)),
+                    "chn_filter_and_stress")
+        return ub, uu, tau
+
+    def operators(self):
+        import numpy as np
+        arrs = [np.zeros((self.n2, 7)) for _ in range(4)] + [np.zeros(self.n2)]
+        self._check(self.L.chn_get_operators(self.ctx, *[C.c_void_p(a.ctypes.data) for a in arrs]),
+                    "chn_get_operators")
+        return arrs
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.chn_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

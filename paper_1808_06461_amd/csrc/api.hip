@@ -1,0 +1,533 @@
+// C ABI of the channel RK3 hot path: context, workspace layout, sub-step driver.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/chn.h"
+#include "kernels.hpp"
+
+namespace {
+
+using chn::FftPlan;
+
+// Semi-implicit low-storage RK3 of Spalart, Moser & Rogers (1991), which the
+// paper cites without printing the values.
+const double kAlpha[3] = {29.0 / 96.0, -3.0 / 40.0, 1.0 / 6.0};
+const double kBeta[3] = {37.0 / 160.0, 5.0 / 24.0, 1.0 / 6.0};
+const double kGamma[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+const double kZeta[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+
+std::string g_create_error;
+
+bool smooth23(int n) {
+  if (n < 1) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  void* take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+}  // namespace
+
+struct chn_ctx {
+  chn_config cfg{};
+  std::vector<double> y;
+  hipStream_t stream = nullptr;
+  int n1 = 0, n2 = 0, n3 = 0, n1h = 0, M = 0, p1 = 0, p3 = 0;
+  double nu = 0.0;
+  bool mixed = false, have_state = false;
+  chn_status sticky = CHN_OK;
+  std::string err;
+  size_t ws_bytes = 0;
+  // state
+  double *v = nullptr, *chi = nullptr, *om2 = nullptr, *nchi_old = nullptr, *nom_old = nullptr;
+  double *U1 = nullptr, *U3 = nullptr, *nu_old = nullptr, *nw_old = nullptr;
+  // phase buffers (element type = fft precision)
+  void* ph[6] = {};
+  void* H[3] = {};
+  void* inter = nullptr;
+  size_t inter_bytes = 0;
+  double* S[8] = {};
+  double* SU[8] = {};
+  double* rowsum = nullptr;
+  float* rowcfl = nullptr;
+  // tables
+  double *A1, *B1, *A2, *B2, *L1d, *U1d, *L1u, *U1u, *L2d, *U2d, *clo, *chi_w, *quad, *inv_dy;
+  void *tw1 = nullptr, *tw3 = nullptr;
+  FftPlan plan1{}, plan3{};
+  double *mean_scr = nullptr, *mean_out = nullptr, *info_dev = nullptr;
+  std::vector<double> hA1, hB1, hA2, hB2, hquad;
+  chn::PencilGeom geom{};
+  chn::PlaneDims dims{};
+  int lds_max = 65536;  // bytes of LDS one workgroup may use on this device
+};
+
+namespace {
+
+size_t layout(const chn_config* c, char* base, chn_ctx* x) {
+  const int n1h = c->n1 / 2, n2 = c->n2, n3 = c->n3;
+  const int p1 = 3 * c->n1 / 2, p3 = 3 * c->n3 / 2;
+  const size_t M = (size_t)n1h * n3, NP = (size_t)n2 * M;
+  const size_t te = c->precision == CHN_MIXED ? 8 : 16;
+  const size_t CB = 16 * NP;
+  Carver cv;
+  cv.base = base;
+  auto D = [&](size_t n) { return reinterpret_cast<double*>(cv.take(n * sizeof(double))); };
+  double* v = reinterpret_cast<double*>(cv.take(CB));
+  double* chi = reinterpret_cast<double*>(cv.take(CB));
+  double* om2 = reinterpret_cast<double*>(cv.take(CB));
+  double* nco = reinterpret_cast<double*>(cv.take(CB));
+  double* noo = reinterpret_cast<double*>(cv.take(CB));
+  double* U1 = D(n2);
+  double* U3 = D(n2);
+  double* nuo = D(n2);
+  double* nwo = D(n2);
+  void* ph[6];
+  for (int f = 0; f < 6; ++f) ph[f] = cv.take(te * NP);
+  void* H[3];
+  for (int f = 0; f < 3; ++f) H[f] = cv.take(te * NP);
+  const size_t ib = te * 6 * (size_t)n2 * p3 * n1h;
+  void* inter = cv.take(ib);
+  double* S[8];
+  for (int k = 0; k < 8; ++k) S[k] = reinterpret_cast<double*>(cv.take(CB));
+  double* SU[8];
+  for (int k = 0; k < 8; ++k) SU[k] = D(NP);
+  double* rowsum = D(2 * (size_t)n2 * p3);
+  float* rowcfl = reinterpret_cast<float*>(cv.take(sizeof(float) * (size_t)n2 * p3));
+  double* tabs = D((size_t)n2 * (4 * 7 + 3 * 3 + 3 * 4 + 4));
+  void* tw1 = cv.take(te * (size_t)p1);
+  void* tw3 = cv.take(te * (size_t)p3);
+  double* mean_scr = D(3 * (size_t)n2 * 5 + 2 * (size_t)n2);
+  double* mean_out = D(8);
+  double* info = D(8);
+  if (x) {
+    x->v = v; x->chi = chi; x->om2 = om2; x->nchi_old = nco; x->nom_old = noo;
+    x->U1 = U1; x->U3 = U3; x->nu_old = nuo; x->nw_old = nwo;
+    for (int f = 0; f < 6; ++f) x->ph[f] = ph[f];
+    for (int f = 0; f < 3; ++f) x->H[f] = H[f];
+    x->inter = inter;
+    x->inter_bytes = ib;
+    for (int k = 0; k < 8; ++k) { x->S[k] = S[k]; x->SU[k] = SU[k]; }
+    x->rowsum = rowsum; x->rowcfl = rowcfl;
+    double* t = tabs;
+    x->A1 = t; t += 7 * n2; x->B1 = t; t += 7 * n2; x->A2 = t; t += 7 * n2; x->B2 = t; t += 7 * n2;
+    x->L1d = t; t += 3 * n2; x->L1u = t; t += 3 * n2; x->L2d = t; t += 3 * n2;
+    x->U1d = t; t += 4 * n2; x->U1u = t; t += 4 * n2; x->U2d = t; t += 4 * n2;
+    x->clo = t; t += n2; x->chi_w = t; t += n2; x->quad = t; t += n2; x->inv_dy = t; t += n2;
+    x->tw1 = tw1; x->tw3 = tw3;
+    x->mean_scr = mean_scr; x->mean_out = mean_out; x->info_dev = info;
+  }
+  return cv.off + 256;
+}
+
+const char* validate(const chn_config* c) {
+  if (!c) return "config is NULL";
+  if (c->n1 < 4 || c->n3 < 4 || (c->n1 % 2) || (c->n3 % 4)) return "n1 must be even and >= 4, n3 a multiple of 4";
+  if (!smooth23(3 * c->n1 / 2) || !smooth23(3 * c->n3 / 2)) return "3*n1/2 and 3*n3/2 must factor into 2s and 3s";
+  if (c->n2 < 9 || c->n2 > 2048) return "n2 must be in [9, 2048]";
+  if (!(c->lx > 0) || !(c->lz > 0) || !(c->re_b > 0)) return "lx, lz and re_b must be positive";
+  if (c->precision != CHN_FP64 && c->precision != CHN_MIXED) return "unknown precision";
+  const int p1 = 3 * c->n1 / 2, p3 = 3 * c->n3 / 2;
+  const int maxv = c->precision == CHN_MIXED ? 48 : 24;
+  if (6 * p1 > maxv * 256) return "3*n1/2 too large for the x-pass kernel";
+  if (p3 > maxv * 256) return "3*n3/2 too large for the z-pass kernels";
+  if (c->y) {
+    if (c->y[0] != -1.0 || c->y[c->n2 - 1] != 1.0) return "y must start at -1 and end at 1";
+    for (int j = 1; j < c->n2; ++j)
+      if (!(c->y[j] > c->y[j - 1])) return "y must be strictly ascending";
+  }
+  return nullptr;
+}
+
+chn_status fail(chn_ctx* x, chn_status s, const std::string& m) {
+  if (x) {
+    x->err = m;
+    if (s == CHN_EDEVICE) x->sticky = CHN_EDEVICE;
+  } else {
+    g_create_error = m;
+  }
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail((ctx), CHN_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T> struct Ty;
+template <> struct Ty<double> { using c = double2; };
+template <> struct Ty<float> { using c = float2; };
+
+
+template <typename T> int z_lines(const chn_ctx* x) {
+  const int maxv = sizeof(T) == 8 ? 24 : 48;
+  const int ls = x->p3 + 1;
+  int K = maxv * 256 / x->p3;
+  const int byl = x->lds_max / (ls * (int)sizeof(typename Ty<T>::c));
+  if (K > byl) K = byl;
+  if (K > 16) K = 16;
+  if (K > x->n1h) K = x->n1h;
+  if (K < 1) K = 1;
+  return K;
+}
+
+// plane phase: ph (6 slots) -> H (3 slots) through the intermediate
+template <typename T, typename TO>
+chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, void* const* out) {
+  using C = typename Ty<T>::c;
+  const int K = z_lines<T>(x);
+  chn::ZinvArgs<T> za{};
+  for (int f = 0; f < 6; ++f) za.in[f] = reinterpret_cast<const C*>(in[f]);
+  if (!omega2_given) za.in[4] = nullptr;
+  za.out = reinterpret_cast<C*>(x->inter);
+  za.tw = reinterpret_cast<const C*>(x->tw3);
+  za.plan = x->plan3;
+  za.d = x->dims;
+  za.K = K;
+  za.lstride = x->p3 + 1;
+  za.nfields = 6;
+  za.nslot = 6;
+  HIPCHK(x, chn::launch_zinv<T>(za, x->stream));
+  chn::XpassArgs<T> xa{};
+  xa.buf = reinterpret_cast<C*>(x->inter);
+  xa.tw = reinterpret_cast<const C*>(x->tw1);
+  xa.plan = x->plan1;
+  xa.d = x->dims;
+  xa.lstride = x->p1 + 1;
+  xa.rowsum = x->rowsum;
+  xa.rowcfl = x->rowcfl;
+  xa.inv_dx = x->n1 / x->cfg.lx;
+  xa.inv_dz = x->n3 / x->cfg.lz;
+  xa.inv_dy = x->inv_dy;
+  HIPCHK(x, chn::launch_xpass<T>(xa, x->stream));
+  chn::ZfwdArgs<T, TO> fa{};
+  fa.buf = reinterpret_cast<const C*>(x->inter);
+  for (int f = 0; f < 3; ++f) fa.out[f] = reinterpret_cast<typename Ty<TO>::c*>(out[f]);
+  fa.tw = reinterpret_cast<const C*>(x->tw3);
+  fa.plan = x->plan3;
+  fa.d = x->dims;
+  fa.K = K;
+  fa.lstride = x->p3 + 1;
+  fa.scale = 1.0 / ((double)x->p1 * x->p3);
+  HIPCHK(x, (chn::launch_zfwd<T, TO>(fa, x->stream)));
+  return CHN_OK;
+}
+
+template <typename TP> chn_status recover(chn_ctx* x, TP* const* out) {
+  chn::RecoverArgs<TP> ra{};
+  ra.g = x->geom;
+  ra.v = x->v;
+  ra.om2 = x->om2;
+  ra.U1 = x->U1;
+  ra.U3 = x->U3;
+  for (int f = 0; f < 5; ++f) ra.out[f] = out[f];
+  ra.S0 = x->S[0];
+  ra.S1 = x->S[1];
+  ra.S2 = x->S[2];
+  HIPCHK(x, chn::launch_recover<TP>(ra, x->stream));
+  return CHN_OK;
+}
+
+template <typename T> chn_status substep(chn_ctx* x, int s, double dt) {
+  // 1. velocities and vorticities into the phase buffers (u1, u2, u3, o1, -, o3)
+  T* po[5] = {reinterpret_cast<T*>(x->ph[0]), reinterpret_cast<T*>(x->ph[1]), reinterpret_cast<T*>(x->ph[2]),
+              reinterpret_cast<T*>(x->ph[3]), reinterpret_cast<T*>(x->ph[5])};
+  chn_status st = recover<T>(x, po);
+  if (st != CHN_OK) return st;
+  // 2. dealiased u x omega
+  st = plane_phase<T, T>(x, x->ph, false, x->H);
+  if (st != CHN_OK) return st;
+  // 3. pencils + mean modes
+  chn::AdvanceArgs<T> aa{};
+  aa.g = x->geom;
+  for (int f = 0; f < 3; ++f) aa.H[f] = reinterpret_cast<const T*>(x->H[f]);
+  aa.v = x->v; aa.chi = x->chi; aa.om2 = x->om2;
+  aa.nchi_old = x->nchi_old; aa.nom_old = x->nom_old;
+  for (int k = 0; k < 8; ++k) { aa.S[k] = x->S[k]; aa.SU[k] = x->SU[k]; }
+  aa.U1 = x->U1; aa.U3 = x->U3; aa.nu_old = x->nu_old; aa.nw_old = x->nw_old;
+  aa.rowsum = x->rowsum;
+  aa.p3 = x->p3;
+  aa.inv_p1p3 = 1.0 / ((double)x->p1 * x->p3);
+  aa.mean_scr = x->mean_scr;
+  aa.mean_out = x->mean_out;
+  aa.mass_flux = x->cfg.mass_flux;
+  aa.dt = dt; aa.nu = x->nu;
+  aa.al = kAlpha[s]; aa.be = kBeta[s]; aa.ga = kGamma[s]; aa.ze = kZeta[s];
+  HIPCHK(x, chn::launch_advance<T>(aa, x->stream));
+  return CHN_OK;
+}
+
+chn_status check(chn_ctx* x) {
+  if (!x) return CHN_EINVAL;
+  if (x->sticky != CHN_OK) return x->sticky;
+  return CHN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t chn_workspace_bytes(const chn_config* cfg) {
+  if (validate(cfg)) return 0;
+  return layout(cfg, nullptr, nullptr);
+}
+
+chn_status chn_create(const chn_config* cfg, void* d_ws, size_t ws_bytes, chn_ctx** out) {
+  if (!out) return fail(nullptr, CHN_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (const char* m = validate(cfg)) return fail(nullptr, CHN_EINVAL, m);
+  const size_t need = layout(cfg, nullptr, nullptr);
+  if (!d_ws || ws_bytes < need) return fail(nullptr, CHN_EINVAL, "workspace missing or smaller than chn_workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256) return fail(nullptr, CHN_EINVAL, "workspace must be 256-byte aligned");
+  chn_ctx* x = new chn_ctx();
+  x->cfg = *cfg;
+  x->stream = reinterpret_cast<hipStream_t>(cfg->stream);
+  x->n1 = cfg->n1; x->n2 = cfg->n2; x->n3 = cfg->n3;
+  x->n1h = cfg->n1 / 2; x->M = x->n1h * x->n3;
+  x->p1 = 3 * cfg->n1 / 2; x->p3 = 3 * cfg->n3 / 2;
+  x->nu = 1.0 / cfg->re_b;
+  x->mixed = cfg->precision == CHN_MIXED;
+  x->ws_bytes = ws_bytes;
+  layout(cfg, reinterpret_cast<char*>(d_ws), x);
+  {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+      x->lds_max = lds;
+    const size_t xl = (size_t)6 * (x->p1 + 1) * (x->mixed ? 8 : 16);
+    if (xl > (size_t)x->lds_max) {
+      delete x;
+      return fail(nullptr, CHN_EINVAL, "3*n1/2 too large for the x-pass LDS tile");
+    }
+  }
+  x->y.resize(x->n2);
+  if (cfg->y) std::memcpy(x->y.data(), cfg->y, sizeof(double) * x->n2);
+  else chn::host::default_mesh(x->n2, x->y.data());
+  x->cfg.y = nullptr;
+  const int n2 = x->n2;
+  // tables
+  x->hA1.resize(7 * n2); x->hB1.resize(7 * n2); x->hA2.resize(7 * n2); x->hB2.resize(7 * n2);
+  x->hquad.resize(n2);
+  std::vector<double> L1d(3 * n2), U1d(4 * n2), L1u(3 * n2), U1u(4 * n2), L2d(3 * n2), U2d(4 * n2);
+  std::vector<double> clo(n2), chw(n2), idy(n2);
+  bool ok = chn::host::compact_bands(n2, x->y.data(), 1, x->hA1.data(), x->hB1.data()) &&
+            chn::host::compact_bands(n2, x->y.data(), 2, x->hA2.data(), x->hB2.data()) &&
+            chn::host::band_lu(n2, x->hA1.data(), +1, L1d.data(), U1d.data()) &&
+            chn::host::band_lu(n2, x->hA1.data(), -1, L1u.data(), U1u.data()) &&
+            chn::host::band_lu(n2, x->hA2.data(), +1, L2d.data(), U2d.data()) &&
+            chn::host::wall_rows(n2, x->hA1.data(), x->hB1.data(), clo.data(), chw.data());
+  if (!ok) {
+    delete x;
+    return fail(nullptr, CHN_EINVAL, "compact-difference system singular on this mesh");
+  }
+  chn::host::quadrature(n2, x->y.data(), x->hquad.data());
+  for (int j = 0; j < n2; ++j) {
+    const double lo = j > 0 ? x->y[j] - x->y[j - 1] : x->y[1] - x->y[0];
+    const double hi = j < n2 - 1 ? x->y[j + 1] - x->y[j] : lo;
+    idy[j] = 1.0 / (lo < hi ? lo : hi);
+  }
+  std::vector<double> tw1, tw3;
+  if (!chn::host::fft_plan(x->p1, &x->plan1, &tw1) || !chn::host::fft_plan(x->p3, &x->plan3, &tw3)) {
+    delete x;
+    return fail(nullptr, CHN_EINVAL, "FFT length not supported");
+  }
+  auto up = [&](double* d, const std::vector<double>& h) {
+    return hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, x->stream);
+  };
+  hipError_t e = hipSuccess;
+  std::vector<double> f1, f3;
+  std::vector<float> g1, g3;
+  if (e == hipSuccess) e = up(x->A1, x->hA1);
+  if (e == hipSuccess) e = up(x->B1, x->hB1);
+  if (e == hipSuccess) e = up(x->A2, x->hA2);
+  if (e == hipSuccess) e = up(x->B2, x->hB2);
+  if (e == hipSuccess) e = up(x->L1d, L1d);
+  if (e == hipSuccess) e = up(x->U1d, U1d);
+  if (e == hipSuccess) e = up(x->L1u, L1u);
+  if (e == hipSuccess) e = up(x->U1u, U1u);
+  if (e == hipSuccess) e = up(x->L2d, L2d);
+  if (e == hipSuccess) e = up(x->U2d, U2d);
+  if (e == hipSuccess) e = up(x->clo, clo);
+  if (e == hipSuccess) e = up(x->chi_w, chw);
+  if (e == hipSuccess) e = up(x->quad, x->hquad);
+  if (e == hipSuccess) e = up(x->inv_dy, idy);
+  if (x->mixed) {
+    g1.assign(tw1.begin(), tw1.end());
+    g3.assign(tw3.begin(), tw3.end());
+    if (e == hipSuccess) e = hipMemcpyAsync(x->tw1, g1.data(), g1.size() * 4, hipMemcpyHostToDevice, x->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(x->tw3, g3.data(), g3.size() * 4, hipMemcpyHostToDevice, x->stream);
+  } else {
+    if (e == hipSuccess) e = hipMemcpyAsync(x->tw1, tw1.data(), tw1.size() * 8, hipMemcpyHostToDevice, x->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(x->tw3, tw3.data(), tw3.size() * 8, hipMemcpyHostToDevice, x->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
+  if (e != hipSuccess) {
+    delete x;
+    return fail(nullptr, CHN_EDEVICE, std::string("uploading tables: ") + hipGetErrorString(e));
+  }
+  chn::PencilGeom& g = x->geom;
+  g.n2 = n2; g.n3 = x->n3; g.n1h = x->n1h; g.M = x->M;
+  g.ka = 2.0 * M_PI / cfg->lx; g.kb = 2.0 * M_PI / cfg->lz;
+  g.A1 = x->A1; g.B1 = x->B1; g.A2 = x->A2; g.B2 = x->B2;
+  g.L1d = x->L1d; g.U1d = x->U1d; g.L1u = x->L1u; g.U1u = x->U1u; g.L2d = x->L2d; g.U2d = x->U2d;
+  g.clo = x->clo; g.chi = x->chi_w; g.quad = x->quad;
+  chn::PlaneDims& d = x->dims;
+  d.n1h = x->n1h; d.n2 = n2; d.n3 = x->n3; d.p1 = x->p1; d.p3 = x->p3; d.lx = cfg->lx; d.lz = cfg->lz;
+  *out = x;
+  return CHN_OK;
+}
+
+chn_status chn_destroy(chn_ctx* ctx) {
+  delete ctx;
+  return CHN_OK;
+}
+
+chn_status chn_set_state(chn_ctx* x, const double* d_v, const double* d_om2, const double* d_u1m,
+                         const double* d_u3m) {
+  if (chn_status s = check(x)) return s;
+  if (!d_v || !d_om2 || !d_u1m || !d_u3m) return fail(x, CHN_EINVAL, "NULL state pointer");
+  chn::ChiArgs ca{};
+  ca.g = x->geom;
+  ca.vin = d_v;
+  ca.omin = d_om2;
+  ca.v = x->v;
+  ca.om2 = x->om2;
+  ca.chi = x->chi;
+  ca.S0 = x->S[0];
+  HIPCHK(x, chn::launch_chi_from_v(ca, x->stream));
+  const size_t n2b = sizeof(double) * x->n2;
+  HIPCHK(x, hipMemcpyAsync(x->U1, d_u1m, n2b, hipMemcpyDeviceToDevice, x->stream));
+  HIPCHK(x, hipMemcpyAsync(x->U3, d_u3m, n2b, hipMemcpyDeviceToDevice, x->stream));
+  const size_t CB = 16 * (size_t)x->n2 * x->M;
+  HIPCHK(x, hipMemsetAsync(x->nchi_old, 0, CB, x->stream));
+  HIPCHK(x, hipMemsetAsync(x->nom_old, 0, CB, x->stream));
+  HIPCHK(x, hipMemsetAsync(x->nu_old, 0, n2b, x->stream));
+  HIPCHK(x, hipMemsetAsync(x->nw_old, 0, n2b, x->stream));
+  x->have_state = true;
+  return CHN_OK;
+}
+
+chn_status chn_step_rk3(chn_ctx* x, double dt, int32_t nsteps, chn_step_info* info) {
+  if (chn_status s = check(x)) return s;
+  if (!x->have_state) return fail(x, CHN_ESTATE, "chn_step_rk3 before chn_set_state");
+  if (!(dt > 0) || nsteps < 0) return fail(x, CHN_EINVAL, "dt must be positive and nsteps >= 0");
+  for (int k = 0; k < nsteps; ++k)
+    for (int s = 0; s < 3; ++s) {
+      const chn_status st = x->mixed ? substep<float>(x, s, dt) : substep<double>(x, s, dt);
+      if (st != CHN_OK) return st;
+    }
+  if (info) {
+    chn::InfoArgs ia{};
+    ia.g = x->geom;
+    ia.rowcfl = x->rowcfl;
+    ia.p3 = x->p3;
+    ia.U1 = x->U1;
+    ia.dt = dt;
+    ia.nu = x->nu;
+    ia.out = x->info_dev;
+    ia.mean_out = x->mean_out;
+    HIPCHK(x, chn::launch_info(ia, x->stream));
+    double h[8] = {0};
+    HIPCHK(x, hipMemcpyAsync(h, x->info_dev, sizeof(h), hipMemcpyDeviceToHost, x->stream));
+    HIPCHK(x, hipStreamSynchronize(x->stream));
+    info->cfl_max = h[0];
+    info->mass_flux = h[1];
+    info->utau_lo = h[2];
+    info->utau_hi = h[3];
+    info->f_mean = h[4];
+    if (h[5] != 0.0 || !std::isfinite(h[0])) return fail(x, CHN_EUNSTABLE, "non-finite values after the step");
+  }
+  return CHN_OK;
+}
+
+chn_status chn_get_fields(chn_ctx* x, uint32_t mask, double* const* d_out) {
+  if (chn_status s = check(x)) return s;
+  if (!x->have_state) return fail(x, CHN_ESTATE, "chn_get_fields before chn_set_state");
+  if (!d_out && mask) return fail(x, CHN_EINVAL, "d_out is NULL");
+  const size_t CB = 16 * (size_t)x->n2 * x->M;
+  const size_t n2b = sizeof(double) * x->n2;
+  const bool need_rec = mask & (CHN_F_U1 | CHN_F_U3 | CHN_F_OMEGA1 | CHN_F_OMEGA3);
+  if (need_rec) {
+    double* po[5] = {x->S[3], x->S[4], x->S[5], x->S[6], x->S[7]};
+    if (chn_status s = recover<double>(x, po)) return s;
+  }
+  int k = 0;
+  for (uint32_t bit = 0; bit < 9; ++bit) {
+    if (!(mask & (1u << bit))) continue;
+    double* dst = d_out[k++];
+    if (!dst) return fail(x, CHN_EINVAL, "NULL output pointer");
+    const void* src = nullptr;
+    size_t bytes = CB;
+    switch (1u << bit) {
+      case CHN_F_V: src = x->v; break;
+      case CHN_F_OMEGA2: src = x->om2; break;
+      case CHN_F_CHI: src = x->chi; break;
+      case CHN_F_U1: src = x->S[3]; break;
+      case CHN_F_U3: src = x->S[5]; break;
+      case CHN_F_OMEGA1: src = x->S[6]; break;
+      case CHN_F_OMEGA3: src = x->S[7]; break;
+      case CHN_F_U1MEAN: src = x->U1; bytes = n2b; break;
+      case CHN_F_U3MEAN: src = x->U3; bytes = n2b; break;
+    }
+    HIPCHK(x, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, x->stream));
+  }
+  return CHN_OK;
+}
+
+chn_status chn_nonlinear(chn_ctx* x, const double* const* d_in, double* const* d_out) {
+  if (chn_status s = check(x)) return s;
+  if (!d_in || !d_out) return fail(x, CHN_EINVAL, "NULL field array");
+  for (int f = 0; f < 6; ++f)
+    if (!d_in[f]) return fail(x, CHN_EINVAL, "NULL input field");
+  for (int f = 0; f < 3; ++f)
+    if (!d_out[f]) return fail(x, CHN_EINVAL, "NULL output field");
+  if (!x->mixed) {
+    const void* in[6];
+    void* out[3];
+    for (int f = 0; f < 6; ++f) in[f] = d_in[f];
+    for (int f = 0; f < 3; ++f) out[f] = d_out[f];
+    return plane_phase<double, double>(x, in, true, out);
+  }
+  const size_t n = 2 * (size_t)x->n2 * x->M;
+  for (int f = 0; f < 6; ++f)
+    HIPCHK(x, chn::launch_convert_d2f(d_in[f], reinterpret_cast<float*>(x->ph[f]), n, x->stream));
+  void* out[3];
+  for (int f = 0; f < 3; ++f) out[f] = d_out[f];
+  return plane_phase<float, double>(x, x->ph, true, out);
+}
+
+chn_status chn_filter_and_stress(chn_ctx* x, int32_t kcx, int32_t kcz, int32_t q1, int32_t q3, double* d_ubar,
+                                 double* d_uubar, double* d_tau) {
+  if (chn_status s = check(x)) return s;
+  if (!x->have_state) return fail(x, CHN_ESTATE, "chn_filter_and_stress before chn_set_state");
+  return fail(x, CHN_EUNSUPPORTED, "filter stage not built yet");
+}
+
+chn_status chn_get_operators(chn_ctx* x, double* a1, double* b1, double* a2, double* b2, double* quad) {
+  if (!x) return CHN_EINVAL;
+  const size_t nb = sizeof(double) * 7 * x->n2;
+  if (a1) std::memcpy(a1, x->hA1.data(), nb);
+  if (b1) std::memcpy(b1, x->hB1.data(), nb);
+  if (a2) std::memcpy(a2, x->hA2.data(), nb);
+  if (b2) std::memcpy(b2, x->hB2.data(), nb);
+  if (quad) std::memcpy(quad, x->hquad.data(), sizeof(double) * x->n2);
+  return CHN_OK;
+}
+
+const char* chn_last_error(const chn_ctx* x) { return x ? x->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

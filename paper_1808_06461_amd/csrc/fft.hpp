@@ -1,0 +1,129 @@
+// Batched in-LDS Stockham FFT for wave64 workgroups (gfx950).
+//
+// A workgroup transforms `nlines` lines of length N held in LDS (line l at
+// lds[l * lstride + e]).  Each pass of radix R reads R strided values per
+// butterfly into registers, the whole workgroup synchronises, and the
+// twiddled radix-R DFTs are written back in place in Stockham (self-sorting)
+// order, so the result is in natural order with no bit reversal.  sgn = -1
+// is the forward (analysis) transform, sgn = +1 the unscaled inverse.
+#pragma once
+#include "common.hpp"
+
+namespace chn {
+
+template <typename T> __device__ __forceinline__ void dft2(c2<T>* v) {
+  c2<T> a = v[0], b = v[1];
+  v[0] = cadd<T>(a, b);
+  v[1] = csub<T>(a, b);
+}
+
+template <typename T> __device__ __forceinline__ void dft3(c2<T>* v, int sgn) {
+  const T c = T(-0.5);
+  const T s = T(0.866025403784438646763723170752936) * T(sgn);
+  c2<T> t = cadd<T>(v[1], v[2]);
+  c2<T> d = csub<T>(v[1], v[2]);
+  c2<T> m = mk<T>(v[0].x + c * t.x, v[0].y + c * t.y);
+  v[0] = cadd<T>(v[0], t);
+  v[1] = mk<T>(m.x - s * d.y, m.y + s * d.x);
+  v[2] = mk<T>(m.x + s * d.y, m.y - s * d.x);
+}
+
+template <typename T> __device__ __forceinline__ void dft4(c2<T>& x0, c2<T>& x1, c2<T>& x2, c2<T>& x3, int sgn) {
+  c2<T> a = cadd<T>(x0, x2), b = csub<T>(x0, x2);
+  c2<T> c = cadd<T>(x1, x3), d = cmuli<T>(csub<T>(x1, x3), sgn);
+  x0 = cadd<T>(a, c);
+  x2 = csub<T>(a, c);
+  x1 = cadd<T>(b, d);
+  x3 = csub<T>(b, d);
+}
+
+template <typename T> __device__ __forceinline__ void dft8(c2<T>* v, int sgn) {
+  const T r2 = T(0.707106781186547524400844362104849);
+  c2<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  c2<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<T>(e0, e1, e2, e3, sgn);
+  dft4<T>(o0, o1, o2, o3, sgn);
+  const T s = T(sgn);
+  // o_q *= exp(sgn 2 pi i q / 8)
+  o1 = mk<T>(r2 * (o1.x - s * o1.y), r2 * (o1.y + s * o1.x));
+  o2 = cmuli<T>(o2, sgn);
+  o3 = mk<T>(r2 * (-o3.x - s * o3.y), r2 * (-o3.y + s * o3.x));
+  v[0] = cadd<T>(e0, o0); v[4] = csub<T>(e0, o0);
+  v[1] = cadd<T>(e1, o1); v[5] = csub<T>(e1, o1);
+  v[2] = cadd<T>(e2, o2); v[6] = csub<T>(e2, o2);
+  v[3] = cadd<T>(e3, o3); v[7] = csub<T>(e3, o3);
+}
+
+template <typename T, int R> __device__ __forceinline__ void dft(c2<T>* v, int sgn) {
+  if constexpr (R == 2) dft2<T>(v);
+  else if constexpr (R == 3) dft3<T>(v, sgn);
+  else if constexpr (R == 4) dft4<T>(v[0], v[1], v[2], v[3], sgn);
+  else dft8<T>(v, sgn);
+}
+
+// One radix-R pass over all lines.  NB = butterflies per thread (compile
+// time, so the staging array lives in registers); the caller guarantees
+// nlines * N / R <= NB * blockDim.x.
+template <typename T, int R, int NB>
+__device__ __forceinline__ void stockham_pass(c2<T>* lds, int lstride, int nlines, int N, int Ns,
+                                              const c2<T>* __restrict__ tw, int sgn) {
+  const int nbl = N / R;
+  const int total = nbl * nlines;
+  const int nt = blockDim.x;
+  c2<T> v[NB][R];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int g = threadIdx.x + q * nt;
+    if (g < total) {
+      const int line = g / nbl;
+      const int j = g - line * nbl;
+      const c2<T>* src = lds + line * lstride + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[r * nbl];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int g = threadIdx.x + q * nt;
+    if (g < total) {
+      const int line = g / nbl;
+      const int j = g - line * nbl;
+      const int k = j % Ns;
+      if (Ns > 1) {
+        const c2<T>* w = tw + k * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          c2<T> t = w[r - 1];
+          if (sgn > 0) t.y = -t.y;
+          v[q][r] = cmul<T>(v[q][r], t);
+        }
+      }
+      dft<T, R>(v[q], sgn);
+      c2<T>* dst = lds + line * lstride + (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform of nlines lines of length pl.n.  MAXV = complex values
+// staged per thread (a multiple of 24); requires nlines * pl.n <= MAXV * blockDim.x.
+template <typename T, int MAXV>
+__device__ void fft_lines(c2<T>* lds, int lstride, int nlines, const FftPlan& pl,
+                          const c2<T>* __restrict__ tw, int sgn) {
+  int Ns = 1;
+  for (int p = 0; p < pl.npass; ++p) {
+    const c2<T>* twp = tw + pl.twoff[p];
+    switch (pl.radix[p]) {
+      case 8: stockham_pass<T, 8, MAXV / 8>(lds, lstride, nlines, pl.n, Ns, twp, sgn); break;
+      case 4: stockham_pass<T, 4, MAXV / 4>(lds, lstride, nlines, pl.n, Ns, twp, sgn); break;
+      case 3: stockham_pass<T, 3, MAXV / 3>(lds, lstride, nlines, pl.n, Ns, twp, sgn); break;
+      default: stockham_pass<T, 2, MAXV / 2>(lds, lstride, nlines, pl.n, Ns, twp, sgn); break;
+    }
+    Ns *= pl.radix[p];
+  }
+}
+
+}  // namespace chn

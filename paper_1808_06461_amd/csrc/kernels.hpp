@@ -1,0 +1,129 @@
+// Kernel argument blocks and launcher declarations (internal to the library).
+#pragma once
+#include "common.hpp"
+
+namespace chn {
+
+struct PlaneDims {
+  int n1h, n2, n3, p1, p3;
+  double lx, lz;
+};
+
+template <typename T> struct ZinvArgs {
+  const c2<T>* in[6];  // u1, u2, u3, omega1, omega2, omega3 spectral [n2][n1h][n3];
+                       // in[4] == nullptr: omega2 = i b u1 - i a u3 formed here
+  c2<T>* out;          // [n2][nslot][p3][n1h]
+  const c2<T>* tw;     // twiddles of the p3 plan
+  FftPlan plan;
+  PlaneDims d;
+  int K;               // kx lines per workgroup
+  int lstride;         // LDS line stride (complex elements)
+  int nfields;         // 6: u1 u2 u3 omega1 omega2 omega3; 3: u1 u2 u3
+  int nslot;           // field slots per plane in `out`
+};
+
+template <typename T> struct XpassArgs {
+  c2<T>* buf;          // [n2][6][p3][n1h], transformed in place
+  const c2<T>* tw;     // twiddles of the p1 plan
+  FftPlan plan;
+  PlaneDims d;
+  int lstride;
+  double* rowsum;      // [2][n2][p3] sums over x of H1 and H3
+  float* rowcfl;       // [n2][p3] max over x of |u1|/dx + |u2|/dy + |u3|/dz
+  double inv_dx, inv_dz;
+  const double* inv_dy;  // [n2]
+};
+
+template <typename T, typename TO> struct ZfwdArgs {
+  const c2<T>* buf;    // [n2][6][p3][n1h]
+  c2<TO>* out[3];      // H1, H2, H3 spectral [n2][n1h][n3]
+  const c2<T>* tw;
+  FftPlan plan;
+  PlaneDims d;
+  int K;
+  int lstride;
+  double scale;        // 1 / (p1 p3)
+};
+
+template <typename T> hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st);
+template <typename T> hipError_t launch_xpass(const XpassArgs<T>& a, hipStream_t st);
+template <typename T, typename TO> hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st);
+
+// ---------------------------------------------------------------- pencils
+// Band tables are [n2][7] (row i holds M[i][i-3..i+3]).  LU factors of a
+// mode-independent band, for a sweep in either direction: L[i][j] is the
+// multiplier of the row at processing distance 3 - j, U[i] = {1/pivot, u1,
+// u2, u3}, u_t the entry at distance t on the not-yet-processed side.
+struct PencilGeom {
+  int n2, n3, n1h, M;         // M = n1h * n3 modes per plane
+  double ka, kb;              // 2 pi / lx, 2 pi / lz
+  const double *A1, *B1, *A2, *B2;
+  const double *L1d, *U1d, *L1u, *U1u, *L2d, *U2d;
+  const double *clo, *chi;    // (D1 f)_0 = clo . f, (D1 f)_{n2-1} = chi . f
+  const double *quad;         // mass-flux weights
+};
+
+template <typename TP> struct RecoverArgs {
+  PencilGeom g;
+  const double* v;            // state u2, complex [n2][M]
+  const double* om2;          // state omega2
+  const double* U1;           // [n2]
+  const double* U3;
+  TP* out[5];                 // u1, u2, u3, omega1, omega3 (interleaved complex)
+  double* S0;                 // lane-indexed scratch, 3 arrays of [n2][2M]
+  double* S1;
+  double* S2;
+};
+
+template <typename TH> struct AdvanceArgs {
+  PencilGeom g;
+  const TH* H[3];             // H1, H2, H3 (interleaved complex [n2][M])
+  double* v;                  // state, updated
+  double* chi;
+  double* om2;
+  double* nchi_old;           // histories, updated
+  double* nom_old;
+  double* S[8];               // lane-indexed scratch [n2][2M]
+  double* SU[8];              // mode-indexed scratch [n2][M]
+  // mean modes
+  double* U1;
+  double* U3;
+  double* nu_old;
+  double* nw_old;
+  const double* rowsum;       // [2][n2][p3]
+  int p3;
+  double inv_p1p3;
+  double* mean_scr;           // [3][n2][5]
+  double* mean_out;           // [0]: mean pressure gradient of the sub-step
+  double mass_flux;
+  double dt, nu, al, be, ga, ze;
+};
+
+struct ChiArgs {
+  PencilGeom g;
+  const double* vin;          // caller's v
+  const double* omin;         // caller's omega2
+  double* v;                  // state
+  double* om2;
+  double* chi;
+  double* S0;
+};
+
+struct InfoArgs {
+  PencilGeom g;
+  const float* rowcfl;        // [n2][p3]
+  int p3;
+  const double* U1;
+  double dt, nu;
+  double* out;                // cfl, mass flux, utau_lo, utau_hi, f (copied), nonfinite flag
+  const double* mean_out;
+};
+
+template <typename TP> hipError_t launch_recover(const RecoverArgs<TP>& a, hipStream_t st);
+template <typename TH> hipError_t launch_advance(const AdvanceArgs<TH>& a, hipStream_t st);
+hipError_t launch_chi_from_v(const ChiArgs& a, hipStream_t st);
+hipError_t launch_info(const InfoArgs& a, hipStream_t st);
+hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_t st);
+hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_t st);
+
+}  // namespace chn

@@ -1,0 +1,244 @@
+// Plane phase of the RK3 sub-step: dealiased u x omega on every x-z plane.
+//
+// Three passes over a [n2][6][p3][n1/2] intermediate (z-major, kx contiguous):
+//   k_zinv : per (y, tile of kx lines): zero-pad kz from n3 to p3 = 3 n3 / 2
+//            slots, form omega2 = i b u1 - i a u3 in Fourier space, inverse
+//            FFT in z, store transposed so kx is contiguous.
+//   k_xpass: per (y, pair of z rows): pad kx to p1 = 3 n1 / 2 (Hermitian
+//            extension), two real inverse transforms per complex FFT, products
+//            H = u x omega, float64 row sums of H1 and H3 (mean modes) and the
+//            row CFL maximum, forward FFT (two real signals per complex FFT),
+//            truncate to kx < n1/2, write back in place.
+//   k_zfwd : per (y, tile of kx lines): forward FFT in z, keep |kz| < n3/2,
+//            scale by 1/(p1 p3), write [n2][n1/2][n3].
+// Section 2.1 / Appendix A of the paper (3/2-rule zero padding, rotational
+// form of the non-linear term).
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace chn {
+
+static constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(256) k_zinv(ZinvArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+  const int y = blockIdx.y;
+  const int kx0 = blockIdx.x * a.K;
+  const int n1h = a.d.n1h, n3 = a.d.n3, p3 = a.d.p3, K = a.K, LS = a.lstride;
+  const int nk = min(K, n1h - kx0);
+  const int half = n3 / 2;
+  const int npad = p3 - 2 * half + 1;
+  const c2<T> zero = mk<T>(T(0), T(0));
+  for (int f = 0; f < a.nfields; ++f) {
+    for (int e = threadIdx.x; e < K * npad; e += blockDim.x) {
+      const int l = e / npad;
+      lds[l * LS + half + (e - l * npad)] = zero;
+    }
+    for (int e = threadIdx.x; e < K * n3; e += blockDim.x) {
+      const int l = e / n3, s = e - l * n3;
+      if (s == half) continue;
+      c2<T> v = zero;
+      if (l < nk) {
+        const size_t idx = ((size_t)y * n1h + kx0 + l) * n3 + s;
+        if (f == 4 && a.in[4] == nullptr) {
+          // omega2 = i (b u1 - a u3)
+          const int kz = s < half ? s : s - n3;
+          const T ka = T(kTwoPi * (kx0 + l) / a.d.lx), kb = T(kTwoPi * kz / a.d.lz);
+          const c2<T> u1 = a.in[0][idx], u3 = a.in[2][idx];
+          const c2<T> t = mk<T>(kb * u1.x - ka * u3.x, kb * u1.y - ka * u3.y);
+          v = mk<T>(-t.y, t.x);
+        } else {
+          v = a.in[f][idx];
+        }
+      }
+      lds[l * LS + (s < half ? s : p3 - (n3 - s))] = v;
+    }
+    __syncthreads();
+    fft_lines<T, MAXV>(lds, LS, K, a.plan, a.tw, +1);
+    c2<T>* out = a.out + ((size_t)(y * a.nslot + f) * p3) * n1h + kx0;
+    for (int e = threadIdx.x; e < nk * p3; e += blockDim.x) {
+      const int z = e / nk, l = e - z * nk;
+      out[(size_t)z * n1h + l] = lds[l * LS + z];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+  const int y = blockIdx.y;
+  const int z0 = blockIdx.x * 2;
+  const int n1h = a.d.n1h, p1 = a.d.p1, p3 = a.d.p3, LS = a.lstride;
+  const int npad = p1 - 2 * n1h + 1;
+  const c2<T> zero = mk<T>(T(0), T(0));
+  // --- load: line 3*row + pair holds field(2 pair) + i field(2 pair + 1), Hermitian-extended
+  for (int e = threadIdx.x; e < 6 * npad; e += blockDim.x) {
+    const int l = e / npad;
+    lds[l * LS + n1h + (e - l * npad)] = zero;
+  }
+  for (int e = threadIdx.x; e < 6 * n1h; e += blockDim.x) {
+    const int l = e / n1h, k = e - l * n1h;
+    const int row = l / 3, pr = l - row * 3;
+    const size_t base = ((size_t)(y * 6 + 2 * pr) * p3 + z0 + row) * n1h + k;
+    const c2<T> X = a.buf[base];
+    const c2<T> Y = a.buf[base + (size_t)p3 * n1h];
+    c2<T>* line = lds + l * LS;
+    if (k == 0) {
+      line[0] = mk<T>(X.x, Y.x);
+    } else {
+      line[k] = mk<T>(X.x - Y.y, X.y + Y.x);
+      line[p1 - k] = mk<T>(X.x + Y.y, Y.x - X.y);
+    }
+  }
+  __syncthreads();
+  fft_lines<T, MAXV>(lds, LS, 6, a.plan, a.tw, +1);
+  // --- products, row sums and CFL
+  double s1[2] = {0.0, 0.0}, s3[2] = {0.0, 0.0}, cf[2] = {0.0, 0.0};
+  const double idy = a.inv_dy[y];
+  for (int x = threadIdx.x; x < p1; x += blockDim.x) {
+    T h3[2];
+#pragma unroll
+    for (int row = 0; row < 2; ++row) {
+      const c2<T> Z0 = lds[(3 * row + 0) * LS + x];
+      const c2<T> Z1 = lds[(3 * row + 1) * LS + x];
+      const c2<T> Z2 = lds[(3 * row + 2) * LS + x];
+      const T u1 = Z0.x, u2 = Z0.y, u3 = Z1.x, o1 = Z1.y, o2 = Z2.x, o3 = Z2.y;
+      const T H1 = u2 * o3 - u3 * o2;
+      const T H2 = u3 * o1 - u1 * o3;
+      h3[row] = u1 * o2 - u2 * o1;
+      s1[row] += (double)H1;
+      s3[row] += (double)h3[row];
+      const double c = fabs((double)u1) * a.inv_dx + fabs((double)u2) * idy + fabs((double)u3) * a.inv_dz;
+      cf[row] = fmax(cf[row], c);
+      lds[(row)*LS + x] = mk<T>(H1, H2);  // line 0: row 0, line 1: row 1 (read above already)
+    }
+    lds[2 * LS + x] = mk<T>(h3[0], h3[1]);
+  }
+  // note: line 1 (row 0 pair 1) was read by this same thread before being overwritten
+  // block reductions (wave64 shuffles, then across the 4 waves)
+  double vals[6] = {s1[0], s1[1], s3[0], s3[1], cf[0], cf[1]};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    double v = vals[q];
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v, off);
+      v = q < 4 ? v + o : fmax(v, o);
+    }
+    vals[q] = v;
+  }
+  __shared__ double red6[6][4];
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) red6[q][wid] = vals[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int row = threadIdx.x;
+    const int nw = blockDim.x >> 6;
+    double t1 = 0.0, t3 = 0.0, tc = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      t1 += red6[0 + row][w];
+      t3 += red6[2 + row][w];
+      tc = fmax(tc, red6[4 + row][w]);
+    }
+    const size_t o = (size_t)y * p3 + z0 + row;
+    a.rowsum[o] = t1;
+    a.rowsum[(size_t)a.d.n2 * p3 + o] = t3;
+    a.rowcfl[o] = tc;
+  }
+  fft_lines<T, MAXV>(lds, LS, 3, a.plan, a.tw, -1);
+  // --- unpack two real spectra per line, truncate, store in place over fields 0..2
+  for (int e = threadIdx.x; e < 3 * n1h; e += blockDim.x) {
+    const int l = e / n1h, k = e - l * n1h;
+    const c2<T> W = lds[l * LS + k];
+    const c2<T> Wm = lds[l * LS + (k == 0 ? 0 : p1 - k)];
+    const c2<T> P = mk<T>(T(0.5) * (W.x + Wm.x), T(0.5) * (W.y - Wm.y));   // (W_k + conj W_m)/2
+    const c2<T> Q = mk<T>(T(0.5) * (W.y + Wm.y), T(-0.5) * (W.x - Wm.x));  // (W_k - conj W_m)/(2i)
+    if (l < 2) {  // row l: H1 = P, H2 = Q
+      a.buf[((size_t)(y * 6 + 0) * p3 + z0 + l) * n1h + k] = P;
+      a.buf[((size_t)(y * 6 + 1) * p3 + z0 + l) * n1h + k] = Q;
+    } else {      // H3 of rows 0 and 1
+      a.buf[((size_t)(y * 6 + 2) * p3 + z0 + 0) * n1h + k] = P;
+      a.buf[((size_t)(y * 6 + 2) * p3 + z0 + 1) * n1h + k] = Q;
+    }
+  }
+}
+
+template <typename T, typename TO, int MAXV>
+__global__ void __launch_bounds__(256) k_zfwd(ZfwdArgs<T, TO> a) {
+  extern __shared__ unsigned char smem_raw[];
+  c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
+  const int y = blockIdx.y;
+  const int kx0 = blockIdx.x * a.K;
+  const int n1h = a.d.n1h, n3 = a.d.n3, p3 = a.d.p3, K = a.K, LS = a.lstride;
+  const int nk = min(K, n1h - kx0);
+  const int half = n3 / 2;
+  const c2<T> zero = mk<T>(T(0), T(0));
+  for (int f = 0; f < 3; ++f) {
+    const c2<T>* in = a.buf + ((size_t)(y * 6 + f) * p3) * n1h + kx0;
+    for (int e = threadIdx.x; e < K * p3; e += blockDim.x) {
+      const int z = e / K, l = e - z * K;
+      lds[l * LS + z] = l < nk ? in[(size_t)z * n1h + l] : zero;
+    }
+    __syncthreads();
+    fft_lines<T, MAXV>(lds, LS, K, a.plan, a.tw, -1);
+    c2<TO>* out = a.out[f] + ((size_t)y * n1h + kx0) * n3;
+    for (int e = threadIdx.x; e < nk * n3; e += blockDim.x) {
+      const int l = e / n3, s = e - l * n3;
+      c2<TO> v = mk<TO>(TO(0), TO(0));
+      if (s != half) {
+        const c2<T> w = lds[l * LS + (s < half ? s : p3 - (n3 - s))];
+        v = mk<TO>(TO((double)w.x * a.scale), TO((double)w.y * a.scale));
+      }
+      out[(size_t)l * n3 + s] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename T> struct FftMaxv;
+template <> struct FftMaxv<double> { static constexpr int v = 24; };
+template <> struct FftMaxv<float> { static constexpr int v = 48; };
+
+template <typename T>
+hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st) {
+  constexpr int MV = FftMaxv<T>::v;
+  dim3 grid((a.d.n1h + a.K - 1) / a.K, a.d.n2);
+  size_t sh = (size_t)a.K * a.lstride * sizeof(c2<T>);
+  hipLaunchKernelGGL((k_zinv<T, MV>), grid, dim3(256), sh, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xpass(const XpassArgs<T>& a, hipStream_t st) {
+  constexpr int MV = FftMaxv<T>::v;
+  dim3 grid(a.d.p3 / 2, a.d.n2);
+  size_t sh = (size_t)6 * a.lstride * sizeof(c2<T>);
+  hipLaunchKernelGGL((k_xpass<T, MV>), grid, dim3(256), sh, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, typename TO>
+hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st) {
+  constexpr int MV = FftMaxv<T>::v;
+  dim3 grid((a.d.n1h + a.K - 1) / a.K, a.d.n2);
+  size_t sh = (size_t)a.K * a.lstride * sizeof(c2<T>);
+  hipLaunchKernelGGL((k_zfwd<T, TO, MV>), grid, dim3(256), sh, st, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_zinv<double>(const ZinvArgs<double>&, hipStream_t);
+template hipError_t launch_zinv<float>(const ZinvArgs<float>&, hipStream_t);
+template hipError_t launch_xpass<double>(const XpassArgs<double>&, hipStream_t);
+template hipError_t launch_xpass<float>(const XpassArgs<float>&, hipStream_t);
+template hipError_t launch_zfwd<double, double>(const ZfwdArgs<double, double>&, hipStream_t);
+template hipError_t launch_zfwd<float, float>(const ZfwdArgs<float, float>&, hipStream_t);
+template hipError_t launch_zfwd<float, double>(const ZfwdArgs<float, double>&, hipStream_t);
+
+}  // namespace chn

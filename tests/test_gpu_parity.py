@@ -1,0 +1,152 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Error metric: e(X) = ||X - X_oracle||_2 / ||X_oracle||_2 over all stored
+coefficients of a field.  Tolerances: float64 path 1e-11 per field after 10
+RK3 steps (chi, whose wall values come from a cancellation in the influence
+matrix, gets the bound derived in the design notes); mixed path 1e-5.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import compact, kmm
+
+torch = pytest.importorskip("torch")
+
+gpu = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1808_06461_amd import chn
+    if not os.path.exists(chn.LIB_PATH):
+        pytest.skip("libchn.so not built")
+    L = chn.lib()
+    names = chn.header_symbols()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _channel(case, y, precision="fp64"):
+    from paper_1808_06461_amd import Channel
+    return Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, mass_flux=case.mass_flux,
+                   precision=precision, y=y)
+
+
+def _setup(case, y):
+    return kmm.Setup(n1=case.n1, n2=case.n2, n3=case.n3, lx=case.lx, lz=case.lz, nu=1 / case.re_b,
+                     dt=case.dt, mass_flux=case.mass_flux, y=y)
+
+
+SMALL = synth.Case(n1=16, n2=33, n3=16, lx=2 * np.pi, lz=np.pi, re_b=2800.0, dt=0.005, amp=0.1,
+                   kmax=5, cfg=21)
+RAGGED = synth.Case(n1=24, n2=25, n3=12, lx=2 * np.pi, lz=np.pi / 2, re_b=1500.0, dt=0.004, amp=0.1,
+                    kmax=None, cfg=22)
+
+
+@gpu
+@pytest.mark.parametrize("n2", [33, 65, 193])
+def test_operators_match_oracle(n2):
+    y = synth.mesh_tanh(n2)
+    case = synth.Case(n1=8, n2=n2, n3=8, lx=2 * np.pi, lz=np.pi, re_b=1000.0, dt=0.01)
+    ch = _channel(case, y)
+    a1, b1, a2, b2, w = ch.operators()
+    A1, B1 = compact.operators(y, 1)
+    A2, B2 = compact.operators(y, 2)
+    for got, ref in ((a1, A1), (b1, B1), (a2, A2), (b2, B2)):
+        # within one rounding of the exactly-rational coefficients
+        scale = np.maximum(np.abs(ref), 1e-16 * np.abs(ref).max(axis=1, keepdims=True))
+        d = np.abs(got - ref) / scale
+        assert d.max() < 2.3e-16, d.max()
+    assert np.abs(w - compact.quadrature_weights(y)).max() < 1e-16
+    ch.close()
+
+
+@gpu
+@pytest.mark.parametrize("case", [SMALL, RAGGED], ids=["small", "ragged"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("mixed", 2e-6)])
+def test_nonlinear_term_parity(case, precision, tol):
+    v, om, U1, U3, y = synth.turbulent_field(case)
+    S = _setup(case, y)
+    st = kmm.make_state(S, v, om, U1, U3)
+    fields = kmm.recover(S, st)
+    ref = kmm.nonlinear(S, fields)
+    ch = _channel(case, y, precision)
+    got = [h.cpu().numpy() for h in ch.nonlinear([torch.from_numpy(f) for f in fields])]
+    for g, r, name in zip(got, ref, ("H1", "H2", "H3")):
+        e = rel(g, r)
+        print(f"{precision} {name}: {e:.2e}")
+        assert e < tol, (name, e)
+    ch.close()
+
+
+@gpu
+@pytest.mark.parametrize("case", [SMALL, RAGGED], ids=["small", "ragged"])
+def test_set_state_and_recovery_parity(case):
+    v, om, U1, U3, y = synth.turbulent_field(case)
+    S = _setup(case, y)
+    st = kmm.make_state(S, v, om, U1, U3)
+    u1, u2, u3, o1, o2, o3 = kmm.recover(S, st)
+    ch = _channel(case, y)
+    ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    got = {k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "chi", "u1", "u3", "omega1",
+                                                        "omega3", "u1mean").items()}
+    for name, r in (("v", st.v), ("omega2", st.om2), ("chi", st.chi), ("u1", u1), ("u3", u3),
+                    ("omega1", o1), ("omega3", o3), ("u1mean", st.U1)):
+        e = rel(got[name], r)
+        print(f"{name}: {e:.2e}")
+        # omega1/omega3 chain two compact D1 solves (cond(A1) ~ 1e4)
+        assert e < 1e-12, (name, e)
+    ch.close()
+
+
+@gpu
+@pytest.mark.parametrize("case", [SMALL, RAGGED], ids=["small", "ragged"])
+def test_one_step_parity(case):
+    v, om, U1, U3, y = synth.turbulent_field(case)
+    S = _setup(case, y)
+    ref, f = kmm.step(S, kmm.make_state(S, v, om, U1, U3), 1)
+    ch = _channel(case, y)
+    ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    info = ch.step(case.dt, 1, info=True)
+    got = {k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "chi", "u1mean", "u3mean").items()}
+    for name, r in (("v", ref.v), ("omega2", ref.om2), ("chi", ref.chi), ("u1mean", ref.U1)):
+        e = rel(got[name], r)
+        print(f"{name}: {e:.2e}")
+        # chi's wall rows are set by the influence-matrix cancellation; on these
+        # coarse test meshes the oracle's own sensitivity to 2 ulp noise in H is ~1e-10
+        assert e < (1e-9 if name == "chi" else 1e-11), (name, e)
+    assert np.abs(got["u3mean"] - ref.U3).max() < 1e-13
+    assert abs(info["f_mean"] - f) < 1e-9 * abs(f)
+    assert abs(info["mass_flux"] - case.mass_flux) < 1e-13
+    ch.close()
+
+
+@gpu
+def test_c1_ten_steps_fp64():
+    """The 64 x 65 x 64, Re_tau ~ 180 workload: 10 RK3 steps at dt = 0.005."""
+    case = synth.CASES["c1"]
+    v, om, U1, U3, y = synth.turbulent_field(case)
+    S = _setup(case, y)
+    ref, f = kmm.step(S, kmm.make_state(S, v, om, U1, U3), 10)
+    ru = kmm.recover(S, ref)
+    ch = _channel(case, y)
+    ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    ch.step(case.dt, 10)
+    got = {k: t.cpu().numpy() for k, t in ch.get_fields(
+        "v", "omega2", "chi", "u1", "u3", "omega1", "omega3", "u1mean", "u3mean").items()}
+    errs = {}
+    for name, r in (("v", ref.v), ("omega2", ref.om2), ("u1", ru[0]), ("u3", ru[2]), ("omega1", ru[3]),
+                    ("omega3", ru[5]), ("u1mean", ref.U1), ("chi", ref.chi)):
+        errs[name] = rel(got[name], r)
+        print(f"{name}: {errs[name]:.2e}")
+    for name, e in errs.items():
+        assert e < 1e-11, (name, e)
+    assert np.abs(got["u3mean"] - ref.U3).max() < 1e-13
+    ch.close()
