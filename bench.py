@@ -1,0 +1,155 @@
+"""Throughput of the channel RK3 step on one MI355X: grid points x RK3 steps per second.
+
+Workload: the 384 x 193 x 384 channel at Re_tau ~ 550 (Re_b = 10000, box
+2pi x 2 x pi, dt from CFL 0.5 at t = 0), seeded k^-5/3 divergence-free
+perturbations on a turbulent mean profile.  Both precisions run from the same
+initial state: the mixed path (FP32 transforms and products, FP64 solves,
+mean modes and mass flux) gives `value`; the FP64 path and the relative
+difference between the two after warmup + steps are reported beside it.
+
+Prints one JSON line (rank 0).  Only single-GPU runs are supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-points x RK3 steps/sec, mixed-prec vs FP64 GPU at stated rel. error"
+UNIT = "grid-points*RK3-steps/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(kind, n1, n2, n3, elem):
+    """Bytes one launch of a kernel kind must move (inputs read once, outputs written once)."""
+    n1h, p3 = n1 // 2, 3 * n3 // 2
+    NP = n2 * n1h * n3          # mode-points per spectral field
+    IP = n2 * p3 * n1h          # points per field of the z-padded intermediate
+    return {
+        "recover": (32 + 5 * elem) * NP,          # v, omega2 (fp64) -> u1 u2 u3 o1 o3
+        "zinv": 5 * elem * NP + 6 * elem * IP,    # 5 spectral fields -> 6 padded lines
+        "xpass": 6 * elem * IP + 3 * elem * IP,   # 6 fields in, H1 H2 H3 out
+        "zfwd": 3 * elem * IP + 3 * elem * NP,    # 3 padded fields -> 3 spectral
+        "advance": (3 * elem + 64 + 80) * NP,     # H, chi, om2, 2 histories -> chi, om2, v, 2 histories
+    }[kind]
+
+
+def run_path(case, v, om, U1, U3, y, precision, steps, warmup):
+    import torch
+
+    from paper_1808_06461_amd import Channel
+    ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, mass_flux=case.mass_flux,
+                 precision=precision, y=y)
+    ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    if warmup:
+        ch.step(case.dt, warmup)
+    ch.timing(True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    ch.step(case.dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    kern = ch.timing_read()
+    ch.timing(False)
+    fields = {k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "u1", "u3", "u1mean").items()}
+    ch.close()
+    return ms, wall, kern, fields
+
+
+def cpu_baseline(case, v, om, U1, U3, y):
+    """The oracle on the host: one RK3 sub-step of the same workload, scaled to a step."""
+    from oracle import kmm
+    S = kmm.Setup(n1=case.n1, n2=case.n2, n3=case.n3, lx=case.lx, lz=case.lz, nu=1 / case.re_b,
+                  dt=case.dt, mass_flux=case.mass_flux, y=y)
+    st = kmm.make_state(S, v, om, U1, U3)
+    t0 = time.perf_counter()
+    kmm.substep(S, st, kmm.zero_history(S), 0)
+    t = time.perf_counter() - t0
+    G = case.n1 * case.n2 * case.n3
+    return {"value": G / (3 * t), "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"one RK3 sub-step (of 3) of the {case.n1}x{case.n2}x{case.n3} workload, "
+                      f"{t:.1f} s, numpy/pocketfft single thread, scaled x3 to a step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+    case = synth.CASES["c2"]
+    v, om, U1, U3, y = synth.turbulent_field(case)
+    G = case.n1 * case.n2 * case.n3
+
+    res = {}
+    for prec in ("fp64", "mixed"):
+        print(f"[bench] {prec}: {args.warmup} warmup + {args.steps} timed RK3 steps", file=sys.stderr, flush=True)
+        res[prec] = run_path(case, v, om, U1, U3, y, prec, args.steps, args.warmup)
+    ms_mixed, _, kern, fm = res["mixed"]
+    ms_fp64, _, kern64, f64 = res["fp64"]
+    step_ms = ms_mixed / args.steps
+    value = G * args.steps / (ms_mixed / 1e3)
+    errs = {k: float(np.linalg.norm(fm[k] - f64[k]) / np.linalg.norm(f64[k])) for k in fm}
+
+    # roofline of the dominant kernel of the mixed path
+    dom = max(kern, key=lambda k: kern[k][0])
+    tot, cnt = kern[dom]
+    avg_s = tot / cnt / 1e3
+    elem = 8
+    alg = algorithmic_bytes(dom, case.n1, case.n2, case.n3, elem)
+    achieved = alg / avg_s / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    per_kernel = {}
+    for k, (t, n) in kern.items():
+        if n:
+            b = algorithmic_bytes(k, case.n1, case.n2, case.n3, elem)
+            per_kernel[k] = {"avg_ms": round(t / n, 4), "launches": n, "alg_GBps": round(b / (t / n / 1e3) / 1e9, 1)}
+    per_kernel64 = {}
+    for k, (t, n) in kern64.items():
+        if n:
+            b = algorithmic_bytes(k, case.n1, case.n2, case.n3, 16)
+            per_kernel64[k] = {"avg_ms": round(t / n, 4), "launches": n, "alg_GBps": round(b / (t / n / 1e3) / 1e9, 1)}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 transforms/products + f64 solves", "data": "synthetic",
+        "config": {"workload": "channel 384x193x384 (Re_tau~550, Re_b=10000, box 2pi x 2 x pi), "
+                               "k^-5/3 perturbations on a Reichardt mean, dt at CFL 0.5, mixed precision",
+                   "grid_points": G, "dt": case.dt},
+        "fp64": {"value": G * args.steps / (ms_fp64 / 1e3), "ms_per_step": ms_fp64 / args.steps,
+                 "kernels": per_kernel64},
+        "mixed_vs_fp64_rel_err": errs,
+        "speedup_mixed_over_fp64": ms_fp64 / ms_mixed,
+        "kernels": per_kernel,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, one sub-step)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(case, v, om, U1, U3, y)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

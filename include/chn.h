@@ -161,6 +161,26 @@ chn_status chn_filter_and_stress(chn_ctx *ctx, int32_t kcx, int32_t kcz, int32_t
 chn_status chn_get_operators(chn_ctx *ctx, double *a1, double *b1, double *a2, double *b2,
                              double *quad);
 
+/* Kernel kinds reported by chn_timing_read. */
+enum {
+  CHN_K_RECOVER = 0, /* velocities/vorticities from v, omega2 (pencils) */
+  CHN_K_ZINV = 1,    /* padded inverse transform in z (planes) */
+  CHN_K_XPASS = 2,   /* inverse x transforms, u x omega, forward x transforms */
+  CHN_K_ZFWD = 3,    /* forward transform in z with truncation */
+  CHN_K_ADVANCE = 4, /* forcings, implicit steps, influence matrix, mean modes */
+  CHN_K_FILTER = 5,  /* kernels of the low-storage stage */
+  CHN_K_COUNT = 6
+};
+
+/* Per-kernel timing.  With enable != 0 every later kernel launch of the
+ * context is bracketed by two HIP events recorded on the context's stream;
+ * enabling or disabling discards earlier records. */
+chn_status chn_timing_enable(chn_ctx *ctx, int32_t enable);
+
+/* Sum of the recorded durations (ms) and the number of launches of one
+ * kernel kind since chn_timing_enable.  Synchronises. */
+chn_status chn_timing_read(chn_ctx *ctx, int32_t kind, double *total_ms, int32_t *count);
+
 /* Message of the last failing call on ctx (or of the last failing
  * chn_create if ctx is NULL). */
 const char *chn_last_error(const chn_ctx *ctx);

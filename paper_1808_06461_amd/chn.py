@@ -56,10 +56,13 @@ def lib():
         L.chn_nonlinear.argtypes = [P, C.POINTER(P), C.POINTER(P)]
         L.chn_filter_and_stress.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P]
         L.chn_get_operators.argtypes = [P, P, P, P, P, P]
+        L.chn_timing_enable.argtypes = [P, C.c_int32]
+        L.chn_timing_read.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.chn_last_error.argtypes = [P]
         L.chn_last_error.restype = C.c_char_p
         for name in ("chn_create", "chn_destroy", "chn_set_state", "chn_step_rk3", "chn_get_fields",
-                     "chn_nonlinear", "chn_filter_and_stress", "chn_get_operators"):
+                     "chn_nonlinear", "chn_filter_and_stress", "chn_get_operators", "chn_timing_enable",
+                     "chn_timing_read"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -174,6 +177,20 @@ class Channel:
         self._check(self.L.chn_get_operators(self.ctx, *[C.c_void_p(a.ctypes.data) for a in arrs]),
                     "chn_get_operators")
         return arrs
+
+    KERNELS = ("recover", "zinv", "xpass", "zfwd", "advance", "filter")
+
+    def timing(self, enable=True):
+        self._check(self.L.chn_timing_enable(self.ctx, 1 if enable else 0), "chn_timing_enable")
+
+    def timing_read(self):
+        """{kernel kind: (total ms, launches)} since timing() was enabled."""
+        out = {}
+        for k, name in enumerate(self.KERNELS):
+            ms, n = C.c_double(), C.c_int32()
+            self._check(self.L.chn_timing_read(self.ctx, k, C.byref(ms), C.byref(n)), "chn_timing_read")
+            out[name] = (ms.value, n.value)
+        return out
 
     def close(self):
         if getattr(self, "ctx", None):

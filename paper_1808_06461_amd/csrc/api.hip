@@ -47,7 +47,7 @@ struct chn_ctx {
   hipStream_t stream = nullptr;
   int n1 = 0, n2 = 0, n3 = 0, n1h = 0, M = 0, p1 = 0, p3 = 0;
   double nu = 0.0;
-  bool mixed = false, have_state = false;
+  bool mixed = false, have_state = false, phase_valid = false;
   chn_status sticky = CHN_OK;
   std::string err;
   size_t ws_bytes = 0;
@@ -72,6 +72,15 @@ struct chn_ctx {
   chn::PencilGeom geom{};
   chn::PlaneDims dims{};
   int lds_max = 65536;  // bytes of LDS one workgroup may use on this device
+  // per-kernel timing (chn_timing_enable): events bracketing every launch
+  bool timing = false;
+  struct Timed { int kind; hipEvent_t a, b; };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  ~chn_ctx() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -109,7 +118,7 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
   double* tabs = D((size_t)n2 * (4 * 7 + 3 * 3 + 3 * 4 + 4));
   void* tw1 = cv.take(te * (size_t)p1);
   void* tw3 = cv.take(te * (size_t)p3);
-  double* mean_scr = D(3 * (size_t)n2 * 5 + 2 * (size_t)n2);
+  double* mean_scr = D(3 * (size_t)n2 * 5 + 4 * (size_t)n2);
   double* mean_out = D(8);
   double* info = D(8);
   if (x) {
@@ -168,6 +177,27 @@ chn_status fail(chn_ctx* x, chn_status s, const std::string& m) {
       return fail((ctx), CHN_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
 
+hipEvent_t pool_event(chn_ctx* x) {
+  if (x->pool_used == x->pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    x->pool.push_back(e);
+  }
+  return x->pool[x->pool_used++];
+}
+
+// Runs one kernel launch; with timing on, brackets it with events on the context's stream.
+template <typename F> hipError_t timed(chn_ctx* x, int kind, F&& launch) {
+  if (!x->timing) return launch();
+  hipEvent_t a = pool_event(x), b = pool_event(x);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, x->stream);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, x->stream);
+  if (e == hipSuccess) x->timed.push_back({kind, a, b});
+  return e;
+}
+
 template <typename T> struct Ty;
 template <> struct Ty<double> { using c = double2; };
 template <> struct Ty<float> { using c = float2; };
@@ -201,7 +231,7 @@ chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, voi
   za.lstride = x->p3 + 1;
   za.nfields = 6;
   za.nslot = 6;
-  HIPCHK(x, chn::launch_zinv<T>(za, x->stream));
+  HIPCHK(x, timed(x, CHN_K_ZINV, [&] { return chn::launch_zinv<T>(za, x->stream); }));
   chn::XpassArgs<T> xa{};
   xa.buf = reinterpret_cast<C*>(x->inter);
   xa.tw = reinterpret_cast<const C*>(x->tw1);
@@ -213,7 +243,7 @@ chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, voi
   xa.inv_dx = x->n1 / x->cfg.lx;
   xa.inv_dz = x->n3 / x->cfg.lz;
   xa.inv_dy = x->inv_dy;
-  HIPCHK(x, chn::launch_xpass<T>(xa, x->stream));
+  HIPCHK(x, timed(x, CHN_K_XPASS, [&] { return chn::launch_xpass<T>(xa, x->stream); }));
   chn::ZfwdArgs<T, TO> fa{};
   fa.buf = reinterpret_cast<const C*>(x->inter);
   for (int f = 0; f < 3; ++f) fa.out[f] = reinterpret_cast<typename Ty<TO>::c*>(out[f]);
@@ -223,7 +253,7 @@ chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, voi
   fa.K = K;
   fa.lstride = x->p3 + 1;
   fa.scale = 1.0 / ((double)x->p1 * x->p3);
-  HIPCHK(x, (chn::launch_zfwd<T, TO>(fa, x->stream)));
+  HIPCHK(x, timed(x, CHN_K_ZFWD, [&] { return chn::launch_zfwd<T, TO>(fa, x->stream); }));
   return CHN_OK;
 }
 
@@ -238,22 +268,36 @@ template <typename TP> chn_status recover(chn_ctx* x, TP* const* out) {
   ra.S0 = x->S[0];
   ra.S1 = x->S[1];
   ra.S2 = x->S[2];
-  HIPCHK(x, chn::launch_recover<TP>(ra, x->stream));
+  HIPCHK(x, timed(x, CHN_K_RECOVER, [&] { return chn::launch_recover<TP>(ra, x->stream); }));
   return CHN_OK;
 }
 
+template <typename T> T* const* phase_ptrs(chn_ctx* x, T** po) {
+  po[0] = reinterpret_cast<T*>(x->ph[0]);
+  po[1] = reinterpret_cast<T*>(x->ph[1]);
+  po[2] = reinterpret_cast<T*>(x->ph[2]);
+  po[3] = reinterpret_cast<T*>(x->ph[3]);
+  po[4] = reinterpret_cast<T*>(x->ph[5]);
+  return po;
+}
+
 template <typename T> chn_status substep(chn_ctx* x, int s, double dt) {
-  // 1. velocities and vorticities into the phase buffers (u1, u2, u3, o1, -, o3)
-  T* po[5] = {reinterpret_cast<T*>(x->ph[0]), reinterpret_cast<T*>(x->ph[1]), reinterpret_cast<T*>(x->ph[2]),
-              reinterpret_cast<T*>(x->ph[3]), reinterpret_cast<T*>(x->ph[5])};
-  chn_status st = recover<T>(x, po);
-  if (st != CHN_OK) return st;
+  T* po[5];
+  phase_ptrs<T>(x, po);
+  // 1. velocities and vorticities of the state (after set_state or chn_nonlinear;
+  //    otherwise the previous sub-step's advance kernel already wrote them)
+  if (!x->phase_valid) {
+    chn_status st = recover<T>(x, po);
+    if (st != CHN_OK) return st;
+    x->phase_valid = true;
+  }
   // 2. dealiased u x omega
-  st = plane_phase<T, T>(x, x->ph, false, x->H);
+  chn_status st = plane_phase<T, T>(x, x->ph, false, x->H);
   if (st != CHN_OK) return st;
-  // 3. pencils + mean modes
-  chn::AdvanceArgs<T> aa{};
+  // 3. pencils + mean modes + next sub-step's velocities and vorticities
+  chn::AdvanceArgs<T, T> aa{};
   aa.g = x->geom;
+  for (int f = 0; f < 5; ++f) aa.ph[f] = po[f];
   for (int f = 0; f < 3; ++f) aa.H[f] = reinterpret_cast<const T*>(x->H[f]);
   aa.v = x->v; aa.chi = x->chi; aa.om2 = x->om2;
   aa.nchi_old = x->nchi_old; aa.nom_old = x->nom_old;
@@ -267,7 +311,7 @@ template <typename T> chn_status substep(chn_ctx* x, int s, double dt) {
   aa.mass_flux = x->cfg.mass_flux;
   aa.dt = dt; aa.nu = x->nu;
   aa.al = kAlpha[s]; aa.be = kBeta[s]; aa.ga = kGamma[s]; aa.ze = kZeta[s];
-  HIPCHK(x, chn::launch_advance<T>(aa, x->stream));
+  HIPCHK(x, timed(x, CHN_K_ADVANCE, [&] { return chn::launch_advance<T, T>(aa, x->stream); }));
   return CHN_OK;
 }
 
@@ -418,6 +462,7 @@ chn_status chn_set_state(chn_ctx* x, const double* d_v, const double* d_om2, con
   HIPCHK(x, hipMemsetAsync(x->nu_old, 0, n2b, x->stream));
   HIPCHK(x, hipMemsetAsync(x->nw_old, 0, n2b, x->stream));
   x->have_state = true;
+  x->phase_valid = false;
   return CHN_OK;
 }
 
@@ -503,6 +548,7 @@ chn_status chn_nonlinear(chn_ctx* x, const double* const* d_in, double* const* d
     return plane_phase<double, double>(x, in, true, out);
   }
   const size_t n = 2 * (size_t)x->n2 * x->M;
+  x->phase_valid = false;  // the phase buffers now hold the caller's fields
   for (int f = 0; f < 6; ++f)
     HIPCHK(x, chn::launch_convert_d2f(d_in[f], reinterpret_cast<float*>(x->ph[f]), n, x->stream));
   void* out[3];
@@ -525,6 +571,32 @@ chn_status chn_get_operators(chn_ctx* x, double* a1, double* b1, double* a2, dou
   if (a2) std::memcpy(a2, x->hA2.data(), nb);
   if (b2) std::memcpy(b2, x->hB2.data(), nb);
   if (quad) std::memcpy(quad, x->hquad.data(), sizeof(double) * x->n2);
+  return CHN_OK;
+}
+
+chn_status chn_timing_enable(chn_ctx* x, int32_t enable) {
+  if (chn_status s = check(x)) return s;
+  x->timing = enable != 0;
+  x->timed.clear();
+  x->pool_used = 0;
+  return CHN_OK;
+}
+
+chn_status chn_timing_read(chn_ctx* x, int32_t kind, double* total_ms, int32_t* count) {
+  if (chn_status s = check(x)) return s;
+  if (!total_ms || !count || kind < 0 || kind >= CHN_K_COUNT) return fail(x, CHN_EINVAL, "bad timing query");
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  double t = 0.0;
+  int n = 0;
+  for (const auto& r : x->timed) {
+    if (r.kind != kind) continue;
+    float ms = 0.0f;
+    HIPCHK(x, hipEventElapsedTime(&ms, r.a, r.b));
+    t += ms;
+    ++n;
+  }
+  *total_ms = t;
+  *count = n;
   return CHN_OK;
 }
 

@@ -75,9 +75,10 @@ template <typename TP> struct RecoverArgs {
   double* S2;
 };
 
-template <typename TH> struct AdvanceArgs {
+template <typename TH, typename TP> struct AdvanceArgs {
   PencilGeom g;
   const TH* H[3];             // H1, H2, H3 (interleaved complex [n2][M])
+  TP* ph[5];                  // next sub-step's u1, u2, u3, omega1, omega3 (interleaved complex)
   double* v;                  // state, updated
   double* chi;
   double* om2;
@@ -93,7 +94,7 @@ template <typename TH> struct AdvanceArgs {
   const double* rowsum;       // [2][n2][p3]
   int p3;
   double inv_p1p3;
-  double* mean_scr;           // [3][n2][5]
+  double* mean_scr;           // [3][n2][5] solves, then NU, NW, D1 U1, D1 U3 [n2] each
   double* mean_out;           // [0]: mean pressure gradient of the sub-step
   double mass_flux;
   double dt, nu, al, be, ga, ze;
@@ -120,7 +121,7 @@ struct InfoArgs {
 };
 
 template <typename TP> hipError_t launch_recover(const RecoverArgs<TP>& a, hipStream_t st);
-template <typename TH> hipError_t launch_advance(const AdvanceArgs<TH>& a, hipStream_t st);
+template <typename TH, typename TP> hipError_t launch_advance(const AdvanceArgs<TH, TP>& a, hipStream_t st);
 hipError_t launch_chi_from_v(const ChiArgs& a, hipStream_t st);
 hipError_t launch_info(const InfoArgs& a, hipStream_t st);
 hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_t st);

@@ -87,6 +87,19 @@ template <> __device__ __forceinline__ double2 load_c<float>(const float* p, siz
   return make_double2((double)f.x, (double)f.y);
 }
 
+// element at a byte offset from a (wave-uniform) base
+template <typename T> __device__ __forceinline__ T& at(T* base, unsigned boff) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff);
+}
+template <typename T> __device__ __forceinline__ const T& at(const T* base, unsigned boff) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+}
+
+// one real component (c = 0: real part, 1: imaginary part) of a complex entry
+template <typename T> __device__ __forceinline__ double load_r(const T* p, size_t idx, int c) {
+  return (double)p[2 * idx + c];
+}
+
 // ---------------------------------------------------------------- recovery
 template <typename TP>
 __global__ void __launch_bounds__(256) k_recover(RecoverArgs<TP> a) {
@@ -176,14 +189,47 @@ __global__ void __launch_bounds__(256) k_recover(RecoverArgs<TP> a) {
   }
 }
 
+// ---------------------------------------------------------------- pipelining
+// Software pipeline over T steps of a sweep: the loads of step t + D are
+// issued right after step t is processed, so D rows of loads are in flight
+// while the recurrence advances (the sweeps are otherwise latency-bound:
+// one dependent row per iteration).  load(t, buf) must accept t >= T.
+template <int D, typename B, typename LoadF, typename StepF>
+__device__ __forceinline__ void pipeline(int T, LoadF&& load, StepF&& step) {
+  B buf[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) load(k, buf[k]);
+  for (int t0 = 0; t0 < T; t0 += D) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int t = t0 + k;
+      if (t < T) {
+        step(t, buf[k]);
+        load(t + D, buf[k]);
+      }
+    }
+  }
+}
+
+template <typename T> __device__ __forceinline__ void store_c(T* p, size_t idx, double x, double y);
+template <> __device__ __forceinline__ void store_c<double>(double* p, size_t idx, double x, double y) {
+  reinterpret_cast<double2*>(p)[idx] = make_double2(x, y);
+}
+template <> __device__ __forceinline__ void store_c<float>(float* p, size_t idx, double x, double y) {
+  reinterpret_cast<float2*>(p)[idx] = make_float2((float)x, (float)y);
+}
+
 // ---------------------------------------------------------------- mean modes
-template <typename TH>
-__device__ void mean_block(const AdvanceArgs<TH>& a) {
+// One workgroup: U1 with constant mass flux and U3 (float64, Section 2.1),
+// then the (0,0) entries of the next sub-step's velocity/vorticity fields.
+template <typename TH, typename TP>
+__device__ void mean_block(const AdvanceArgs<TH, TP>& a) {
   const PencilGeom& g = a.g;
   const int n = g.n2;
   const int t = threadIdx.x;
   double* NU = a.mean_scr + 3 * (size_t)n * 5;
   double* NW = NU + n;
+  double* DU = NW + n;  // D1 U1, D1 U3
   // plane means of H1 and H3: float64 sums of the per-row sums over x
   if (t < 64) {
     for (int r = t; r < n; r += 64) {
@@ -200,7 +246,7 @@ __device__ void mean_block(const AdvanceArgs<TH>& a) {
   }
   __syncthreads();
   // three serial solves with M0 = A2 - cb B2 (Dirichlet end rows): role 0 the
-  // particular U1, role 1 the mass-flux influence function (rhs 1), role 2 U3
+  // particular U1, role 1 the mass-flux influence function (rhs A2 1), role 2 U3
   const double cb = a.dt * a.be * a.nu, f2 = a.al * a.dt * a.nu;
   if (t < 3) {
     const double* X = t == 2 ? a.U3 : a.U1;
@@ -236,24 +282,24 @@ __device__ void mean_block(const AdvanceArgs<TH>& a) {
         m7[6 - d] -= lm * U[3];
         rhs -= lm * yb[3 - d];
       }
-      double* s = scr + (size_t)r * 5;
-      s[0] = 1.0 / m7[3];
-      s[1] = m7[4];
-      s[2] = m7[5];
-      s[3] = m7[6];
-      s[4] = rhs;
+      double* sr = scr + (size_t)r * 5;
+      sr[0] = 1.0 / m7[3];
+      sr[1] = m7[4];
+      sr[2] = m7[5];
+      sr[3] = m7[6];
+      sr[4] = rhs;
       for (int q = 0; q < 2; ++q)
         for (int k = 0; k < 4; ++k) uh[q][k] = uh[q + 1][k];
-      for (int k = 0; k < 4; ++k) uh[2][k] = s[k];
+      for (int k = 0; k < 4; ++k) uh[2][k] = sr[k];
       yb[0] = yb[1];
       yb[1] = yb[2];
       yb[2] = rhs;
     }
     double xb[3] = {0, 0, 0};
     for (int r = n - 1; r >= 0; --r) {
-      double* s = scr + (size_t)r * 5;
-      const double x = (s[4] - s[1] * xb[0] - s[2] * xb[1] - s[3] * xb[2]) * s[0];
-      s[4] = x;
+      double* sr = scr + (size_t)r * 5;
+      const double x = (sr[4] - sr[1] * xb[0] - sr[2] * xb[1] - sr[3] * xb[2]) * sr[0];
+      sr[4] = x;
       push_x(xb, x);
     }
   }
@@ -278,15 +324,71 @@ __device__ void mean_block(const AdvanceArgs<TH>& a) {
     }
     if (t == 0) a.mean_out[0] = phi / (a.dt * (a.al + a.be));
   }
+  __syncthreads();
+  // D1 U1 (lane 0) and D1 U3 (lane 1) with the precomputed LU of A1
+  if (t < 2) {
+    const double* X = t == 0 ? a.U1 : a.U3;
+    double* Y = DU + (size_t)t * n;
+    double yb[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+      double r = 0.0;
+      for (int o = 0; o < 7; ++o) {
+        const int j = i + o - 3;
+        if (j >= 0 && j < n) r += g.B1[i * 7 + o] * X[j];
+      }
+      const double yi = elim3(r, g.L1d + i * 3, yb);
+      Y[i] = yi;
+      yb[0] = yb[1];
+      yb[1] = yb[2];
+      yb[2] = yi;
+    }
+    double xb[3] = {0, 0, 0};
+    for (int i = n - 1; i >= 0; --i) {
+      const double x = back3(Y[i], g.U1d + i * 4, xb);
+      Y[i] = x;
+      push_x(xb, x);
+    }
+  }
+  __syncthreads();
+  // (0,0) entries of the next sub-step's fields: u1 = U1, u3 = U3,
+  // omega1 = D1 U3, omega3 = -D1 U1, u2 = 0
+  if (t < 64) {
+    for (int r = t; r < n; r += 64) {
+      const size_t m0 = (size_t)r * g.M;
+      store_c<TP>(a.ph[0], m0, a.U1[r], 0.0);
+      store_c<TP>(a.ph[1], m0, 0.0, 0.0);
+      store_c<TP>(a.ph[2], m0, a.U3[r], 0.0);
+      store_c<TP>(a.ph[3], m0, DU[n + r], 0.0);
+      store_c<TP>(a.ph[4], m0, -DU[r], 0.0);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- advance
-template <typename TH>
-__global__ void __launch_bounds__(256) k_advance(AdvanceArgs<TH> a) {
+// One sub-step of the pencil phase, fused with the recovery of the next
+// sub-step's velocities and vorticities:
+//   S1 down : G = i(a H1 + b H3); eliminate A1 (dG) = B1 G
+//   S2 up   : finish dG; N_chi, N_omega2; implicit right-hand sides (lag 3);
+//             Helmholtz factor on the fly; eliminate chi_p, omega2, chi_h
+//   S3 down : finish chi_p, omega2, chi_h; Poisson rhs (lag 3); P factor on
+//             the fly; eliminate v_p, v_h
+//   S4 up   : finish v_p, v_h; dense wall rows of D1; 2x2 influence system
+//   S5 down : v, chi = particular + c_lo, c_hi homogeneous; eliminate A1 (dv) = B1 v
+//   R2 up   : finish dv; u1, u3 by continuity; eliminate A1 (du) = B1 u
+//   R3 down : finish du1, du3; omega1 = du3 - i b v, omega3 = i a v - du1
+template <typename TH, typename TP>
+__global__ void __launch_bounds__(256)
+    k_advance(AdvanceArgs<TH, TP> a,
+              // read-only tables as noalias parameters, so the wave-uniform row
+              // loads go through the scalar cache instead of vector registers
+              const double* __restrict__ B1, const double* __restrict__ A2, const double* __restrict__ B2,
+              const double* __restrict__ L1d, const double* __restrict__ U1d, const double* __restrict__ L1u,
+              const double* __restrict__ U1u, const double* __restrict__ clo, const double* __restrict__ chw) {
   if (blockIdx.x == gridDim.x - 1) {
     mean_block(a);
     return;
   }
+  constexpr int D = 4, D2 = 3, D3 = 3;
   const PencilGeom& g = a.g;
   const Lane L = lane_setup(g);
   const int n = g.n2;
@@ -298,221 +400,277 @@ __global__ void __launch_bounds__(256) k_advance(AdvanceArgs<TH> a) {
   const double f2 = a.al * a.dt * a.nu;
   const double dga = a.dt * a.ga, dze = a.dt * a.ze;
   const double hk = 1.0 + cb * L.k2;
+  const bool wph = L.act && L.m != 0;  // the (0,0) phase entries come from the mean block
+  // Row bases are wave-uniform (scalar registers); per-lane offsets are
+  // 32-bit byte offsets, so every access is one scalar base + one shared VGPR.
+  const unsigned ocol = 2u * (unsigned)L.m + (1u - (unsigned)L.c);  // the other component
+  const unsigned bcol = 8u * (unsigned)col, bocol = 8u * ocol, bm = 8u * (unsigned)L.m;
+  const unsigned hcol = (unsigned)sizeof(TH) * (unsigned)col, hocol = (unsigned)sizeof(TH) * ocol;
+  const unsigned pcol = (unsigned)sizeof(TP) * (unsigned)col;
+  auto LR = [&](auto* p, int i) { return p + (size_t)i * st; };       // lane-indexed [n2][2M]
+  auto MR = [&](auto* p, int i) { return p + (size_t)i * M; };        // mode-indexed [n2][M]
+  auto HR = [&](const TH* p, int i) { return p + 2 * (size_t)i * M; };
 
-  auto gval = [&](int i) -> double {
+  // G = i(a H1 + b H3): lane c needs the other component (oc) of H1 and H3
+  const double sg = L.c == 0 ? -1.0 : 1.0;
+  auto gval = [&](double h1o, double h3o) -> double {
     if (!L.live) return 0.0;
-    const double2 h1 = load_c<TH>(a.H[0], (size_t)i * M + L.m);
-    const double2 h3 = load_c<TH>(a.H[2], (size_t)i * M + L.m);
-    return L.c == 0 ? -(L.A * h1.y + L.B * h3.y) : (L.A * h1.x + L.B * h3.x);
+    return sg * (L.A * h1o + L.B * h3o);
   };
 
-  // S1, downward: G = i(a H1 + b H3); eliminate A1 (dG) = B1 G
+  // ---- S1 (down): G = i(a H1 + b H3), eliminate A1 (dG) = B1 G (look-ahead 3);
+  // N_omega2 = i b H1 - i a H3 and the omega2 right-hand side
+  // A2 q + f2 B2 omega2, q = f1 omega2 + dt (gamma N + zeta N_old), accumulated
+  // as columns arrive (acc[k] is row t + k); history N_omega2
   {
+    struct B { double h1, h3, om, noo; };
     double w[7] = {0, 0, 0, 0, 0, 0, 0};
     double yb[3] = {0, 0, 0};
-    for (int k = 0; k < 3; ++k) w[3 + k] = gval(k);
-    for (int i = 0; i < n; ++i) {
-      w[6] = (i + 3 < n) ? gval(i + 3) : 0.0;
-      const double yi = elim3(dot7(g.B1 + i * 7, w), g.L1d + i * 3, yb);
-      if (L.act) a.S[0][i * st + col] = yi;
-      yb[0] = yb[1];
-      yb[1] = yb[2];
-      yb[2] = yi;
-      push_back(w, 0.0);
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    auto loadcol = [&](int j, B& b) {
+      if (j < n) {
+        b.h1 = (double)at(HR(a.H[0], j), hocol);
+        b.h3 = (double)at(HR(a.H[2], j), hocol);
+        b.om = at(LR(a.om2, j), bcol);
+        b.noo = at(LR(a.nom_old, j), bcol);
+      } else {
+        b.h1 = b.h3 = b.om = b.noo = 0.0;
+      }
+    };
+    auto column = [&](int j, int tb, const B& b) -> double {
+      const double nom = L.live ? sg * (L.B * b.h1 - L.A * b.h3) : 0.0;  // i b H1 - i a H3
+      const double q = f1 * b.om + dga * nom + dze * b.noo;
+      if (L.act) at(LR(a.nom_old, j), bcol) = nom;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const int r = tb + k, o = j - r + 3;
+        if (o >= 0 && o <= 6 && r >= 1 && r <= n - 2) acc[k] += A2[r * 7 + o] * q + f2 * B2[r * 7 + o] * b.om;
+      }
+      return gval(b.h1, b.h3);
+    };
+    for (int j = 0; j < 3; ++j) {
+      B b;
+      loadcol(j, b);
+      w[3 + j] = column(j, 0, b);
     }
+    pipeline<D, B>(
+        n, [&](int t, B& b) { loadcol(t + 3, b); },
+        [&](int t, B& b) {
+          w[6] = (t + 3 < n) ? column(t + 3, t, b) : 0.0;
+          const double yi = elim3(dot7(B1 + t * 7, w), L1d + t * 3, yb);
+          if (L.act) {
+            at(LR(a.S[0], t), bcol) = yi;
+            at(LR(a.S[2], t), bcol) = acc[0];  // omega2 rhs of row t (0 on the wall rows)
+          }
+          yb[0] = yb[1];
+          yb[1] = yb[2];
+          yb[2] = yi;
+          push_back(w, 0.0);
+          push_back(acc, 0.0);
+        });
   }
-  // S2, upward: finish dG; N_chi, N_omega2; right-hand sides of the implicit
-  // steps (lag 3 rows); eliminate the Helmholtz matrix (factored on the fly)
-  // for chi_p, omega2 and the homogeneous chi_h (lane c = 0: 1 at the lower
-  // wall, lane c = 1: 1 at the upper wall)
+  // ---- S2 (up): finish dG; N_chi = -dG - k^2 H2 and the chi right-hand side
+  // (acc[k] is row i + 3 - k, complete when column i - ... arrives: lag 3);
+  // Helmholtz matrix factored on the fly; eliminate chi_p, omega2 and the
+  // homogeneous chi_h (lane c = 0: 1 at the lower wall, c = 1: upper wall)
   {
+    struct B { double s0, h2, chi, nco, rom; };
     double xb[3] = {0, 0, 0};
-    double qc[7] = {0, 0, 0, 0, 0, 0, 0}, xc[7] = {0, 0, 0, 0, 0, 0, 0};
-    double qo[7] = {0, 0, 0, 0, 0, 0, 0}, xo[7] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
     double ycb[3] = {0, 0, 0}, yob[3] = {0, 0, 0}, yhb[3] = {0, 0, 0};
-    for (int i = n - 1; i >= -3; --i) {
-      double qcv = 0.0, xcv = 0.0, qov = 0.0, xov = 0.0;
-      if (i >= 0) {
-        const double dG = back3(a.S[0][i * st + col], g.U1d + i * 4, xb);
-        push_x(xb, dG);
-        double nchi = 0.0, nom = 0.0;
-        if (L.live) {
-          const size_t mi = (size_t)i * M + L.m;
-          const double2 h1 = load_c<TH>(a.H[0], mi);
-          const double2 h2 = load_c<TH>(a.H[1], mi);
-          const double2 h3 = load_c<TH>(a.H[2], mi);
-          nchi = -dG - L.k2 * (L.c == 0 ? h2.x : h2.y);
-          nom = L.c == 0 ? (-L.B * h1.y + L.A * h3.y) : (L.B * h1.x - L.A * h3.x);
-        }
-        const size_t ix = i * st + col;
-        xcv = a.chi[ix];
-        xov = a.om2[ix];
-        qcv = f1 * xcv + dga * nchi + dze * a.nchi_old[ix];
-        qov = f1 * xov + dga * nom + dze * a.nom_old[ix];
-        if (L.act) {
-          a.nchi_old[ix] = nchi;
-          a.nom_old[ix] = nom;
-        }
-      }
-      push_front(qc, qcv);
-      push_front(xc, xcv);
-      push_front(qo, qov);
-      push_front(xo, xov);
-      const int r = i + 3;
-      if (r <= n - 1) {
-        double m7[7], rc = 0.0, ro = 0.0, rh = 0.0;
-        if (r == 0 || r == n - 1) {
-#pragma unroll
-          for (int o = 0; o < 7; ++o) m7[o] = o == 3 ? 1.0 : 0.0;
-          rh = (r == 0) == (L.c == 0) ? 1.0 : 0.0;
-        } else {
-          const double* A2r = g.A2 + r * 7;
-          const double* B2r = g.B2 + r * 7;
-#pragma unroll
-          for (int o = 0; o < 7; ++o) {
-            rc += A2r[o] * qc[o] + f2 * B2r[o] * xc[o];
-            ro += A2r[o] * qo[o] + f2 * B2r[o] * xo[o];
-            m7[o] = hk * A2r[o] - cb * B2r[o];
+    pipeline<D2, B>(
+        n + 3,
+        [&](int t, B& b) {
+          const int i = n - 1 - t;
+          if (i >= 0) {
+            b.s0 = at(LR(a.S[0], i), bcol);
+            b.h2 = (double)at(HR(a.H[1], i), hcol);
+            b.chi = at(LR(a.chi, i), bcol);
+            b.nco = at(LR(a.nchi_old, i), bcol);
           }
-        }
-        // upward elimination of columns r+3, r+2, r+1
+          const int r = i + 3;
+          b.rom = (r <= n - 1 && t < n + 3) ? at(LR(a.S[2], r), bcol) : 0.0;
+        },
+        [&](int t, B& b) {
+          const int i = n - 1 - t;
+          if (i >= 0) {
+            const double dG = back3(b.s0, U1d + i * 4, xb);
+            push_x(xb, dG);
+            const double nchi = L.live ? -dG - L.k2 * b.h2 : 0.0;
+            const double q = f1 * b.chi + dga * nchi + dze * b.nco;
+            if (L.act) at(LR(a.nchi_old, i), bcol) = nchi;
 #pragma unroll
-        for (int d = 3; d >= 1; --d) {
-          const double lm = m7[3 + d] * uh[3 - d][0];
-          m7[2 + d] -= lm * uh[3 - d][1];
-          m7[1 + d] -= lm * uh[3 - d][2];
-          m7[0 + d] -= lm * uh[3 - d][3];
-          rc -= lm * ycb[3 - d];
-          ro -= lm * yob[3 - d];
-          rh -= lm * yhb[3 - d];
-        }
-        const double u0 = 1.0 / m7[3];
-        const size_t mr = (size_t)r * M + L.m;
-        if (L.act && L.c == 0) {
-          a.SU[0][mr] = u0;
-          a.SU[1][mr] = m7[2];
-          a.SU[2][mr] = m7[1];
-          a.SU[3][mr] = m7[0];
-        }
-        const size_t ix = r * st + col;
-        if (L.act) {
-          a.S[1][ix] = rc;
-          a.S[2][ix] = ro;
-          a.S[3][ix] = rh;
-        }
+            for (int k = 0; k < 7; ++k) {
+              const int r = i + 3 - k;
+              if (r >= 1 && r <= n - 2) acc[k] += A2[r * 7 + k] * q + f2 * B2[r * 7 + k] * b.chi;
+            }
+          }
+          const int r = i + 3;
+          if (r <= n - 1) {
+            double m7[7], rc = acc[0], ro = b.rom, rh = 0.0;
+            if (r == 0 || r == n - 1) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          uh[0][k] = uh[1][k];
-          uh[1][k] = uh[2][k];
-        }
-        uh[2][0] = u0; uh[2][1] = m7[2]; uh[2][2] = m7[1]; uh[2][3] = m7[0];
-        ycb[0] = ycb[1]; ycb[1] = ycb[2]; ycb[2] = rc;
-        yob[0] = yob[1]; yob[1] = yob[2]; yob[2] = ro;
-        yhb[0] = yhb[1]; yhb[1] = yhb[2]; yhb[2] = rh;
-      }
-    }
+              for (int o = 0; o < 7; ++o) m7[o] = o == 3 ? 1.0 : 0.0;
+              rh = (r == 0) == (L.c == 0) ? 1.0 : 0.0;
+            } else {
+#pragma unroll
+              for (int o = 0; o < 7; ++o) m7[o] = hk * A2[r * 7 + o] - cb * B2[r * 7 + o];
+            }
+#pragma unroll
+            for (int d = 3; d >= 1; --d) {
+              const double lm = m7[3 + d] * uh[3 - d][0];
+              m7[2 + d] -= lm * uh[3 - d][1];
+              m7[1 + d] -= lm * uh[3 - d][2];
+              m7[0 + d] -= lm * uh[3 - d][3];
+              rc -= lm * ycb[3 - d];
+              ro -= lm * yob[3 - d];
+              rh -= lm * yhb[3 - d];
+            }
+            const double u0 = 1.0 / m7[3];
+            if (L.act && L.c == 0) {
+              at(MR(a.SU[0], r), bm) = u0;
+              at(MR(a.SU[1], r), bm) = m7[2];
+              at(MR(a.SU[2], r), bm) = m7[1];
+              at(MR(a.SU[3], r), bm) = m7[0];
+            }
+            if (L.act) {
+              at(LR(a.S[1], r), bcol) = rc;
+              at(LR(a.S[2], r), bcol) = ro;
+              at(LR(a.S[3], r), bcol) = rh;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              uh[0][k] = uh[1][k];
+              uh[1][k] = uh[2][k];
+            }
+            uh[2][0] = u0; uh[2][1] = m7[2]; uh[2][2] = m7[1]; uh[2][3] = m7[0];
+            ycb[0] = ycb[1]; ycb[1] = ycb[2]; ycb[2] = rc;
+            yob[0] = yob[1]; yob[1] = yob[2]; yob[2] = ro;
+            yhb[0] = yhb[1]; yhb[1] = yhb[2]; yhb[2] = rh;
+          }
+          push_back(acc, 0.0);
+        });
   }
-  // S3, downward: finish chi_p, omega2 (final), chi_h; right-hand sides of
-  // the Poisson step (lag 3); eliminate P = B2 - k^2 A2 (on the fly) for v_p, v_h
+  // ---- S3
   {
+    struct B { double u[4]; double s1, s2, s3; };
     double xcb[3] = {0, 0, 0}, xob[3] = {0, 0, 0}, xhb[3] = {0, 0, 0};
     double wcp[7] = {0, 0, 0, 0, 0, 0, 0}, wch[7] = {0, 0, 0, 0, 0, 0, 0};
     double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
     double yvb[3] = {0, 0, 0}, yhb[3] = {0, 0, 0};
-    for (int i = 0; i <= n + 2; ++i) {
-      double cp = 0.0, ch = 0.0;
-      if (i < n) {
-        const size_t mi = (size_t)i * M + L.m;
-        const double U[4] = {a.SU[0][mi], a.SU[1][mi], a.SU[2][mi], a.SU[3][mi]};
-        const size_t ix = i * st + col;
-        cp = back3(a.S[1][ix], U, xcb);
-        const double om = back3(a.S[2][ix], U, xob);
-        ch = back3(a.S[3][ix], U, xhb);
-        push_x(xcb, cp);
-        push_x(xob, om);
-        push_x(xhb, ch);
-        if (L.act) {
-          a.om2[ix] = L.live ? om : 0.0;
-          a.chi[ix] = cp;
-          a.S[4][ix] = ch;
-        }
-      }
-      push_back(wcp, cp);
-      push_back(wch, ch);
-      const int r = i - 3;
-      if (r >= 0) {
-        double p7[7], rv = 0.0, rhv = 0.0;
-        if (r == 0 || r == n - 1) {
+    pipeline<D3, B>(
+        n + 3,
+        [&](int i, B& b) {
+          if (i < n) {
+            const int ixr = i;
 #pragma unroll
-          for (int o = 0; o < 7; ++o) p7[o] = o == 3 ? 1.0 : 0.0;
-        } else {
-          const double* A2r = g.A2 + r * 7;
-          const double* B2r = g.B2 + r * 7;
-#pragma unroll
-          for (int o = 0; o < 7; ++o) {
-            rv += A2r[o] * wcp[o];
-            rhv += A2r[o] * wch[o];
-            p7[o] = B2r[o] - L.k2 * A2r[o];
+            for (int k = 0; k < 4; ++k) b.u[k] = at(MR(a.SU[k], i), bm);
+            b.s1 = at(LR(a.S[1], ixr), bcol);
+            b.s2 = at(LR(a.S[2], ixr), bcol);
+            b.s3 = at(LR(a.S[3], ixr), bcol);
           }
-        }
-        // downward elimination of columns r-3, r-2, r-1
+        },
+        [&](int i, B& b) {
+          double cp = 0.0, ch = 0.0;
+          if (i < n) {
+            const int ixr = i;
+            cp = back3(b.s1, b.u, xcb);
+            const double om = back3(b.s2, b.u, xob);
+            ch = back3(b.s3, b.u, xhb);
+            push_x(xcb, cp);
+            push_x(xob, om);
+            push_x(xhb, ch);
+            if (L.act) {
+              at(LR(a.om2, ixr), bcol) = L.live ? om : 0.0;
+              at(LR(a.chi, ixr), bcol) = cp;
+              at(LR(a.S[4], ixr), bcol) = ch;
+            }
+          }
+          push_back(wcp, cp);
+          push_back(wch, ch);
+          const int r = i - 3;
+          if (r >= 0) {
+            double p7[7], rv = 0.0, rhv = 0.0;
+            if (r == 0 || r == n - 1) {
 #pragma unroll
-        for (int d = 3; d >= 1; --d) {
-          const double lm = p7[3 - d] * uh[3 - d][0];
-          p7[4 - d] -= lm * uh[3 - d][1];
-          p7[5 - d] -= lm * uh[3 - d][2];
-          p7[6 - d] -= lm * uh[3 - d][3];
-          rv -= lm * yvb[3 - d];
-          rhv -= lm * yhb[3 - d];
-        }
-        const double u0 = 1.0 / p7[3];
-        const size_t mr = (size_t)r * M + L.m;
-        if (L.act && L.c == 0) {
-          a.SU[4][mr] = u0;
-          a.SU[5][mr] = p7[4];
-          a.SU[6][mr] = p7[5];
-          a.SU[7][mr] = p7[6];
-        }
-        const size_t ix = r * st + col;
-        if (L.act) {
-          a.S[5][ix] = rv;
-          a.S[6][ix] = rhv;
-        }
+              for (int o = 0; o < 7; ++o) p7[o] = o == 3 ? 1.0 : 0.0;
+            } else {
+              const double* A2r = A2 + r * 7;
+              const double* B2r = B2 + r * 7;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          uh[0][k] = uh[1][k];
-          uh[1][k] = uh[2][k];
-        }
-        uh[2][0] = u0; uh[2][1] = p7[4]; uh[2][2] = p7[5]; uh[2][3] = p7[6];
-        yvb[0] = yvb[1]; yvb[1] = yvb[2]; yvb[2] = rv;
-        yhb[0] = yhb[1]; yhb[1] = yhb[2]; yhb[2] = rhv;
-      }
-    }
+              for (int o = 0; o < 7; ++o) {
+                rv += A2r[o] * wcp[o];
+                rhv += A2r[o] * wch[o];
+                p7[o] = B2r[o] - L.k2 * A2r[o];
+              }
+            }
+#pragma unroll
+            for (int d = 3; d >= 1; --d) {
+              const double lm = p7[3 - d] * uh[3 - d][0];
+              p7[4 - d] -= lm * uh[3 - d][1];
+              p7[5 - d] -= lm * uh[3 - d][2];
+              p7[6 - d] -= lm * uh[3 - d][3];
+              rv -= lm * yvb[3 - d];
+              rhv -= lm * yhb[3 - d];
+            }
+            const double u0 = 1.0 / p7[3];
+            if (L.act && L.c == 0) {
+              at(MR(a.SU[4], r), bm) = u0;
+              at(MR(a.SU[5], r), bm) = p7[4];
+              at(MR(a.SU[6], r), bm) = p7[5];
+              at(MR(a.SU[7], r), bm) = p7[6];
+            }
+            const int ixr = r;
+            if (L.act) {
+              at(LR(a.S[5], ixr), bcol) = rv;
+              at(LR(a.S[6], ixr), bcol) = rhv;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              uh[0][k] = uh[1][k];
+              uh[1][k] = uh[2][k];
+            }
+            uh[2][0] = u0; uh[2][1] = p7[4]; uh[2][2] = p7[5]; uh[2][3] = p7[6];
+            yvb[0] = yvb[1]; yvb[1] = yvb[2]; yvb[2] = rv;
+            yhb[0] = yhb[1]; yhb[1] = yhb[2]; yhb[2] = rhv;
+          }
+        });
   }
-  // S4, upward: finish v_p, v_h; wall derivatives (D1 v)_{0, n2-1} by the
-  // dense wall rows of D1; 2x2 influence system for c_lo, c_hi
+  // ---- S4
   double clo_c = 0.0, chi_c = 0.0;
   {
+    struct B { double u[4]; double s5, s6; };
     double xvb[3] = {0, 0, 0}, xhb[3] = {0, 0, 0};
     double gplo = 0.0, gphi = 0.0, ghlo = 0.0, ghhi = 0.0;
-    for (int r = n - 1; r >= 0; --r) {
-      const size_t mr = (size_t)r * M + L.m;
-      const double U[4] = {a.SU[4][mr], a.SU[5][mr], a.SU[6][mr], a.SU[7][mr]};
-      const size_t ix = r * st + col;
-      const double vp = back3(a.S[5][ix], U, xvb);
-      const double vh = back3(a.S[6][ix], U, xhb);
-      push_x(xvb, vp);
-      push_x(xhb, vh);
-      if (L.act) {
-        a.v[ix] = vp;
-        a.S[7][ix] = vh;
-      }
-      gplo = fma(g.clo[r], vp, gplo);
-      gphi = fma(g.chi[r], vp, gphi);
-      ghlo = fma(g.clo[r], vh, ghlo);
-      ghhi = fma(g.chi[r], vh, ghhi);
-    }
+    pipeline<D, B>(
+        n,
+        [&](int t, B& b) {
+          const int r = n - 1 - t;
+          if (r >= 0) {
+            const int ixr = r;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) b.u[k] = at(MR(a.SU[4 + k], r), bm);
+            b.s5 = at(LR(a.S[5], ixr), bcol);
+            b.s6 = at(LR(a.S[6], ixr), bcol);
+          }
+        },
+        [&](int t, B& b) {
+          const int r = n - 1 - t;
+          const int ixr = r;
+          const double vp = back3(b.s5, b.u, xvb);
+          const double vh = back3(b.s6, b.u, xhb);
+          push_x(xvb, vp);
+          push_x(xhb, vh);
+          if (L.act) {
+            at(LR(a.v, ixr), bcol) = vp;
+            at(LR(a.S[7], ixr), bcol) = vh;
+          }
+          gplo = fma(clo[r], vp, gplo);
+          gphi = fma(chw[r], vp, gphi);
+          ghlo = fma(clo[r], vh, ghlo);
+          ghhi = fma(chw[r], vh, ghhi);
+        });
     const double oglo = __shfl_xor(ghlo, 1), oghi = __shfl_xor(ghhi, 1);
     const double m00 = L.c == 0 ? ghlo : oglo;  // lower-wall homogeneous solution, lower wall
     const double m10 = L.c == 0 ? ghhi : oghi;  // ... upper wall
@@ -524,19 +682,129 @@ __global__ void __launch_bounds__(256) k_advance(AdvanceArgs<TH> a) {
       chi_c = (-gphi * m00 + gplo * m10) / det;
     }
   }
-  // S5: v = v_p + c_lo v_lo + c_hi v_hi, chi likewise
-  for (int r = 0; r < n; ++r) {
-    const size_t ix = r * st + col;
-    const double vh = a.S[7][ix], ch = a.S[4][ix];
-    const double vho = __shfl_xor(vh, 1), cho = __shfl_xor(ch, 1);
-    const double vlo = L.c == 0 ? vh : vho, vhi = L.c == 0 ? vho : vh;
-    const double clo = L.c == 0 ? ch : cho, chh = L.c == 0 ? cho : ch;
-    if (L.act) {
-      const double v = a.v[ix] + clo_c * vlo + chi_c * vhi;
-      const double c = a.chi[ix] + clo_c * clo + chi_c * chh;
-      a.v[ix] = L.live ? v : 0.0;
-      a.chi[ix] = L.live ? c : 0.0;
-    }
+  // ---- S5 (+ R1)
+  {
+    struct B { double vh, ch, vp, cp; };
+    double w[7] = {0, 0, 0, 0, 0, 0, 0};
+    double yb[3] = {0, 0, 0};
+    pipeline<D, B>(
+        n + 3,
+        [&](int i, B& b) {
+          if (i < n) {
+            const int ixr = i;
+            b.vh = at(LR(a.S[7], ixr), bcol);
+            b.ch = at(LR(a.S[4], ixr), bcol);
+            b.vp = at(LR(a.v, ixr), bcol);
+            b.cp = at(LR(a.chi, ixr), bcol);
+          } else {
+            b.vh = b.ch = b.vp = b.cp = 0.0;
+          }
+        },
+        [&](int i, B& b) {
+          const double vho = __shfl_xor(b.vh, 1), cho = __shfl_xor(b.ch, 1);
+          double vn = 0.0;
+          if (i < n) {
+            const int ixr = i;
+            const double vlo = L.c == 0 ? b.vh : vho, vhi = L.c == 0 ? vho : b.vh;
+            const double clo = L.c == 0 ? b.ch : cho, chh = L.c == 0 ? cho : b.ch;
+            vn = L.live ? b.vp + clo_c * vlo + chi_c * vhi : 0.0;
+            const double cn = L.live ? b.cp + clo_c * clo + chi_c * chh : 0.0;
+            if (L.act) {
+              at(LR(a.v, ixr), bcol) = vn;
+              at(LR(a.chi, ixr), bcol) = cn;
+            }
+            if (wph) at(LR(a.ph[1], ixr), pcol) = (TP)vn;
+          }
+          push_back(w, vn);
+          const int r = i - 3;
+          if (r >= 0) {
+            const double yr = elim3(dot7(B1 + r * 7, w), L1d + r * 3, yb);
+            if (L.act) at(LR(a.S[0], r), bcol) = yr;
+            yb[0] = yb[1];
+            yb[1] = yb[2];
+            yb[2] = yr;
+          }
+        });
+  }
+  // ---- R2
+  {
+    struct B { double s0, om; };  // om: the other component of omega2
+    double xb[3] = {0, 0, 0};
+    double w1[7] = {0, 0, 0, 0, 0, 0, 0}, w3[7] = {0, 0, 0, 0, 0, 0, 0};
+    double y1b[3] = {0, 0, 0}, y3b[3] = {0, 0, 0};
+    pipeline<D, B>(
+        n + 3,
+        [&](int t, B& b) {
+          const int i = n - 1 - t;
+          if (i >= 0) {
+            b.s0 = at(LR(a.S[0], i), bcol);
+            b.om = at(LR(a.om2, i), bocol);
+          } else {
+            b.s0 = 0.0;
+            b.om = 0.0;
+          }
+        },
+        [&](int t, B& b) {
+          const int i = n - 1 - t;
+          double u1 = 0.0, u3 = 0.0;
+          const double dv = i >= 0 ? back3(b.s0, U1d + (i >= 0 ? i : 0) * 4, xb) : 0.0;
+          const double dvo = __shfl_xor(dv, 1);
+          if (i >= 0) {
+            push_x(xb, dv);
+            if (L.live) {
+              // u1 = i(a dv - b omega2)/k^2, u3 = i(b dv + a omega2)/k^2 (dvo, om: other component)
+              u1 = sg * (L.A * dvo - L.B * b.om) * L.ik2;
+              u3 = sg * (L.B * dvo + L.A * b.om) * L.ik2;
+            }
+            if (wph) {
+              at(LR(a.ph[0], i), pcol) = (TP)u1;
+              at(LR(a.ph[2], i), pcol) = (TP)u3;
+            }
+          }
+          push_front(w1, u1);
+          push_front(w3, u3);
+          const int r = i + 3;
+          if (r <= n - 1) {
+            const double* bb = B1 + r * 7;
+            const double* l = L1u + r * 3;
+            const double y1 = elim3(dot7(bb, w1), l, y1b);
+            const double y3 = elim3(dot7(bb, w3), l, y3b);
+            if (L.act) {
+              at(LR(a.S[1], r), bcol) = y1;
+              at(LR(a.S[2], r), bcol) = y3;
+            }
+            y1b[0] = y1b[1]; y1b[1] = y1b[2]; y1b[2] = y1;
+            y3b[0] = y3b[1]; y3b[1] = y3b[2]; y3b[2] = y3;
+          }
+        });
+  }
+  // ---- R3
+  {
+    struct B { double s1, s2, v; };  // v: the other component
+    double x1[3] = {0, 0, 0}, x3[3] = {0, 0, 0};
+    pipeline<D, B>(
+        n,
+        [&](int r, B& b) {
+          if (r < n) {
+            b.s1 = at(LR(a.S[1], r), bcol);
+            b.s2 = at(LR(a.S[2], r), bcol);
+            b.v = at(LR(a.v, r), bocol);
+          }
+        },
+        [&](int r, B& b) {
+          const double* U = U1u + r * 4;
+          const double du1 = back3(b.s1, U, x1);
+          const double du3 = back3(b.s2, U, x3);
+          push_x(x1, du1);
+          push_x(x3, du3);
+          // omega1 = du3 - i b v, omega3 = i a v - du1
+          const double o1 = du3 - sg * L.B * b.v;
+          const double o3 = sg * L.A * b.v - du1;
+          if (wph) {
+            at(LR(a.ph[3], r), pcol) = (TP)o1;
+            at(LR(a.ph[4], r), pcol) = (TP)o3;
+          }
+        });
   }
 }
 
@@ -637,8 +905,9 @@ template <typename TP> hipError_t launch_recover(const RecoverArgs<TP>& a, hipSt
   hipLaunchKernelGGL((k_recover<TP>), dim3(pencil_blocks(a.g.M)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
-template <typename TH> hipError_t launch_advance(const AdvanceArgs<TH>& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_advance<TH>), dim3(pencil_blocks(a.g.M) + 1), dim3(256), 0, st, a);
+template <typename TH, typename TP> hipError_t launch_advance(const AdvanceArgs<TH, TP>& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_advance<TH, TP>), dim3(pencil_blocks(a.g.M) + 1), dim3(256), 0, st, a, a.g.B1, a.g.A2,
+                     a.g.B2, a.g.L1d, a.g.U1d, a.g.L1u, a.g.U1u, a.g.clo, a.g.chi);
   return hipGetLastError();
 }
 hipError_t launch_chi_from_v(const ChiArgs& a, hipStream_t st) {
@@ -660,7 +929,7 @@ hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_
 
 template hipError_t launch_recover<double>(const RecoverArgs<double>&, hipStream_t);
 template hipError_t launch_recover<float>(const RecoverArgs<float>&, hipStream_t);
-template hipError_t launch_advance<double>(const AdvanceArgs<double>&, hipStream_t);
-template hipError_t launch_advance<float>(const AdvanceArgs<float>&, hipStream_t);
+template hipError_t launch_advance<double, double>(const AdvanceArgs<double, double>&, hipStream_t);
+template hipError_t launch_advance<float, float>(const AdvanceArgs<float, float>&, hipStream_t);
 
 }  // namespace chn
