@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchn.so")
-HIP_SOURCES = ["api.hip", "plane.hip", "pencil.hip"]
+HIP_SOURCES = ["api.hip", "plane.hip", "pencil.hip", "lowstorage.hip"]
 HOST_SOURCES = ["coeffs.cpp"]
 ARCH = os.environ.get("CHN_OFFLOAD_ARCH", "gfx950")
 

@@ -1,6 +1,7 @@
 // C ABI of the channel RK3 hot path: context, workspace layout, sub-step driver.
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -20,6 +21,8 @@ const double kGamma[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
 const double kZeta[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 
 std::string g_create_error;
+
+constexpr int kMaxQ = 4096;  // largest q1, q3 of the filter stage's output grid
 
 bool smooth23(int n) {
   if (n < 1) return false;
@@ -66,6 +69,8 @@ struct chn_ctx {
   // tables
   double *A1, *B1, *A2, *B2, *L1d, *U1d, *L1u, *U1u, *L2d, *U2d, *clo, *chi_w, *quad, *inv_dy;
   void *tw1 = nullptr, *tw3 = nullptr;
+  double2 *tw1d = nullptr, *tw3d = nullptr, *twq = nullptr;  // float64 tables (filter stage)
+  std::vector<double> twq_host;
   FftPlan plan1{}, plan3{};
   double *mean_scr = nullptr, *mean_out = nullptr, *info_dev = nullptr;
   std::vector<double> hA1, hB1, hA2, hB2, hquad;
@@ -118,6 +123,9 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
   double* tabs = D((size_t)n2 * (4 * 7 + 3 * 3 + 3 * 4 + 4));
   void* tw1 = cv.take(te * (size_t)p1);
   void* tw3 = cv.take(te * (size_t)p3);
+  void* tw1d = cv.take(16 * (size_t)p1);
+  void* tw3d = cv.take(16 * (size_t)p3);
+  void* twq = cv.take(16 * (size_t)kMaxQ * 2);
   double* mean_scr = D(3 * (size_t)n2 * 5 + 4 * (size_t)n2);
   double* mean_out = D(8);
   double* info = D(8);
@@ -136,6 +144,9 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
     x->U1d = t; t += 4 * n2; x->U1u = t; t += 4 * n2; x->U2d = t; t += 4 * n2;
     x->clo = t; t += n2; x->chi_w = t; t += n2; x->quad = t; t += n2; x->inv_dy = t; t += n2;
     x->tw1 = tw1; x->tw3 = tw3;
+    x->tw1d = reinterpret_cast<double2*>(tw1d);
+    x->tw3d = reinterpret_cast<double2*>(tw3d);
+    x->twq = reinterpret_cast<double2*>(twq);
     x->mean_scr = mean_scr; x->mean_out = mean_out; x->info_dev = info;
   }
   return cv.off + 256;
@@ -315,6 +326,134 @@ template <typename T> chn_status substep(chn_ctx* x, int s, double dt) {
   return CHN_OK;
 }
 
+chn_status check(chn_ctx* x);
+
+template <typename T>
+chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_ubar, double* d_uubar,
+                        double* d_tau) {
+  using C = typename Ty<T>::c;
+  const int n2 = x->n2, n1h = x->n1h, n3 = x->n3, p1 = x->p1, p3 = x->p3;
+  const size_t te = sizeof(C);
+  if (!d_ubar || !d_uubar) return fail(x, CHN_EINVAL, "NULL output pointer");
+  if (kcx < 0 || kcz < 0 || kcx >= n1h || kcz >= n3 / 2) return fail(x, CHN_EINVAL, "need 0 <= kcx < n1/2, 0 <= kcz < n3/2");
+  if (q1 <= 2 * kcx || q3 <= 2 * kcz || (q1 % 2) || (q3 % 2) || !smooth23(q1) || !smooth23(q3) || q1 > kMaxQ ||
+      q3 > kMaxQ)
+    return fail(x, CHN_EINVAL, "q1, q3 must be even, 2,3-smooth, <= 4096 and exceed 2 kcx, 2 kcz");
+  const int kc1 = kcx + 1, nz = 2 * kcz + 1;
+  const size_t NP = (size_t)n2 * x->M;
+  // buffer reuse: x-filter output in the free slots 3..5 of each plane of the
+  // intermediate, pp in the H buffers, the q-grid intermediate in the intermediate
+  if ((size_t)6 * p3 * kc1 * 16 > (size_t)3 * p3 * n1h * te) return fail(x, CHN_EUNSUPPORTED, "kcx too large for the workspace");
+  if ((size_t)6 * n2 * kc1 * nz * 16 > 3 * NP * te) return fail(x, CHN_EUNSUPPORTED, "cut-off too large for the workspace");
+  if ((size_t)9 * n2 * q3 * kc1 * 16 > x->inter_bytes) return fail(x, CHN_EUNSUPPORTED, "q grid too large for the workspace");
+  if (p1 > 12 * 256) return fail(x, CHN_EUNSUPPORTED, "3*n1/2 too large for the filter x-pass");
+  const size_t lds_x = std::max((size_t)2 * (p1 + 1) * te, (size_t)3 * (p1 + 1) * 16);
+  const size_t lds_t = (size_t)5 * (q1 + 1) * 16;
+  auto lines = [&](int len, int cap) {
+    int K = 24 * 256 / len;
+    const int byl = x->lds_max / ((len + 1) * 16);
+    if (K > byl) K = byl;
+    if (K > 16) K = 16;
+    if (K > cap) K = cap;
+    return K < 1 ? 1 : K;
+  };
+  const int Kf = lines(p3, kc1), Kq = lines(q3, kc1);
+  if (lds_x > (size_t)x->lds_max || lds_t > (size_t)x->lds_max || (size_t)(p3 + 1) * 16 > (size_t)x->lds_max ||
+      3 * p1 > 24 * 256 || p3 > 24 * 256 || 5 * q1 > 24 * 256 || q3 > 24 * 256)
+    return fail(x, CHN_EUNSUPPORTED, "plane too large for the filter kernels' LDS tiles on this device");
+  // q-grid FFT tables
+  FftPlan pq1{}, pq3{};
+  std::vector<double> t1, t3;
+  if (!chn::host::fft_plan(q1, &pq1, &t1) || !chn::host::fft_plan(q3, &pq3, &t3))
+    return fail(x, CHN_EINVAL, "q grid not supported");
+  x->twq_host.assign(t1.begin(), t1.end());
+  x->twq_host.resize(2 * kMaxQ, 0.0);
+  x->twq_host.insert(x->twq_host.end(), t3.begin(), t3.end());
+  HIPCHK(x, hipMemcpyAsync(x->twq, x->twq_host.data(), x->twq_host.size() * 8, hipMemcpyHostToDevice, x->stream));
+  const double2* twq1 = x->twq;
+  const double2* twq3 = x->twq + kMaxQ;
+  // 1. float64 spectra of u1, u2, u3 (and the vorticities, unused here)
+  double* su[5] = {x->S[3], x->S[4], x->S[5], x->S[6], x->S[7]};
+  if (chn_status st = recover<double>(x, su)) return st;
+  const void* fin[6] = {x->S[3], x->S[4], x->S[5], nullptr, nullptr, nullptr};
+  if (x->mixed) {
+    x->phase_valid = false;
+    for (int f = 0; f < 3; ++f)
+      HIPCHK(x, timed(x, CHN_K_FILTER, [&] {
+        return chn::launch_convert_d2f(x->S[3 + f], reinterpret_cast<float*>(x->ph[f]), 2 * NP, x->stream);
+      }));
+    for (int f = 0; f < 3; ++f) fin[f] = x->ph[f];
+  }
+  // 2. z inverse of the fluctuations
+  chn::ZinvArgs<T> za{};
+  for (int f = 0; f < 3; ++f) za.in[f] = reinterpret_cast<const C*>(fin[f]);
+  za.out = reinterpret_cast<C*>(x->inter);
+  za.tw = reinterpret_cast<const C*>(x->tw3);
+  za.plan = x->plan3;
+  za.d = x->dims;
+  za.K = z_lines<T>(x);
+  za.lstride = p3 + 1;
+  za.nfields = 3;
+  za.nslot = 6;
+  za.zero_mean = 1;
+  HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_zinv<T>(za, x->stream); }));
+  // 3. products and float64 forward in x
+  chn::XfilterArgs<T> xa{};
+  xa.buf = reinterpret_cast<const C*>(x->inter);
+  xa.out = reinterpret_cast<double2*>(reinterpret_cast<char*>(x->inter) + (size_t)3 * p3 * n1h * te);
+  xa.plane_stride = (size_t)6 * p3 * n1h * te / 16;
+  xa.tw = reinterpret_cast<const C*>(x->tw1);
+  xa.plan = x->plan1;
+  xa.tw_d = x->tw1d;
+  xa.plan_d = x->plan1;
+  xa.d = x->dims;
+  xa.lst = p1 + 1;
+  xa.lsd = p1 + 1;
+  xa.kcx = kcx;
+  HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_xfilter<T>(xa, lds_x, x->stream); }));
+  // 4. float64 forward in z, retained set, mean terms
+  chn::ZfilterArgs fa{};
+  fa.xout = xa.out;
+  fa.plane_stride = xa.plane_stride;
+  for (int f = 0; f < 3; ++f) fa.u[f] = x->S[3 + f];
+  fa.pp = reinterpret_cast<double2*>(x->H[0]);
+  fa.uubar = reinterpret_cast<double2*>(d_uubar);
+  fa.ubar = reinterpret_cast<double2*>(d_ubar);
+  fa.tw = x->tw3d;
+  fa.plan = x->plan3;
+  fa.d = x->dims;
+  fa.kcx = kcx;
+  fa.kcz = kcz;
+  fa.K = Kf;
+  fa.lstride = p3 + 1;
+  fa.scale = 1.0 / ((double)p1 * p3);
+  HIPCHK(x, timed(x, CHN_K_FILTER, [&] {
+    return chn::launch_zfilter(fa, (size_t)Kf * (p3 + 1) * 16, x->stream);
+  }));
+  if (!d_tau) return CHN_OK;
+  // 5. q grid: inverse in z, then in x with tau = pp - ub ub
+  chn::ZinvQArgs qa{};
+  qa.pp = fa.pp;
+  for (int f = 0; f < 3; ++f) qa.u[f] = x->S[3 + f];
+  qa.out = reinterpret_cast<double2*>(x->inter);
+  qa.tw = twq3;
+  qa.plan = pq3;
+  qa.n1h = n1h; qa.n2 = n2; qa.n3 = n3; qa.q3 = q3; qa.kcx = kcx; qa.kcz = kcz; qa.K = Kq;
+  qa.lstride = q3 + 1;
+  HIPCHK(x, timed(x, CHN_K_FILTER, [&] {
+    return chn::launch_zinv_q(qa, (size_t)Kq * (q3 + 1) * 16, x->stream);
+  }));
+  chn::XtauArgs ta{};
+  ta.in = qa.out;
+  ta.tau = d_tau;
+  ta.tw = twq1;
+  ta.plan = pq1;
+  ta.n2 = n2; ta.q1 = q1; ta.q3 = q3; ta.kcx = kcx;
+  ta.lstride = q1 + 1;
+  HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_xtau(ta, lds_t, x->stream); }));
+  return CHN_OK;
+}
+
 chn_status check(chn_ctx* x) {
   if (!x) return CHN_EINVAL;
   if (x->sticky != CHN_OK) return x->sticky;
@@ -418,6 +557,8 @@ chn_status chn_create(const chn_config* cfg, void* d_ws, size_t ws_bytes, chn_ct
     if (e == hipSuccess) e = hipMemcpyAsync(x->tw1, tw1.data(), tw1.size() * 8, hipMemcpyHostToDevice, x->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(x->tw3, tw3.data(), tw3.size() * 8, hipMemcpyHostToDevice, x->stream);
   }
+  if (e == hipSuccess) e = hipMemcpyAsync(x->tw1d, tw1.data(), tw1.size() * 8, hipMemcpyHostToDevice, x->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(x->tw3d, tw3.data(), tw3.size() * 8, hipMemcpyHostToDevice, x->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
   if (e != hipSuccess) {
     delete x;
@@ -560,7 +701,8 @@ chn_status chn_filter_and_stress(chn_ctx* x, int32_t kcx, int32_t kcz, int32_t q
                                  double* d_uubar, double* d_tau) {
   if (chn_status s = check(x)) return s;
   if (!x->have_state) return fail(x, CHN_ESTATE, "chn_filter_and_stress before chn_set_state");
-  return fail(x, CHN_EUNSUPPORTED, "filter stage not built yet");
+  return x->mixed ? filter_stage<float>(x, kcx, kcz, q1, q3, d_ubar, d_uubar, d_tau)
+                  : filter_stage<double>(x, kcx, kcz, q1, q3, d_ubar, d_uubar, d_tau);
 }
 
 chn_status chn_get_operators(chn_ctx* x, double* a1, double* b1, double* a2, double* b2, double* quad) {

@@ -20,6 +20,7 @@ template <typename T> struct ZinvArgs {
   int lstride;         // LDS line stride (complex elements)
   int nfields;         // 6: u1 u2 u3 omega1 omega2 omega3; 3: u1 u2 u3
   int nslot;           // field slots per plane in `out`
+  int zero_mean;       // nonzero: the (0,0) coefficient of every input is taken as 0
 };
 
 template <typename T> struct XpassArgs {
@@ -48,6 +49,56 @@ template <typename T, typename TO> struct ZfwdArgs {
 template <typename T> hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st);
 template <typename T> hipError_t launch_xpass(const XpassArgs<T>& a, hipStream_t st);
 template <typename T, typename TO> hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st);
+
+// ---------------------------------------------------------------- filter stage
+template <typename T> struct XfilterArgs {
+  const c2<T>* buf;      // [n2][6][p3][n1h], slots 0..2 = u1, u2, u3 after the z inverse
+  double2* out;          // per plane y at out + y * plane_stride: [6][p3][kcx+1]
+  size_t plane_stride;   // in double2 elements
+  const c2<T>* tw;       // p1 plan, context precision
+  FftPlan plan;
+  const double2* tw_d;   // p1 plan, float64
+  FftPlan plan_d;
+  PlaneDims d;
+  int lst, lsd;          // LDS line strides (context-precision and float64 lines)
+  int kcx;
+};
+
+struct ZfilterArgs {
+  const double2* xout;   // output of k_xfilter
+  size_t plane_stride;
+  const double* u[3];    // float64 spectral u1, u2, u3 (full mode set)
+  double2* pp;           // [6][n2][kcx+1][2kcz+1] F(u'_i u'_j)
+  double2* uubar;        // [6][n2][kcx+1][2kcz+1] F(u_i u_j)
+  double2* ubar;         // [3][n2][kcx+1][2kcz+1] F(u_i)
+  const double2* tw;     // p3 plan, float64
+  FftPlan plan;
+  PlaneDims d;
+  int kcx, kcz, K, lstride;
+  double scale;          // 1 / (p1 p3)
+};
+
+struct ZinvQArgs {
+  const double2* pp;
+  const double* u[3];
+  double2* out;          // [n2][9][q3][kcx+1]
+  const double2* tw;     // q3 plan
+  FftPlan plan;
+  int n1h, n2, n3, q3, kcx, kcz, K, lstride;
+};
+
+struct XtauArgs {
+  const double2* in;     // [n2][9][q3][kcx+1]
+  double* tau;           // [6][n2][q3][q1]
+  const double2* tw;     // q1 plan
+  FftPlan plan;
+  int n2, q1, q3, kcx, lstride;
+};
+
+template <typename T> hipError_t launch_xfilter(const XfilterArgs<T>& a, size_t lds_bytes, hipStream_t st);
+hipError_t launch_zfilter(const ZfilterArgs& a, size_t lds_bytes, hipStream_t st);
+hipError_t launch_zinv_q(const ZinvQArgs& a, size_t lds_bytes, hipStream_t st);
+hipError_t launch_xtau(const XtauArgs& a, size_t lds_bytes, hipStream_t st);
 
 // ---------------------------------------------------------------- pencils
 // Band tables are [n2][7] (row i holds M[i][i-3..i+3]).  LU factors of a

@@ -1,0 +1,271 @@
+// Low-storage database stage (Section 3.1 of the paper): sharp Fourier cut-off
+// in x and z, the filtered products F(u_i u_j) and the sub-grid stress
+// tau_ij = F(u_i u_j) - F(u_i) F(u_j) on a q1 x q3 grid of every plane.
+//
+// The plane means U_i(y) are removed before the products (u' = u - U, by
+// zeroing the (0,0) coefficient), so the transforms carry only fluctuations:
+//   F(u_i u_j) = F(u'_i u'_j) + U_i F(u'_j) + U_j F(u'_i) + U_i U_j delta_k0,
+//   tau_ij     = F(u'_i u'_j) - F(u'_i) F(u'_j)      (the plane means cancel).
+// Inverse transforms and products run in the context's precision; the
+// pruned forward transforms of the products (kx <= kcx, |kz| <= kcz), the
+// mean-term assembly and the q-grid stage run in float64.
+//
+//   k_zinv (plane.hip) : u1, u2, u3 with zero (0,0) mode, padded inverse in z
+//   k_xfilter : inverse in x, six products, float64 forward in x, keep kx <= kcx
+//   k_zfilter : float64 forward in z, keep |kz| <= kcz; F(u_i), F(u_i u_j)
+//   k_zinv_q  : the nine retained fields padded to q3, inverse in z
+//   k_xtau    : inverse in x on q1 points, tau_ij = pp_ij - ub_i ub_j
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace chn {
+
+// pairs (11, 12, 13, 22, 23, 33)
+__device__ __constant__ int kPairI[6] = {0, 0, 0, 1, 1, 2};
+__device__ __constant__ int kPairJ[6] = {0, 1, 2, 1, 2, 2};
+
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  c2<T>* lt = reinterpret_cast<c2<T>*>(smem_raw);   // 2 lines: u1 + i u2, u3
+  double2* ld = reinterpret_cast<double2*>(smem_raw);  // 3 lines of products (reuses the space)
+  const int y = blockIdx.y, z = blockIdx.x;
+  const int n1h = a.d.n1h, p1 = a.d.p1, p3 = a.d.p3, LT = a.lst, LD = a.lsd;
+  const int npad = p1 - 2 * n1h + 1;
+  const c2<T> zero = mk<T>(T(0), T(0));
+  for (int e = threadIdx.x; e < 2 * npad; e += blockDim.x) {
+    const int l = e / npad;
+    lt[l * LT + n1h + (e - l * npad)] = zero;
+  }
+  for (int e = threadIdx.x; e < 2 * n1h; e += blockDim.x) {
+    const int l = e / n1h, k = e - l * n1h;
+    const size_t base = ((size_t)(y * 6 + 2 * l) * p3 + z) * n1h + k;
+    const c2<T> X = a.buf[base];
+    const c2<T> Y = l == 0 ? a.buf[base + (size_t)p3 * n1h] : zero;
+    c2<T>* line = lt + l * LT;
+    if (k == 0) {
+      line[0] = mk<T>(X.x, Y.x);
+    } else {
+      line[k] = mk<T>(X.x - Y.y, X.y + Y.x);
+      line[p1 - k] = mk<T>(X.x + Y.y, Y.x - X.y);
+    }
+  }
+  __syncthreads();
+  fft_lines<T, MAXV>(lt, LT, 2, a.plan, a.tw, +1);
+  // products in the context precision, staged in registers, then stored as
+  // float64 lines (pp11 + i pp22, pp12 + i pp13, pp23 + i pp33)
+  constexpr int NQ = 12;  // points per thread (p1 <= 12 * 256)
+  double pr[NQ][6];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int x = threadIdx.x + q * blockDim.x;
+    if (x < p1) {
+      const c2<T> A = lt[x], B = lt[LT + x];
+      const T u1 = A.x, u2 = A.y, u3 = B.x;
+      pr[q][0] = (double)(u1 * u1);
+      pr[q][1] = (double)(u1 * u2);
+      pr[q][2] = (double)(u1 * u3);
+      pr[q][3] = (double)(u2 * u2);
+      pr[q][4] = (double)(u2 * u3);
+      pr[q][5] = (double)(u3 * u3);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int x = threadIdx.x + q * blockDim.x;
+    if (x < p1) {
+      ld[0 * LD + x] = make_double2(pr[q][0], pr[q][3]);
+      ld[1 * LD + x] = make_double2(pr[q][1], pr[q][2]);
+      ld[2 * LD + x] = make_double2(pr[q][4], pr[q][5]);
+    }
+  }
+  __syncthreads();
+  for (int l = 0; l < 3; ++l) fft_lines<double, 24>(ld + l * LD, LD, 1, a.plan_d, a.tw_d, -1);
+  // unpack the two real spectra of each line, keep kx <= kcx
+  const int kc1 = a.kcx + 1;
+  double2* out = a.out + ((size_t)y * a.plane_stride) + (size_t)z * kc1;
+  for (int e = threadIdx.x; e < 3 * kc1; e += blockDim.x) {
+    const int l = e / kc1, k = e - l * kc1;
+    const double2 W = ld[l * LD + k];
+    const double2 Wm = ld[l * LD + (k == 0 ? 0 : p1 - k)];
+    const double2 P = make_double2(0.5 * (W.x + Wm.x), 0.5 * (W.y - Wm.y));   // (W_k + conj W_m)/2
+    const double2 Q = make_double2(0.5 * (W.y + Wm.y), -0.5 * (W.x - Wm.x));  // (W_k - conj W_m)/(2i)
+    // line 0: pairs 0 (11), 3 (22); line 1: 1 (12), 2 (13); line 2: 4 (23), 5 (33)
+    const int pa = l == 0 ? 0 : (l == 1 ? 1 : 4);
+    const int pb = l == 0 ? 3 : (l == 1 ? 2 : 5);
+    out[(size_t)pa * p3 * kc1 + k] = P;
+    out[(size_t)pb * p3 * kc1 + k] = Q;
+  }
+}
+
+// Per (y, tile of retained kx): forward z transform of the six products,
+// F(u'_i u'_j) on |kz| <= kcz -> pp; F(u_i u_j) with the mean terms -> uubar;
+// F(u_i) -> ubar.
+__global__ void __launch_bounds__(256) k_zfilter(ZfilterArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  double2* lds = reinterpret_cast<double2*>(smem_raw);
+  const int y = blockIdx.y;
+  const int kx0 = blockIdx.x * a.K;
+  const int n1h = a.d.n1h, n3 = a.d.n3, p3 = a.d.p3, K = a.K, LS = a.lstride;
+  const int kc1 = a.kcx + 1, nz = 2 * a.kcz + 1;
+  const int nk = min(K, kc1 - kx0);
+  const size_t M = (size_t)n1h * n3;
+  const double2* in = a.xout + (size_t)y * a.plane_stride;
+  // plane means U_i = Re u_i(0, 0)
+  const double U[3] = {a.u[0][(size_t)y * M * 2], a.u[1][(size_t)y * M * 2], a.u[2][(size_t)y * M * 2]};
+  auto slot = [&](int s) { return s <= a.kcz ? s : n3 - (nz - s); };  // retained slot -> stored slot
+  const double2* uh[3] = {reinterpret_cast<const double2*>(a.u[0]), reinterpret_cast<const double2*>(a.u[1]),
+                          reinterpret_cast<const double2*>(a.u[2])};
+  // F(u_i) on the retained set
+  for (int e = threadIdx.x; e < 3 * nk * nz; e += blockDim.x) {
+    const int i = e / (nk * nz), r = e - i * nk * nz, l = r / nz, s = r - l * nz;
+    const double2 v = uh[i][(size_t)y * M + (size_t)(kx0 + l) * n3 + slot(s)];
+    a.ubar[(((size_t)i * a.d.n2 + y) * kc1 + kx0 + l) * nz + s] = v;
+  }
+  for (int f = 0; f < 6; ++f) {
+    const double2* src = in + (size_t)f * p3 * kc1 + kx0;
+    for (int e = threadIdx.x; e < K * p3; e += blockDim.x) {
+      const int z = e / K, l = e - z * K;
+      lds[l * LS + z] = l < nk ? src[(size_t)z * kc1 + l] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    fft_lines<double, 24>(lds, LS, K, a.plan, a.tw, -1);
+    const int i = kPairI[f], j = kPairJ[f];
+    for (int e = threadIdx.x; e < nk * nz; e += blockDim.x) {
+      const int l = e / nz, s = e - l * nz;
+      const int kz = s <= a.kcz ? s : s - nz;
+      const double2 w = lds[l * LS + (kz >= 0 ? kz : p3 + kz)];
+      const double2 pp = make_double2(w.x * a.scale, w.y * a.scale);
+      const size_t o = (((size_t)f * a.d.n2 + y) * kc1 + kx0 + l) * nz + s;
+      a.pp[o] = pp;
+      // mean terms: U_i F(u'_j) + U_j F(u'_i) (+ U_i U_j at k = 0)
+      const bool k0 = (kx0 + l == 0) && kz == 0;
+      double2 uj = make_double2(0.0, 0.0), ui = make_double2(0.0, 0.0);
+      if (!k0) {
+        const size_t mi = (size_t)y * M + (size_t)(kx0 + l) * n3 + slot(s);
+        ui = uh[i][mi];
+        uj = uh[j][mi];
+      }
+      double2 uu = make_double2(pp.x + U[i] * uj.x + U[j] * ui.x, pp.y + U[i] * uj.y + U[j] * ui.y);
+      if (k0) uu.x += U[i] * U[j];
+      a.uubar[o] = uu;
+    }
+    __syncthreads();
+  }
+}
+
+// Per (y, tile of retained kx): the nine retained fields (six pp, three
+// F(u'_i) with zero (0,0) mode) padded from 2 kcz + 1 to q3 slots, inverse in
+// z, stored [y][9][q3][kcx+1].
+__global__ void __launch_bounds__(256) k_zinv_q(ZinvQArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  double2* lds = reinterpret_cast<double2*>(smem_raw);
+  const int y = blockIdx.y;
+  const int kx0 = blockIdx.x * a.K;
+  const int n3 = a.n3, q3 = a.q3, K = a.K, LS = a.lstride;
+  const int kc1 = a.kcx + 1, nz = 2 * a.kcz + 1;
+  const int nk = min(K, kc1 - kx0);
+  const size_t M = (size_t)a.n1h * n3;
+  for (int f = 0; f < 9; ++f) {
+    for (int e = threadIdx.x; e < K * q3; e += blockDim.x) {
+      const int l = e / q3;
+      lds[l * LS + (e - l * q3)] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nk * nz; e += blockDim.x) {
+      const int l = e / nz, s = e - l * nz;
+      const int kz = s <= a.kcz ? s : s - nz;
+      double2 v;
+      if (f < 6) {
+        v = a.pp[(((size_t)f * a.n2 + y) * kc1 + kx0 + l) * nz + s];
+      } else {
+        const int kx = kx0 + l;
+        const int st = kz >= 0 ? kz : n3 + kz;
+        v = (kx == 0 && kz == 0) ? make_double2(0.0, 0.0)
+                                  : reinterpret_cast<const double2*>(a.u[f - 6])[(size_t)y * M + (size_t)kx * n3 + st];
+      }
+      lds[l * LS + (kz >= 0 ? kz : q3 + kz)] = v;
+    }
+    __syncthreads();
+    fft_lines<double, 24>(lds, LS, K, a.plan, a.tw, +1);
+    double2* out = a.out + ((size_t)(y * 9 + f) * q3) * kc1 + kx0;
+    for (int e = threadIdx.x; e < nk * q3; e += blockDim.x) {
+      const int z = e / nk, l = e - z * nk;
+      out[(size_t)z * kc1 + l] = lds[l * LS + z];
+    }
+    __syncthreads();
+  }
+}
+
+// Per (y, z row of the q grid): inverse in x of the nine fields (two real
+// fields per complex line, Hermitian-extended from kcx + 1 modes to q1
+// points), tau_ij = pp_ij - ub_i ub_j.
+__global__ void __launch_bounds__(256) k_xtau(XtauArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  double2* lds = reinterpret_cast<double2*>(smem_raw);
+  const int y = blockIdx.y, z = blockIdx.x;
+  const int q1 = a.q1, q3 = a.q3, LS = a.lstride;
+  const int kc1 = a.kcx + 1;
+  // line L holds field 2L + i field 2L+1 (fields 0..5 pp, 6..8 ub; field 9 = 0)
+  for (int e = threadIdx.x; e < 5 * q1; e += blockDim.x) {
+    const int l = e / q1;
+    lds[l * LS + (e - l * q1)] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 5 * kc1; e += blockDim.x) {
+    const int l = e / kc1, k = e - l * kc1;
+    const double2* src = a.in + ((size_t)(y * 9) * q3 + z) * kc1 + k;
+    const size_t fs = (size_t)q3 * kc1;
+    const double2 X = src[(size_t)(2 * l) * fs];
+    const double2 Y = (2 * l + 1 < 9) ? src[(size_t)(2 * l + 1) * fs] : make_double2(0.0, 0.0);
+    double2* line = lds + l * LS;
+    if (k == 0) {
+      line[0] = make_double2(X.x, Y.x);
+    } else {
+      line[k] = make_double2(X.x - Y.y, X.y + Y.x);
+      line[q1 - k] = make_double2(X.x + Y.y, Y.x - X.y);
+    }
+  }
+  __syncthreads();
+  fft_lines<double, 24>(lds, LS, 5, a.plan, a.tw, +1);
+  for (int x = threadIdx.x; x < q1; x += blockDim.x) {
+    double f[10];
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      const double2 v = lds[l * LS + x];
+      f[2 * l] = v.x;
+      f[2 * l + 1] = v.y;
+    }
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const double t = f[p] - f[6 + kPairI[p]] * f[6 + kPairJ[p]];
+      a.tau[(((size_t)p * a.n2 + y) * q3 + z) * q1 + x] = t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename T>
+hipError_t launch_xfilter(const XfilterArgs<T>& a, size_t lds_bytes, hipStream_t st) {
+  constexpr int MV = sizeof(T) == 8 ? 24 : 48;
+  hipLaunchKernelGGL((k_xfilter<T, MV>), dim3(a.d.p3, a.d.n2), dim3(256), lds_bytes, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_zfilter(const ZfilterArgs& a, size_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(k_zfilter, dim3((a.kcx + 1 + a.K - 1) / a.K, a.d.n2), dim3(256), lds_bytes, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_zinv_q(const ZinvQArgs& a, size_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(k_zinv_q, dim3((a.kcx + 1 + a.K - 1) / a.K, a.n2), dim3(256), lds_bytes, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_xtau(const XtauArgs& a, size_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(k_xtau, dim3(a.q3, a.n2), dim3(256), lds_bytes, st, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_xfilter<double>(const XfilterArgs<double>&, size_t, hipStream_t);
+template hipError_t launch_xfilter<float>(const XfilterArgs<float>&, size_t, hipStream_t);
+
+}  // namespace chn

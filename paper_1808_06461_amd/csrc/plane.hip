@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) k_zinv(ZinvArgs<T> a) {
       const int l = e / n3, s = e - l * n3;
       if (s == half) continue;
       c2<T> v = zero;
-      if (l < nk) {
+      if (l < nk && !(a.zero_mean && kx0 + l == 0 && s == 0)) {
         const size_t idx = ((size_t)y * n1h + kx0 + l) * n3 + s;
         if (f == 4 && a.in[4] == nullptr) {
           // omega2 = i (b u1 - a u3)

@@ -1,0 +1,77 @@
+"""Parity of the low-storage stage (chn_filter_and_stress) with the oracle.
+
+Float64 path: 1e-12 relative per output component.  Mixed path (float32
+inverse transforms and products, float64 forward accumulation): 1e-5
+relative on F(u_i u_j) and tau_ij, the bound the workload states.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import kmm, lowstorage
+
+torch = pytest.importorskip("torch")
+gpu = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+CASES = {
+    "small": (synth.Case(n1=32, n2=17, n3=24, lx=2 * np.pi, lz=np.pi, re_b=2000.0, dt=0.0, amp=0.1,
+                         mean="reichardt", re_tau=180.0, cfg=31), 3, 2, 16, 12),
+    "ragged": (synth.Case(n1=48, n2=13, n3=36, lx=2 * np.pi, lz=np.pi, re_b=2000.0, dt=0.0, amp=0.1,
+                          mean="reichardt", re_tau=180.0, cfg=32), 5, 4, 24, 18),
+    "mid": (synth.Case(n1=192, n2=25, n3=144, lx=2 * np.pi, lz=np.pi, re_b=18863.0, dt=0.0, amp=0.1,
+                       mean="reichardt", re_tau=950.0, spectrum=-8.0 / 3.0, cfg=33), 12, 9, 54, 48),
+}
+
+
+def _run(name, precision):
+    from paper_1808_06461_amd import Channel
+    case, kcx, kcz, q1, q3 = CASES[name]
+    v, om, U1, U3, y = synth.turbulent_field(case)
+    S = kmm.Setup(n1=case.n1, n2=case.n2, n3=case.n3, lx=case.lx, lz=case.lz, nu=1 / case.re_b, dt=1e-3,
+                  mass_flux=2.0, y=y)
+    st = kmm.make_state(S, v, om, U1, U3)
+    u1, u2, u3, *_ = kmm.recover(S, st)
+    ub, uu, tau = lowstorage.filter_and_stress(u1, u2, u3, kcx, kcz, q1, q3)
+    ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, precision=precision, y=y)
+    ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    gub, guu, gtau = (t.cpu().numpy() for t in ch.filter_and_stress(kcx, kcz, q1, q3))
+    ch.close()
+    return (ub, uu, tau), (gub, guu, gtau)
+
+
+@gpu
+@pytest.mark.parametrize("name", ["small", "ragged", "mid"])
+def test_filter_and_stress_fp64(name):
+    (ub, uu, tau), (gub, guu, gtau) = _run(name, "fp64")
+    for i in range(3):
+        assert rel(gub[i], ub[i]) < 1e-13, ("ubar", i, rel(gub[i], ub[i]))
+    for p in range(6):
+        e_uu, e_tau = rel(guu[p], uu[p]), rel(gtau[p], tau[p])
+        print(f"fp64 {name} pair {p}: uu {e_uu:.2e} tau {e_tau:.2e}")
+        assert e_uu < 1e-12 and e_tau < 1e-10, (p, e_uu, e_tau)
+
+
+@gpu
+@pytest.mark.parametrize("name", ["small", "ragged", "mid"])
+def test_filter_and_stress_mixed(name):
+    (ub, uu, tau), (gub, guu, gtau) = _run(name, "mixed")
+    for i in range(3):
+        assert rel(gub[i], ub[i]) < 1e-13
+    for p in range(6):
+        e_uu, e_tau = rel(guu[p], uu[p]), rel(gtau[p], tau[p])
+        print(f"mixed {name} pair {p}: uu {e_uu:.2e} tau {e_tau:.2e}")
+        assert e_uu < 1e-5 and e_tau < 1e-5, (p, e_uu, e_tau)
+
+
+@gpu
+def test_device_limits_report():
+    import torch as T
+    p = T.cuda.get_device_properties(0)
+    print("device:", p.name, "LDS/block:", getattr(p, "shared_memory_per_block", None),
+          "LDS/block optin:", getattr(p, "shared_memory_per_block_optin", None),
+          "multiprocessors:", p.multi_processor_count)
