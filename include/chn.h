@@ -161,6 +161,36 @@ chn_status chn_filter_and_stress(chn_ctx *ctx, int32_t kcx, int32_t kcz, int32_t
 chn_status chn_get_operators(chn_ctx *ctx, double *a1, double *b1, double *a2, double *b2,
                              double *quad);
 
+/* ---------------------------------------------------------------- ensembles
+ * An ensemble advances n independent channels of uneven sizes together:
+ * every phase of the RK3 sub-step is one batched launch over all channels
+ * (a work list of (channel, block) items, larger channels first, and one
+ * argument block per channel in device memory), and one RK3 step of the
+ * whole ensemble is a captured HIP graph replayed nsteps times.  All
+ * configurations must share the precision and the stream.  The ensemble
+ * runs on a private stream ordered after and before the configured stream
+ * by events.  Same conventions as single contexts (caller-owned workspace). */
+typedef struct chn_ens chn_ens;
+
+/* Workspace bytes for n channels (0 if any configuration is invalid). */
+size_t chn_ens_workspace_bytes(int32_t n, const chn_config *cfgs);
+
+/* Creates the n channel contexts inside d_workspace and the batched
+ * launch tables.  Synchronises. */
+chn_status chn_ens_create(int32_t n, const chn_config *cfgs, void *d_workspace, size_t ws_bytes,
+                          chn_ens **out);
+chn_status chn_ens_destroy(chn_ens *ens);
+
+/* Context handle of channel i (for chn_set_state, chn_get_fields,
+ * chn_filter_and_stress, ...); owned by the ensemble. */
+chn_ctx *chn_ens_context(chn_ens *ens, int32_t i);
+
+/* Advances every channel nsteps RK3 steps; dt is a HOST array of n step
+ * sizes.  Every channel must have a state (chn_set_state). */
+chn_status chn_ens_step(chn_ens *ens, const double *dt, int32_t nsteps);
+
+const char *chn_ens_last_error(const chn_ens *ens);
+
 /* Kernel kinds reported by chn_timing_read. */
 enum {
   CHN_K_RECOVER = 0, /* velocities/vorticities from v, omega2 (pencils) */

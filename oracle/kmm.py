@@ -138,20 +138,30 @@ def make_state(S, v, om2, U1, U3):
                  U1=np.array(U1, float), U3=np.array(U3, float))
 
 
-def recover(S, st):
-    """Velocities and vorticities in Fourier space (Appendix C, first steps of the sub-step).
+def velocities(S, st):
+    """u1, u3 in Fourier space from continuity (Appendix C, first steps of the sub-step).
 
-    From continuity i a u1 + dv/dy + i b u3 = 0 and omega2 = i b u1 - i a u3:
-      u1 = i(a dv - b omega2)/k^2,  u3 = i(b dv + a omega2)/k^2,
-      omega1 = du3/dy - i b v,      omega3 = i a v - du1/dy.
-    Mode (0,0): u1 = U1, u3 = U3, v = omega2 = 0.
+    From i a u1 + dv/dy + i b u3 = 0 and omega2 = i b u1 - i a u3:
+      u1 = i(a dv - b omega2)/k^2,  u3 = i(b dv + a omega2)/k^2;
+    mode (0,0): u1 = U1, u3 = U3.
     """
     k2 = np.where(S.live, S.k2, 1.0)[None]
     dv = d1(S, st.v)
     u1 = np.where(S.live[None], 1j * (S.a * dv - S.b * st.om2) / k2, 0)
     u3 = np.where(S.live[None], 1j * (S.b * dv + S.a * st.om2) / k2, 0)
+    del dv
     u1[:, 0, 0] = st.U1
     u3[:, 0, 0] = st.U3
+    return u1, u3
+
+
+def recover(S, st):
+    """Velocities and vorticities in Fourier space (Appendix C, first steps of the sub-step).
+
+    u1, u3 as in ``velocities``; omega1 = du3/dy - i b v, omega3 = i a v - du1/dy,
+    with v = omega2 = 0 in mode (0,0).
+    """
+    u1, u3 = velocities(S, st)
     du1 = d1(S, u1)
     du3 = d1(S, u3)
     om1 = du3 - 1j * S.b * st.v

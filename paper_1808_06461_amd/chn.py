@@ -58,11 +58,20 @@ def lib():
         L.chn_get_operators.argtypes = [P, P, P, P, P, P]
         L.chn_timing_enable.argtypes = [P, C.c_int32]
         L.chn_timing_read.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.chn_ens_workspace_bytes.argtypes = [C.c_int32, C.POINTER(Config)]
+        L.chn_ens_workspace_bytes.restype = C.c_size_t
+        L.chn_ens_create.argtypes = [C.c_int32, C.POINTER(Config), P, C.c_size_t, C.POINTER(P)]
+        L.chn_ens_destroy.argtypes = [P]
+        L.chn_ens_context.argtypes = [P, C.c_int32]
+        L.chn_ens_context.restype = P
+        L.chn_ens_step.argtypes = [P, C.POINTER(C.c_double), C.c_int32]
+        L.chn_ens_last_error.argtypes = [P]
+        L.chn_ens_last_error.restype = C.c_char_p
         L.chn_last_error.argtypes = [P]
         L.chn_last_error.restype = C.c_char_p
         for name in ("chn_create", "chn_destroy", "chn_set_state", "chn_step_rk3", "chn_get_fields",
                      "chn_nonlinear", "chn_filter_and_stress", "chn_get_operators", "chn_timing_enable",
-                     "chn_timing_read"):
+                     "chn_timing_read", "chn_ens_create", "chn_ens_destroy", "chn_ens_step"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -196,6 +205,72 @@ class Channel:
         if getattr(self, "ctx", None):
             self.L.chn_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _EnsChannel(Channel):
+    """A channel context owned by an Ensemble (same methods as Channel)."""
+
+    def __init__(self, ens, i, cfg):
+        self.L = ens.L
+        self.device = ens.device
+        self.n1, self.n2, self.n3 = cfg.n1, cfg.n2, cfg.n3
+        self.n1h = cfg.n1 // 2
+        self.ctx = C.c_void_p(self.L.chn_ens_context(ens.ens, i))
+        self._owner = ens
+
+    def close(self):
+        self.ctx = None
+
+
+class Ensemble:
+    """Uneven channels advanced together by batched launches in a HIP graph."""
+
+    def __init__(self, specs, precision="fp64", device="cuda:0"):
+        """specs: list of dicts with n1, n2, n3, lx, lz, re_b, mass_flux, y."""
+        self.L = lib()
+        self.device = torch.device(device)
+        prec = {"fp64": FP64, "mixed": MIXED}[precision]
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device)
+        self._ys = []
+        cfgs = (Config * len(specs))()
+        for k, sp in enumerate(specs):
+            yarr = (C.c_double * sp["n2"])(*[float(v) for v in sp["y"]])
+            self._ys.append(yarr)
+            cfgs[k] = Config(sp["n1"], sp["n2"], sp["n3"], sp["lx"], sp["lz"], sp["re_b"], sp.get("mass_flux", 2.0),
+                             prec, C.cast(yarr, C.POINTER(C.c_double)), C.c_void_p(stream.cuda_stream))
+        self.cfgs = cfgs
+        self.n = len(specs)
+        nbytes = self.L.chn_ens_workspace_bytes(self.n, cfgs)
+        if nbytes == 0:
+            raise ChnError("invalid ensemble configuration")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.ens = C.c_void_p()
+        s = self.L.chn_ens_create(self.n, cfgs, C.c_void_p(base + off), nbytes, C.byref(self.ens))
+        if s != 0:
+            raise ChnError(f"chn_ens_create: {STATUS.get(s, s)}: {self.L.chn_ens_last_error(None).decode()}")
+        self.channels = [_EnsChannel(self, i, cfgs[i]) for i in range(self.n)]
+
+    def step(self, dts, nsteps=1):
+        arr = (C.c_double * self.n)(*[float(d) for d in dts])
+        s = self.L.chn_ens_step(self.ens, arr, int(nsteps))
+        if s != 0:
+            raise ChnError(f"chn_ens_step: {STATUS.get(s, s)}: {self.L.chn_ens_last_error(self.ens).decode()}")
+
+    def close(self):
+        if getattr(self, "ens", None):
+            for c in self.channels:
+                c.close()
+            self.L.chn_ens_destroy(self.ens)
+            self.ens = None
 
     def __del__(self):
         try:

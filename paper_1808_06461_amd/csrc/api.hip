@@ -226,12 +226,12 @@ template <typename T> int z_lines(const chn_ctx* x) {
   return K;
 }
 
-// plane phase: ph (6 slots) -> H (3 slots) through the intermediate
 template <typename T, typename TO>
-chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, void* const* out) {
+void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* const* out, chn::ZinvArgs<T>& za,
+                chn::XpassArgs<T>& xa, chn::ZfwdArgs<T, TO>& fa) {
   using C = typename Ty<T>::c;
   const int K = z_lines<T>(x);
-  chn::ZinvArgs<T> za{};
+  za = {};
   for (int f = 0; f < 6; ++f) za.in[f] = reinterpret_cast<const C*>(in[f]);
   if (!omega2_given) za.in[4] = nullptr;
   za.out = reinterpret_cast<C*>(x->inter);
@@ -242,8 +242,7 @@ chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, voi
   za.lstride = x->p3 + 1;
   za.nfields = 6;
   za.nslot = 6;
-  HIPCHK(x, timed(x, CHN_K_ZINV, [&] { return chn::launch_zinv<T>(za, x->stream); }));
-  chn::XpassArgs<T> xa{};
+  xa = {};
   xa.buf = reinterpret_cast<C*>(x->inter);
   xa.tw = reinterpret_cast<const C*>(x->tw1);
   xa.plan = x->plan1;
@@ -254,8 +253,7 @@ chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, voi
   xa.inv_dx = x->n1 / x->cfg.lx;
   xa.inv_dz = x->n3 / x->cfg.lz;
   xa.inv_dy = x->inv_dy;
-  HIPCHK(x, timed(x, CHN_K_XPASS, [&] { return chn::launch_xpass<T>(xa, x->stream); }));
-  chn::ZfwdArgs<T, TO> fa{};
+  fa = {};
   fa.buf = reinterpret_cast<const C*>(x->inter);
   for (int f = 0; f < 3; ++f) fa.out[f] = reinterpret_cast<typename Ty<TO>::c*>(out[f]);
   fa.tw = reinterpret_cast<const C*>(x->tw3);
@@ -264,6 +262,17 @@ chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, voi
   fa.K = K;
   fa.lstride = x->p3 + 1;
   fa.scale = 1.0 / ((double)x->p1 * x->p3);
+}
+
+// plane phase: ph (6 slots) -> H (3 slots) through the intermediate
+template <typename T, typename TO>
+chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, void* const* out) {
+  chn::ZinvArgs<T> za;
+  chn::XpassArgs<T> xa;
+  chn::ZfwdArgs<T, TO> fa;
+  plane_args<T, TO>(x, in, omega2_given, out, za, xa, fa);
+  HIPCHK(x, timed(x, CHN_K_ZINV, [&] { return chn::launch_zinv<T>(za, x->stream); }));
+  HIPCHK(x, timed(x, CHN_K_XPASS, [&] { return chn::launch_xpass<T>(xa, x->stream); }));
   HIPCHK(x, timed(x, CHN_K_ZFWD, [&] { return chn::launch_zfwd<T, TO>(fa, x->stream); }));
   return CHN_OK;
 }
@@ -292,6 +301,8 @@ template <typename T> T* const* phase_ptrs(chn_ctx* x, T** po) {
   return po;
 }
 
+template <typename T> void advance_args(chn_ctx* x, int s, double dt, chn::AdvanceArgs<T, T>& aa);
+
 template <typename T> chn_status substep(chn_ctx* x, int s, double dt) {
   T* po[5];
   phase_ptrs<T>(x, po);
@@ -306,7 +317,16 @@ template <typename T> chn_status substep(chn_ctx* x, int s, double dt) {
   chn_status st = plane_phase<T, T>(x, x->ph, false, x->H);
   if (st != CHN_OK) return st;
   // 3. pencils + mean modes + next sub-step's velocities and vorticities
-  chn::AdvanceArgs<T, T> aa{};
+  chn::AdvanceArgs<T, T> aa;
+  advance_args<T>(x, s, dt, aa);
+  HIPCHK(x, timed(x, CHN_K_ADVANCE, [&] { return chn::launch_advance<T, T>(aa, x->stream); }));
+  return CHN_OK;
+}
+
+template <typename T> void advance_args(chn_ctx* x, int s, double dt, chn::AdvanceArgs<T, T>& aa) {
+  T* po[5];
+  phase_ptrs<T>(x, po);
+  aa = {};
   aa.g = x->geom;
   for (int f = 0; f < 5; ++f) aa.ph[f] = po[f];
   for (int f = 0; f < 3; ++f) aa.H[f] = reinterpret_cast<const T*>(x->H[f]);
@@ -322,8 +342,6 @@ template <typename T> chn_status substep(chn_ctx* x, int s, double dt) {
   aa.mass_flux = x->cfg.mass_flux;
   aa.dt = dt; aa.nu = x->nu;
   aa.al = kAlpha[s]; aa.be = kBeta[s]; aa.ga = kGamma[s]; aa.ze = kZeta[s];
-  HIPCHK(x, timed(x, CHN_K_ADVANCE, [&] { return chn::launch_advance<T, T>(aa, x->stream); }));
-  return CHN_OK;
 }
 
 chn_status check(chn_ctx* x);
@@ -457,6 +475,221 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
 chn_status check(chn_ctx* x) {
   if (!x) return CHN_EINVAL;
   if (x->sticky != CHN_OK) return x->sticky;
+  return CHN_OK;
+}
+
+}  // namespace
+
+
+// ---------------------------------------------------------------- ensembles
+struct chn_ens {
+  int n = 0;
+  bool mixed = false;
+  hipStream_t user = nullptr, own = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<chn_ctx*> ctx;
+  std::string err;
+  // device tables
+  void* d_zinv = nullptr;
+  void* d_xpass = nullptr;
+  void* d_zfwd = nullptr;
+  void* d_adv = nullptr;      // [3][n] advance argument blocks
+  int4 *d_wz = nullptr, *d_wx = nullptr, *d_wa = nullptr;
+  int nz = 0, nx = 0, na = 0;
+  size_t lds_z = 0, lds_x = 0;
+  std::vector<char> h_adv;    // host copy of the advance blocks (dt dependent)
+  std::vector<double> last_dt;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~chn_ens() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (chn_ctx* c : ctx) delete c;
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (own) (void)hipStreamDestroy(own);
+  }
+};
+
+namespace {
+
+// Per-channel workspace sizes and the ensemble's own tables, 256-byte aligned.
+struct EnsLayout {
+  std::vector<size_t> off, bytes;
+  size_t tables = 0, total = 0;
+};
+
+size_t arg_bytes(bool mixed) {
+  return mixed ? sizeof(chn::ZinvArgs<float>) + sizeof(chn::XpassArgs<float>) + sizeof(chn::ZfwdArgs<float, float>) +
+                     3 * sizeof(chn::AdvanceArgs<float, float>)
+               : sizeof(chn::ZinvArgs<double>) + sizeof(chn::XpassArgs<double>) +
+                     sizeof(chn::ZfwdArgs<double, double>) + 3 * sizeof(chn::AdvanceArgs<double, double>);
+}
+
+bool ens_layout(int n, const chn_config* cfgs, EnsLayout* L) {
+  if (n < 1 || !cfgs) return false;
+  size_t off = 0, items = 0;
+  for (int i = 0; i < n; ++i) {
+    if (validate(&cfgs[i])) return false;
+    if (cfgs[i].precision != cfgs[0].precision || cfgs[i].stream != cfgs[0].stream) return false;
+    const size_t b = layout(&cfgs[i], nullptr, nullptr);
+    off = (off + 255) & ~(size_t)255;
+    L->off.push_back(off);
+    L->bytes.push_back(b);
+    off += b;
+    const int n1h = cfgs[i].n1 / 2, p3 = 3 * cfgs[i].n3 / 2;
+    const size_t M = (size_t)n1h * cfgs[i].n3;
+    items += (size_t)cfgs[i].n2 * (n1h + p3) + (2 * M + 255) / 256 + 1;
+  }
+  off = (off + 255) & ~(size_t)255;
+  L->tables = off;
+  L->total = off + (size_t)n * arg_bytes(cfgs[0].precision == CHN_MIXED) + 256 * 4 + items * sizeof(int4) * 2 + 4096;
+  return true;
+}
+
+template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
+  const int n = e->n;
+  // larger channels first: a static longest-processing-time order
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    const chn_ctx *A = e->ctx[a], *B = e->ctx[b];
+    return (size_t)A->n2 * A->M > (size_t)B->n2 * B->M;
+  });
+  std::vector<chn::ZinvArgs<T>> za(n);
+  std::vector<chn::XpassArgs<T>> xa(n);
+  std::vector<chn::ZfwdArgs<T, T>> fa(n);
+  std::vector<int4> wz, wx, wa;
+  e->lds_z = e->lds_x = 0;
+  for (int i = 0; i < n; ++i) {
+    chn_ctx* x = e->ctx[i];
+    plane_args<T, T>(x, x->ph, false, x->H, za[i], xa[i], fa[i]);
+    e->lds_z = std::max(e->lds_z, (size_t)za[i].K * za[i].lstride * sizeof(typename Ty<T>::c));
+    e->lds_x = std::max(e->lds_x, (size_t)6 * xa[i].lstride * sizeof(typename Ty<T>::c));
+  }
+  for (int c : order) {
+    chn_ctx* x = e->ctx[c];
+    const int nbz = (x->n1h + za[c].K - 1) / za[c].K;
+    for (int y = 0; y < x->n2; ++y)
+      for (int b = 0; b < nbz; ++b) wz.push_back(make_int4(c, b, y, 0));
+    for (int y = 0; y < x->n2; ++y)
+      for (int b = 0; b < x->p3 / 2; ++b) wx.push_back(make_int4(c, b, y, 0));
+    const int nb = (int)((2 * (size_t)x->M + 255) / 256);
+    wa.push_back(make_int4(c, 0, 0, 1));  // mean-mode workgroup
+    for (int b = 0; b < nb; ++b) wa.push_back(make_int4(c, b, 0, 0));
+  }
+  // device placement
+  char* p = tables;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += (bytes + 255) & ~(size_t)255;
+    return q;
+  };
+  e->d_zinv = take(sizeof(za[0]) * n);
+  e->d_xpass = take(sizeof(xa[0]) * n);
+  e->d_zfwd = take(sizeof(fa[0]) * n);
+  e->d_adv = take(sizeof(chn::AdvanceArgs<T, T>) * 3 * n);
+  e->d_wz = reinterpret_cast<int4*>(take(sizeof(int4) * wz.size()));
+  e->d_wx = reinterpret_cast<int4*>(take(sizeof(int4) * wx.size()));
+  e->d_wa = reinterpret_cast<int4*>(take(sizeof(int4) * wa.size()));
+  e->nz = (int)wz.size();
+  e->nx = (int)wx.size();
+  e->na = (int)wa.size();
+  hipError_t r = hipMemcpyAsync(e->d_zinv, za.data(), sizeof(za[0]) * n, hipMemcpyHostToDevice, e->user);
+  if (r == hipSuccess) r = hipMemcpyAsync(e->d_xpass, xa.data(), sizeof(xa[0]) * n, hipMemcpyHostToDevice, e->user);
+  if (r == hipSuccess) r = hipMemcpyAsync(e->d_zfwd, fa.data(), sizeof(fa[0]) * n, hipMemcpyHostToDevice, e->user);
+  if (r == hipSuccess) r = hipMemcpyAsync(e->d_wz, wz.data(), sizeof(int4) * wz.size(), hipMemcpyHostToDevice, e->user);
+  if (r == hipSuccess) r = hipMemcpyAsync(e->d_wx, wx.data(), sizeof(int4) * wx.size(), hipMemcpyHostToDevice, e->user);
+  if (r == hipSuccess) r = hipMemcpyAsync(e->d_wa, wa.data(), sizeof(int4) * wa.size(), hipMemcpyHostToDevice, e->user);
+  if (r == hipSuccess) r = hipStreamSynchronize(e->user);
+  if (r != hipSuccess) {
+    e->err = std::string("uploading ensemble tables: ") + hipGetErrorString(r);
+    return CHN_EDEVICE;
+  }
+  e->h_adv.resize(sizeof(chn::AdvanceArgs<T, T>) * 3 * n);
+  return CHN_OK;
+}
+
+#define ENSCHK(e, call)                                                        \
+  do {                                                                         \
+    hipError_t r_ = (call);                                                    \
+    if (r_ != hipSuccess) {                                                    \
+      (e)->err = std::string(#call ": ") + hipGetErrorString(r_);              \
+      return CHN_EDEVICE;                                                      \
+    }                                                                          \
+  } while (0)
+
+template <typename T> chn_status ens_step(chn_ens* e, const double* dt, int nsteps) {
+  const int n = e->n;
+  for (int i = 0; i < n; ++i) {
+    chn_ctx* x = e->ctx[i];
+    if (chn_status s = check(x)) {
+      e->err = "channel " + std::to_string(i) + ": " + x->err;
+      return s;
+    }
+    if (!x->have_state) {
+      e->err = "channel " + std::to_string(i) + " has no state";
+      return CHN_ESTATE;
+    }
+    if (!(dt[i] > 0)) {
+      e->err = "dt must be positive";
+      return CHN_EINVAL;
+    }
+    if (!x->phase_valid) {  // velocities/vorticities of a new state
+      T* po[5];
+      phase_ptrs<T>(x, po);
+      if (chn_status s = recover<T>(x, po)) {
+        e->err = x->err;
+        return s;
+      }
+      x->phase_valid = true;
+    }
+  }
+  // advance argument blocks for these step sizes (the graph reads them from device memory)
+  if (e->last_dt.size() != (size_t)n || !std::equal(e->last_dt.begin(), e->last_dt.end(), dt)) {
+    auto* h = reinterpret_cast<chn::AdvanceArgs<T, T>*>(e->h_adv.data());
+    for (int s = 0; s < 3; ++s)
+      for (int i = 0; i < n; ++i) advance_args<T>(e->ctx[i], s, dt[i], h[s * n + i]);
+    ENSCHK(e, hipMemcpyAsync(e->d_adv, e->h_adv.data(), e->h_adv.size(), hipMemcpyHostToDevice, e->user));
+    e->last_dt.assign(dt, dt + n);
+  }
+  ENSCHK(e, hipEventRecord(e->ev_in, e->user));
+  ENSCHK(e, hipStreamWaitEvent(e->own, e->ev_in, 0));
+  chn::BatchPlan<T> bp{};
+  bp.zinv = reinterpret_cast<const chn::ZinvArgs<T>*>(e->d_zinv);
+  bp.xpass = reinterpret_cast<const chn::XpassArgs<T>*>(e->d_xpass);
+  bp.zfwd = reinterpret_cast<const chn::ZfwdArgs<T, T>*>(e->d_zfwd);
+  bp.wz = e->d_wz;
+  bp.wx = e->d_wx;
+  bp.nz = e->nz;
+  bp.nx = e->nx;
+  bp.lds_z = e->lds_z;
+  bp.lds_x = e->lds_x;
+  const auto* adv = reinterpret_cast<const chn::AdvanceArgs<T, T>*>(e->d_adv);
+  auto one_step = [&]() -> hipError_t {
+    for (int s = 0; s < 3; ++s) {
+      hipError_t r = chn::launch_plane_batch<T>(bp, e->own);
+      if (r == hipSuccess) r = chn::launch_advance_batch<T>(adv + s * n, e->d_wa, e->na, e->own);
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  };
+  if (!e->exec) {  // capture one RK3 step of the whole ensemble once
+    ENSCHK(e, hipStreamBeginCapture(e->own, hipStreamCaptureModeThreadLocal));
+    const hipError_t r = one_step();
+    hipGraph_t g = nullptr;
+    const hipError_t r2 = hipStreamEndCapture(e->own, &g);
+    if (r != hipSuccess || r2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      e->err = std::string("capturing the ensemble step: ") + hipGetErrorString(r != hipSuccess ? r : r2);
+      return CHN_EDEVICE;
+    }
+    e->graph = g;
+    ENSCHK(e, hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0));
+  }
+  for (int k = 0; k < nsteps; ++k) ENSCHK(e, hipGraphLaunch(e->exec, e->own));
+  ENSCHK(e, hipEventRecord(e->ev_out, e->own));
+  ENSCHK(e, hipStreamWaitEvent(e->user, e->ev_out, 0));
   return CHN_OK;
 }
 
@@ -741,6 +974,62 @@ chn_status chn_timing_read(chn_ctx* x, int32_t kind, double* total_ms, int32_t* 
   *count = n;
   return CHN_OK;
 }
+
+size_t chn_ens_workspace_bytes(int32_t n, const chn_config* cfgs) {
+  EnsLayout L;
+  return ens_layout(n, cfgs, &L) ? L.total : 0;
+}
+
+chn_status chn_ens_create(int32_t n, const chn_config* cfgs, void* d_ws, size_t ws_bytes, chn_ens** out) {
+  if (!out) return fail(nullptr, CHN_EINVAL, "out is NULL");
+  *out = nullptr;
+  EnsLayout L;
+  if (!ens_layout(n, cfgs, &L)) return fail(nullptr, CHN_EINVAL, "invalid ensemble configuration (sizes, or mixed precisions/streams)");
+  if (!d_ws || ws_bytes < L.total || reinterpret_cast<uintptr_t>(d_ws) % 256)
+    return fail(nullptr, CHN_EINVAL, "ensemble workspace missing, misaligned or too small");
+  chn_ens* e = new chn_ens();
+  e->n = n;
+  e->mixed = cfgs[0].precision == CHN_MIXED;
+  e->user = reinterpret_cast<hipStream_t>(cfgs[0].stream);
+  char* base = reinterpret_cast<char*>(d_ws);
+  for (int i = 0; i < n; ++i) {
+    chn_ctx* c = nullptr;
+    const chn_status s = chn_create(&cfgs[i], base + L.off[i], L.bytes[i], &c);
+    if (s != CHN_OK) {
+      g_create_error = "channel " + std::to_string(i) + ": " + g_create_error;
+      delete e;
+      return s;
+    }
+    e->ctx.push_back(c);
+  }
+  if (hipStreamCreate(&e->own) != hipSuccess || hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming) != hipSuccess) {
+    delete e;
+    return fail(nullptr, CHN_EDEVICE, "creating the ensemble stream/events");
+  }
+  const chn_status s = e->mixed ? ens_build<float>(e, base + L.tables) : ens_build<double>(e, base + L.tables);
+  if (s != CHN_OK) {
+    g_create_error = e->err;
+    delete e;
+    return s;
+  }
+  *out = e;
+  return CHN_OK;
+}
+
+chn_status chn_ens_destroy(chn_ens* e) {
+  delete e;
+  return CHN_OK;
+}
+
+chn_ctx* chn_ens_context(chn_ens* e, int32_t i) { return (e && i >= 0 && i < e->n) ? e->ctx[i] : nullptr; }
+
+chn_status chn_ens_step(chn_ens* e, const double* dt, int32_t nsteps) {
+  if (!e || !dt || nsteps < 0) return CHN_EINVAL;
+  return e->mixed ? ens_step<float>(e, dt, nsteps) : ens_step<double>(e, dt, nsteps);
+}
+
+const char* chn_ens_last_error(const chn_ens* e) { return e ? e->err.c_str() : g_create_error.c_str(); }
 
 const char* chn_last_error(const chn_ctx* x) { return x ? x->err.c_str() : g_create_error.c_str(); }
 

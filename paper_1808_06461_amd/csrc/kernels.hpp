@@ -171,6 +171,20 @@ struct InfoArgs {
   const double* mean_out;
 };
 
+// batched plane phase: descriptors and work lists (context, bx, by, -) in device memory
+template <typename T> struct BatchPlan {
+  const ZinvArgs<T>* zinv;
+  const XpassArgs<T>* xpass;
+  const ZfwdArgs<T, T>* zfwd;
+  const int4* wz;   // work list of the z passes
+  const int4* wx;   // work list of the x pass
+  int nz, nx;       // work items
+  size_t lds_z, lds_x;
+};
+template <typename T> hipError_t launch_plane_batch(const BatchPlan<T>& b, hipStream_t st);
+template <typename T>
+hipError_t launch_advance_batch(const AdvanceArgs<T, T>* d, const int4* w, int nblocks, hipStream_t st);
+
 template <typename TP> hipError_t launch_recover(const RecoverArgs<TP>& a, hipStream_t st);
 template <typename TH, typename TP> hipError_t launch_advance(const AdvanceArgs<TH, TP>& a, hipStream_t st);
 hipError_t launch_chi_from_v(const ChiArgs& a, hipStream_t st);

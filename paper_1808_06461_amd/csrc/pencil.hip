@@ -28,9 +28,9 @@ struct Lane {
   double A, B, k2, ik2;
 };
 
-__device__ __forceinline__ Lane lane_setup(const PencilGeom& g) {
+__device__ __forceinline__ Lane lane_setup(const PencilGeom& g, int bx) {
   Lane L;
-  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gl = bx * blockDim.x + threadIdx.x;
   int m = gl >> 1;
   L.c = gl & 1;
   L.act = m < g.M;
@@ -104,7 +104,7 @@ template <typename T> __device__ __forceinline__ double load_r(const T* p, size_
 template <typename TP>
 __global__ void __launch_bounds__(256) k_recover(RecoverArgs<TP> a) {
   const PencilGeom& g = a.g;
-  const Lane L = lane_setup(g);
+  const Lane L = lane_setup(g, blockIdx.x);
   const int n = g.n2;
   const size_t st = 2 * (size_t)g.M;
   const size_t col = L.col;
@@ -377,20 +377,17 @@ __device__ void mean_block(const AdvanceArgs<TH, TP>& a) {
 //   R2 up   : finish dv; u1, u3 by continuity; eliminate A1 (du) = B1 u
 //   R3 down : finish du1, du3; omega1 = du3 - i b v, omega3 = i a v - du1
 template <typename TH, typename TP>
-__global__ void __launch_bounds__(256)
-    k_advance(AdvanceArgs<TH, TP> a,
-              // read-only tables as noalias parameters, so the wave-uniform row
-              // loads go through the scalar cache instead of vector registers
-              const double* __restrict__ B1, const double* __restrict__ A2, const double* __restrict__ B2,
-              const double* __restrict__ L1d, const double* __restrict__ U1d, const double* __restrict__ L1u,
-              const double* __restrict__ U1u, const double* __restrict__ clo, const double* __restrict__ chw) {
-  if (blockIdx.x == gridDim.x - 1) {
-    mean_block(a);
-    return;
-  }
+__device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int bx,
+                                             // read-only tables as noalias parameters, so the wave-uniform
+                                             // row loads go through the scalar cache, not vector registers
+                                             const double* __restrict__ B1, const double* __restrict__ A2,
+                                             const double* __restrict__ B2, const double* __restrict__ L1d,
+                                             const double* __restrict__ U1d, const double* __restrict__ L1u,
+                                             const double* __restrict__ U1u, const double* __restrict__ clo,
+                                             const double* __restrict__ chw) {
   constexpr int D = 4, D2 = 3, D3 = 3;
   const PencilGeom& g = a.g;
-  const Lane L = lane_setup(g);
+  const Lane L = lane_setup(g, bx);
   const int n = g.n2;
   const size_t st = 2 * (size_t)g.M;
   const size_t M = g.M;
@@ -808,10 +805,37 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+template <typename TH, typename TP>
+__global__ void __launch_bounds__(256)
+    k_advance(AdvanceArgs<TH, TP> a, const double* __restrict__ B1, const double* __restrict__ A2,
+              const double* __restrict__ B2, const double* __restrict__ L1d, const double* __restrict__ U1d,
+              const double* __restrict__ L1u, const double* __restrict__ U1u, const double* __restrict__ clo,
+              const double* __restrict__ chw) {
+  if (blockIdx.x == gridDim.x - 1) {
+    mean_block(a);
+    return;
+  }
+  advance_body(a, blockIdx.x, B1, A2, B2, L1d, U1d, L1u, U1u, clo, chw);
+}
+
+// Batched over contexts: work item (context, block, -, mean flag).
+template <typename TH, typename TP>
+__global__ void __launch_bounds__(256) k_advance_batch(const AdvanceArgs<TH, TP>* __restrict__ d,
+                                                       const int4* __restrict__ w) {
+  const int4 q = w[blockIdx.x];
+  const AdvanceArgs<TH, TP>& a = d[q.x];
+  if (q.w) {
+    mean_block(a);
+    return;
+  }
+  const PencilGeom& g = a.g;
+  advance_body(a, q.y, g.B1, g.A2, g.B2, g.L1d, g.U1d, g.L1u, g.U1u, g.clo, g.chi);
+}
+
 // ---------------------------------------------------------------- set state
 __global__ void __launch_bounds__(256) k_chi_from_v(ChiArgs a) {
   const PencilGeom& g = a.g;
-  const Lane L = lane_setup(g);
+  const Lane L = lane_setup(g, blockIdx.x);
   const int n = g.n2;
   const size_t st = 2 * (size_t)g.M;
   const size_t col = L.col;
@@ -929,6 +953,14 @@ hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_
 
 template hipError_t launch_recover<double>(const RecoverArgs<double>&, hipStream_t);
 template hipError_t launch_recover<float>(const RecoverArgs<float>&, hipStream_t);
+template <typename T>
+hipError_t launch_advance_batch(const AdvanceArgs<T, T>* d, const int4* w, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_advance_batch<T, T>), dim3(nblocks), dim3(256), 0, st, d, w);
+  return hipGetLastError();
+}
+template hipError_t launch_advance_batch<double>(const AdvanceArgs<double, double>*, const int4*, int, hipStream_t);
+template hipError_t launch_advance_batch<float>(const AdvanceArgs<float, float>*, const int4*, int, hipStream_t);
+
 template hipError_t launch_advance<double, double>(const AdvanceArgs<double, double>&, hipStream_t);
 template hipError_t launch_advance<float, float>(const AdvanceArgs<float, float>&, hipStream_t);
 

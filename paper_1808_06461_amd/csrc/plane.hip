@@ -21,11 +21,11 @@ namespace chn {
 static constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 template <typename T, int MAXV>
-__global__ void __launch_bounds__(256) k_zinv(ZinvArgs<T> a) {
+__device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-  const int y = blockIdx.y;
-  const int kx0 = blockIdx.x * a.K;
+  const int y = by;
+  const int kx0 = bx * a.K;
   const int n1h = a.d.n1h, n3 = a.d.n3, p3 = a.d.p3, K = a.K, LS = a.lstride;
   const int nk = min(K, n1h - kx0);
   const int half = n3 / 2;
@@ -67,11 +67,11 @@ __global__ void __launch_bounds__(256) k_zinv(ZinvArgs<T> a) {
 }
 
 template <typename T, int MAXV>
-__global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) {
+__device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-  const int y = blockIdx.y;
-  const int z0 = blockIdx.x * 2;
+  const int y = by;
+  const int z0 = bx * 2;
   const int n1h = a.d.n1h, p1 = a.d.p1, p3 = a.d.p3, LS = a.lstride;
   const int npad = p1 - 2 * n1h + 1;
   const c2<T> zero = mk<T>(T(0), T(0));
@@ -170,11 +170,11 @@ __global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) {
 }
 
 template <typename T, typename TO, int MAXV>
-__global__ void __launch_bounds__(256) k_zfwd(ZfwdArgs<T, TO> a) {
+__device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-  const int y = blockIdx.y;
-  const int kx0 = blockIdx.x * a.K;
+  const int y = by;
+  const int kx0 = bx * a.K;
   const int n1h = a.d.n1h, n3 = a.d.n3, p3 = a.d.p3, K = a.K, LS = a.lstride;
   const int nk = min(K, n1h - kx0);
   const int half = n3 / 2;
@@ -199,6 +199,33 @@ __global__ void __launch_bounds__(256) k_zfwd(ZfwdArgs<T, TO> a) {
     }
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------- entry points
+// Single-context launches index blocks by (blockIdx.x, blockIdx.y); batched
+// launches (ensembles) read (context, bx, by) from a work list and the
+// context's arguments from a descriptor array.
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(256) k_zinv(ZinvArgs<T> a) { zinv_body<T, MAXV>(a, blockIdx.x, blockIdx.y); }
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) { xpass_body<T, MAXV>(a, blockIdx.x, blockIdx.y); }
+template <typename T, typename TO, int MAXV>
+__global__ void __launch_bounds__(256) k_zfwd(ZfwdArgs<T, TO> a) { zfwd_body<T, TO, MAXV>(a, blockIdx.x, blockIdx.y); }
+
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(256) k_zinv_batch(const ZinvArgs<T>* __restrict__ d, const int4* __restrict__ w) {
+  const int4 q = w[blockIdx.x];
+  zinv_body<T, MAXV>(d[q.x], q.y, q.z);
+}
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(256) k_xpass_batch(const XpassArgs<T>* __restrict__ d, const int4* __restrict__ w) {
+  const int4 q = w[blockIdx.x];
+  xpass_body<T, MAXV>(d[q.x], q.y, q.z);
+}
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(256) k_zfwd_batch(const ZfwdArgs<T, T>* __restrict__ d, const int4* __restrict__ w) {
+  const int4 q = w[blockIdx.x];
+  zfwd_body<T, T, MAXV>(d[q.x], q.y, q.z);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -232,6 +259,21 @@ hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st) {
   hipLaunchKernelGGL((k_zfwd<T, TO, MV>), grid, dim3(256), sh, st, a);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_plane_batch(const BatchPlan<T>& b, hipStream_t st) {
+  constexpr int MV = FftMaxv<T>::v;
+  hipLaunchKernelGGL((k_zinv_batch<T, MV>), dim3(b.nz), dim3(256), b.lds_z, st, b.zinv, b.wz);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_xpass_batch<T, MV>), dim3(b.nx), dim3(256), b.lds_x, st, b.xpass, b.wx);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_zfwd_batch<T, MV>), dim3(b.nz), dim3(256), b.lds_z, st, b.zfwd, b.wz);
+  return hipGetLastError();
+}
+template hipError_t launch_plane_batch<double>(const BatchPlan<double>&, hipStream_t);
+template hipError_t launch_plane_batch<float>(const BatchPlan<float>&, hipStream_t);
 
 template hipError_t launch_zinv<double>(const ZinvArgs<double>&, hipStream_t);
 template hipError_t launch_zinv<float>(const ZinvArgs<float>&, hipStream_t);

@@ -198,3 +198,19 @@ CASES = {
     "c5": Case(n1=1536, n2=385, n3=1152, lx=2 * np.pi, lz=np.pi, re_b=18863.0, dt=0.0,
                amp=0.1, kmax=None, mean="reichardt", re_tau=950.0, cfg=5),
 }
+
+
+def ensemble_cases(n=96, cfg=4):
+    """Uneven minimal channels: n1 in {32,48,64}, n2 in {49,65,97}, n3 in {32,48},
+    Re_tau ~ U[180, 400] (Re_b from Dean's correlation), box pi x 2 x pi/2,
+    Reichardt mean + 0.1 RMS perturbations, each channel with its own seed."""
+    g = rng(cfg, 0)
+    out = []
+    for i in range(n):
+        n1 = int(g.choice([32, 48, 64]))
+        n2 = int(g.choice([49, 65, 97]))
+        n3 = int(g.choice([32, 48]))
+        rt = float(g.uniform(180.0, 400.0))
+        out.append(Case(n1=n1, n2=n2, n3=n3, lx=np.pi, lz=np.pi / 2, re_b=dean_re_b(rt), dt=0.0, amp=0.1,
+                        mean="reichardt", re_tau=rt, cfg=1000 + i))
+    return out

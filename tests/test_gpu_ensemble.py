@@ -1,0 +1,71 @@
+"""Ensemble path (batched launches over uneven channels, HIP graph) against
+single-context runs and, for one channel, the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import kmm
+
+torch = pytest.importorskip("torch")
+gpu = pytest.mark.gpu
+
+SPECS = [
+    synth.Case(n1=16, n2=33, n3=16, lx=2 * np.pi, lz=np.pi, re_b=2800.0, dt=0.004, amp=0.1, kmax=5, cfg=41),
+    synth.Case(n1=24, n2=25, n3=12, lx=np.pi, lz=np.pi / 2, re_b=1500.0, dt=0.003, amp=0.1, cfg=42),
+    synth.Case(n1=32, n2=17, n3=24, lx=np.pi, lz=np.pi / 2, re_b=2000.0, dt=0.002, amp=0.1, cfg=43),
+    synth.Case(n1=16, n2=49, n3=32, lx=np.pi, lz=np.pi / 2, re_b=3000.0, dt=0.003, amp=0.1, cfg=44),
+    synth.Case(n1=48, n2=25, n3=16, lx=2 * np.pi, lz=np.pi, re_b=2500.0, dt=0.004, amp=0.1, cfg=45),
+]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _spec(c, y):
+    return dict(n1=c.n1, n2=c.n2, n3=c.n3, lx=c.lx, lz=c.lz, re_b=c.re_b, mass_flux=c.mass_flux, y=y)
+
+
+@gpu
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_ensemble_matches_single_contexts(precision):
+    from paper_1808_06461_amd import Channel
+    from paper_1808_06461_amd.chn import Ensemble
+    fields = [synth.turbulent_field(c) for c in SPECS]
+    ens = Ensemble([_spec(c, f[4]) for c, f in zip(SPECS, fields)], precision=precision)
+    for ch, (v, om, U1, U3, y) in zip(ens.channels, fields):
+        ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    ens.step([c.dt for c in SPECS], 2)
+    for k, (c, (v, om, U1, U3, y)) in enumerate(zip(SPECS, fields)):
+        got = {n: t.cpu().numpy() for n, t in ens.channels[k].get_fields("v", "omega2", "chi", "u1mean").items()}
+        single = Channel(c.n1, c.n2, c.n3, c.lx, c.lz, c.re_b, precision=precision, y=y)
+        single.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+        single.step(c.dt, 2)
+        ref = {n: t.cpu().numpy() for n, t in single.get_fields("v", "omega2", "chi", "u1mean").items()}
+        single.close()
+        for n in ref:
+            e = rel(got[n], ref[n])
+            print(f"{precision} channel {k} {n}: {e:.2e}")
+            assert e < 1e-14, (k, n, e)
+    ens.close()
+
+
+@gpu
+def test_ensemble_channel_matches_oracle():
+    from paper_1808_06461_amd.chn import Ensemble
+    fields = [synth.turbulent_field(c) for c in SPECS]
+    ens = Ensemble([_spec(c, f[4]) for c, f in zip(SPECS, fields)])
+    for ch, (v, om, U1, U3, y) in zip(ens.channels, fields):
+        ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    ens.step([c.dt for c in SPECS], 1)
+    k = 3
+    c = SPECS[k]
+    v, om, U1, U3, y = fields[k]
+    S = kmm.Setup(n1=c.n1, n2=c.n2, n3=c.n3, lx=c.lx, lz=c.lz, nu=1 / c.re_b, dt=c.dt, mass_flux=c.mass_flux, y=y)
+    ref, _ = kmm.step(S, kmm.make_state(S, v, om, U1, U3), 1)
+    got = {n: t.cpu().numpy() for n, t in ens.channels[k].get_fields("v", "omega2", "u1mean").items()}
+    for n, r in (("v", ref.v), ("omega2", ref.om2), ("u1mean", ref.U1)):
+        e = rel(got[n], r)
+        print(f"oracle channel {k} {n}: {e:.2e}")
+        assert e < 1e-11, (n, e)
+    ens.close()
