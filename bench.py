@@ -68,6 +68,40 @@ def run_path(case, v, om, U1, U3, y, precision, steps, warmup):
     return ms, wall, kern, fields
 
 
+def ensemble_run(steps=50, precision="mixed"):
+    """The 96-channel ensemble (uneven sizes) advanced `steps` RK3 steps in the graph."""
+    import torch
+
+    import synth
+    from paper_1808_06461_amd.chn import Ensemble
+    cases = synth.ensemble_cases(96)
+    fields = [synth.turbulent_field(c) for c in cases]
+    specs = [dict(n1=c.n1, n2=c.n2, n3=c.n3, lx=c.lx, lz=c.lz, re_b=c.re_b, mass_flux=c.mass_flux, y=f[4])
+             for c, f in zip(cases, fields)]
+    ens = Ensemble(specs, precision=precision)
+    dts = []
+    for ch, (v, om, U1, U3, y) in zip(ens.channels, fields):
+        args = [torch.from_numpy(a) for a in (v, om, U1, U3)]
+        ch.set_state(*args)
+        info = ch.step(1e-6, 1, info=True)   # probe: CFL per unit dt at t = 0
+        dts.append(0.5 * 1e-6 / info["cfl_max"])
+        ch.set_state(*args)
+    ens.step(dts, 1)  # warm-up: graph capture and instantiation
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    ens.step(dts, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    G = sum(c.n1 * c.n2 * c.n3 for c in cases)
+    ens.close()
+    return {"workload": "96 minimal channels, n1 in {32,48,64}, n2 in {49,65,97}, n3 in {32,48}, "
+                        "Re_tau in [180,400], one HIP graph per RK3 step of the whole ensemble",
+            "precision": precision, "steps": steps, "grid_points": G, "ms_per_step": ms / steps,
+            "value": G * steps / (ms / 1e3), "unit": UNIT}
+
+
 def cpu_baseline(case, v, om, U1, U3, y):
     """The oracle on the host: one RK3 sub-step of the same workload, scaled to a step."""
     from oracle import kmm
@@ -89,6 +123,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--only", choices=("fp64", "mixed"), default=None,
+                    help="run one precision only (for profiling; the JSON then lacks the comparison)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -101,6 +138,12 @@ def main():
     G = case.n1 * case.n2 * case.n3
 
     res = {}
+    if args.only:
+        print(f"[bench] {args.only} only: {args.warmup} warmup + {args.steps} timed RK3 steps", file=sys.stderr)
+        ms, _, kern, _ = run_path(case, v, om, U1, U3, y, args.only, args.steps, args.warmup)
+        print(json.dumps({"precision": args.only, "ms_per_step": ms / args.steps,
+                          "value": G * args.steps / (ms / 1e3), "kernels_ms": {k: t / max(n, 1) for k, (t, n) in kern.items()}}))
+        return
     for prec in ("fp64", "mixed"):
         print(f"[bench] {prec}: {args.warmup} warmup + {args.steps} timed RK3 steps", file=sys.stderr, flush=True)
         res[prec] = run_path(case, v, om, U1, U3, y, prec, args.steps, args.warmup)
@@ -145,6 +188,9 @@ def main():
         "kernels": per_kernel,
         "roofline": roof,
     }
+    if not args.no_ensemble:
+        print("[bench] ensemble of 96 channels, 50 steps", file=sys.stderr, flush=True)
+        out["ensemble"] = ensemble_run()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, one sub-step)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, v, om, U1, U3, y)

@@ -69,3 +69,47 @@ def test_ensemble_channel_matches_oracle():
         print(f"oracle channel {k} {n}: {e:.2e}")
         assert e < 1e-11, (n, e)
     ens.close()
+
+
+def c4_ensemble(precision="fp64", n=96):
+    """The 96-channel workload (sizes, Re_tau and seeds from synth.ensemble_cases),
+    each channel's dt from CFL 0.5 at t = 0 measured by a probe step."""
+    from paper_1808_06461_amd.chn import Ensemble
+    cases = synth.ensemble_cases(n)
+    fields = [synth.turbulent_field(c) for c in cases]
+    ens = Ensemble([_spec(c, f[4]) for c, f in zip(cases, fields)], precision=precision)
+    dts = []
+    for ch, (v, om, U1, U3, y) in zip(ens.channels, fields):
+        ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+        info = ch.step(1e-6, 1, info=True)
+        dts.append(0.5 * 1e-6 / info["cfl_max"])
+        ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    return ens, cases, fields, dts
+
+
+@gpu
+def test_c4_ensemble_fifty_steps():
+    """96 uneven minimal channels, 50 RK3 steps in the graph: finite, walls, mass flux,
+    and two channels bitwise equal to single-context runs."""
+    from oracle import compact
+    from paper_1808_06461_amd import Channel
+    ens, cases, fields, dts = c4_ensemble()
+    ens.step(dts, 50)
+    for k, (c, ch) in enumerate(zip(cases, ens.channels)):
+        got = {n: t.cpu().numpy() for n, t in ch.get_fields("v", "omega2", "u1mean").items()}
+        assert all(np.isfinite(a).all() for a in got.values()), k
+        assert np.abs(got["v"][[0, -1]]).max() == 0.0
+        w = compact.quadrature_weights(fields[k][4])
+        assert abs(w @ got["u1mean"] - 2.0) < 1e-12, (k, w @ got["u1mean"])
+    for k in (0, len(cases) - 1):
+        c = cases[k]
+        v, om, U1, U3, y = fields[k]
+        single = Channel(c.n1, c.n2, c.n3, c.lx, c.lz, c.re_b, y=y)
+        single.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+        single.step(dts[k], 50)
+        ref = single.get_fields("v", "omega2")
+        got = ens.channels[k].get_fields("v", "omega2")
+        for n in ref:
+            assert torch.equal(got[n], ref[n]), (k, n)
+        single.close()
+    ens.close()
