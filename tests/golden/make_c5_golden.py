@@ -1,12 +1,14 @@
 """Oracle reference for the low-storage stage on the 1536 x 385 x 1152 field.
 
 Runs only the oracle (float64, CPU): the seeded Re_tau ~ 950 field, u1, u2, u3
-by continuity (full field), then the cut-off filter and stresses on a few
-sampled wall-normal planes (the stage is plane-local).  Stores, per sampled
+by continuity (computed in blocks of kx columns, keeping only the sampled
+planes), then the cut-off filter and stresses on those wall-normal planes
+(the stage is plane-local).  Stores, per sampled
 plane, seeded samples of F(u_i), F(u_i u_j) and tau_ij in
 tests/golden/c5_filter.npz.  kc = (N1/16, N3/16) = (96, 72), q = (432, 324).
-Run: python tests/golden/make_c5_golden.py   (about 10 min, ~40 GB RAM)
+Run: python tests/golden/make_c5_golden.py   (about 10 min, ~20 GB RAM)
 """
+import copy
 import os
 import sys
 import time
@@ -30,16 +32,31 @@ def main(out=os.path.join(os.path.dirname(os.path.abspath(__file__)), "c5_filter
     v, om, U1, U3, y = synth.turbulent_field(c)
     print(f"field {time.time() - t0:.0f}s", flush=True)
     S = kmm.Setup(n1=c.n1, n2=c.n2, n3=c.n3, lx=c.lx, lz=c.lz, nu=1 / c.re_b, dt=1e-3, mass_flux=c.mass_flux, y=y)
-    live = S.live[None]
-    st = kmm.State(v=np.where(live, v, 0), chi=None, om2=np.where(live, om, 0), U1=U1, U3=U3)
+    v *= S.live[None]
+    om *= S.live[None]
+    pl = list(PLANES)
+    u = np.zeros((3, len(pl), c.n1 // 2, c.n3), complex)
+    u[1] = v[pl]
+    # kmm.velocities on blocks of kx columns; a block starting at k0 > 0 also
+    # takes column k0 - 1, whose first slot velocities() reserves for the mean
+    step = 48
+    for k0 in range(0, c.n1 // 2, step):
+        lo = max(k0 - 1, 0)
+        hi = min(k0 + step, c.n1 // 2)
+        Sb = copy.copy(S)
+        for name in ("a", "b", "k2", "live"):
+            setattr(Sb, name, getattr(S, name)[lo:hi])
+        stb = kmm.State(v=v[:, lo:hi], chi=None, om2=om[:, lo:hi], U1=U1, U3=U3)
+        b1, b3 = kmm.velocities(Sb, stb)
+        u[0][:, k0:hi] = b1[pl, k0 - lo:]
+        u[2][:, k0:hi] = b3[pl, k0 - lo:]
+        del b1, b3
     del v, om
-    u1, u3 = kmm.velocities(S, st)
-    u2 = st.v
     print(f"velocities {time.time() - t0:.0f}s", flush=True)
     g = np.random.default_rng(5050)
     res = {"planes": np.array(PLANES), "kc": np.array([KCX, KCZ, Q1, Q3])}
-    for p in PLANES:
-        ub, uu, tau = lowstorage.filter_and_stress(u1[p:p + 1], u2[p:p + 1], u3[p:p + 1], KCX, KCZ, Q1, Q3)
+    for n, p in enumerate(PLANES):
+        ub, uu, tau = lowstorage.filter_and_stress(u[0][n:n + 1], u[1][n:n + 1], u[2][n:n + 1], KCX, KCZ, Q1, Q3)
         ik, iz = g.integers(0, KCX + 1, NS), g.integers(0, 2 * KCZ + 1, NS)
         tz, tx = g.integers(0, Q3, NS), g.integers(0, Q1, NS)
         res[f"y{p}_ik"], res[f"y{p}_iz"], res[f"y{p}_tz"], res[f"y{p}_tx"] = ik, iz, tz, tx
