@@ -14,7 +14,12 @@ tau_ij = F(u_i u_j) - F(u_i) F(u_j) follows.  Readings:
   which represents every retained product mode exactly,
 * tau_ij is evaluated pointwise on a (q3, q1) grid of the periodic plane,
   from the zero-padded inverse transforms of F(u_i) and F(u_i u_j),
-* the SGS definition's typo (a repeated index j) is read as tau_ij = F(u_i u_j) - F(u_i) F(u_j).
+* the SGS definition's typo (a repeated index j) is read as tau_ij = F(u_i u_j) - F(u_i) F(u_j),
+* tau_ij is unchanged when a plane-constant field c_i(y) is added to u_i (F
+  keeps the (0,0) mode, so the c_i c_j and c_i F(u_j) terms cancel exactly);
+  tau is therefore evaluated from the fluctuations u_i - <u_i>, which avoids
+  cancelling the large U_i U_j terms in rounding.  F(u_i u_j) itself is
+  formed from the full fields.
 
 Output layouts: retained modes ``[n2][kcx+1][2kcz+1]`` with kz in FFT slot
 order (0..kcz, then -kcz..-1); tau ``[6][n2][q3][q1]`` for the pairs
@@ -57,13 +62,19 @@ def filter_and_stress(u1, u2, u3, kcx, kcz, q1, q3):
     n1 = 2 * n1h
     p1, p3 = fourier.padded_size(n1), fourier.padded_size(n3)
     ub = np.stack([truncate(u, kcx, kcz) for u in (u1, u2, u3)])
-    phys = [fourier.to_physical(u, p1, p3) for u in (u1, u2, u3)]
-    uu = []
-    for i, j in PAIRS:
-        full = fourier.to_spectral(phys[i] * phys[j], n1, n3)
-        uu.append(truncate(full, kcx, kcz))
-    uu = np.stack(uu)
-    ubq = synth_plane(ub, q1, q3)
-    uuq = synth_plane(uu, q1, q3)
+
+    def filtered_products(fields):
+        phys = [fourier.to_physical(u, p1, p3) for u in fields]
+        return np.stack([truncate(fourier.to_spectral(phys[i] * phys[j], n1, n3), kcx, kcz) for i, j in PAIRS])
+
+    uu = filtered_products((u1, u2, u3))
+    # tau from the fluctuations (plane means removed, see the module docstring)
+    fl = []
+    for u in (u1, u2, u3):
+        f = np.array(u, copy=True)
+        f[:, 0, 0] = 0.0
+        fl.append(f)
+    ubq = synth_plane(np.stack([truncate(f, kcx, kcz) for f in fl]), q1, q3)
+    uuq = synth_plane(filtered_products(fl), q1, q3)
     tau = np.stack([uuq[p] - ubq[i] * ubq[j] for p, (i, j) in enumerate(PAIRS)])
     return ub, uu, tau
