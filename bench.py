@@ -37,7 +37,8 @@ def algorithmic_bytes(kind, n1, n2, n3, elem):
         "zinv": 5 * elem * NP + 6 * elem * IP,    # 5 spectral fields -> 6 padded lines
         "xpass": 6 * elem * IP + 3 * elem * IP,   # 6 fields in, H1 H2 H3 out
         "zfwd": 3 * elem * IP + 3 * elem * NP,    # 3 padded fields -> 3 spectral
-        "advance": (3 * elem + 64 + 80) * NP,     # H, chi, om2, 2 histories -> chi, om2, v, 2 histories
+        # H, chi, om2, 2 histories -> chi, om2, v, 2 histories, next sub-step's u1 u2 u3 o1 o3
+        "advance": (3 * elem + 64 + 80 + 5 * elem) * NP,
     }[kind]
 
 
@@ -48,6 +49,8 @@ def run_path(case, v, om, U1, U3, y, precision, steps, warmup):
     ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, mass_flux=case.mass_flux,
                  precision=precision, y=y)
     ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    plan = ch.autotune(reps=3)  # plane-phase schedule, chosen before the timed steps
+    print(f"[bench] {precision}: autotuned plane schedule {plan}", file=sys.stderr, flush=True)
     if warmup:
         ch.step(case.dt, warmup)
     ch.timing(True)
@@ -65,6 +68,7 @@ def run_path(case, v, om, U1, U3, y, precision, steps, warmup):
     ch.timing(False)
     fields = {k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "u1", "u3", "u1mean").items()}
     ch.close()
+    kern["_plan"] = plan
     return ms, wall, kern, fields
 
 
@@ -102,6 +106,66 @@ def ensemble_run(steps=50, precision="mixed"):
             "value": G * steps / (ms / 1e3), "unit": UNIT}
 
 
+def c3_run(reps=3):
+    """One GPU's share of the Re_tau = 5300 channel, timed per phase (mixed precision):
+    the 48-plane slab of 8192 x 6144 modes through the three plane kernels, and
+    196608 modes x 1537 wall-normal nodes through the pencil kernel."""
+    import torch
+
+    import synth
+    from paper_1808_06461_amd import Channel
+    c = synth.C3_PLANES
+    n1, n3, P = c["n1"], c["n3"], c["nplanes"]
+    ch = Channel(n1, P, n3, c["lx"], c["lz"], synth.dean_re_b(c["re_tau"]), precision="mixed",
+                 planes_only=True, plane_chunk=8)
+    fields = [torch.empty((P, n1 // 2, n3), dtype=torch.complex64, device="cuda") for _ in range(6)]
+    synth.c3_fill_slab(fields, (), cfg=c["cfg"])
+    fields[4] = None  # omega2 formed in the z pass, as in the RK3 sub-step
+    out = [torch.empty((P, n1 // 2, n3), dtype=torch.complex64, device="cuda") for _ in range(3)]
+    ch.plane_products(fields, out)
+    ch.timing(True)
+    for _ in range(reps):
+        ch.plane_products(fields, out)
+    kern = ch.timing_read()
+    ch.timing(False)
+    planes = {"shape": f"{P} planes x {n1} x {n3} modes ({3 * n1 // 2} x {3 * n3 // 2} padded)",
+              "plan": ch.plan()}
+    tot = 0.0
+    for k in ("zinv", "xpass", "zfwd"):
+        t, n = kern[k]
+        b = algorithmic_bytes(k, n1, P, n3, 8)
+        planes[k] = {"ms": round(t / reps, 3), "alg_GBps": round(b / (t / reps / 1e3) / 1e9, 1)}
+        tot += t / reps
+    planes["ms_total"] = round(tot, 3)
+    ch.close()
+    del fields, out
+    torch.cuda.empty_cache()
+    case = synth.c3_pencil_case()
+    v, om, U1, U3, y = synth.turbulent_field(case)
+    ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, mass_flux=case.mass_flux,
+                 precision="mixed", y=y)
+    state = [torch.from_numpy(a) for a in (v, om, U1, U3)]
+    del v, om
+    ch.set_state(*state)
+    probe = ch.step(1e-6, 1, info=True)
+    dt = 0.5 * 1e-6 / probe["cfl_max"]
+    ch.set_state(*state)
+    ch.step(dt, 1)
+    ch.timing(True)
+    ch.step(dt, 1)
+    kern = ch.timing_read()
+    ch.timing(False)
+    t, n = kern["advance"]
+    b = algorithmic_bytes("advance", case.n1, case.n2, case.n3, 8)
+    pencils = {"shape": f"{case.n1 // 2 * case.n3} modes x {case.n2} nodes", "ms_per_substep": round(t / n, 3),
+               "alg_GBps": round(b / (t / n / 1e3) / 1e9, 1), "dt": dt}
+    ch.close()
+    torch.cuda.empty_cache()
+    return {"workload": "one GPU's share of Re_tau 5300 (8192 x 1537 x 6144): 48-plane slab and 1/128 of the "
+                        "modes as 1537-point pencils, mixed precision, seeded spectra", "planes": planes,
+            "pencils": pencils}
+
+
 def cpu_baseline(case, v, om, U1, U3, y):
     """The oracle on the host: one RK3 sub-step of the same workload, scaled to a step."""
     from oracle import kmm
@@ -124,6 +188,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the per-phase timing of the Re_tau 5300 share")
     ap.add_argument("--only", choices=("fp64", "mixed"), default=None,
                     help="run one precision only (for profiling; the JSON then lacks the comparison)")
     args = ap.parse_args()
@@ -153,26 +218,27 @@ def main():
     value = G * args.steps / (ms_mixed / 1e3)
     errs = {k: float(np.linalg.norm(fm[k] - f64[k]) / np.linalg.norm(f64[k])) for k in fm}
 
+    plan_mixed, plan64 = kern.pop("_plan"), kern64.pop("_plan")
+    nsub = 3 * args.steps  # sub-steps in the timed region; a kernel kind may launch once per plane chunk
     # roofline of the dominant kernel of the mixed path
     dom = max(kern, key=lambda k: kern[k][0])
     tot, cnt = kern[dom]
-    avg_s = tot / cnt / 1e3
     elem = 8
-    alg = algorithmic_bytes(dom, case.n1, case.n2, case.n3, elem)
+    alg = algorithmic_bytes(dom, case.n1, case.n2, case.n3, elem)  # per sub-step (all planes / modes)
+    avg_s = tot / nsub / 1e3
     achieved = alg / avg_s / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "algorithmic_bytes_per_launch": alg, "avg_launch_ms": round(avg_s * 1e3, 4)}
-    per_kernel = {}
-    for k, (t, n) in kern.items():
-        if n:
-            b = algorithmic_bytes(k, case.n1, case.n2, case.n3, elem)
-            per_kernel[k] = {"avg_ms": round(t / n, 4), "launches": n, "alg_GBps": round(b / (t / n / 1e3) / 1e9, 1)}
-    per_kernel64 = {}
-    for k, (t, n) in kern64.items():
-        if n:
-            b = algorithmic_bytes(k, case.n1, case.n2, case.n3, 16)
-            per_kernel64[k] = {"avg_ms": round(t / n, 4), "launches": n, "alg_GBps": round(b / (t / n / 1e3) / 1e9, 1)}
+            "algorithmic_bytes_per_launch": alg * nsub // cnt, "avg_launch_ms": round(tot / cnt, 4)}
+
+    def table(kk, e):
+        out = {}
+        for k, (t, n) in kk.items():
+            if n:
+                b = algorithmic_bytes(k, case.n1, case.n2, case.n3, e) * (n if k == "recover" else nsub)
+                out[k] = {"avg_ms": round(t / n, 4), "launches": n, "alg_GBps": round(b / (t / 1e3) / 1e9, 1)}
+        return out
+    per_kernel, per_kernel64 = table(kern, elem), table(kern64, 16)
 
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -183,6 +249,7 @@ def main():
                    "grid_points": G, "dt": case.dt},
         "fp64": {"value": G * args.steps / (ms_fp64 / 1e3), "ms_per_step": ms_fp64 / args.steps,
                  "kernels": per_kernel64},
+        "plane_schedule": {"mixed": plan_mixed, "fp64": plan64},
         "mixed_vs_fp64_rel_err": errs,
         "speedup_mixed_over_fp64": ms_fp64 / ms_mixed,
         "kernels": per_kernel,
@@ -191,6 +258,9 @@ def main():
     if not args.no_ensemble:
         print("[bench] ensemble of 96 channels, 50 steps", file=sys.stderr, flush=True)
         out["ensemble"] = ensemble_run()
+    if not args.no_c3:
+        print("[bench] Re_tau 5300 share: plane slab and pencil share", file=sys.stderr, flush=True)
+        out["c3_share"] = c3_run()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, one sub-step)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, v, om, U1, U3, y)

@@ -77,6 +77,12 @@ typedef struct {
                            y[n2-1] = 1; NULL selects y_j = tanh(2 s_j)/tanh(2),
                            s_j uniform on [-1, 1] */
   void *stream;         /* hipStream_t the context runs on (NULL = default stream) */
+  int32_t planes_only;  /* nonzero: a plane-phase context (one GPU's slab of x-z
+                           planes): only chn_plane_products, the schedule and
+                           timing calls are available, and the workspace holds
+                           only the transform buffers of plane_chunk planes */
+  int32_t plane_chunk;  /* planes per plane-phase launch (0: all n2; required
+                           for planes_only) */
 } chn_config;
 
 /* Per-step diagnostics, filled by chn_step_rk3 for its last step. */
@@ -155,6 +161,16 @@ chn_status chn_nonlinear(chn_ctx *ctx, const double *const *d_in, double *const 
 chn_status chn_filter_and_stress(chn_ctx *ctx, int32_t kcx, int32_t kcz, int32_t q1, int32_t q3,
                                  double *d_ubar, double *d_uubar, double *d_tau);
 
+/* Dealiased products of Section 2.1 on every plane (the plane phase of the
+ * sub-step): d_in[0..5] = u1, u2, u3, omega1, omega2, omega3 and d_out[0..2] =
+ * H1, H2, H3 of H = u x omega, DEVICE pointers in the layout
+ * [n2][n1/2][n3] but in the context's transform precision: complex64 for
+ * CHN_MIXED, complex128 for CHN_FP64.  d_in[4] may be NULL (omega2 is then
+ * formed as i b u1 - i a u3).  Outputs are truncated to the retained modes
+ * (Nyquist slot zero) and scaled as the forward transform of Section 2.1.
+ * Works on every context; the only compute call of a planes_only context. */
+chn_status chn_plane_products(chn_ctx *ctx, const void *const *d_in, void *const *d_out);
+
 /* Copies the library's compact-difference tables to host arrays (each
  * n2 x 7, row i holding M[i][i-3..i+3]) and the mass-flux quadrature weights
  * (n2).  Any pointer may be NULL.  Synchronises. */
@@ -210,6 +226,38 @@ chn_status chn_timing_enable(chn_ctx *ctx, int32_t enable);
 /* Sum of the recorded durations (ms) and the number of launches of one
  * kernel kind since chn_timing_enable.  Synchronises. */
 chn_status chn_timing_read(chn_ctx *ctx, int32_t kind, double *total_ms, int32_t *count);
+
+/* ---------------------------------------------------------------- schedule
+ * How the plane phase (the padded transforms and products of Section 2.1)
+ * is cut into workgroups.  x_rows: rows of the x pass per workgroup, 2
+ * (six transform lines in LDS at once) or 1 (lines staged one at a time
+ * through LDS, values held in registers: the only choice for long rows).
+ * z_lines: lines per z-pass workgroup (more lines give longer coalesced
+ * segments of the transposed stores, fewer give more workgroups and less
+ * LDS per workgroup).  y_chunk: planes per launch (smaller chunks keep the
+ * z-padded intermediate of a chunk in the last-level cache between the three
+ * kernels; at most the plane_chunk of a planes_only context).  Results agree
+ * to rounding between schedules. */
+typedef struct {
+  int32_t x_rows;
+  int32_t z_lines;
+  int32_t y_chunk;  /* planes per launch of the three plane kernels */
+} chn_plan;
+
+/* Current schedule (chn_create picks 2 rows when they fit, 16 lines capped
+ * by registers and LDS, and plane_chunk or all planes). */
+chn_status chn_get_plan(chn_ctx *ctx, chn_plan *plan);
+
+/* Sets the schedule; CHN_EINVAL (context unchanged) if it does not fit the
+ * grid or the device's LDS.  Channels of an ensemble keep the schedule
+ * their batched tables were built with. */
+chn_status chn_set_plan(chn_ctx *ctx, const chn_plan *plan);
+
+/* Autotuner: times the plane phase (reps repetitions after one warm-up) for
+ * every schedule that fits, keeps the fastest and writes it to *chosen
+ * (may be NULL).  Only scratch buffers are written; the state is
+ * untouched.  Synchronises. */
+chn_status chn_autotune(chn_ctx *ctx, int32_t reps, chn_plan *chosen);
 
 /* Message of the last failing call on ctx (or of the last failing
  * chn_create if ctx is NULL). */

@@ -27,7 +27,12 @@ STATUS = {0: "CHN_OK", 1: "CHN_EINVAL", 2: "CHN_ENOMEM", 3: "CHN_EDEVICE", 4: "C
 class Config(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n3", C.c_int32), ("lx", C.c_double),
                 ("lz", C.c_double), ("re_b", C.c_double), ("mass_flux", C.c_double),
-                ("precision", C.c_int32), ("y", C.POINTER(C.c_double)), ("stream", C.c_void_p)]
+                ("precision", C.c_int32), ("y", C.POINTER(C.c_double)), ("stream", C.c_void_p),
+                ("planes_only", C.c_int32), ("plane_chunk", C.c_int32)]
+
+
+class Plan(C.Structure):
+    _fields_ = [("x_rows", C.c_int32), ("z_lines", C.c_int32), ("y_chunk", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -56,6 +61,10 @@ def lib():
         L.chn_nonlinear.argtypes = [P, C.POINTER(P), C.POINTER(P)]
         L.chn_filter_and_stress.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P]
         L.chn_get_operators.argtypes = [P, P, P, P, P, P]
+        L.chn_get_plan.argtypes = [P, C.POINTER(Plan)]
+        L.chn_plane_products.argtypes = [P, C.POINTER(P), C.POINTER(P)]
+        L.chn_set_plan.argtypes = [P, C.POINTER(Plan)]
+        L.chn_autotune.argtypes = [P, C.c_int32, C.POINTER(Plan)]
         L.chn_timing_enable.argtypes = [P, C.c_int32]
         L.chn_timing_read.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.chn_ens_workspace_bytes.argtypes = [C.c_int32, C.POINTER(Config)]
@@ -71,7 +80,8 @@ def lib():
         L.chn_last_error.restype = C.c_char_p
         for name in ("chn_create", "chn_destroy", "chn_set_state", "chn_step_rk3", "chn_get_fields",
                      "chn_nonlinear", "chn_filter_and_stress", "chn_get_operators", "chn_timing_enable",
-                     "chn_timing_read", "chn_ens_create", "chn_ens_destroy", "chn_ens_step"):
+                     "chn_timing_read", "chn_ens_create", "chn_ens_destroy", "chn_ens_step", "chn_get_plan",
+                     "chn_set_plan", "chn_autotune", "chn_plane_products"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -95,7 +105,7 @@ class Channel:
     """One channel context on one GPU stream (see include/chn.h)."""
 
     def __init__(self, n1, n2, n3, lx, lz, re_b, mass_flux=2.0, precision="fp64", y=None,
-                 device="cuda:0"):
+                 device="cuda:0", planes_only=False, plane_chunk=0):
         self.L = lib()
         self.device = torch.device(device)
         self.n1, self.n2, self.n3 = n1, n2, n3
@@ -109,7 +119,7 @@ class Channel:
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
         self.cfg = Config(n1, n2, n3, lx, lz, re_b, mass_flux, self.precision, yp,
-                          C.c_void_p(self.stream.cuda_stream))
+                          C.c_void_p(self.stream.cuda_stream), int(bool(planes_only)), int(plane_chunk))
         nbytes = self.L.chn_workspace_bytes(C.byref(self.cfg))
         if nbytes == 0:
             raise ChnError("invalid channel configuration")
@@ -171,6 +181,21 @@ class Channel:
         self._check(self.L.chn_nonlinear(self.ctx, a, b), "chn_nonlinear")
         return outs
 
+    def plane_products(self, fields, out=None):
+        """H1, H2, H3 from (u1, u2, u3, omega1, omega2 or None, omega3), device tensors in the
+        transform precision (complex64 for mixed, complex128 for fp64), [n2][n1/2][n3]."""
+        dt = torch.complex64 if self.precision == MIXED else torch.complex128
+        for f in fields:
+            if f is not None and (f.dtype != dt or not f.is_contiguous() or f.device != self.device
+                                  or tuple(f.shape) != (self.n2, self.n1h, self.n3)):
+                raise ChnError(f"plane_products needs contiguous {dt} [{self.n2}, {self.n1h}, {self.n3}] on {self.device}")
+        if out is None:
+            out = [torch.empty((self.n2, self.n1h, self.n3), dtype=dt, device=self.device) for _ in range(3)]
+        a = (C.c_void_p * 6)(*[None if f is None else f.data_ptr() for f in fields])
+        b = (C.c_void_p * 3)(*[t.data_ptr() for t in out])
+        self._check(self.L.chn_plane_products(self.ctx, a, b), "chn_plane_products")
+        return out
+
     def filter_and_stress(self, kcx, kcz, q1, q3, with_tau=True):
         nk = (self.n2, kcx + 1, 2 * kcz + 1)
         ub = torch.empty((3,) + nk, dtype=torch.complex128, device=self.device)
@@ -179,6 +204,20 @@ class Channel:
         self._check(self.L.chn_filter_and_stress(self.ctx, kcx, kcz, q1, q3, _ptr(ub), _ptr(uu), _ptr(tau)),
                     "chn_filter_and_stress")
         return ub, uu, tau
+
+    def plan(self):
+        p = Plan()
+        self._check(self.L.chn_get_plan(self.ctx, C.byref(p)), "chn_get_plan")
+        return {"x_rows": p.x_rows, "z_lines": p.z_lines, "y_chunk": p.y_chunk}
+
+    def set_plan(self, x_rows, z_lines, y_chunk=None):
+        p = Plan(int(x_rows), int(z_lines), int(self.n2 if y_chunk is None else y_chunk))
+        self._check(self.L.chn_set_plan(self.ctx, C.byref(p)), "chn_set_plan")
+
+    def autotune(self, reps=3):
+        p = Plan()
+        self._check(self.L.chn_autotune(self.ctx, int(reps), C.byref(p)), "chn_autotune")
+        return {"x_rows": p.x_rows, "z_lines": p.z_lines, "y_chunk": p.y_chunk}
 
     def operators(self):
         import numpy as np

@@ -77,6 +77,12 @@ struct chn_ctx {
   chn::PencilGeom geom{};
   chn::PlaneDims dims{};
   int lds_max = 65536;  // bytes of LDS one workgroup may use on this device
+  // plane-phase schedule (chn_set_plan / chn_autotune)
+  int xrows = 2;        // x-pass rows per workgroup (2, or 1 for long rows)
+  int zK = 1;           // lines per z-pass workgroup
+  int ychunk = 1;       // planes per plane-phase launch
+  int ychunk_max = 1;   // planes the intermediate holds
+  bool planes_only = false;
   // per-kernel timing (chn_timing_enable): events bracketing every launch
   bool timing = false;
   struct Timed { int kind; hipEvent_t a, b; };
@@ -95,7 +101,11 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
   const int p1 = 3 * c->n1 / 2, p3 = 3 * c->n3 / 2;
   const size_t M = (size_t)n1h * n3, NP = (size_t)n2 * M;
   const size_t te = c->precision == CHN_MIXED ? 8 : 16;
-  const size_t CB = 16 * NP;
+  // a planes_only context keeps no state, phase or pencil buffers
+  const bool po = c->planes_only != 0;
+  const size_t CB = po ? 0 : 16 * NP;
+  const size_t NPb = po ? 0 : NP;
+  const int ych = po ? c->plane_chunk : n2;
   Carver cv;
   cv.base = base;
   auto D = [&](size_t n) { return reinterpret_cast<double*>(cv.take(n * sizeof(double))); };
@@ -109,15 +119,15 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
   double* nuo = D(n2);
   double* nwo = D(n2);
   void* ph[6];
-  for (int f = 0; f < 6; ++f) ph[f] = cv.take(te * NP);
+  for (int f = 0; f < 6; ++f) ph[f] = cv.take(te * NPb);
   void* H[3];
-  for (int f = 0; f < 3; ++f) H[f] = cv.take(te * NP);
-  const size_t ib = te * 6 * (size_t)n2 * p3 * n1h;
+  for (int f = 0; f < 3; ++f) H[f] = cv.take(te * NPb);
+  const size_t ib = te * 6 * (size_t)ych * p3 * n1h;
   void* inter = cv.take(ib);
   double* S[8];
   for (int k = 0; k < 8; ++k) S[k] = reinterpret_cast<double*>(cv.take(CB));
   double* SU[8];
-  for (int k = 0; k < 8; ++k) SU[k] = D(NP);
+  for (int k = 0; k < 8; ++k) SU[k] = D(NPb);
   double* rowsum = D(2 * (size_t)n2 * p3);
   float* rowcfl = reinterpret_cast<float*>(cv.take(sizeof(float) * (size_t)n2 * p3));
   double* tabs = D((size_t)n2 * (4 * 7 + 3 * 3 + 3 * 4 + 4));
@@ -159,9 +169,12 @@ const char* validate(const chn_config* c) {
   if (c->n2 < 9 || c->n2 > 2048) return "n2 must be in [9, 2048]";
   if (!(c->lx > 0) || !(c->lz > 0) || !(c->re_b > 0)) return "lx, lz and re_b must be positive";
   if (c->precision != CHN_FP64 && c->precision != CHN_MIXED) return "unknown precision";
+  if (c->plane_chunk < 0 || c->plane_chunk > c->n2) return "plane_chunk must be in [0, n2]";
+  if (c->planes_only && c->plane_chunk < 1) return "a planes_only context needs plane_chunk >= 1";
   const int p1 = 3 * c->n1 / 2, p3 = 3 * c->n3 / 2;
   const int maxv = c->precision == CHN_MIXED ? 48 : 24;
-  if (6 * p1 > maxv * 256) return "3*n1/2 too large for the x-pass kernel";
+  const int vb = c->precision == CHN_MIXED ? 8 : 16;
+  if (!chn::xpass_two_rows(p1, vb) && chn::xrow_threads(p1, vb) == 0) return "3*n1/2 too large for the x-pass kernel";
   if (p3 > maxv * 256) return "3*n3/2 too large for the z-pass kernels";
   if (c->y) {
     if (c->y[0] != -1.0 || c->y[c->n2 - 1] != 1.0) return "y must start at -1 and end at 1";
@@ -214,17 +227,32 @@ template <> struct Ty<double> { using c = double2; };
 template <> struct Ty<float> { using c = float2; };
 
 
-template <typename T> int z_lines(const chn_ctx* x) {
-  const int maxv = sizeof(T) == 8 ? 24 : 48;
-  const int ls = x->p3 + 1;
+// Largest number of z lines one workgroup can transform (staging registers and LDS).
+int z_lines_max(const chn_ctx* x) {
+  const int maxv = x->mixed ? 48 : 24;
+  const int cb = x->mixed ? 8 : 16;
   int K = maxv * 256 / x->p3;
-  const int byl = x->lds_max / (ls * (int)sizeof(typename Ty<T>::c));
+  const int byl = x->lds_max / ((x->p3 + 1) * cb);
   if (K > byl) K = byl;
-  if (K > 16) K = 16;
   if (K > x->n1h) K = x->n1h;
-  if (K < 1) K = 1;
   return K;
 }
+// Default schedule: 16 z lines per workgroup (capped), two x rows when six lines fit.
+void default_plan(chn_ctx* x) {
+  const int cb = x->mixed ? 8 : 16;
+  x->zK = std::max(1, std::min(16, z_lines_max(x)));
+  x->ychunk = x->planes_only || x->cfg.plane_chunk > 0 ? x->cfg.plane_chunk : x->n2;
+  x->xrows = chn::xpass_two_rows(x->p1, cb) && (size_t)6 * (x->p1 + 1) * cb <= (size_t)x->lds_max ? 2 : 1;
+}
+bool plan_fits(const chn_ctx* x, int xrows, int zK, int ych) {
+  const int cb = x->mixed ? 8 : 16;
+  if (ych < 1 || ych > x->ychunk_max) return false;
+  if (zK < 1 || zK > z_lines_max(x)) return false;
+  if (xrows == 2) return chn::xpass_two_rows(x->p1, cb) && (size_t)6 * (x->p1 + 1) * cb <= (size_t)x->lds_max;
+  if (xrows == 1) return chn::xrow_threads(x->p1, cb) > 0 && (size_t)x->p1 * cb <= (size_t)x->lds_max;
+  return false;
+}
+template <typename T> int z_lines(const chn_ctx* x) { return x->zK; }
 
 template <typename T, typename TO>
 void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* const* out, chn::ZinvArgs<T>& za,
@@ -242,6 +270,8 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   za.lstride = x->p3 + 1;
   za.nfields = 6;
   za.nslot = 6;
+  za.y0 = 0;
+  za.ny = x->n2;
   xa = {};
   xa.buf = reinterpret_cast<C*>(x->inter);
   xa.tw = reinterpret_cast<const C*>(x->tw1);
@@ -253,6 +283,9 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   xa.inv_dx = x->n1 / x->cfg.lx;
   xa.inv_dz = x->n3 / x->cfg.lz;
   xa.inv_dy = x->inv_dy;
+  xa.rows = x->xrows;
+  xa.y0 = 0;
+  xa.ny = x->n2;
   fa = {};
   fa.buf = reinterpret_cast<const C*>(x->inter);
   for (int f = 0; f < 3; ++f) fa.out[f] = reinterpret_cast<typename Ty<TO>::c*>(out[f]);
@@ -262,6 +295,8 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   fa.K = K;
   fa.lstride = x->p3 + 1;
   fa.scale = 1.0 / ((double)x->p1 * x->p3);
+  fa.y0 = 0;
+  fa.ny = x->n2;
 }
 
 // plane phase: ph (6 slots) -> H (3 slots) through the intermediate
@@ -271,9 +306,14 @@ chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, voi
   chn::XpassArgs<T> xa;
   chn::ZfwdArgs<T, TO> fa;
   plane_args<T, TO>(x, in, omega2_given, out, za, xa, fa);
-  HIPCHK(x, timed(x, CHN_K_ZINV, [&] { return chn::launch_zinv<T>(za, x->stream); }));
-  HIPCHK(x, timed(x, CHN_K_XPASS, [&] { return chn::launch_xpass<T>(xa, x->stream); }));
-  HIPCHK(x, timed(x, CHN_K_ZFWD, [&] { return chn::launch_zfwd<T, TO>(fa, x->stream); }));
+  // chunks of planes: the intermediate holds the chunk from its plane 0
+  for (int y0 = 0; y0 < x->n2; y0 += x->ychunk) {
+    za.y0 = xa.y0 = fa.y0 = y0;
+    za.ny = xa.ny = fa.ny = std::min(x->ychunk, x->n2 - y0);
+    HIPCHK(x, timed(x, CHN_K_ZINV, [&] { return chn::launch_zinv<T>(za, x->stream); }));
+    HIPCHK(x, timed(x, CHN_K_XPASS, [&] { return chn::launch_xpass<T>(xa, x->stream); }));
+    HIPCHK(x, timed(x, CHN_K_ZFWD, [&] { return chn::launch_zfwd<T, TO>(fa, x->stream); }));
+  }
   return CHN_OK;
 }
 
@@ -345,13 +385,22 @@ template <typename T> void advance_args(chn_ctx* x, int s, double dt, chn::Advan
 }
 
 chn_status check(chn_ctx* x);
+chn_status need_fields(chn_ctx* x);
 
-template <typename T>
+// The filter stage transforms in float64 on both paths.  tau_ij is a small
+// difference of F(u_i u_j) and F(u_i) F(u_j) (about 1e-2 to 1e-3 of either
+// term on the 1536 x 385 x 1152 field), so the 1.6e-7 relative error of
+// float32 transforms reaches 1e-4 in tau.  The mixed path stores the
+// velocity coefficients in float32 (every term of tau then sees the same
+// rounded data) and keeps the transforms and products in float64.
 chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_ubar, double* d_uubar,
                         double* d_tau) {
-  using C = typename Ty<T>::c;
+  using C = double2;
   const int n2 = x->n2, n1h = x->n1h, n3 = x->n3, p1 = x->p1, p3 = x->p3;
   const size_t te = sizeof(C);
+  // slots of the intermediate per plane: float64 data in a float32-sized buffer on the mixed path
+  const int nslot = x->mixed ? 3 : 6;
+  const size_t plane_bytes = (size_t)(x->mixed ? 6 * 8 : 6 * 16) * p3 * n1h;
   if (!d_ubar || !d_uubar) return fail(x, CHN_EINVAL, "NULL output pointer");
   if (kcx < 0 || kcz < 0 || kcx >= n1h || kcz >= n3 / 2) return fail(x, CHN_EINVAL, "need 0 <= kcx < n1/2, 0 <= kcz < n3/2");
   if (q1 <= 2 * kcx || q3 <= 2 * kcz || (q1 % 2) || (q3 % 2) || !smooth23(q1) || !smooth23(q3) || q1 > kMaxQ ||
@@ -360,12 +409,15 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   const int kc1 = kcx + 1, nz = 2 * kcz + 1;
   const size_t NP = (size_t)n2 * x->M;
   // buffer reuse: x-filter output in the free slots 3..5 of each plane of the
-  // intermediate, pp in the H buffers, the q-grid intermediate in the intermediate
-  if ((size_t)6 * p3 * kc1 * 16 > (size_t)3 * p3 * n1h * te) return fail(x, CHN_EUNSUPPORTED, "kcx too large for the workspace");
-  if ((size_t)6 * n2 * kc1 * nz * 16 > 3 * NP * te) return fail(x, CHN_EUNSUPPORTED, "cut-off too large for the workspace");
+  // intermediate (float64 contexts) or in S[0..2] (mixed), pp in the H
+  // buffers, the q-grid intermediate in the intermediate
+  const size_t hbytes = 3 * NP * (x->mixed ? 8 : 16);
+  if (!x->mixed && (size_t)6 * p3 * kc1 * 16 > (size_t)3 * p3 * n1h * te) return fail(x, CHN_EUNSUPPORTED, "kcx too large for the workspace");
+  if (x->mixed && (size_t)6 * n2 * p3 * kc1 * 16 > 3 * 16 * NP) return fail(x, CHN_EUNSUPPORTED, "kcx too large for the workspace");
+  if ((size_t)6 * n2 * kc1 * nz * 16 > hbytes) return fail(x, CHN_EUNSUPPORTED, "cut-off too large for the workspace");
   if ((size_t)9 * n2 * q3 * kc1 * 16 > x->inter_bytes) return fail(x, CHN_EUNSUPPORTED, "q grid too large for the workspace");
   if (p1 > 12 * 256) return fail(x, CHN_EUNSUPPORTED, "3*n1/2 too large for the filter x-pass");
-  const size_t lds_x = std::max((size_t)2 * (p1 + 1) * te, (size_t)3 * (p1 + 1) * 16);
+  const size_t lds_x = (size_t)3 * (p1 + 1) * 16;
   const size_t lds_t = (size_t)5 * (q1 + 1) * 16;
   auto lines = [&](int len, int cap) {
     int K = 24 * 256 / len;
@@ -377,7 +429,8 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   };
   const int Kf = lines(p3, kc1), Kq = lines(q3, kc1);
   if (lds_x > (size_t)x->lds_max || lds_t > (size_t)x->lds_max || (size_t)(p3 + 1) * 16 > (size_t)x->lds_max ||
-      3 * p1 > 24 * 256 || p3 > 24 * 256 || 5 * q1 > 24 * 256 || q3 > 24 * 256)
+      2 * p1 > 24 * 256 || p1 > 24 * 256 || p3 > 24 * 256 || 5 * q1 > 24 * 256 ||
+      q3 > 24 * 256)
     return fail(x, CHN_EUNSUPPORTED, "plane too large for the filter kernels' LDS tiles on this device");
   // q-grid FFT tables
   FftPlan pq1{}, pq3{};
@@ -390,37 +443,46 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   HIPCHK(x, hipMemcpyAsync(x->twq, x->twq_host.data(), x->twq_host.size() * 8, hipMemcpyHostToDevice, x->stream));
   const double2* twq1 = x->twq;
   const double2* twq3 = x->twq + kMaxQ;
-  // 1. float64 spectra of u1, u2, u3 (and the vorticities, unused here)
+  // 1. float64 spectra of u1, u2, u3 (and the vorticities, unused here);
+  //    mixed: rounded to float32 in place (the stored data of that path)
   double* su[5] = {x->S[3], x->S[4], x->S[5], x->S[6], x->S[7]};
   if (chn_status st = recover<double>(x, su)) return st;
-  const void* fin[6] = {x->S[3], x->S[4], x->S[5], nullptr, nullptr, nullptr};
   if (x->mixed) {
     x->phase_valid = false;
-    for (int f = 0; f < 3; ++f)
-      HIPCHK(x, timed(x, CHN_K_FILTER, [&] {
-        return chn::launch_convert_d2f(x->S[3 + f], reinterpret_cast<float*>(x->ph[f]), 2 * NP, x->stream);
-      }));
-    for (int f = 0; f < 3; ++f) fin[f] = x->ph[f];
+    for (int f = 0; f < 3; ++f) {
+      float* tmp = reinterpret_cast<float*>(x->ph[f]);
+      HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_convert_d2f(x->S[3 + f], tmp, 2 * NP, x->stream); }));
+      HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_convert_f2d(tmp, x->S[3 + f], 2 * NP, x->stream); }));
+    }
   }
   // 2. z inverse of the fluctuations
-  chn::ZinvArgs<T> za{};
-  for (int f = 0; f < 3; ++f) za.in[f] = reinterpret_cast<const C*>(fin[f]);
+  chn::ZinvArgs<double> za{};
+  for (int f = 0; f < 3; ++f) za.in[f] = reinterpret_cast<const C*>(x->S[3 + f]);
   za.out = reinterpret_cast<C*>(x->inter);
-  za.tw = reinterpret_cast<const C*>(x->tw3);
+  za.tw = x->tw3d;
   za.plan = x->plan3;
   za.d = x->dims;
-  za.K = z_lines<T>(x);
+  za.K = lines(p3, n1h);
   za.lstride = p3 + 1;
   za.nfields = 3;
-  za.nslot = 6;
+  za.nslot = nslot;
   za.zero_mean = 1;
-  HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_zinv<T>(za, x->stream); }));
+  za.y0 = 0;
+  za.ny = n2;
+  if ((size_t)za.K * za.lstride * 16 > (size_t)x->lds_max) return fail(x, CHN_EUNSUPPORTED, "z lines exceed LDS");
+  HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_zinv<double>(za, x->stream); }));
   // 3. products and float64 forward in x
-  chn::XfilterArgs<T> xa{};
+  chn::XfilterArgs<double> xa{};
   xa.buf = reinterpret_cast<const C*>(x->inter);
-  xa.out = reinterpret_cast<double2*>(reinterpret_cast<char*>(x->inter) + (size_t)3 * p3 * n1h * te);
-  xa.plane_stride = (size_t)6 * p3 * n1h * te / 16;
-  xa.tw = reinterpret_cast<const C*>(x->tw1);
+  xa.nslot = nslot;
+  if (x->mixed) {
+    xa.out = reinterpret_cast<double2*>(x->S[0]);
+    xa.plane_stride = (size_t)6 * p3 * kc1;
+  } else {
+    xa.out = reinterpret_cast<double2*>(reinterpret_cast<char*>(x->inter) + (size_t)3 * p3 * n1h * te);
+    xa.plane_stride = plane_bytes / 16;
+  }
+  xa.tw = x->tw1d;
   xa.plan = x->plan1;
   xa.tw_d = x->tw1d;
   xa.plan_d = x->plan1;
@@ -428,7 +490,7 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   xa.lst = p1 + 1;
   xa.lsd = p1 + 1;
   xa.kcx = kcx;
-  HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_xfilter<T>(xa, lds_x, x->stream); }));
+  HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_xfilter<double>(xa, lds_x, x->stream); }));
   // 4. float64 forward in z, retained set, mean terms
   chn::ZfilterArgs fa{};
   fa.xout = xa.out;
@@ -470,6 +532,10 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   ta.lstride = q1 + 1;
   HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_xtau(ta, lds_t, x->stream); }));
   return CHN_OK;
+}
+
+chn_status need_fields(chn_ctx* x) {
+  return x->planes_only ? fail(x, CHN_EUNSUPPORTED, "not available on a planes_only context") : CHN_OK;
 }
 
 chn_status check(chn_ctx* x) {
@@ -532,6 +598,8 @@ bool ens_layout(int n, const chn_config* cfgs, EnsLayout* L) {
   for (int i = 0; i < n; ++i) {
     if (validate(&cfgs[i])) return false;
     if (cfgs[i].precision != cfgs[0].precision || cfgs[i].stream != cfgs[0].stream) return false;
+    // batched plane kernels use the two-row x-pass only
+    if (!chn::xpass_two_rows(3 * cfgs[i].n1 / 2, cfgs[i].precision == CHN_MIXED ? 8 : 16)) return false;
     const size_t b = layout(&cfgs[i], nullptr, nullptr);
     off = (off + 255) & ~(size_t)255;
     L->off.push_back(off);
@@ -717,6 +785,8 @@ chn_status chn_create(const chn_config* cfg, void* d_ws, size_t ws_bytes, chn_ct
   x->p1 = 3 * cfg->n1 / 2; x->p3 = 3 * cfg->n3 / 2;
   x->nu = 1.0 / cfg->re_b;
   x->mixed = cfg->precision == CHN_MIXED;
+  x->planes_only = cfg->planes_only != 0;
+  x->ychunk_max = x->planes_only ? cfg->plane_chunk : x->n2;
   x->ws_bytes = ws_bytes;
   layout(cfg, reinterpret_cast<char*>(d_ws), x);
   {
@@ -724,10 +794,10 @@ chn_status chn_create(const chn_config* cfg, void* d_ws, size_t ws_bytes, chn_ct
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
       x->lds_max = lds;
-    const size_t xl = (size_t)6 * (x->p1 + 1) * (x->mixed ? 8 : 16);
-    if (xl > (size_t)x->lds_max) {
+    default_plan(x);
+    if (!plan_fits(x, x->xrows, x->zK, x->ychunk)) {
       delete x;
-      return fail(nullptr, CHN_EINVAL, "3*n1/2 too large for the x-pass LDS tile");
+      return fail(nullptr, CHN_EINVAL, "plane too large for the x- or z-pass LDS tiles on this device");
     }
   }
   x->y.resize(x->n2);
@@ -746,7 +816,7 @@ chn_status chn_create(const chn_config* cfg, void* d_ws, size_t ws_bytes, chn_ct
             chn::host::band_lu(n2, x->hA1.data(), -1, L1u.data(), U1u.data()) &&
             chn::host::band_lu(n2, x->hA2.data(), +1, L2d.data(), U2d.data()) &&
             chn::host::wall_rows(n2, x->hA1.data(), x->hB1.data(), clo.data(), chw.data());
-  if (!ok) {
+  if (!ok && !x->planes_only) {  // a plane-phase context uses the mesh for the CFL only
     delete x;
     return fail(nullptr, CHN_EINVAL, "compact-difference system singular on this mesh");
   }
@@ -817,6 +887,7 @@ chn_status chn_destroy(chn_ctx* ctx) {
 chn_status chn_set_state(chn_ctx* x, const double* d_v, const double* d_om2, const double* d_u1m,
                          const double* d_u3m) {
   if (chn_status s = check(x)) return s;
+  if (chn_status s = need_fields(x)) return s;
   if (!d_v || !d_om2 || !d_u1m || !d_u3m) return fail(x, CHN_EINVAL, "NULL state pointer");
   chn::ChiArgs ca{};
   ca.g = x->geom;
@@ -842,6 +913,7 @@ chn_status chn_set_state(chn_ctx* x, const double* d_v, const double* d_om2, con
 
 chn_status chn_step_rk3(chn_ctx* x, double dt, int32_t nsteps, chn_step_info* info) {
   if (chn_status s = check(x)) return s;
+  if (chn_status s = need_fields(x)) return s;
   if (!x->have_state) return fail(x, CHN_ESTATE, "chn_step_rk3 before chn_set_state");
   if (!(dt > 0) || nsteps < 0) return fail(x, CHN_EINVAL, "dt must be positive and nsteps >= 0");
   for (int k = 0; k < nsteps; ++k)
@@ -909,6 +981,7 @@ chn_status chn_get_fields(chn_ctx* x, uint32_t mask, double* const* d_out) {
 
 chn_status chn_nonlinear(chn_ctx* x, const double* const* d_in, double* const* d_out) {
   if (chn_status s = check(x)) return s;
+  if (chn_status s = need_fields(x)) return s;
   if (!d_in || !d_out) return fail(x, CHN_EINVAL, "NULL field array");
   for (int f = 0; f < 6; ++f)
     if (!d_in[f]) return fail(x, CHN_EINVAL, "NULL input field");
@@ -930,12 +1003,26 @@ chn_status chn_nonlinear(chn_ctx* x, const double* const* d_in, double* const* d
   return plane_phase<float, double>(x, x->ph, true, out);
 }
 
+chn_status chn_plane_products(chn_ctx* x, const void* const* d_in, void* const* d_out) {
+  if (chn_status s = check(x)) return s;
+  if (!d_in || !d_out) return fail(x, CHN_EINVAL, "NULL field array");
+  for (int f = 0; f < 6; ++f)
+    if (!d_in[f] && f != 4) return fail(x, CHN_EINVAL, "NULL input field");
+  for (int f = 0; f < 3; ++f)
+    if (!d_out[f]) return fail(x, CHN_EINVAL, "NULL output field");
+  const void* in[6];
+  void* out[3];
+  for (int f = 0; f < 6; ++f) in[f] = d_in[f];
+  for (int f = 0; f < 3; ++f) out[f] = d_out[f];
+  const bool om2 = d_in[4] != nullptr;
+  return x->mixed ? plane_phase<float, float>(x, in, om2, out) : plane_phase<double, double>(x, in, om2, out);
+}
+
 chn_status chn_filter_and_stress(chn_ctx* x, int32_t kcx, int32_t kcz, int32_t q1, int32_t q3, double* d_ubar,
                                  double* d_uubar, double* d_tau) {
   if (chn_status s = check(x)) return s;
   if (!x->have_state) return fail(x, CHN_ESTATE, "chn_filter_and_stress before chn_set_state");
-  return x->mixed ? filter_stage<float>(x, kcx, kcz, q1, q3, d_ubar, d_uubar, d_tau)
-                  : filter_stage<double>(x, kcx, kcz, q1, q3, d_ubar, d_uubar, d_tau);
+  return filter_stage(x, kcx, kcz, q1, q3, d_ubar, d_uubar, d_tau);
 }
 
 chn_status chn_get_operators(chn_ctx* x, double* a1, double* b1, double* a2, double* b2, double* quad) {
@@ -946,6 +1033,87 @@ chn_status chn_get_operators(chn_ctx* x, double* a1, double* b1, double* a2, dou
   if (a2) std::memcpy(a2, x->hA2.data(), nb);
   if (b2) std::memcpy(b2, x->hB2.data(), nb);
   if (quad) std::memcpy(quad, x->hquad.data(), sizeof(double) * x->n2);
+  return CHN_OK;
+}
+
+chn_status chn_get_plan(chn_ctx* x, chn_plan* plan) {
+  if (!x || !plan) return CHN_EINVAL;
+  plan->x_rows = x->xrows;
+  plan->z_lines = x->zK;
+  plan->y_chunk = x->ychunk;
+  return CHN_OK;
+}
+
+chn_status chn_set_plan(chn_ctx* x, const chn_plan* plan) {
+  if (chn_status s = check(x)) return s;
+  if (!plan || !plan_fits(x, plan->x_rows, plan->z_lines, plan->y_chunk))
+    return fail(x, CHN_EINVAL, "schedule does not fit this grid or the device's LDS");
+  x->xrows = plan->x_rows;
+  x->zK = plan->z_lines;
+  x->ychunk = plan->y_chunk;
+  return CHN_OK;
+}
+
+chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
+  if (chn_status s = check(x)) return s;
+  if (x->planes_only) return fail(x, CHN_EUNSUPPORTED, "autotune needs the context's own field buffers (not planes_only)");
+  if (reps < 1) reps = 3;
+  struct Cand { int xr, K, ych; };
+  std::vector<Cand> cand;
+  const int kmax = z_lines_max(x);
+  std::vector<int> chunks;
+  for (int c : {x->ychunk_max, 64, 32, 16})
+    if (c >= 1 && c <= x->ychunk_max && std::find(chunks.begin(), chunks.end(), c) == chunks.end()) chunks.push_back(c);
+  for (int xr = 2; xr >= 1; --xr)
+    for (int K : {1, 2, 4, 8, 12, 16, kmax})
+      for (int c : chunks)
+        if (plan_fits(x, xr, K, c) &&
+            std::none_of(cand.begin(), cand.end(), [&](const Cand& q) { return q.xr == xr && q.K == K && q.ych == c; }))
+          cand.push_back({xr, K, c});
+  if (cand.empty()) return fail(x, CHN_EINVAL, "no schedule fits");
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(x, hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(x, CHN_EDEVICE, "hipEventCreate failed");
+  }
+  const bool timing = x->timing;
+  x->timing = false;
+  float best = 0.0f;
+  Cand pick = cand[0];
+  chn_status st = CHN_OK;
+  for (const auto& c : cand) {
+    x->xrows = c.xr;
+    x->zK = c.K;
+    x->ychunk = c.ych;
+    auto run = [&]() { return x->mixed ? plane_phase<float, float>(x, x->ph, false, x->H)
+                                       : plane_phase<double, double>(x, x->ph, false, x->H); };
+    if ((st = run()) != CHN_OK) break;
+    hipError_t e = hipEventRecord(a, x->stream);
+    for (int r = 0; r < reps && st == CHN_OK && e == hipSuccess; ++r) st = run();
+    if (e == hipSuccess) e = hipEventRecord(b, x->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (st == CHN_OK && e != hipSuccess) st = fail(x, CHN_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+    if (st != CHN_OK) break;
+    if (best == 0.0f || ms < best) {
+      best = ms;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  x->timing = timing;
+  x->xrows = pick.xr;
+  x->zK = pick.K;
+  x->ychunk = pick.ych;
+  if (st != CHN_OK) return st;
+  if (chosen) {
+    chosen->x_rows = pick.xr;
+    chosen->z_lines = pick.K;
+    chosen->y_chunk = pick.ych;
+  }
   return CHN_OK;
 }
 

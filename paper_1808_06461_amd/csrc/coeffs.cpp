@@ -215,8 +215,9 @@ bool fft_plan(int n, FftPlan* pl, std::vector<double>* tw) {
   for (int p = 0; p < np; ++p) {
     const int R = pl->radix[p];
     pl->twoff[p] = (int)(tw->size() / 2);
-    for (int k = 0; k < Ns; ++k)
-      for (int r = 1; r < R; ++r) {
+    // r-major, so that lanes with consecutive k read consecutive twiddles
+    for (int r = 1; r < R; ++r)
+      for (int k = 0; k < Ns; ++k) {
         const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)(r * k) /
                                 (long double)(Ns * R);
         tw->push_back((double)cosl(ang));

@@ -61,12 +61,19 @@ template <typename T, int R> __device__ __forceinline__ void dft(c2<T>* v, int s
   else dft8<T>(v, sgn);
 }
 
+// x / d as a multiply-high with m = ceil(2^32 / d) (m = 0 for d = 1): exact
+// while x * d < 2^32, which holds for the element indices of a workgroup
+__device__ __forceinline__ unsigned qmagic(unsigned d) { return d <= 1 ? 0u : 0xFFFFFFFFu / d + 1u; }
+__device__ __forceinline__ unsigned qdiv(unsigned x, unsigned d, unsigned m) {
+  return m == 0 ? x : __umulhi(x, m);
+}
+
 // One radix-R pass over all lines.  NB = butterflies per thread (compile
 // time, so the staging array lives in registers); the caller guarantees
 // nlines * N / R <= NB * blockDim.x.
 template <typename T, int R, int NB>
-__device__ __forceinline__ void stockham_pass(c2<T>* lds, int lstride, int nlines, int N, int Ns,
-                                              const c2<T>* __restrict__ tw, int sgn) {
+__device__ __forceinline__ void stockham_pass(c2<T>* lds, int lstride, int nlines, int N, int Ns, unsigned mb,
+                                              unsigned mk, const c2<T>* __restrict__ tw, int sgn) {
   const int nbl = N / R;
   const int total = nbl * nlines;
   const int nt = blockDim.x;
@@ -75,7 +82,7 @@ __device__ __forceinline__ void stockham_pass(c2<T>* lds, int lstride, int nline
   for (int q = 0; q < NB; ++q) {
     const int g = threadIdx.x + q * nt;
     if (g < total) {
-      const int line = g / nbl;
+      const int line = (int)qdiv((unsigned)g, (unsigned)nbl, mb);
       const int j = g - line * nbl;
       const c2<T>* src = lds + line * lstride + j;
 #pragma unroll
@@ -87,14 +94,13 @@ __device__ __forceinline__ void stockham_pass(c2<T>* lds, int lstride, int nline
   for (int q = 0; q < NB; ++q) {
     const int g = threadIdx.x + q * nt;
     if (g < total) {
-      const int line = g / nbl;
+      const int line = (int)qdiv((unsigned)g, (unsigned)nbl, mb);
       const int j = g - line * nbl;
-      const int k = j % Ns;
+      const int k = j - (int)qdiv((unsigned)j, (unsigned)Ns, mk) * Ns;
       if (Ns > 1) {
-        const c2<T>* w = tw + k * (R - 1);
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          c2<T> t = w[r - 1];
+          c2<T> t = tw[(r - 1) * Ns + k];
           if (sgn > 0) t.y = -t.y;
           v[q][r] = cmul<T>(v[q][r], t);
         }
@@ -111,18 +117,20 @@ __device__ __forceinline__ void stockham_pass(c2<T>* lds, int lstride, int nline
 // Full transform of nlines lines of length pl.n.  MAXV = complex values
 // staged per thread (a multiple of 24); requires nlines * pl.n <= MAXV * blockDim.x.
 template <typename T, int MAXV>
-__device__ void fft_lines(c2<T>* lds, int lstride, int nlines, const FftPlan& pl,
+__device__ __forceinline__ void fft_lines(c2<T>* lds, int lstride, int nlines, const FftPlan& pl,
                           const c2<T>* __restrict__ tw, int sgn) {
   int Ns = 1;
   for (int p = 0; p < pl.npass; ++p) {
     const c2<T>* twp = tw + pl.twoff[p];
-    switch (pl.radix[p]) {
-      case 8: stockham_pass<T, 8, MAXV / 8>(lds, lstride, nlines, pl.n, Ns, twp, sgn); break;
-      case 4: stockham_pass<T, 4, MAXV / 4>(lds, lstride, nlines, pl.n, Ns, twp, sgn); break;
-      case 3: stockham_pass<T, 3, MAXV / 3>(lds, lstride, nlines, pl.n, Ns, twp, sgn); break;
-      default: stockham_pass<T, 2, MAXV / 2>(lds, lstride, nlines, pl.n, Ns, twp, sgn); break;
+    const int R = pl.radix[p];
+    const unsigned mb = qmagic((unsigned)(pl.n / R)), mk = qmagic((unsigned)Ns);
+    switch (R) {
+      case 8: stockham_pass<T, 8, MAXV / 8>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
+      case 4: stockham_pass<T, 4, MAXV / 4>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
+      case 3: stockham_pass<T, 3, MAXV / 3>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
+      default: stockham_pass<T, 2, MAXV / 2>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
     }
-    Ns *= pl.radix[p];
+    Ns *= R;
   }
 }
 

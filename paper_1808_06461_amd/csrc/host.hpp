@@ -12,7 +12,7 @@ struct FftPlan {
   int n;
   int npass;
   int radix[16];
-  int twoff[16];
+  int twoff[16];  // pass p twiddles: tw[twoff + (r - 1) * Ns + k], r = 1..R-1, k < Ns
 };
 constexpr int kMaxPass = 16;
 #endif

@@ -21,6 +21,7 @@ template <typename T> struct ZinvArgs {
   int nfields;         // 6: u1 u2 u3 omega1 omega2 omega3; 3: u1 u2 u3
   int nslot;           // field slots per plane in `out`
   int zero_mean;       // nonzero: the (0,0) coefficient of every input is taken as 0
+  int y0, ny;          // planes y0 .. y0 + ny - 1 of the inputs; `out` holds them from plane 0
 };
 
 template <typename T> struct XpassArgs {
@@ -33,6 +34,8 @@ template <typename T> struct XpassArgs {
   float* rowcfl;       // [n2][p3] max over x of |u1|/dx + |u2|/dy + |u3|/dz
   double inv_dx, inv_dz;
   const double* inv_dy;  // [n2]
+  int rows;              // rows per workgroup: 2 (six lines in LDS) or 1 (long rows)
+  int y0, ny;            // buf holds planes y0 .. y0 + ny - 1 (from its plane 0)
 };
 
 template <typename T, typename TO> struct ZfwdArgs {
@@ -44,15 +47,20 @@ template <typename T, typename TO> struct ZfwdArgs {
   int K;
   int lstride;
   double scale;        // 1 / (p1 p3)
+  int y0, ny;          // buf holds planes y0 .. y0 + ny - 1 (from its plane 0); out is global
 };
 
 template <typename T> hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st);
 template <typename T> hipError_t launch_xpass(const XpassArgs<T>& a, hipStream_t st);
+// x-pass kernel choice for rows of p1 points of bytes_per_value-byte complex values
+bool xpass_two_rows(int p1, int bytes_per_value);
+int xrow_threads(int p1, int bytes_per_value);  // 0: too long
 template <typename T, typename TO> hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st);
 
 // ---------------------------------------------------------------- filter stage
 template <typename T> struct XfilterArgs {
-  const c2<T>* buf;      // [n2][6][p3][n1h], slots 0..2 = u1, u2, u3 after the z inverse
+  const c2<T>* buf;      // [n2][nslot][p3][n1h], slots 0..2 = u1, u2, u3 after the z inverse
+  int nslot;
   double2* out;          // per plane y at out + y * plane_stride: [6][p3][kcx+1]
   size_t plane_stride;   // in double2 elements
   const c2<T>* tw;       // p1 plan, context precision

@@ -6,9 +6,8 @@
 // zeroing the (0,0) coefficient), so the transforms carry only fluctuations:
 //   F(u_i u_j) = F(u'_i u'_j) + U_i F(u'_j) + U_j F(u'_i) + U_i U_j delta_k0,
 //   tau_ij     = F(u'_i u'_j) - F(u'_i) F(u'_j)      (the plane means cancel).
-// Inverse transforms and products run in the context's precision; the
-// pruned forward transforms of the products (kx <= kcx, |kz| <= kcz), the
-// mean-term assembly and the q-grid stage run in float64.
+// Every transform, product and sum runs in float64 (the mixed path rounds
+// the velocity coefficients to float32 first, see the host side).
 //
 //   k_zinv (plane.hip) : u1, u2, u3 with zero (0,0) mode, padded inverse in z
 //   k_xfilter : inverse in x, six products, float64 forward in x, keep kx <= kcx
@@ -39,7 +38,7 @@ __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
   }
   for (int e = threadIdx.x; e < 2 * n1h; e += blockDim.x) {
     const int l = e / n1h, k = e - l * n1h;
-    const size_t base = ((size_t)(y * 6 + 2 * l) * p3 + z) * n1h + k;
+    const size_t base = ((size_t)(y * a.nslot + 2 * l) * p3 + z) * n1h + k;
     const c2<T> X = a.buf[base];
     const c2<T> Y = l == 0 ? a.buf[base + (size_t)p3 * n1h] : zero;
     c2<T>* line = lt + l * LT;

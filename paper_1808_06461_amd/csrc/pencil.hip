@@ -385,7 +385,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
                                              const double* __restrict__ U1d, const double* __restrict__ L1u,
                                              const double* __restrict__ U1u, const double* __restrict__ clo,
                                              const double* __restrict__ chw) {
-  constexpr int D = 4, D2 = 3, D3 = 3;
+  constexpr int D = 3, D2 = 2, D3 = 2;
   const PencilGeom& g = a.g;
   const Lane L = lane_setup(g, bx);
   const int n = g.n2;
@@ -805,8 +805,10 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
   }
 }
 
+// At most 168 VGPRs (three waves per SIMD): a 384 x 384 mode plane gives
+// 577 workgroups, which then fit the 768 resident slots in one round.
 template <typename TH, typename TP>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
     k_advance(AdvanceArgs<TH, TP> a, const double* __restrict__ B1, const double* __restrict__ A2,
               const double* __restrict__ B2, const double* __restrict__ L1d, const double* __restrict__ U1d,
               const double* __restrict__ L1u, const double* __restrict__ U1u, const double* __restrict__ clo,
@@ -820,7 +822,7 @@ __global__ void __launch_bounds__(256)
 
 // Batched over contexts: work item (context, block, -, mean flag).
 template <typename TH, typename TP>
-__global__ void __launch_bounds__(256) k_advance_batch(const AdvanceArgs<TH, TP>* __restrict__ d,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_advance_batch(const AdvanceArgs<TH, TP>* __restrict__ d,
                                                        const int4* __restrict__ w) {
   const int4 q = w[blockIdx.x];
   const AdvanceArgs<TH, TP>& a = d[q.x];

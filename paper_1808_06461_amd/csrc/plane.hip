@@ -24,13 +24,30 @@ template <typename T, int MAXV>
 __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-  const int y = by;
+  const int y = a.y0 + by;  // plane of the inputs; `by` indexes `out`
   const int kx0 = bx * a.K;
   const int n1h = a.d.n1h, n3 = a.d.n3, p3 = a.d.p3, K = a.K, LS = a.lstride;
   const int nk = min(K, n1h - kx0);
   const int half = n3 / 2;
   const int npad = p3 - 2 * half + 1;
   const c2<T> zero = mk<T>(T(0), T(0));
+  auto value = [&](int f, int l, int s) -> c2<T> {
+    c2<T> v = zero;
+    if (l < nk && !(a.zero_mean && kx0 + l == 0 && s == 0)) {
+      const size_t idx = ((size_t)y * n1h + kx0 + l) * n3 + s;
+      if (f == 4 && a.in[4] == nullptr) {
+        // omega2 = i (b u1 - a u3)
+        const int kz = s < half ? s : s - n3;
+        const T ka = T(kTwoPi * (kx0 + l) / a.d.lx), kb = T(kTwoPi * kz / a.d.lz);
+        const c2<T> u1 = a.in[0][idx], u3 = a.in[2][idx];
+        const c2<T> t = mk<T>(kb * u1.x - ka * u3.x, kb * u1.y - ka * u3.y);
+        v = mk<T>(-t.y, t.x);
+      } else {
+        v = a.in[f][idx];
+      }
+    }
+    return v;
+  };
   for (int f = 0; f < a.nfields; ++f) {
     for (int e = threadIdx.x; e < K * npad; e += blockDim.x) {
       const int l = e / npad;
@@ -39,25 +56,11 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
     for (int e = threadIdx.x; e < K * n3; e += blockDim.x) {
       const int l = e / n3, s = e - l * n3;
       if (s == half) continue;
-      c2<T> v = zero;
-      if (l < nk && !(a.zero_mean && kx0 + l == 0 && s == 0)) {
-        const size_t idx = ((size_t)y * n1h + kx0 + l) * n3 + s;
-        if (f == 4 && a.in[4] == nullptr) {
-          // omega2 = i (b u1 - a u3)
-          const int kz = s < half ? s : s - n3;
-          const T ka = T(kTwoPi * (kx0 + l) / a.d.lx), kb = T(kTwoPi * kz / a.d.lz);
-          const c2<T> u1 = a.in[0][idx], u3 = a.in[2][idx];
-          const c2<T> t = mk<T>(kb * u1.x - ka * u3.x, kb * u1.y - ka * u3.y);
-          v = mk<T>(-t.y, t.x);
-        } else {
-          v = a.in[f][idx];
-        }
-      }
-      lds[l * LS + (s < half ? s : p3 - (n3 - s))] = v;
+      lds[l * LS + (s < half ? s : p3 - (n3 - s))] = value(f, l, s);
     }
     __syncthreads();
     fft_lines<T, MAXV>(lds, LS, K, a.plan, a.tw, +1);
-    c2<T>* out = a.out + ((size_t)(y * a.nslot + f) * p3) * n1h + kx0;
+    c2<T>* out = a.out + ((size_t)(by * a.nslot + f) * p3) * n1h + kx0;
     for (int e = threadIdx.x; e < nk * p3; e += blockDim.x) {
       const int z = e / nk, l = e - z * nk;
       out[(size_t)z * n1h + l] = lds[l * LS + z];
@@ -70,7 +73,8 @@ template <typename T, int MAXV>
 __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
-  const int y = by;
+  const int y = by;         // plane of buf
+  const int yg = a.y0 + by;  // global plane (row sums, CFL, mesh)
   const int z0 = bx * 2;
   const int n1h = a.d.n1h, p1 = a.d.p1, p3 = a.d.p3, LS = a.lstride;
   const int npad = p1 - 2 * n1h + 1;
@@ -98,7 +102,7 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
   fft_lines<T, MAXV>(lds, LS, 6, a.plan, a.tw, +1);
   // --- products, row sums and CFL
   double s1[2] = {0.0, 0.0}, s3[2] = {0.0, 0.0}, cf[2] = {0.0, 0.0};
-  const double idy = a.inv_dy[y];
+  const double idy = a.inv_dy[yg];
   for (int x = threadIdx.x; x < p1; x += blockDim.x) {
     T h3[2];
 #pragma unroll
@@ -146,7 +150,7 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
       t3 += red6[2 + row][w];
       tc = fmax(tc, red6[4 + row][w]);
     }
-    const size_t o = (size_t)y * p3 + z0 + row;
+    const size_t o = (size_t)yg * p3 + z0 + row;
     a.rowsum[o] = t1;
     a.rowsum[(size_t)a.d.n2 * p3 + o] = t3;
     a.rowcfl[o] = tc;
@@ -169,6 +173,110 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
   }
 }
 
+// Long rows (one row per workgroup, NT threads): the three input lines go
+// through LDS one at a time and the physical values stay in registers
+// (thread t owns x = t + NT q, q < QX); the products are formed in registers,
+// then H1 + i H2 and H3 are transformed forward one line at a time.  Used
+// when six lines of the row do not fit the two-row kernel.
+template <typename T, int NT, int QX, int MAXV>
+__device__ __forceinline__ void xrow_body(const XpassArgs<T>& a, int z, int y) {
+  extern __shared__ unsigned char smem_raw[];
+  c2<T>* line = reinterpret_cast<c2<T>*>(smem_raw);
+  const int n1h = a.d.n1h, p1 = a.d.p1, p3 = a.d.p3;
+  const c2<T> zero = mk<T>(T(0), T(0));
+  // line l (fields 2l + i 2l+1, Hermitian-extended) -> physical values of this thread
+  auto inverse = [&](int l, c2<T>(&r)[QX]) {
+    for (int x = n1h + threadIdx.x; x <= p1 - n1h; x += NT) line[x] = zero;
+    const size_t base = ((size_t)(y * 6 + 2 * l) * p3 + z) * n1h;
+    for (int k = threadIdx.x; k < n1h; k += NT) {
+      const c2<T> X = a.buf[base + k];
+      const c2<T> Y = a.buf[base + (size_t)p3 * n1h + k];
+      if (k == 0) {
+        line[0] = mk<T>(X.x, Y.x);
+      } else {
+        line[k] = mk<T>(X.x - Y.y, X.y + Y.x);
+        line[p1 - k] = mk<T>(X.x + Y.y, Y.x - X.y);
+      }
+    }
+    __syncthreads();
+    fft_lines<T, MAXV>(line, p1, 1, a.plan, a.tw, +1);
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+      const int x = threadIdx.x + q * NT;
+      r[q] = x < p1 ? line[x] : zero;
+    }
+    __syncthreads();
+  };
+  c2<T> r0[QX], r1[QX], r2[QX];
+  inverse(0, r0);
+  inverse(1, r1);
+  inverse(2, r2);
+  // products (r0 <- H1 + i H2, r1 <- H3), row sums and CFL
+  double s1 = 0.0, s3 = 0.0, cf = 0.0;
+  const double idy = a.inv_dy[a.y0 + y];
+#pragma unroll
+  for (int q = 0; q < QX; ++q) {
+    const T u1 = r0[q].x, u2 = r0[q].y, u3 = r1[q].x, o1 = r1[q].y, o2 = r2[q].x, o3 = r2[q].y;
+    const T H1 = u2 * o3 - u3 * o2;
+    const T H2 = u3 * o1 - u1 * o3;
+    const T H3 = u1 * o2 - u2 * o1;
+    if (threadIdx.x + q * NT < p1) {
+      s1 += (double)H1;
+      s3 += (double)H3;
+      cf = fmax(cf, fabs((double)u1) * a.inv_dx + fabs((double)u2) * idy + fabs((double)u3) * a.inv_dz);
+    }
+    r0[q] = mk<T>(H1, H2);
+    r1[q] = mk<T>(H3, T(0));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s1 += __shfl_xor(s1, off);
+    s3 += __shfl_xor(s3, off);
+    cf = fmax(cf, __shfl_xor(cf, off));
+  }
+  __shared__ double red[3][NT / 64];
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wid] = s1;
+    red[1][wid] = s3;
+    red[2][wid] = cf;
+  }
+  // forward transforms: line 0 = H1 + i H2 (two real spectra), line 1 = H3
+  auto forward = [&](int l, const c2<T>(&r)[QX]) {
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+      const int x = threadIdx.x + q * NT;
+      if (x < p1) line[x] = r[q];
+    }
+    __syncthreads();
+    if (l == 0 && threadIdx.x == 0) {
+      double t1 = 0.0, t3 = 0.0, tc = 0.0;
+      for (int w = 0; w < NT / 64; ++w) {
+        t1 += red[0][w];
+        t3 += red[1][w];
+        tc = fmax(tc, red[2][w]);
+      }
+      const size_t o = (size_t)(a.y0 + y) * p3 + z;
+      a.rowsum[o] = t1;
+      a.rowsum[(size_t)a.d.n2 * p3 + o] = t3;
+      a.rowcfl[o] = tc;
+    }
+    fft_lines<T, MAXV>(line, p1, 1, a.plan, a.tw, -1);
+    for (int k = threadIdx.x; k < n1h; k += NT) {
+      const c2<T> W = line[k];
+      if (l == 0) {
+        const c2<T> Wm = line[k == 0 ? 0 : p1 - k];
+        a.buf[((size_t)(y * 6 + 0) * p3 + z) * n1h + k] = mk<T>(T(0.5) * (W.x + Wm.x), T(0.5) * (W.y - Wm.y));
+        a.buf[((size_t)(y * 6 + 1) * p3 + z) * n1h + k] = mk<T>(T(0.5) * (W.y + Wm.y), T(-0.5) * (W.x - Wm.x));
+      } else {
+        a.buf[((size_t)(y * 6 + 2) * p3 + z) * n1h + k] = W;
+      }
+    }
+    __syncthreads();
+  };
+  forward(0, r0);
+  forward(1, r1);
+}
+
 template <typename T, typename TO, int MAXV>
 __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
@@ -179,6 +287,7 @@ __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int 
   const int nk = min(K, n1h - kx0);
   const int half = n3 / 2;
   const c2<T> zero = mk<T>(T(0), T(0));
+#pragma unroll
   for (int f = 0; f < 3; ++f) {
     const c2<T>* in = a.buf + ((size_t)(y * 6 + f) * p3) * n1h + kx0;
     for (int e = threadIdx.x; e < K * p3; e += blockDim.x) {
@@ -187,7 +296,7 @@ __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int 
     }
     __syncthreads();
     fft_lines<T, MAXV>(lds, LS, K, a.plan, a.tw, -1);
-    c2<TO>* out = a.out[f] + ((size_t)y * n1h + kx0) * n3;
+    c2<TO>* out = a.out[f] + ((size_t)(a.y0 + y) * n1h + kx0) * n3;
     for (int e = threadIdx.x; e < nk * n3; e += blockDim.x) {
       const int l = e / n3, s = e - l * n3;
       c2<TO> v = mk<TO>(TO(0), TO(0));
@@ -209,6 +318,8 @@ template <typename T, int MAXV>
 __global__ void __launch_bounds__(256) k_zinv(ZinvArgs<T> a) { zinv_body<T, MAXV>(a, blockIdx.x, blockIdx.y); }
 template <typename T, int MAXV>
 __global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) { xpass_body<T, MAXV>(a, blockIdx.x, blockIdx.y); }
+template <typename T, int NT, int QX, int MAXV>
+__global__ void __launch_bounds__(NT) k_xrow(XpassArgs<T> a) { xrow_body<T, NT, QX, MAXV>(a, blockIdx.x, blockIdx.y); }
 template <typename T, typename TO, int MAXV>
 __global__ void __launch_bounds__(256) k_zfwd(ZfwdArgs<T, TO> a) { zfwd_body<T, TO, MAXV>(a, blockIdx.x, blockIdx.y); }
 
@@ -233,30 +344,96 @@ template <typename T> struct FftMaxv;
 template <> struct FftMaxv<double> { static constexpr int v = 24; };
 template <> struct FftMaxv<float> { static constexpr int v = 48; };
 
+// Staging registers of the transforms: the smallest MAXV (complex values
+// per thread) that holds every pass of nlines lines over nt threads.  The
+// register allocation of a kernel follows its largest radix path, so a
+// tight MAXV raises occupancy.
+bool staging_fits(const FftPlan& pl, int nlines, int nt, int m) {
+  for (int p = 0; p < pl.npass; ++p) {
+    const int R = pl.radix[p];
+    const long need = ((long)nlines * (pl.n / R) + nt - 1) / nt;
+    if (m / R < need) return false;
+  }
+  return true;
+}
+template <typename T> int pick_staging(const FftPlan& pl, int nlines, int nt) {
+  static const int cf[4] = {16, 24, 32, 48}, cd[4] = {8, 12, 16, 24};
+  const int* c = sizeof(T) == 4 ? cf : cd;
+  for (int i = 0; i < 4; ++i)
+    if (staging_fits(pl, nlines, nt, c[i])) return c[i];
+  return 0;
+}
+
+#define CHN_STAGED(T, m, ...)                                 \
+  do {                                                           \
+    if constexpr (sizeof(T) == 4) {                              \
+      if (m == 16) { constexpr int MV = 16; __VA_ARGS__; }            \
+      else if (m == 24) { constexpr int MV = 24; __VA_ARGS__; }       \
+      else if (m == 32) { constexpr int MV = 32; __VA_ARGS__; }       \
+      else if (m == 48) { constexpr int MV = 48; __VA_ARGS__; }       \
+      else return hipErrorInvalidValue;                          \
+    } else {                                                     \
+      if (m == 8) { constexpr int MV = 8; __VA_ARGS__; }              \
+      else if (m == 12) { constexpr int MV = 12; __VA_ARGS__; }       \
+      else if (m == 16) { constexpr int MV = 16; __VA_ARGS__; }       \
+      else if (m == 24) { constexpr int MV = 24; __VA_ARGS__; }       \
+      else return hipErrorInvalidValue;                          \
+    }                                                            \
+  } while (0)
+
 template <typename T>
 hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st) {
-  constexpr int MV = FftMaxv<T>::v;
-  dim3 grid((a.d.n1h + a.K - 1) / a.K, a.d.n2);
+  const int m = pick_staging<T>(a.plan, a.K, 256);
+  dim3 grid((a.d.n1h + a.K - 1) / a.K, a.ny);
   size_t sh = (size_t)a.K * a.lstride * sizeof(c2<T>);
-  hipLaunchKernelGGL((k_zinv<T, MV>), grid, dim3(256), sh, st, a);
+  CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV>), grid, dim3(256), sh, st, a));
   return hipGetLastError();
+}
+
+// Rows of p1 points: two rows per workgroup while six lines fit the
+// staging registers, otherwise one row per workgroup of 256 / 512 / 1024
+// threads holding QX points each (xrow_limit gives the largest p1).
+template <typename T> struct XrowCfg;
+template <> struct XrowCfg<float> { static constexpr int QX = 12, MV = 16; };
+template <> struct XrowCfg<double> { static constexpr int QX = 6, MV = 8; };
+
+int xrow_threads(int p1, int bytes_per_value) {
+  const int qx = bytes_per_value == 8 ? 12 : 6;
+  for (int nt = 256; nt <= 1024; nt *= 2)
+    if (p1 <= nt * qx) return nt;
+  return 0;
+}
+bool xpass_two_rows(int p1, int bytes_per_value) {
+  return 6 * p1 <= (bytes_per_value == 8 ? 48 : 24) * 256;
 }
 
 template <typename T>
 hipError_t launch_xpass(const XpassArgs<T>& a, hipStream_t st) {
-  constexpr int MV = FftMaxv<T>::v;
-  dim3 grid(a.d.p3 / 2, a.d.n2);
-  size_t sh = (size_t)6 * a.lstride * sizeof(c2<T>);
-  hipLaunchKernelGGL((k_xpass<T, MV>), grid, dim3(256), sh, st, a);
+  if (a.rows == 2) {
+    if (!xpass_two_rows(a.d.p1, (int)sizeof(c2<T>)) || a.d.p3 % 2) return hipErrorInvalidValue;
+    const int m = pick_staging<T>(a.plan, 6, 256);
+    dim3 grid(a.d.p3 / 2, a.ny);
+    size_t sh = (size_t)6 * a.lstride * sizeof(c2<T>);
+    CHN_STAGED(T, m, hipLaunchKernelGGL((k_xpass<T, MV>), grid, dim3(256), sh, st, a));
+    return hipGetLastError();
+  }
+  constexpr int QX = XrowCfg<T>::QX, XM = XrowCfg<T>::MV;
+  const int nt = xrow_threads(a.d.p1, (int)sizeof(c2<T>));
+  dim3 grid(a.d.p3, a.ny);
+  const size_t sh = (size_t)a.d.p1 * sizeof(c2<T>);
+  if (nt == 256) hipLaunchKernelGGL((k_xrow<T, 256, QX, XM>), grid, dim3(256), sh, st, a);
+  else if (nt == 512) hipLaunchKernelGGL((k_xrow<T, 512, QX, XM>), grid, dim3(512), sh, st, a);
+  else if (nt == 1024) hipLaunchKernelGGL((k_xrow<T, 1024, QX, XM>), grid, dim3(1024), sh, st, a);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <typename T, typename TO>
 hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st) {
-  constexpr int MV = FftMaxv<T>::v;
-  dim3 grid((a.d.n1h + a.K - 1) / a.K, a.d.n2);
+  const int m = pick_staging<T>(a.plan, a.K, 256);
+  dim3 grid((a.d.n1h + a.K - 1) / a.K, a.ny);
   size_t sh = (size_t)a.K * a.lstride * sizeof(c2<T>);
-  hipLaunchKernelGGL((k_zfwd<T, TO, MV>), grid, dim3(256), sh, st, a);
+  CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV>), grid, dim3(256), sh, st, a));
   return hipGetLastError();
 }
 

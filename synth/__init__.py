@@ -214,3 +214,76 @@ def ensemble_cases(n=96, cfg=4):
         out.append(Case(n1=n1, n2=n2, n3=n3, lx=np.pi, lz=np.pi / 2, re_b=dean_re_b(rt), dt=0.0, amp=0.1,
                         mean="reichardt", re_tau=rt, cfg=1000 + i))
     return out
+
+
+# One GPU's share of the Re_tau = 5300 channel (box 2pi x 2 x pi, 8192 x 1537 x 6144):
+# a slab of 48 x-z planes for the transforms and products, and 1/128 of the
+# (kx, kz) modes as full 1537-point wall-normal lines for the pencil phase.
+C3_PLANES = dict(n1=8192, n3=6144, nplanes=48, lx=2 * np.pi, lz=np.pi, re_tau=5300.0, cfg=3)
+
+
+def c3_amplitude(n1: int = 8192, n3: int = 6144) -> np.ndarray:
+    """k_h^(-4/3) over [n1/2][n3] (index units, 1 at (0,0)), zero Nyquist slot; float32."""
+    kx = np.arange(n1 // 2, dtype=np.float32)[:, None]
+    s = np.arange(n3)
+    kz = np.where(s < n3 // 2, s, s - n3).astype(np.float32)[None, :]
+    kh = np.sqrt(kx * kx + kz * kz)
+    kh[0, 0] = 1.0
+    amp = kh ** np.float32(-4.0 / 3.0)
+    amp[:, n3 // 2] = 0.0
+    return amp
+
+
+def c3_plane_fields(plane: int, n1: int = 8192, n3: int = 6144, cfg: int = 3):
+    """Six spectral fields (u1, u2, u3, omega1, omega2, omega3) of one x-z plane,
+    complex64 [n1/2][n3]: complex Gaussian coefficients times k_h^(-4/3)
+    (k_h in index units, k_h = 1 for the (0,0) mode), Hermitian kx = 0 line,
+    zero Nyquist slot, each field scaled to a physical RMS of 0.1."""
+    n1h = n1 // 2
+    amp = c3_amplitude(n1, n3)
+    out = []
+    for f in range(6):
+        g = rng(cfg, 100000 + plane * 8 + f)
+        c = g.standard_normal((n1h, n3), dtype=np.float32) + 1j * g.standard_normal((n1h, n3), dtype=np.float32)
+        c = (c * amp).astype(np.complex64)
+        # Hermitian kx = 0 line: c(0, -kz) = conj c(0, kz), c(0, 0) real
+        pos = np.arange(1, n3 // 2)
+        c[0, n3 - pos] = np.conj(c[0, pos])
+        c[0, 0] = c[0, 0].real
+        # physical mean square = |c00|^2 + 2 sum_{kx>0}|c|^2 + sum_{kx=0, kz!=0}|c|^2
+        ms = float(np.sum(np.abs(c[1:]) ** 2) * 2 + np.sum(np.abs(c[0]) ** 2))
+        out.append((c * np.float32(0.1 / math.sqrt(ms))).astype(np.complex64))
+    return out
+
+
+def c3_pencil_case() -> Case:
+    """The pencil share as a channel of the same wall-normal size: 256 x 768 =
+    196608 Fourier modes (1/128 of the 4096 x 6144 modes) on 1537 nodes."""
+    rt = C3_PLANES["re_tau"]
+    return Case(n1=512, n2=1537, n3=768, lx=2 * np.pi, lz=np.pi, re_b=dean_re_b(rt), dt=0.0, amp=0.1,
+                kmax=None, mean="reichardt", re_tau=rt, cfg=6)
+
+
+def c3_fill_slab(fields, planes_from_numpy=(), cfg: int = 3, device="cuda"):
+    """Fills six device tensors [nplanes][n1/2][n3] (complex64) with the slab's
+    spectra: planes listed in planes_from_numpy come from c3_plane_fields (the
+    oracle's inputs); the others are drawn on the device from a seeded torch
+    generator with the same amplitude law (each field scaled to RMS 0.1)."""
+    import torch
+    P, n1h, n3 = fields[0].shape
+    amp = torch.from_numpy(c3_amplitude(2 * n1h, n3)).to(device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(SEED_ROOT + cfg)
+    pos = torch.arange(1, n3 // 2, device=device)
+    for p in range(P):
+        if p in planes_from_numpy:
+            for f, c in enumerate(c3_plane_fields(p, 2 * n1h, n3, cfg)):
+                fields[f][p].copy_(torch.from_numpy(c))
+            continue
+        for f in range(6):
+            c = torch.complex(torch.randn(n1h, n3, generator=gen, device=device),
+                              torch.randn(n1h, n3, generator=gen, device=device)) * amp
+            c[0, n3 - pos] = torch.conj(c[0, pos])
+            c[0, 0] = complex(float(c[0, 0].real))
+            ms = float((c[1:].abs() ** 2).sum() * 2 + (c[0].abs() ** 2).sum())
+            fields[f][p].copy_(c * (0.1 / math.sqrt(ms)))

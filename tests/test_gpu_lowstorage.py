@@ -1,8 +1,9 @@
 """Parity of the low-storage stage (chn_filter_and_stress) with the oracle.
 
-Float64 path: 1e-12 relative per output component.  Mixed path (float32
-inverse transforms and products, float64 forward accumulation): 1e-5
-relative on F(u_i u_j) and tau_ij, the bound the workload states.
+Float64 path: 1e-12 relative per output component.  Mixed path (velocity
+coefficients stored in float32, transforms and products in float64): 1e-7
+on F(u_i) (the float32 rounding of the data) and 1e-5 relative on
+F(u_i u_j) and tau_ij, the bound the workload states.
 """
 import numpy as np
 import pytest
@@ -60,8 +61,8 @@ def test_filter_and_stress_fp64(name):
 @pytest.mark.parametrize("name", ["small", "ragged", "mid"])
 def test_filter_and_stress_mixed(name):
     (ub, uu, tau), (gub, guu, gtau) = _run(name, "mixed")
-    for i in range(3):
-        assert rel(gub[i], ub[i]) < 1e-13
+    for i in range(3):  # the mixed path stores the velocity coefficients in float32
+        assert rel(gub[i], ub[i]) < 1e-7, ("ubar", i, rel(gub[i], ub[i]))
     for p in range(6):
         e_uu, e_tau = rel(guu[p], uu[p]), rel(gtau[p], tau[p])
         print(f"mixed {name} pair {p}: uu {e_uu:.2e} tau {e_tau:.2e}")
