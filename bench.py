@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-points x RK3 steps/sec, mixed-prec vs FP64 GPU at stated rel. error"
 UNIT = "grid-points*RK3-steps/s"
 HBM_PEAK_GBS = 8000.0
+FIXED_PLAN = None  # (x_rows, z_lines, y_chunk) from --plan; None: autotune
 
 
 def algorithmic_bytes(kind, n1, n2, n3, elem):
@@ -42,6 +43,46 @@ def algorithmic_bytes(kind, n1, n2, n3, elem):
     }[kind]
 
 
+# Source files that make up each kernel kind; the HBM traffic measured with
+# rocprofv3 counters (profiles/traffic_<kind>_channel_384x193x384.md) is used
+# only while these files are unchanged since the measurement.
+KERNEL_SOURCES = {
+    "advance": ["pencil.hip", "kernels.hpp", "common.hpp"],
+    "zinv": ["plane.hip", "fft.hpp", "kernels.hpp", "common.hpp"],
+    "xpass": ["plane.hip", "fft.hpp", "kernels.hpp", "common.hpp"],
+    "zfwd": ["plane.hip", "fft.hpp", "kernels.hpp", "common.hpp"],
+}
+
+
+def kernel_source_hash(kind):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kind, []):
+        with open(os.path.join(ROOT, "paper_1808_06461_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kind, precision="mixed"):
+    """HBM bytes per launch from the committed counter summary, or None if the
+    kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kind}_channel_384x193x384.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_hash(kind) or vals.get("precision") != precision:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def run_path(case, v, om, U1, U3, y, precision, steps, warmup):
     import torch
 
@@ -49,8 +90,12 @@ def run_path(case, v, om, U1, U3, y, precision, steps, warmup):
     ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, mass_flux=case.mass_flux,
                  precision=precision, y=y)
     ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
-    plan = ch.autotune(reps=3)  # plane-phase schedule, chosen before the timed steps
-    print(f"[bench] {precision}: autotuned plane schedule {plan}", file=sys.stderr, flush=True)
+    if FIXED_PLAN:
+        ch.set_plan(*FIXED_PLAN)
+        plan = ch.plan()
+    else:
+        plan = ch.autotune(reps=3)  # plane-phase schedule, chosen before the timed steps
+    print(f"[bench] {precision}: plane schedule {plan}", file=sys.stderr, flush=True)
     if warmup:
         ch.step(case.dt, warmup)
     ch.timing(True)
@@ -189,13 +234,35 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the per-phase timing of the Re_tau 5300 share")
+    ap.add_argument("--plan", default=None, metavar="XROWS,ZLINES,YCHUNK",
+                    help="fixed plane-phase schedule instead of the autotuner (for profiling one schedule)")
+    ap.add_argument("--source-hash", default=None, metavar="KIND",
+                    help="print the source hash a traffic summary of this kernel kind must carry, then exit")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="also run five plain device copies of BYTES bytes (calibrates HBM byte counters)")
     ap.add_argument("--only", choices=("fp64", "mixed"), default=None,
                     help="run one precision only (for profiling; the JSON then lacks the comparison)")
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_source_hash(args.source_hash))
+        return
+    if args.plan:
+        global FIXED_PLAN
+        FIXED_PLAN = tuple(int(v) for v in args.plan.split(","))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: 5 copies of {args.copy_probe} bytes", file=sys.stderr, flush=True)
+        del src, dst
 
     import synth
     case = synth.CASES["c2"]
@@ -206,7 +273,8 @@ def main():
     if args.only:
         print(f"[bench] {args.only} only: {args.warmup} warmup + {args.steps} timed RK3 steps", file=sys.stderr)
         ms, _, kern, _ = run_path(case, v, om, U1, U3, y, args.only, args.steps, args.warmup)
-        print(json.dumps({"precision": args.only, "ms_per_step": ms / args.steps,
+        plan = kern.pop("_plan")
+        print(json.dumps({"precision": args.only, "ms_per_step": ms / args.steps, "plane_schedule": plan,
                           "value": G * args.steps / (ms / 1e3), "kernels_ms": {k: t / max(n, 1) for k, (t, n) in kern.items()}}))
         return
     for prec in ("fp64", "mixed"):
@@ -228,7 +296,7 @@ def main():
     avg_s = tot / nsub / 1e3
     achieved = alg / avg_s / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
             "algorithmic_bytes_per_launch": alg * nsub // cnt, "avg_launch_ms": round(tot / cnt, 4)}
 
     def table(kk, e):

@@ -25,4 +25,16 @@ template <typename T> __device__ __forceinline__ c2<T> cmuli(c2<T> a, int sgn) {
 }
 template <typename T> __device__ __forceinline__ c2<T> cconj(c2<T> a) { return mk<T>(a.x, -a.y); }
 
+// XCD-aware order of a launch's n workgroups.  The dispatcher deals
+// workgroup w to XCD w % 8, and each XCD has its own L2; this gives XCD x the
+// contiguous range of logical tiles [x q + min(x, r), ...) (q = n / 8,
+// r = n % 8), so neighbouring tiles, which share cache lines at their edges,
+// run on one XCD close together in time.  A bijection of [0, n).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int w, int n) {
+  const int q = n / kXcds, r = n % kXcds;
+  const int x = w % kXcds, j = w / kXcds;
+  return x * q + (x < r ? x : r) + j;
+}
+
 }  // namespace chn

@@ -314,14 +314,27 @@ __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int 
 // Single-context launches index blocks by (blockIdx.x, blockIdx.y); batched
 // launches (ensembles) read (context, bx, by) from a work list and the
 // context's arguments from a descriptor array.
+// z passes: tiles of K kx lines; the logical tile order is XCD-aware so that
+// tiles sharing the cache lines of the transposed intermediate meet in one L2
+__device__ __forceinline__ int2 z_tile() {
+  const int n = gridDim.x * gridDim.y;
+  const int t = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, n);
+  return make_int2(t % gridDim.x, t / gridDim.x);
+}
 template <typename T, int MAXV>
-__global__ void __launch_bounds__(256) k_zinv(ZinvArgs<T> a) { zinv_body<T, MAXV>(a, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(256) k_zinv(ZinvArgs<T> a) {
+  const int2 t = z_tile();
+  zinv_body<T, MAXV>(a, t.x, t.y);
+}
 template <typename T, int MAXV>
 __global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) { xpass_body<T, MAXV>(a, blockIdx.x, blockIdx.y); }
 template <typename T, int NT, int QX, int MAXV>
 __global__ void __launch_bounds__(NT) k_xrow(XpassArgs<T> a) { xrow_body<T, NT, QX, MAXV>(a, blockIdx.x, blockIdx.y); }
 template <typename T, typename TO, int MAXV>
-__global__ void __launch_bounds__(256) k_zfwd(ZfwdArgs<T, TO> a) { zfwd_body<T, TO, MAXV>(a, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(256) k_zfwd(ZfwdArgs<T, TO> a) {
+  const int2 t = z_tile();
+  zfwd_body<T, TO, MAXV>(a, t.x, t.y);
+}
 
 template <typename T, int MAXV>
 __global__ void __launch_bounds__(256) k_zinv_batch(const ZinvArgs<T>* __restrict__ d, const int4* __restrict__ w) {
