@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-points x RK3 steps/sec, mixed-prec vs FP64 GPU at stated rel. error"
 UNIT = "grid-points*RK3-steps/s"
 HBM_PEAK_GBS = 8000.0
-FIXED_PLAN = None  # (x_rows, z_lines, y_chunk) from --plan; None: autotune
+FIXED_PLAN = None  # (x_rows, z_lines, y_chunk[, fixed_radix]) from --plan; None: autotune
 
 
 def algorithmic_bytes(kind, n1, n2, n3, elem):
@@ -234,7 +234,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the per-phase timing of the Re_tau 5300 share")
-    ap.add_argument("--plan", default=None, metavar="XROWS,ZLINES,YCHUNK",
+    ap.add_argument("--plan", default=None, metavar="XROWS,ZLINES,YCHUNK[,FIXED]",
                     help="fixed plane-phase schedule instead of the autotuner (for profiling one schedule)")
     ap.add_argument("--source-hash", default=None, metavar="KIND",
                     help="print the source hash a traffic summary of this kernel kind must carry, then exit")

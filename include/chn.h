@@ -241,11 +241,14 @@ chn_status chn_timing_read(chn_ctx *ctx, int32_t kind, double *total_ms, int32_t
 typedef struct {
   int32_t x_rows;
   int32_t z_lines;
-  int32_t y_chunk;  /* planes per launch of the three plane kernels */
+  int32_t y_chunk;      /* planes per launch of the three plane kernels */
+  int32_t fixed_radix;  /* 1: transforms whose length has a compile-time radix
+                           schedule (576 points) use it; 0: the runtime plan */
 } chn_plan;
 
 /* Current schedule (chn_create picks 2 rows when they fit, 16 lines capped
- * by registers and LDS, and plane_chunk or all planes). */
+ * by registers and LDS, plane_chunk or all planes, and the runtime radix
+ * plan). */
 chn_status chn_get_plan(chn_ctx *ctx, chn_plan *plan);
 
 /* Sets the schedule; CHN_EINVAL (context unchanged) if it does not fit the

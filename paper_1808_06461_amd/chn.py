@@ -32,7 +32,8 @@ class Config(C.Structure):
 
 
 class Plan(C.Structure):
-    _fields_ = [("x_rows", C.c_int32), ("z_lines", C.c_int32), ("y_chunk", C.c_int32)]
+    _fields_ = [("x_rows", C.c_int32), ("z_lines", C.c_int32), ("y_chunk", C.c_int32),
+                ("fixed_radix", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -208,16 +209,16 @@ class Channel:
     def plan(self):
         p = Plan()
         self._check(self.L.chn_get_plan(self.ctx, C.byref(p)), "chn_get_plan")
-        return {"x_rows": p.x_rows, "z_lines": p.z_lines, "y_chunk": p.y_chunk}
+        return {"x_rows": p.x_rows, "z_lines": p.z_lines, "y_chunk": p.y_chunk, "fixed_radix": p.fixed_radix}
 
-    def set_plan(self, x_rows, z_lines, y_chunk=None):
-        p = Plan(int(x_rows), int(z_lines), int(self.n2 if y_chunk is None else y_chunk))
+    def set_plan(self, x_rows, z_lines, y_chunk=None, fixed_radix=0):
+        p = Plan(int(x_rows), int(z_lines), int(self.n2 if y_chunk is None else y_chunk), int(fixed_radix))
         self._check(self.L.chn_set_plan(self.ctx, C.byref(p)), "chn_set_plan")
 
     def autotune(self, reps=3):
         p = Plan()
         self._check(self.L.chn_autotune(self.ctx, int(reps), C.byref(p)), "chn_autotune")
-        return {"x_rows": p.x_rows, "z_lines": p.z_lines, "y_chunk": p.y_chunk}
+        return {"x_rows": p.x_rows, "z_lines": p.z_lines, "y_chunk": p.y_chunk, "fixed_radix": p.fixed_radix}
 
     def operators(self):
         import numpy as np

@@ -81,6 +81,7 @@ struct chn_ctx {
   int xrows = 2;        // x-pass rows per workgroup (2, or 1 for long rows)
   int zK = 1;           // lines per z-pass workgroup
   int ychunk = 1;       // planes per plane-phase launch
+  int ffix = 0;         // compile-time radix schedules where available
   int ychunk_max = 1;   // planes the intermediate holds
   bool planes_only = false;
   // per-kernel timing (chn_timing_enable): events bracketing every launch
@@ -272,6 +273,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   za.nslot = 6;
   za.y0 = 0;
   za.ny = x->n2;
+  za.fixed = x->ffix;
   xa = {};
   xa.buf = reinterpret_cast<C*>(x->inter);
   xa.tw = reinterpret_cast<const C*>(x->tw1);
@@ -286,6 +288,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   xa.rows = x->xrows;
   xa.y0 = 0;
   xa.ny = x->n2;
+  xa.fixed = x->ffix;
   fa = {};
   fa.buf = reinterpret_cast<const C*>(x->inter);
   for (int f = 0; f < 3; ++f) fa.out[f] = reinterpret_cast<typename Ty<TO>::c*>(out[f]);
@@ -297,6 +300,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   fa.scale = 1.0 / ((double)x->p1 * x->p3);
   fa.y0 = 0;
   fa.ny = x->n2;
+  fa.fixed = x->ffix;
 }
 
 // plane phase: ph (6 slots) -> H (3 slots) through the intermediate
@@ -1041,16 +1045,19 @@ chn_status chn_get_plan(chn_ctx* x, chn_plan* plan) {
   plan->x_rows = x->xrows;
   plan->z_lines = x->zK;
   plan->y_chunk = x->ychunk;
+  plan->fixed_radix = x->ffix;
   return CHN_OK;
 }
 
 chn_status chn_set_plan(chn_ctx* x, const chn_plan* plan) {
   if (chn_status s = check(x)) return s;
-  if (!plan || !plan_fits(x, plan->x_rows, plan->z_lines, plan->y_chunk))
+  if (!plan || !plan_fits(x, plan->x_rows, plan->z_lines, plan->y_chunk) ||
+      (plan->fixed_radix != 0 && plan->fixed_radix != 1))
     return fail(x, CHN_EINVAL, "schedule does not fit this grid or the device's LDS");
   x->xrows = plan->x_rows;
   x->zK = plan->z_lines;
   x->ychunk = plan->y_chunk;
+  x->ffix = plan->fixed_radix;
   return CHN_OK;
 }
 
@@ -1058,18 +1065,21 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
   if (chn_status s = check(x)) return s;
   if (x->planes_only) return fail(x, CHN_EUNSUPPORTED, "autotune needs the context's own field buffers (not planes_only)");
   if (reps < 1) reps = 3;
-  struct Cand { int xr, K, ych; };
+  struct Cand { int xr, K, ych, fx; };
   std::vector<Cand> cand;
   const int kmax = z_lines_max(x);
   std::vector<int> chunks;
   for (int c : {x->ychunk_max, 64, 32, 16})
     if (c >= 1 && c <= x->ychunk_max && std::find(chunks.begin(), chunks.end(), c) == chunks.end()) chunks.push_back(c);
-  for (int xr = 2; xr >= 1; --xr)
-    for (int K : {1, 2, 4, 8, 12, 16, kmax})
-      for (int c : chunks)
-        if (plan_fits(x, xr, K, c) &&
-            std::none_of(cand.begin(), cand.end(), [&](const Cand& q) { return q.xr == xr && q.K == K && q.ych == c; }))
-          cand.push_back({xr, K, c});
+  const bool has_fixed = chn::plan_is_576(x->plan1) || chn::plan_is_576(x->plan3);
+  for (int fx = 0; fx <= (has_fixed ? 1 : 0); ++fx)
+    for (int xr = 2; xr >= 1; --xr)
+      for (int K : {1, 2, 4, 8, 12, 16, kmax})
+        for (int c : chunks)
+          if (plan_fits(x, xr, K, c) && std::none_of(cand.begin(), cand.end(), [&](const Cand& q) {
+                return q.xr == xr && q.K == K && q.ych == c && q.fx == fx;
+              }))
+            cand.push_back({xr, K, c, fx});
   if (cand.empty()) return fail(x, CHN_EINVAL, "no schedule fits");
   hipEvent_t a = nullptr, b = nullptr;
   HIPCHK(x, hipEventCreate(&a));
@@ -1086,6 +1096,7 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
     x->xrows = c.xr;
     x->zK = c.K;
     x->ychunk = c.ych;
+    x->ffix = c.fx;
     auto run = [&]() { return x->mixed ? plane_phase<float, float>(x, x->ph, false, x->H)
                                        : plane_phase<double, double>(x, x->ph, false, x->H); };
     if ((st = run()) != CHN_OK) break;
@@ -1108,11 +1119,13 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
   x->xrows = pick.xr;
   x->zK = pick.K;
   x->ychunk = pick.ych;
+  x->ffix = pick.fx;
   if (st != CHN_OK) return st;
   if (chosen) {
     chosen->x_rows = pick.xr;
     chosen->z_lines = pick.K;
     chosen->y_chunk = pick.ych;
+    chosen->fixed_radix = pick.fx;
   }
   return CHN_OK;
 }

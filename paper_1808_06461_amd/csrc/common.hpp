@@ -25,6 +25,12 @@ template <typename T> __device__ __forceinline__ c2<T> cmuli(c2<T> a, int sgn) {
 }
 template <typename T> __device__ __forceinline__ c2<T> cconj(c2<T> a) { return mk<T>(a.x, -a.y); }
 
+// Plans with a compile-time radix schedule (FN template argument of the plane kernels).
+__host__ __device__ inline bool plan_is_576(const FftPlan& pl) {
+  return pl.n == 576 && pl.npass == 4 && pl.radix[0] == 8 && pl.radix[1] == 8 && pl.radix[2] == 3 &&
+         pl.radix[3] == 3;
+}
+
 // XCD-aware order of a launch's n workgroups.  The dispatcher deals
 // workgroup w to XCD w % 8, and each XCD has its own L2; this gives XCD x the
 // contiguous range of logical tiles [x q + min(x, r), ...) (q = n / 8,

@@ -114,11 +114,65 @@ __device__ __forceinline__ void stockham_pass(c2<T>* lds, int lstride, int nline
   __syncthreads();
 }
 
+// The same pass with the line length and Ns known at compile time: divisions
+// by constants, LDS and twiddle offsets folded into the instructions.  Same
+// arithmetic, in the same order, as the runtime pass.
+template <typename T, int R, int NB, int N, int NS>
+__device__ __forceinline__ void stockham_pass_c(c2<T>* lds, int lstride, int nlines, const c2<T>* __restrict__ tw,
+                                                int sgn) {
+  constexpr int nbl = N / R;
+  const int total = nbl * nlines;
+  const int nt = blockDim.x;
+  c2<T> v[NB][R];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int g = threadIdx.x + q * nt;
+    if (g < total) {
+      const int line = (unsigned)g / (unsigned)nbl;
+      const int j = g - line * nbl;
+      const c2<T>* src = lds + line * lstride + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[r * nbl];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int g = threadIdx.x + q * nt;
+    if (g < total) {
+      const int line = (unsigned)g / (unsigned)nbl;
+      const int j = g - line * nbl;
+      const int k = (unsigned)j % (unsigned)NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          c2<T> t = tw[(r - 1) * NS + k];
+          if (sgn > 0) t.y = -t.y;
+          v[q][r] = cmul<T>(v[q][r], t);
+        }
+      }
+      dft<T, R>(v[q], sgn);
+      c2<T>* dst = lds + line * lstride + (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * NS] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
 // Full transform of nlines lines of length pl.n.  MAXV = complex values
 // staged per thread (a multiple of 24); requires nlines * pl.n <= MAXV * blockDim.x.
-template <typename T, int MAXV>
+template <typename T, int MAXV, int FN = 0>
 __device__ __forceinline__ void fft_lines(c2<T>* lds, int lstride, int nlines, const FftPlan& pl,
                           const c2<T>* __restrict__ tw, int sgn) {
+  // 576 = 3/2 x 384 (the 384-mode directions): radices 8, 8, 3, 3 at compile time
+  if constexpr (FN == 576) {
+    stockham_pass_c<T, 8, MAXV / 8, 576, 1>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
+    stockham_pass_c<T, 8, MAXV / 8, 576, 8>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
+    stockham_pass_c<T, 3, MAXV / 3, 576, 64>(lds, lstride, nlines, tw + pl.twoff[2], sgn);
+    stockham_pass_c<T, 3, MAXV / 3, 576, 192>(lds, lstride, nlines, tw + pl.twoff[3], sgn);
+    return;
+  } else {
   int Ns = 1;
   for (int p = 0; p < pl.npass; ++p) {
     const c2<T>* twp = tw + pl.twoff[p];
@@ -131,6 +185,7 @@ __device__ __forceinline__ void fft_lines(c2<T>* lds, int lstride, int nlines, c
       default: stockham_pass<T, 2, MAXV / 2>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
     }
     Ns *= R;
+  }
   }
 }
 

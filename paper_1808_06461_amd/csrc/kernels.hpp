@@ -22,6 +22,7 @@ template <typename T> struct ZinvArgs {
   int nslot;           // field slots per plane in `out`
   int zero_mean;       // nonzero: the (0,0) coefficient of every input is taken as 0
   int y0, ny;          // planes y0 .. y0 + ny - 1 of the inputs; `out` holds them from plane 0
+  int fixed;           // nonzero: compile-time radix schedule where one exists for the plan
 };
 
 template <typename T> struct XpassArgs {
@@ -36,6 +37,7 @@ template <typename T> struct XpassArgs {
   const double* inv_dy;  // [n2]
   int rows;              // rows per workgroup: 2 (six lines in LDS) or 1 (long rows)
   int y0, ny;            // buf holds planes y0 .. y0 + ny - 1 (from its plane 0)
+  int fixed;             // nonzero: compile-time radix schedule where one exists for the plan
 };
 
 template <typename T, typename TO> struct ZfwdArgs {
@@ -48,6 +50,7 @@ template <typename T, typename TO> struct ZfwdArgs {
   int lstride;
   double scale;        // 1 / (p1 p3)
   int y0, ny;          // buf holds planes y0 .. y0 + ny - 1 (from its plane 0); out is global
+  int fixed;           // nonzero: compile-time radix schedule where one exists for the plan
 };
 
 template <typename T> hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st);

@@ -20,7 +20,7 @@ namespace chn {
 
 static constexpr double kTwoPi = 6.283185307179586476925286766559;
 
-template <typename T, int MAXV>
+template <typename T, int MAXV, int FN = 0>
 __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
@@ -59,7 +59,7 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
       lds[l * LS + (s < half ? s : p3 - (n3 - s))] = value(f, l, s);
     }
     __syncthreads();
-    fft_lines<T, MAXV>(lds, LS, K, a.plan, a.tw, +1);
+    fft_lines<T, MAXV, FN>(lds, LS, K, a.plan, a.tw, +1);
     c2<T>* out = a.out + ((size_t)(by * a.nslot + f) * p3) * n1h + kx0;
     for (int e = threadIdx.x; e < nk * p3; e += blockDim.x) {
       const int z = e / nk, l = e - z * nk;
@@ -69,7 +69,7 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
   }
 }
 
-template <typename T, int MAXV>
+template <typename T, int MAXV, int FN = 0>
 __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
@@ -99,7 +99,7 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
     }
   }
   __syncthreads();
-  fft_lines<T, MAXV>(lds, LS, 6, a.plan, a.tw, +1);
+  fft_lines<T, MAXV, FN>(lds, LS, 6, a.plan, a.tw, +1);
   // --- products, row sums and CFL
   double s1[2] = {0.0, 0.0}, s3[2] = {0.0, 0.0}, cf[2] = {0.0, 0.0};
   const double idy = a.inv_dy[yg];
@@ -155,7 +155,7 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
     a.rowsum[(size_t)a.d.n2 * p3 + o] = t3;
     a.rowcfl[o] = tc;
   }
-  fft_lines<T, MAXV>(lds, LS, 3, a.plan, a.tw, -1);
+  fft_lines<T, MAXV, FN>(lds, LS, 3, a.plan, a.tw, -1);
   // --- unpack two real spectra per line, truncate, store in place over fields 0..2
   for (int e = threadIdx.x; e < 3 * n1h; e += blockDim.x) {
     const int l = e / n1h, k = e - l * n1h;
@@ -277,7 +277,7 @@ __device__ __forceinline__ void xrow_body(const XpassArgs<T>& a, int z, int y) {
   forward(1, r1);
 }
 
-template <typename T, typename TO, int MAXV>
+template <typename T, typename TO, int MAXV, int FN = 0>
 __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
@@ -295,7 +295,7 @@ __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int 
       lds[l * LS + z] = l < nk ? in[(size_t)z * n1h + l] : zero;
     }
     __syncthreads();
-    fft_lines<T, MAXV>(lds, LS, K, a.plan, a.tw, -1);
+    fft_lines<T, MAXV, FN>(lds, LS, K, a.plan, a.tw, -1);
     c2<TO>* out = a.out[f] + ((size_t)(a.y0 + y) * n1h + kx0) * n3;
     for (int e = threadIdx.x; e < nk * n3; e += blockDim.x) {
       const int l = e / n3, s = e - l * n3;
@@ -321,19 +321,19 @@ __device__ __forceinline__ int2 z_tile() {
   const int t = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, n);
   return make_int2(t % gridDim.x, t / gridDim.x);
 }
-template <typename T, int MAXV>
+template <typename T, int MAXV, int FN>
 __global__ void __launch_bounds__(256) k_zinv(ZinvArgs<T> a) {
   const int2 t = z_tile();
-  zinv_body<T, MAXV>(a, t.x, t.y);
+  zinv_body<T, MAXV, FN>(a, t.x, t.y);
 }
-template <typename T, int MAXV>
-__global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) { xpass_body<T, MAXV>(a, blockIdx.x, blockIdx.y); }
+template <typename T, int MAXV, int FN>
+__global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) { xpass_body<T, MAXV, FN>(a, blockIdx.x, blockIdx.y); }
 template <typename T, int NT, int QX, int MAXV>
 __global__ void __launch_bounds__(NT) k_xrow(XpassArgs<T> a) { xrow_body<T, NT, QX, MAXV>(a, blockIdx.x, blockIdx.y); }
-template <typename T, typename TO, int MAXV>
+template <typename T, typename TO, int MAXV, int FN>
 __global__ void __launch_bounds__(256) k_zfwd(ZfwdArgs<T, TO> a) {
   const int2 t = z_tile();
-  zfwd_body<T, TO, MAXV>(a, t.x, t.y);
+  zfwd_body<T, TO, MAXV, FN>(a, t.x, t.y);
 }
 
 template <typename T, int MAXV>
@@ -399,7 +399,8 @@ hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st) {
   const int m = pick_staging<T>(a.plan, a.K, 256);
   dim3 grid((a.d.n1h + a.K - 1) / a.K, a.ny);
   size_t sh = (size_t)a.K * a.lstride * sizeof(c2<T>);
-  CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV>), grid, dim3(256), sh, st, a));
+  if (a.fixed && plan_is_576(a.plan)) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 576>), grid, dim3(256), sh, st, a));
+  else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 0>), grid, dim3(256), sh, st, a));
   return hipGetLastError();
 }
 
@@ -427,7 +428,8 @@ hipError_t launch_xpass(const XpassArgs<T>& a, hipStream_t st) {
     const int m = pick_staging<T>(a.plan, 6, 256);
     dim3 grid(a.d.p3 / 2, a.ny);
     size_t sh = (size_t)6 * a.lstride * sizeof(c2<T>);
-    CHN_STAGED(T, m, hipLaunchKernelGGL((k_xpass<T, MV>), grid, dim3(256), sh, st, a));
+    if (a.fixed && plan_is_576(a.plan)) CHN_STAGED(T, m, hipLaunchKernelGGL((k_xpass<T, MV, 576>), grid, dim3(256), sh, st, a));
+    else CHN_STAGED(T, m, hipLaunchKernelGGL((k_xpass<T, MV, 0>), grid, dim3(256), sh, st, a));
     return hipGetLastError();
   }
   constexpr int QX = XrowCfg<T>::QX, XM = XrowCfg<T>::MV;
@@ -446,7 +448,8 @@ hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st) {
   const int m = pick_staging<T>(a.plan, a.K, 256);
   dim3 grid((a.d.n1h + a.K - 1) / a.K, a.ny);
   size_t sh = (size_t)a.K * a.lstride * sizeof(c2<T>);
-  CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV>), grid, dim3(256), sh, st, a));
+  if (a.fixed && plan_is_576(a.plan)) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 576>), grid, dim3(256), sh, st, a));
+  else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 0>), grid, dim3(256), sh, st, a));
   return hipGetLastError();
 }
 

@@ -2,8 +2,9 @@
 
 Every schedule must give the oracle's non-linear term to the same bounds as
 the default one (float64 1e-13, mixed 2e-6 relative per component): the
-two-row and the one-row x pass, and z-pass workgroups of one line up to the
-largest that fits.  The autotuner must pick a schedule that fits and leave
+two-row and the one-row x pass, z-pass workgroups of one line up to the
+largest that fits, planes in chunks, and the runtime or compile-time radix
+schedule (576-point lines).  The autotuner must pick a schedule that fits and leave
 results within those bounds.
 """
 import numpy as np
@@ -22,6 +23,9 @@ CASES = {
                          kmax=None, cfg=22),
     "wide": synth.Case(n1=96, n2=17, n3=48, lx=2 * np.pi, lz=np.pi, re_b=3000.0, dt=0.002, amp=0.1, kmax=None,
                        cfg=23),
+    # 576-point lines in x and z: the compile-time radix schedule applies
+    "p576": synth.Case(n1=384, n2=9, n3=384, lx=2 * np.pi, lz=np.pi, re_b=10000.0, dt=0.002, amp=0.1,
+                       kmax=None, cfg=24),
 }
 TOL = {"fp64": 1e-13, "mixed": 2e-6}
 
@@ -65,12 +69,15 @@ def test_every_schedule_matches_oracle(name, precision):
             except ChnError:
                 break
         assert kmax >= 1
-        for x_rows in (2, 1):
-            for k in sorted({1, 2, 3, kmax}):
-                if k > kmax:
-                    continue
-                ch.set_plan(x_rows, k)
-                _check(ch, fields, ref, TOL[precision], f"{precision} rows={x_rows} lines={k}")
+        for fixed in (0, 1):
+            for x_rows in (2, 1):
+                for k in sorted({1, 2, 3, kmax}):
+                    if k > kmax:
+                        continue
+                    ch.set_plan(x_rows, k, None, fixed)
+                    _check(ch, fields, ref, TOL[precision], f"{precision} rows={x_rows} lines={k} fixed={fixed}")
+        ch.set_plan(2, 1, max(1, case.n2 // 3))  # planes in chunks
+        _check(ch, fields, ref, TOL[precision], f"{precision} chunked planes")
         with pytest.raises(ChnError):
             ch.set_plan(3, 1)
         with pytest.raises(ChnError):
