@@ -66,6 +66,11 @@ struct chn_ctx {
   double* SU[8] = {};
   double* rowsum = nullptr;
   float* rowcfl = nullptr;
+  // homogeneous solutions of the three sub-steps for the time step htab_dt
+  double* hc[3] = {};
+  double* hv[3] = {};
+  double* hm[3] = {};
+  double htab_dt = 0.0;  // 0: not computed
   // tables
   double *A1, *B1, *A2, *B2, *L1d, *U1d, *L1u, *U1u, *L2d, *U2d, *clo, *chi_w, *quad, *inv_dy;
   void *tw1 = nullptr, *tw3 = nullptr;
@@ -129,6 +134,14 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
   for (int k = 0; k < 8; ++k) S[k] = reinterpret_cast<double*>(cv.take(CB));
   double* SU[8];
   for (int k = 0; k < 8; ++k) SU[k] = D(NPb);
+  double* hc[3];
+  double* hv[3];
+  double* hm[3];
+  for (int k = 0; k < 3; ++k) {
+    hc[k] = reinterpret_cast<double*>(cv.take(CB));
+    hv[k] = reinterpret_cast<double*>(cv.take(CB));
+    hm[k] = D(po ? 0 : 4 * M);
+  }
   double* rowsum = D(2 * (size_t)n2 * p3);
   float* rowcfl = reinterpret_cast<float*>(cv.take(sizeof(float) * (size_t)n2 * p3));
   double* tabs = D((size_t)n2 * (4 * 7 + 3 * 3 + 3 * 4 + 4));
@@ -149,6 +162,7 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
     x->inter_bytes = ib;
     for (int k = 0; k < 8; ++k) { x->S[k] = S[k]; x->SU[k] = SU[k]; }
     x->rowsum = rowsum; x->rowcfl = rowcfl;
+    for (int k = 0; k < 3; ++k) { x->hc[k] = hc[k]; x->hv[k] = hv[k]; x->hm[k] = hm[k]; }
     double* t = tabs;
     x->A1 = t; t += 7 * n2; x->B1 = t; t += 7 * n2; x->A2 = t; t += 7 * n2; x->B2 = t; t += 7 * n2;
     x->L1d = t; t += 3 * n2; x->L1u = t; t += 3 * n2; x->L2d = t; t += 3 * n2;
@@ -347,6 +361,27 @@ template <typename T> T* const* phase_ptrs(chn_ctx* x, T** po) {
 
 template <typename T> void advance_args(chn_ctx* x, int s, double dt, chn::AdvanceArgs<T, T>& aa);
 
+// Homogeneous solutions for the time step dt (recomputed when dt changes).
+chn_status homog_tables(chn_ctx* x, double dt, hipStream_t st) {
+  if (x->htab_dt == dt) return CHN_OK;
+  chn::HomogArgs h{};
+  h.g = x->geom;
+  h.nu = x->nu;
+  h.dt = dt;
+  for (int k = 0; k < 3; ++k) {
+    h.be[k] = kBeta[k];
+    h.hc[k] = x->hc[k];
+    h.hv[k] = x->hv[k];
+    h.hm[k] = x->hm[k];
+  }
+  h.S0 = x->S[3];
+  h.S1 = x->S[4];
+  for (int k = 0; k < 8; ++k) h.SU[k] = x->SU[k];
+  HIPCHK(x, chn::launch_homog(h, st));
+  x->htab_dt = dt;
+  return CHN_OK;
+}
+
 template <typename T> chn_status substep(chn_ctx* x, int s, double dt) {
   T* po[5];
   phase_ptrs<T>(x, po);
@@ -361,6 +396,7 @@ template <typename T> chn_status substep(chn_ctx* x, int s, double dt) {
   chn_status st = plane_phase<T, T>(x, x->ph, false, x->H);
   if (st != CHN_OK) return st;
   // 3. pencils + mean modes + next sub-step's velocities and vorticities
+  if (chn_status hs = homog_tables(x, dt, x->stream)) return hs;
   chn::AdvanceArgs<T, T> aa;
   advance_args<T>(x, s, dt, aa);
   HIPCHK(x, timed(x, CHN_K_ADVANCE, [&] { return chn::launch_advance<T, T>(aa, x->stream); }));
@@ -386,6 +422,9 @@ template <typename T> void advance_args(chn_ctx* x, int s, double dt, chn::Advan
   aa.mass_flux = x->cfg.mass_flux;
   aa.dt = dt; aa.nu = x->nu;
   aa.al = kAlpha[s]; aa.be = kBeta[s]; aa.ga = kGamma[s]; aa.ze = kZeta[s];
+  aa.hc = x->hc[s];
+  aa.hv = x->hv[s];
+  aa.hm = x->hm[s];
 }
 
 chn_status check(chn_ctx* x);
@@ -717,6 +756,12 @@ template <typename T> chn_status ens_step(chn_ens* e, const double* dt, int nste
       x->phase_valid = true;
     }
   }
+  // homogeneous solutions for these step sizes (outside the graph, on the configured stream)
+  for (int i = 0; i < n; ++i)
+    if (chn_status hs = homog_tables(e->ctx[i], dt[i], e->user)) {
+      e->err = "channel " + std::to_string(i) + ": " + e->ctx[i]->err;
+      return hs;
+    }
   // advance argument blocks for these step sizes (the graph reads them from device memory)
   if (e->last_dt.size() != (size_t)n || !std::equal(e->last_dt.begin(), e->last_dt.end(), dt)) {
     auto* h = reinterpret_cast<chn::AdvanceArgs<T, T>*>(e->h_adv.data());

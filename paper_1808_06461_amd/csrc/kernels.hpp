@@ -160,6 +160,25 @@ template <typename TH, typename TP> struct AdvanceArgs {
   double* mean_out;           // [0]: mean pressure gradient of the sub-step
   double mass_flux;
   double dt, nu, al, be, ga, ze;
+  // homogeneous solutions of this sub-step (k_homog): lane c holds the one
+  // with chi = 1 at wall c (c = 0 lower, 1 upper)
+  const double* hc;           // chi_h, lane-indexed [n2][2M]
+  const double* hv;           // v_h, lane-indexed [n2][2M]
+  const double* hm;           // [M][4]: D1 v_h at (lower, upper) wall for c = 0, then c = 1
+};
+
+// Homogeneous solutions of the three sub-steps for a time step dt: the
+// Helmholtz step with chi = 1 at one wall and zero forcing, then the Poisson
+// step for v, and the wall values of D1 v (influence matrix of Appendix B).
+struct HomogArgs {
+  PencilGeom g;
+  double nu, dt, be[3];
+  double* hc[3];              // per sub-step, lane-indexed [n2][2M]
+  double* hv[3];
+  double* hm[3];              // per sub-step [M][4]
+  double* S0;                 // lane-indexed scratch [n2][2M]
+  double* S1;
+  double* SU[8];              // mode-indexed scratch [n2][M]
 };
 
 struct ChiArgs {
@@ -198,6 +217,7 @@ hipError_t launch_advance_batch(const AdvanceArgs<T, T>* d, const int4* w, int n
 
 template <typename TP> hipError_t launch_recover(const RecoverArgs<TP>& a, hipStream_t st);
 template <typename TH, typename TP> hipError_t launch_advance(const AdvanceArgs<TH, TP>& a, hipStream_t st);
+hipError_t launch_homog(const HomogArgs& a, hipStream_t st);
 hipError_t launch_chi_from_v(const ChiArgs& a, hipStream_t st);
 hipError_t launch_info(const InfoArgs& a, hipStream_t st);
 hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_t st);

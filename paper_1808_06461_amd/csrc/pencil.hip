@@ -369,11 +369,13 @@ __device__ void mean_block(const AdvanceArgs<TH, TP>& a) {
 // sub-step's velocities and vorticities:
 //   S1 down : G = i(a H1 + b H3); eliminate A1 (dG) = B1 G
 //   S2 up   : finish dG; N_chi, N_omega2; implicit right-hand sides (lag 3);
-//             Helmholtz factor on the fly; eliminate chi_p, omega2, chi_h
-//   S3 down : finish chi_p, omega2, chi_h; Poisson rhs (lag 3); P factor on
-//             the fly; eliminate v_p, v_h
-//   S4 up   : finish v_p, v_h; dense wall rows of D1; 2x2 influence system
-//   S5 down : v, chi = particular + c_lo, c_hi homogeneous; eliminate A1 (dv) = B1 v
+//             Helmholtz factor on the fly; eliminate chi_p, omega2
+//   S3 down : finish chi_p, omega2; Poisson rhs (lag 3); P factor on the
+//             fly; eliminate v_p
+//   S4 up   : finish v_p; dense wall rows of D1; 2x2 influence system with
+//             the homogeneous solutions' wall derivatives (k_homog tables)
+//   S5 down : v, chi = particular + c_lo, c_hi homogeneous (tables);
+//             eliminate A1 (dv) = B1 v
 //   R2 up   : finish dv; u1, u3 by continuity; eliminate A1 (du) = B1 u
 //   R3 down : finish du1, du3; omega1 = du3 - i b v, omega3 = i a v - du1
 template <typename TH, typename TP>
@@ -385,7 +387,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
                                              const double* __restrict__ U1d, const double* __restrict__ L1u,
                                              const double* __restrict__ U1u, const double* __restrict__ clo,
                                              const double* __restrict__ chw) {
-  constexpr int D = 3, D2 = 2, D3 = 2;
+  constexpr int D = 3, D2 = 3, D3 = 3;
   const PencilGeom& g = a.g;
   const Lane L = lane_setup(g, bx);
   const int n = g.n2;
@@ -468,14 +470,13 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
   }
   // ---- S2 (up): finish dG; N_chi = -dG - k^2 H2 and the chi right-hand side
   // (acc[k] is row i + 3 - k, complete when column i - ... arrives: lag 3);
-  // Helmholtz matrix factored on the fly; eliminate chi_p, omega2 and the
-  // homogeneous chi_h (lane c = 0: 1 at the lower wall, c = 1: upper wall)
+  // Helmholtz matrix factored on the fly; eliminate chi_p and omega2
   {
     struct B { double s0, h2, chi, nco, rom; };
     double xb[3] = {0, 0, 0};
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    double ycb[3] = {0, 0, 0}, yob[3] = {0, 0, 0}, yhb[3] = {0, 0, 0};
+    double ycb[3] = {0, 0, 0}, yob[3] = {0, 0, 0};
     pipeline<D2, B>(
         n + 3,
         [&](int t, B& b) {
@@ -505,11 +506,10 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           }
           const int r = i + 3;
           if (r <= n - 1) {
-            double m7[7], rc = acc[0], ro = b.rom, rh = 0.0;
+            double m7[7], rc = acc[0], ro = b.rom;
             if (r == 0 || r == n - 1) {
 #pragma unroll
               for (int o = 0; o < 7; ++o) m7[o] = o == 3 ? 1.0 : 0.0;
-              rh = (r == 0) == (L.c == 0) ? 1.0 : 0.0;
             } else {
 #pragma unroll
               for (int o = 0; o < 7; ++o) m7[o] = hk * A2[r * 7 + o] - cb * B2[r * 7 + o];
@@ -522,7 +522,6 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
               m7[0 + d] -= lm * uh[3 - d][3];
               rc -= lm * ycb[3 - d];
               ro -= lm * yob[3 - d];
-              rh -= lm * yhb[3 - d];
             }
             const double u0 = 1.0 / m7[3];
             if (L.act && L.c == 0) {
@@ -534,7 +533,6 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             if (L.act) {
               at(LR(a.S[1], r), bcol) = rc;
               at(LR(a.S[2], r), bcol) = ro;
-              at(LR(a.S[3], r), bcol) = rh;
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -544,51 +542,44 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             uh[2][0] = u0; uh[2][1] = m7[2]; uh[2][2] = m7[1]; uh[2][3] = m7[0];
             ycb[0] = ycb[1]; ycb[1] = ycb[2]; ycb[2] = rc;
             yob[0] = yob[1]; yob[1] = yob[2]; yob[2] = ro;
-            yhb[0] = yhb[1]; yhb[1] = yhb[2]; yhb[2] = rh;
           }
           push_back(acc, 0.0);
         });
   }
-  // ---- S3
+  // ---- S3 (down): finish chi_p and omega2; Poisson right-hand side A2 chi_p
+  // (lag 3), Poisson matrix factored on the fly; eliminate v_p
   {
-    struct B { double u[4]; double s1, s2, s3; };
-    double xcb[3] = {0, 0, 0}, xob[3] = {0, 0, 0}, xhb[3] = {0, 0, 0};
-    double wcp[7] = {0, 0, 0, 0, 0, 0, 0}, wch[7] = {0, 0, 0, 0, 0, 0, 0};
+    struct B { double u[4]; double s1, s2; };
+    double xcb[3] = {0, 0, 0}, xob[3] = {0, 0, 0};
+    double wcp[7] = {0, 0, 0, 0, 0, 0, 0};
     double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    double yvb[3] = {0, 0, 0}, yhb[3] = {0, 0, 0};
+    double yvb[3] = {0, 0, 0};
     pipeline<D3, B>(
         n + 3,
         [&](int i, B& b) {
           if (i < n) {
-            const int ixr = i;
 #pragma unroll
             for (int k = 0; k < 4; ++k) b.u[k] = at(MR(a.SU[k], i), bm);
-            b.s1 = at(LR(a.S[1], ixr), bcol);
-            b.s2 = at(LR(a.S[2], ixr), bcol);
-            b.s3 = at(LR(a.S[3], ixr), bcol);
+            b.s1 = at(LR(a.S[1], i), bcol);
+            b.s2 = at(LR(a.S[2], i), bcol);
           }
         },
         [&](int i, B& b) {
-          double cp = 0.0, ch = 0.0;
+          double cp = 0.0;
           if (i < n) {
-            const int ixr = i;
             cp = back3(b.s1, b.u, xcb);
             const double om = back3(b.s2, b.u, xob);
-            ch = back3(b.s3, b.u, xhb);
             push_x(xcb, cp);
             push_x(xob, om);
-            push_x(xhb, ch);
             if (L.act) {
-              at(LR(a.om2, ixr), bcol) = L.live ? om : 0.0;
-              at(LR(a.chi, ixr), bcol) = cp;
-              at(LR(a.S[4], ixr), bcol) = ch;
+              at(LR(a.om2, i), bcol) = L.live ? om : 0.0;
+              at(LR(a.chi, i), bcol) = cp;
             }
           }
           push_back(wcp, cp);
-          push_back(wch, ch);
           const int r = i - 3;
           if (r >= 0) {
-            double p7[7], rv = 0.0, rhv = 0.0;
+            double p7[7], rv = 0.0;
             if (r == 0 || r == n - 1) {
 #pragma unroll
               for (int o = 0; o < 7; ++o) p7[o] = o == 3 ? 1.0 : 0.0;
@@ -598,7 +589,6 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
 #pragma unroll
               for (int o = 0; o < 7; ++o) {
                 rv += A2r[o] * wcp[o];
-                rhv += A2r[o] * wch[o];
                 p7[o] = B2r[o] - L.k2 * A2r[o];
               }
             }
@@ -609,7 +599,6 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
               p7[5 - d] -= lm * uh[3 - d][2];
               p7[6 - d] -= lm * uh[3 - d][3];
               rv -= lm * yvb[3 - d];
-              rhv -= lm * yhb[3 - d];
             }
             const double u0 = 1.0 / p7[3];
             if (L.act && L.c == 0) {
@@ -618,11 +607,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
               at(MR(a.SU[6], r), bm) = p7[5];
               at(MR(a.SU[7], r), bm) = p7[6];
             }
-            const int ixr = r;
-            if (L.act) {
-              at(LR(a.S[5], ixr), bcol) = rv;
-              at(LR(a.S[6], ixr), bcol) = rhv;
-            }
+            if (L.act) at(LR(a.S[5], r), bcol) = rv;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
               uh[0][k] = uh[1][k];
@@ -630,49 +615,39 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             }
             uh[2][0] = u0; uh[2][1] = p7[4]; uh[2][2] = p7[5]; uh[2][3] = p7[6];
             yvb[0] = yvb[1]; yvb[1] = yvb[2]; yvb[2] = rv;
-            yhb[0] = yhb[1]; yhb[1] = yhb[2]; yhb[2] = rhv;
           }
         });
   }
-  // ---- S4
+  // ---- S4 (up): finish v_p; dense wall rows of D1 on v_p; 2x2 influence
+  // system with the tabulated wall derivatives of the homogeneous v
   double clo_c = 0.0, chi_c = 0.0;
   {
-    struct B { double u[4]; double s5, s6; };
-    double xvb[3] = {0, 0, 0}, xhb[3] = {0, 0, 0};
-    double gplo = 0.0, gphi = 0.0, ghlo = 0.0, ghhi = 0.0;
+    struct B { double u[4]; double s5; };
+    double xvb[3] = {0, 0, 0};
+    double gplo = 0.0, gphi = 0.0;
     pipeline<D, B>(
         n,
         [&](int t, B& b) {
           const int r = n - 1 - t;
           if (r >= 0) {
-            const int ixr = r;
 #pragma unroll
             for (int k = 0; k < 4; ++k) b.u[k] = at(MR(a.SU[4 + k], r), bm);
-            b.s5 = at(LR(a.S[5], ixr), bcol);
-            b.s6 = at(LR(a.S[6], ixr), bcol);
+            b.s5 = at(LR(a.S[5], r), bcol);
           }
         },
         [&](int t, B& b) {
           const int r = n - 1 - t;
-          const int ixr = r;
           const double vp = back3(b.s5, b.u, xvb);
-          const double vh = back3(b.s6, b.u, xhb);
           push_x(xvb, vp);
-          push_x(xhb, vh);
-          if (L.act) {
-            at(LR(a.v, ixr), bcol) = vp;
-            at(LR(a.S[7], ixr), bcol) = vh;
-          }
+          if (L.act) at(LR(a.v, r), bcol) = vp;
           gplo = fma(clo[r], vp, gplo);
           gphi = fma(chw[r], vp, gphi);
-          ghlo = fma(clo[r], vh, ghlo);
-          ghhi = fma(chw[r], vh, ghhi);
         });
-    const double oglo = __shfl_xor(ghlo, 1), oghi = __shfl_xor(ghhi, 1);
-    const double m00 = L.c == 0 ? ghlo : oglo;  // lower-wall homogeneous solution, lower wall
-    const double m10 = L.c == 0 ? ghhi : oghi;  // ... upper wall
-    const double m01 = L.c == 0 ? oglo : ghlo;  // upper-wall homogeneous solution, lower wall
-    const double m11 = L.c == 0 ? oghi : ghhi;
+    const double* hm = a.hm + 4 * (size_t)L.m;
+    const double m00 = hm[0];  // lower-wall homogeneous solution, D1 at the lower wall
+    const double m10 = hm[1];  // ... at the upper wall
+    const double m01 = hm[2];  // upper-wall homogeneous solution, lower wall
+    const double m11 = hm[3];
     if (L.live) {
       const double det = m00 * m11 - m01 * m10;
       clo_c = (-gplo * m11 + gphi * m01) / det;
@@ -688,11 +663,10 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
         n + 3,
         [&](int i, B& b) {
           if (i < n) {
-            const int ixr = i;
-            b.vh = at(LR(a.S[7], ixr), bcol);
-            b.ch = at(LR(a.S[4], ixr), bcol);
-            b.vp = at(LR(a.v, ixr), bcol);
-            b.cp = at(LR(a.chi, ixr), bcol);
+            b.vh = at(LR(a.hv, i), bcol);
+            b.ch = at(LR(a.hc, i), bcol);
+            b.vp = at(LR(a.v, i), bcol);
+            b.cp = at(LR(a.chi, i), bcol);
           } else {
             b.vh = b.ch = b.vp = b.cp = 0.0;
           }
@@ -834,6 +808,143 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
   advance_body(a, q.y, g.B1, g.A2, g.B2, g.L1d, g.U1d, g.L1u, g.U1u, g.clo, g.chi);
 }
 
+// ---------------------------------------------------------------- homogeneous solutions
+// For each sub-step s of a time step dt, per mode: chi_h with chi = 1 at wall
+// c (lane c) and zero forcing from the Helmholtz step, v_h from the Poisson
+// step with right-hand side A2 chi_h, and D1 v_h at both walls.  The same
+// sweeps (directions, on-the-fly factorisation, operation order) as the
+// particular solutions in k_advance.
+__global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
+  const PencilGeom& g = a.g;
+  const Lane L = lane_setup(g, blockIdx.x);
+  const int n = g.n2;
+  const size_t st = 2 * (size_t)g.M, M = g.M;
+  const size_t col = L.col, m = L.m;
+  const double* A2 = g.A2;
+  const double* B2 = g.B2;
+  for (int s = 0; s < 3; ++s) {
+    const double cb = a.dt * a.be[s] * a.nu;
+    const double hk = 1.0 + cb * L.k2;
+    // Helmholtz, upward: factor rows, eliminate the wall forcing
+    {
+      double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+      double yhb[3] = {0, 0, 0};
+      for (int r = n - 1; r >= 0; --r) {
+        double m7[7], rh = 0.0;
+        if (r == 0 || r == n - 1) {
+#pragma unroll
+          for (int o = 0; o < 7; ++o) m7[o] = o == 3 ? 1.0 : 0.0;
+          rh = (r == 0) == (L.c == 0) ? 1.0 : 0.0;
+        } else {
+#pragma unroll
+          for (int o = 0; o < 7; ++o) m7[o] = hk * A2[r * 7 + o] - cb * B2[r * 7 + o];
+        }
+#pragma unroll
+        for (int d = 3; d >= 1; --d) {
+          const double lm = m7[3 + d] * uh[3 - d][0];
+          m7[2 + d] -= lm * uh[3 - d][1];
+          m7[1 + d] -= lm * uh[3 - d][2];
+          m7[0 + d] -= lm * uh[3 - d][3];
+          rh -= lm * yhb[3 - d];
+        }
+        const double u0 = 1.0 / m7[3];
+        if (L.act && L.c == 0) {
+          a.SU[0][r * M + m] = u0;
+          a.SU[1][r * M + m] = m7[2];
+          a.SU[2][r * M + m] = m7[1];
+          a.SU[3][r * M + m] = m7[0];
+        }
+        if (L.act) a.S0[r * st + col] = rh;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          uh[0][k] = uh[1][k];
+          uh[1][k] = uh[2][k];
+        }
+        uh[2][0] = u0; uh[2][1] = m7[2]; uh[2][2] = m7[1]; uh[2][3] = m7[0];
+        yhb[0] = yhb[1]; yhb[1] = yhb[2]; yhb[2] = rh;
+      }
+    }
+    // Helmholtz back-substitution, downward: chi_h; Poisson right-hand side
+    // A2 chi_h (lag 3), Poisson rows factored, eliminated
+    {
+      double xhb[3] = {0, 0, 0};
+      double wch[7] = {0, 0, 0, 0, 0, 0, 0};
+      double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+      double yhb[3] = {0, 0, 0};
+      for (int i = 0; i < n + 3; ++i) {
+        double ch = 0.0;
+        if (i < n) {
+          const double u[4] = {a.SU[0][i * M + m], a.SU[1][i * M + m], a.SU[2][i * M + m], a.SU[3][i * M + m]};
+          ch = back3(a.S0[i * st + col], u, xhb);
+          push_x(xhb, ch);
+          if (L.act) a.hc[s][i * st + col] = ch;
+        }
+        push_back(wch, ch);
+        const int r = i - 3;
+        if (r >= 0) {
+          double p7[7], rhv = 0.0;
+          if (r == 0 || r == n - 1) {
+#pragma unroll
+            for (int o = 0; o < 7; ++o) p7[o] = o == 3 ? 1.0 : 0.0;
+          } else {
+            const double* A2r = A2 + r * 7;
+            const double* B2r = B2 + r * 7;
+#pragma unroll
+            for (int o = 0; o < 7; ++o) {
+              rhv += A2r[o] * wch[o];
+              p7[o] = B2r[o] - L.k2 * A2r[o];
+            }
+          }
+#pragma unroll
+          for (int d = 3; d >= 1; --d) {
+            const double lm = p7[3 - d] * uh[3 - d][0];
+            p7[4 - d] -= lm * uh[3 - d][1];
+            p7[5 - d] -= lm * uh[3 - d][2];
+            p7[6 - d] -= lm * uh[3 - d][3];
+            rhv -= lm * yhb[3 - d];
+          }
+          const double u0 = 1.0 / p7[3];
+          if (L.act && L.c == 0) {
+            a.SU[4][r * M + m] = u0;
+            a.SU[5][r * M + m] = p7[4];
+            a.SU[6][r * M + m] = p7[5];
+            a.SU[7][r * M + m] = p7[6];
+          }
+          if (L.act) a.S1[r * st + col] = rhv;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            uh[0][k] = uh[1][k];
+            uh[1][k] = uh[2][k];
+          }
+          uh[2][0] = u0; uh[2][1] = p7[4]; uh[2][2] = p7[5]; uh[2][3] = p7[6];
+          yhb[0] = yhb[1]; yhb[1] = yhb[2]; yhb[2] = rhv;
+        }
+      }
+    }
+    // Poisson back-substitution, upward: v_h and D1 v_h at both walls
+    {
+      double xhb[3] = {0, 0, 0};
+      double glo = 0.0, ghi = 0.0;
+      for (int r = n - 1; r >= 0; --r) {
+        const double u[4] = {a.SU[4][r * M + m], a.SU[5][r * M + m], a.SU[6][r * M + m], a.SU[7][r * M + m]};
+        const double vh = back3(a.S1[r * st + col], u, xhb);
+        push_x(xhb, vh);
+        if (L.act) a.hv[s][r * st + col] = vh;
+        glo = fma(g.clo[r], vh, glo);
+        ghi = fma(g.chi[r], vh, ghi);
+      }
+      const double olo = __shfl_xor(glo, 1), ohi = __shfl_xor(ghi, 1);
+      if (L.act && L.c == 0) {
+        double* hm = a.hm[s] + 4 * m;
+        hm[0] = glo;
+        hm[1] = ghi;
+        hm[2] = olo;
+        hm[3] = ohi;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- set state
 __global__ void __launch_bounds__(256) k_chi_from_v(ChiArgs a) {
   const PencilGeom& g = a.g;
@@ -931,6 +1042,11 @@ template <typename TP> hipError_t launch_recover(const RecoverArgs<TP>& a, hipSt
   hipLaunchKernelGGL((k_recover<TP>), dim3(pencil_blocks(a.g.M)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
+hipError_t launch_homog(const HomogArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_homog, dim3(pencil_blocks(a.g.M)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 template <typename TH, typename TP> hipError_t launch_advance(const AdvanceArgs<TH, TP>& a, hipStream_t st) {
   hipLaunchKernelGGL((k_advance<TH, TP>), dim3(pencil_blocks(a.g.M) + 1), dim3(256), 0, st, a, a.g.B1, a.g.A2,
                      a.g.B2, a.g.L1d, a.g.U1d, a.g.L1u, a.g.U1u, a.g.clo, a.g.chi);
