@@ -29,15 +29,24 @@ def _run(cmd):
 def build(verbose=False):
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    jobs = []  # (command, object); compiled concurrently
     for src in HOST_SOURCES:  # plain host C++ (quad precision tables)
         o = os.path.join(objdir, src + ".o")
-        _run([HIPCC, "-x", "c++", *COMMON, "-c", src, "-o", o])
-        objs.append(o)
+        jobs.append(([HIPCC, "-x", "c++", *COMMON, "-c", src, "-o", o], o))
     for src in HIP_SOURCES:
         o = os.path.join(objdir, src + ".o")
-        _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", src, "-o", o])
-        objs.append(o)
+        jobs.append(([HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", src, "-o", o], o))
+    procs = [(subprocess.Popen(cmd, cwd=CSRC, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True), cmd)
+             for cmd, _ in jobs]
+    failed = None
+    for p, cmd in procs:
+        out, err = p.communicate()
+        if p.returncode != 0 and failed is None:
+            sys.stderr.write(" ".join(cmd) + "\n" + out + err)
+            failed = cmd[-1]
+    if failed:
+        raise RuntimeError(f"build step failed: {failed}")
+    objs = [o for _, o in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, *DEVICE, "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -253,17 +253,18 @@ int z_lines_max(const chn_ctx* x) {
   return K;
 }
 // Default schedule: 16 z lines per workgroup (capped), two x rows when six lines fit.
+bool plan_fits(const chn_ctx* x, int xrows, int zK, int ych);
 void default_plan(chn_ctx* x) {
-  const int cb = x->mixed ? 8 : 16;
   x->zK = std::max(1, std::min(16, z_lines_max(x)));
   x->ychunk = x->planes_only || x->cfg.plane_chunk > 0 ? x->cfg.plane_chunk : x->n2;
-  x->xrows = chn::xpass_two_rows(x->p1, cb) && (size_t)6 * (x->p1 + 1) * cb <= (size_t)x->lds_max ? 2 : 1;
+  x->xrows = plan_fits(x, 2, x->zK, x->ychunk) ? 2 : 1;
 }
 bool plan_fits(const chn_ctx* x, int xrows, int zK, int ych) {
   const int cb = x->mixed ? 8 : 16;
   if (ych < 1 || ych > x->ychunk_max) return false;
   if (zK < 1 || zK > z_lines_max(x)) return false;
-  if (xrows == 2) return chn::xpass_two_rows(x->p1, cb) && (size_t)6 * (x->p1 + 1) * cb <= (size_t)x->lds_max;
+  if (xrows == 2 || xrows == 4 || xrows == 8)
+    return chn::staging_for(x->plan1, 3 * xrows, cb) > 0 && (size_t)3 * xrows * (x->p1 + 1) * cb <= (size_t)x->lds_max;
   if (xrows == 1) return chn::xrow_threads(x->p1, cb) > 0 && (size_t)x->p1 * cb <= (size_t)x->lds_max;
   return false;
 }
@@ -606,6 +607,8 @@ struct chn_ens {
   int4 *d_wz = nullptr, *d_wx = nullptr, *d_wa = nullptr;
   int nz = 0, nx = 0, na = 0;
   size_t lds_z = 0, lds_x = 0;
+  int mz = 0, mx = 0;  // transform staging of the batched z and x passes
+  int rz = 2;          // rows per batched x-pass workgroup
   std::vector<char> h_adv;    // host copy of the advance blocks (dt dependent)
   std::vector<double> last_dt;
   hipGraph_t graph = nullptr;
@@ -671,12 +674,38 @@ template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
   std::vector<chn::XpassArgs<T>> xa(n);
   std::vector<chn::ZfwdArgs<T, T>> fa(n);
   std::vector<int4> wz, wx, wa;
+  const int cb = (int)sizeof(typename Ty<T>::c);
+  // rows per x-pass workgroup: the most (8, 4, 2) whose transforms every
+  // channel holds in the smallest staging size (short rows fill workgroups)
+  e->rz = 2;
+  for (int rz : {8, 4}) {
+    bool ok = true;
+    for (int i = 0; i < n && ok; ++i) {
+      const int m = chn::staging_for(e->ctx[i]->plan1, 3 * rz, cb);
+      ok = m > 0 && m <= (cb == 8 ? 16 : 8) &&
+           (size_t)3 * rz * (e->ctx[i]->p1 + 1) * cb <= (size_t)e->ctx[i]->lds_max;
+    }
+    if (ok) {
+      e->rz = rz;
+      break;
+    }
+  }
   e->lds_z = e->lds_x = 0;
+  e->mz = e->mx = 0;
   for (int i = 0; i < n; ++i) {
     chn_ctx* x = e->ctx[i];
     plane_args<T, T>(x, x->ph, false, x->H, za[i], xa[i], fa[i]);
-    e->lds_z = std::max(e->lds_z, (size_t)za[i].K * za[i].lstride * sizeof(typename Ty<T>::c));
-    e->lds_x = std::max(e->lds_x, (size_t)6 * xa[i].lstride * sizeof(typename Ty<T>::c));
+    xa[i].rows = e->rz;
+    const int mz = chn::staging_for(x->plan3, za[i].K, cb);
+    const int mx = chn::staging_for(x->plan1, 3 * e->rz, cb);
+    if (!mz || !mx) {
+      e->err = "channel " + std::to_string(i) + ": transform staging does not fit";
+      return CHN_EINVAL;
+    }
+    e->mz = std::max(e->mz, mz);
+    e->mx = std::max(e->mx, mx);
+    e->lds_z = std::max(e->lds_z, (size_t)za[i].K * za[i].lstride * cb);
+    e->lds_x = std::max(e->lds_x, (size_t)3 * e->rz * xa[i].lstride * cb);
   }
   for (int c : order) {
     chn_ctx* x = e->ctx[c];
@@ -684,7 +713,7 @@ template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
     for (int y = 0; y < x->n2; ++y)
       for (int b = 0; b < nbz; ++b) wz.push_back(make_int4(c, b, y, 0));
     for (int y = 0; y < x->n2; ++y)
-      for (int b = 0; b < x->p3 / 2; ++b) wx.push_back(make_int4(c, b, y, 0));
+      for (int b = 0; b < (x->p3 + e->rz - 1) / e->rz; ++b) wx.push_back(make_int4(c, b, y, 0));
     const int nb = (int)((2 * (size_t)x->M + 255) / 256);
     wa.push_back(make_int4(c, 0, 0, 1));  // mean-mode workgroup
     for (int b = 0; b < nb; ++b) wa.push_back(make_int4(c, b, 0, 0));
@@ -782,6 +811,9 @@ template <typename T> chn_status ens_step(chn_ens* e, const double* dt, int nste
   bp.nx = e->nx;
   bp.lds_z = e->lds_z;
   bp.lds_x = e->lds_x;
+  bp.mz = e->mz;
+  bp.mx = e->mx;
+  bp.rz = e->rz;
   const auto* adv = reinterpret_cast<const chn::AdvanceArgs<T, T>*>(e->d_adv);
   auto one_step = [&]() -> hipError_t {
     for (int s = 0; s < 3; ++s) {
@@ -843,11 +875,6 @@ chn_status chn_create(const chn_config* cfg, void* d_ws, size_t ws_bytes, chn_ct
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
       x->lds_max = lds;
-    default_plan(x);
-    if (!plan_fits(x, x->xrows, x->zK, x->ychunk)) {
-      delete x;
-      return fail(nullptr, CHN_EINVAL, "plane too large for the x- or z-pass LDS tiles on this device");
-    }
   }
   x->y.resize(x->n2);
   if (cfg->y) std::memcpy(x->y.data(), cfg->y, sizeof(double) * x->n2);
@@ -879,6 +906,11 @@ chn_status chn_create(const chn_config* cfg, void* d_ws, size_t ws_bytes, chn_ct
   if (!chn::host::fft_plan(x->p1, &x->plan1, &tw1) || !chn::host::fft_plan(x->p3, &x->plan3, &tw3)) {
     delete x;
     return fail(nullptr, CHN_EINVAL, "FFT length not supported");
+  }
+  default_plan(x);
+  if (!plan_fits(x, x->xrows, x->zK, x->ychunk)) {
+    delete x;
+    return fail(nullptr, CHN_EINVAL, "plane too large for the x- or z-pass LDS tiles on this device");
   }
   auto up = [&](double* d, const std::vector<double>& h) {
     return hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, x->stream);
@@ -1118,7 +1150,7 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
     if (c >= 1 && c <= x->ychunk_max && std::find(chunks.begin(), chunks.end(), c) == chunks.end()) chunks.push_back(c);
   const bool has_fixed = chn::plan_is_576(x->plan1) || chn::plan_is_576(x->plan3);
   for (int fx = 0; fx <= (has_fixed ? 1 : 0); ++fx)
-    for (int xr = 2; xr >= 1; --xr)
+    for (int xr : {8, 4, 2, 1})
       for (int K : {1, 2, 4, 8, 12, 16, kmax})
         for (int c : chunks)
           if (plan_fits(x, xr, K, c) && std::none_of(cand.begin(), cand.end(), [&](const Cand& q) {

@@ -35,7 +35,7 @@ template <typename T> struct XpassArgs {
   float* rowcfl;       // [n2][p3] max over x of |u1|/dx + |u2|/dy + |u3|/dz
   double inv_dx, inv_dz;
   const double* inv_dy;  // [n2]
-  int rows;              // rows per workgroup: 2 (six lines in LDS) or 1 (long rows)
+  int rows;              // rows per workgroup: 2, 4, 8 (3 rows lines in LDS) or 1 (long rows)
   int y0, ny;            // buf holds planes y0 .. y0 + ny - 1 (from its plane 0)
   int fixed;             // nonzero: compile-time radix schedule where one exists for the plan
 };
@@ -210,7 +210,12 @@ template <typename T> struct BatchPlan {
   const int4* wx;   // work list of the x pass
   int nz, nx;       // work items
   size_t lds_z, lds_x;
+  int mz, mx;       // transform staging (complex values per thread) of the z and x passes
+  int rz;           // rows per x-pass workgroup
 };
+// Smallest staging size that holds every pass of nlines lines over 256 threads
+// (bytes_per_value: 8 for complex float, 16 for complex double); 0 if none.
+int staging_for(const FftPlan& pl, int nlines, int bytes_per_value);
 template <typename T> hipError_t launch_plane_batch(const BatchPlan<T>& b, hipStream_t st);
 template <typename T>
 hipError_t launch_advance_batch(const AdvanceArgs<T, T>* d, const int4* w, int nblocks, hipStream_t st);

@@ -69,27 +69,35 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
   }
 }
 
-template <typename T, int MAXV, int FN = 0>
+// x pass over RZ rows (z0 .. z0 + RZ - 1) of one plane per workgroup: line
+// 3 row + pair holds field(2 pair) + i field(2 pair + 1), Hermitian-extended;
+// after the products, line row holds H1 + i H2 of that row and line RZ + j
+// holds H3 of rows 2j (real part) and 2j + 1 (imaginary part).  Rows beyond
+// p3 (a ragged last group) are zero and not stored.
+template <typename T, int MAXV, int FN = 0, int RZ = 2>
 __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
   const int y = by;         // plane of buf
   const int yg = a.y0 + by;  // global plane (row sums, CFL, mesh)
-  const int z0 = bx * 2;
+  const int z0 = bx * RZ;
   const int n1h = a.d.n1h, p1 = a.d.p1, p3 = a.d.p3, LS = a.lstride;
   const int npad = p1 - 2 * n1h + 1;
   const c2<T> zero = mk<T>(T(0), T(0));
-  // --- load: line 3*row + pair holds field(2 pair) + i field(2 pair + 1), Hermitian-extended
-  for (int e = threadIdx.x; e < 6 * npad; e += blockDim.x) {
+  // --- load
+  for (int e = threadIdx.x; e < 3 * RZ * npad; e += blockDim.x) {
     const int l = e / npad;
     lds[l * LS + n1h + (e - l * npad)] = zero;
   }
-  for (int e = threadIdx.x; e < 6 * n1h; e += blockDim.x) {
+  for (int e = threadIdx.x; e < 3 * RZ * n1h; e += blockDim.x) {
     const int l = e / n1h, k = e - l * n1h;
     const int row = l / 3, pr = l - row * 3;
-    const size_t base = ((size_t)(y * 6 + 2 * pr) * p3 + z0 + row) * n1h + k;
-    const c2<T> X = a.buf[base];
-    const c2<T> Y = a.buf[base + (size_t)p3 * n1h];
+    c2<T> X = zero, Y = zero;
+    if (z0 + row < p3) {
+      const size_t base = ((size_t)(y * 6 + 2 * pr) * p3 + z0 + row) * n1h + k;
+      X = a.buf[base];
+      Y = a.buf[base + (size_t)p3 * n1h];
+    }
     c2<T>* line = lds + l * LS;
     if (k == 0) {
       line[0] = mk<T>(X.x, Y.x);
@@ -99,14 +107,16 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
     }
   }
   __syncthreads();
-  fft_lines<T, MAXV, FN>(lds, LS, 6, a.plan, a.tw, +1);
+  fft_lines<T, MAXV, FN>(lds, LS, 3 * RZ, a.plan, a.tw, +1);
   // --- products, row sums and CFL
-  double s1[2] = {0.0, 0.0}, s3[2] = {0.0, 0.0}, cf[2] = {0.0, 0.0};
+  double s1[RZ], s3[RZ], cf[RZ];
+#pragma unroll
+  for (int row = 0; row < RZ; ++row) s1[row] = s3[row] = cf[row] = 0.0;
   const double idy = a.inv_dy[yg];
   for (int x = threadIdx.x; x < p1; x += blockDim.x) {
-    T h3[2];
+    T h3[RZ];
 #pragma unroll
-    for (int row = 0; row < 2; ++row) {
+    for (int row = 0; row < RZ; ++row) {
       const c2<T> Z0 = lds[(3 * row + 0) * LS + x];
       const c2<T> Z1 = lds[(3 * row + 1) * LS + x];
       const c2<T> Z2 = lds[(3 * row + 2) * LS + x];
@@ -118,57 +128,57 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
       s3[row] += (double)h3[row];
       const double c = fabs((double)u1) * a.inv_dx + fabs((double)u2) * idy + fabs((double)u3) * a.inv_dz;
       cf[row] = fmax(cf[row], c);
-      lds[(row)*LS + x] = mk<T>(H1, H2);  // line 0: row 0, line 1: row 1 (read above already)
+      // line `row` belongs to row row / 3 <= row, already read at this x
+      lds[row * LS + x] = mk<T>(H1, H2);
     }
-    lds[2 * LS + x] = mk<T>(h3[0], h3[1]);
-  }
-  // note: line 1 (row 0 pair 1) was read by this same thread before being overwritten
-  // block reductions (wave64 shuffles, then across the 4 waves)
-  double vals[6] = {s1[0], s1[1], s3[0], s3[1], cf[0], cf[1]};
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    double v = vals[q];
+    for (int j = 0; j < RZ / 2; ++j) lds[(RZ + j) * LS + x] = mk<T>(h3[2 * j], h3[2 * j + 1]);
+  }
+  // block reductions: wave64 shuffles, then across the waves through LDS
+  __shared__ double red[3 * RZ][4];
+  const int wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 3 * RZ; ++q) {
+    const int row = q % RZ, kind = q / RZ;
+    double v = kind == 0 ? s1[row] : (kind == 1 ? s3[row] : cf[row]);
     for (int off = 32; off > 0; off >>= 1) {
       const double o = __shfl_xor(v, off);
-      v = q < 4 ? v + o : fmax(v, o);
+      v = kind < 2 ? v + o : fmax(v, o);
     }
-    vals[q] = v;
-  }
-  __shared__ double red6[6][4];
-  const int wid = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int q = 0; q < 6; ++q) red6[q][wid] = vals[q];
+    if ((threadIdx.x & 63) == 0) red[q][wid] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 2) {
+  if (threadIdx.x < RZ && z0 + (int)threadIdx.x < p3) {
     const int row = threadIdx.x;
     const int nw = blockDim.x >> 6;
     double t1 = 0.0, t3 = 0.0, tc = 0.0;
     for (int w = 0; w < nw; ++w) {
-      t1 += red6[0 + row][w];
-      t3 += red6[2 + row][w];
-      tc = fmax(tc, red6[4 + row][w]);
+      t1 += red[row][w];
+      t3 += red[RZ + row][w];
+      tc = fmax(tc, red[2 * RZ + row][w]);
     }
     const size_t o = (size_t)yg * p3 + z0 + row;
     a.rowsum[o] = t1;
     a.rowsum[(size_t)a.d.n2 * p3 + o] = t3;
     a.rowcfl[o] = tc;
   }
-  fft_lines<T, MAXV, FN>(lds, LS, 3, a.plan, a.tw, -1);
+  fft_lines<T, MAXV, FN>(lds, LS, RZ + RZ / 2, a.plan, a.tw, -1);
   // --- unpack two real spectra per line, truncate, store in place over fields 0..2
-  for (int e = threadIdx.x; e < 3 * n1h; e += blockDim.x) {
+  for (int e = threadIdx.x; e < (RZ + RZ / 2) * n1h; e += blockDim.x) {
     const int l = e / n1h, k = e - l * n1h;
     const c2<T> W = lds[l * LS + k];
     const c2<T> Wm = lds[l * LS + (k == 0 ? 0 : p1 - k)];
     const c2<T> P = mk<T>(T(0.5) * (W.x + Wm.x), T(0.5) * (W.y - Wm.y));   // (W_k + conj W_m)/2
     const c2<T> Q = mk<T>(T(0.5) * (W.y + Wm.y), T(-0.5) * (W.x - Wm.x));  // (W_k - conj W_m)/(2i)
-    if (l < 2) {  // row l: H1 = P, H2 = Q
-      a.buf[((size_t)(y * 6 + 0) * p3 + z0 + l) * n1h + k] = P;
-      a.buf[((size_t)(y * 6 + 1) * p3 + z0 + l) * n1h + k] = Q;
-    } else {      // H3 of rows 0 and 1
-      a.buf[((size_t)(y * 6 + 2) * p3 + z0 + 0) * n1h + k] = P;
-      a.buf[((size_t)(y * 6 + 2) * p3 + z0 + 1) * n1h + k] = Q;
+    if (l < RZ) {  // row l: H1 = P, H2 = Q
+      if (z0 + l < p3) {
+        a.buf[((size_t)(y * 6 + 0) * p3 + z0 + l) * n1h + k] = P;
+        a.buf[((size_t)(y * 6 + 1) * p3 + z0 + l) * n1h + k] = Q;
+      }
+    } else {       // H3 of rows 2j and 2j + 1
+      const int r0 = 2 * (l - RZ);
+      if (z0 + r0 < p3) a.buf[((size_t)(y * 6 + 2) * p3 + z0 + r0) * n1h + k] = P;
+      if (z0 + r0 + 1 < p3) a.buf[((size_t)(y * 6 + 2) * p3 + z0 + r0 + 1) * n1h + k] = Q;
     }
   }
 }
@@ -326,8 +336,8 @@ __global__ void __launch_bounds__(256) k_zinv(ZinvArgs<T> a) {
   const int2 t = z_tile();
   zinv_body<T, MAXV, FN>(a, t.x, t.y);
 }
-template <typename T, int MAXV, int FN>
-__global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) { xpass_body<T, MAXV, FN>(a, blockIdx.x, blockIdx.y); }
+template <typename T, int MAXV, int FN, int RZ>
+__global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) { xpass_body<T, MAXV, FN, RZ>(a, blockIdx.x, blockIdx.y); }
 template <typename T, int NT, int QX, int MAXV>
 __global__ void __launch_bounds__(NT) k_xrow(XpassArgs<T> a) { xrow_body<T, NT, QX, MAXV>(a, blockIdx.x, blockIdx.y); }
 template <typename T, typename TO, int MAXV, int FN>
@@ -341,10 +351,10 @@ __global__ void __launch_bounds__(256) k_zinv_batch(const ZinvArgs<T>* __restric
   const int4 q = w[blockIdx.x];
   zinv_body<T, MAXV>(d[q.x], q.y, q.z);
 }
-template <typename T, int MAXV>
+template <typename T, int MAXV, int RZ>
 __global__ void __launch_bounds__(256) k_xpass_batch(const XpassArgs<T>* __restrict__ d, const int4* __restrict__ w) {
   const int4 q = w[blockIdx.x];
-  xpass_body<T, MAXV>(d[q.x], q.y, q.z);
+  xpass_body<T, MAXV, 0, RZ>(d[q.x], q.y, q.z);
 }
 template <typename T, int MAXV>
 __global__ void __launch_bounds__(256) k_zfwd_batch(const ZfwdArgs<T, T>* __restrict__ d, const int4* __restrict__ w) {
@@ -421,15 +431,24 @@ bool xpass_two_rows(int p1, int bytes_per_value) {
   return 6 * p1 <= (bytes_per_value == 8 ? 48 : 24) * 256;
 }
 
+#define CHN_ROWS(rz, ...)                                   \
+  do {                                                      \
+    if (rz == 2) { constexpr int RZ = 2; __VA_ARGS__; }     \
+    else if (rz == 4) { constexpr int RZ = 4; __VA_ARGS__; } \
+    else if (rz == 8) { constexpr int RZ = 8; __VA_ARGS__; } \
+    else return hipErrorInvalidValue;                       \
+  } while (0)
+
 template <typename T>
 hipError_t launch_xpass(const XpassArgs<T>& a, hipStream_t st) {
-  if (a.rows == 2) {
-    if (!xpass_two_rows(a.d.p1, (int)sizeof(c2<T>)) || a.d.p3 % 2) return hipErrorInvalidValue;
-    const int m = pick_staging<T>(a.plan, 6, 256);
-    dim3 grid(a.d.p3 / 2, a.ny);
-    size_t sh = (size_t)6 * a.lstride * sizeof(c2<T>);
-    if (a.fixed && plan_is_576(a.plan)) CHN_STAGED(T, m, hipLaunchKernelGGL((k_xpass<T, MV, 576>), grid, dim3(256), sh, st, a));
-    else CHN_STAGED(T, m, hipLaunchKernelGGL((k_xpass<T, MV, 0>), grid, dim3(256), sh, st, a));
+  if (a.rows >= 2) {
+    const int m = pick_staging<T>(a.plan, 3 * a.rows, 256);
+    dim3 grid((a.d.p3 + a.rows - 1) / a.rows, a.ny);
+    size_t sh = (size_t)3 * a.rows * a.lstride * sizeof(c2<T>);
+    if (a.fixed && plan_is_576(a.plan))
+      CHN_ROWS(a.rows, CHN_STAGED(T, m, hipLaunchKernelGGL((k_xpass<T, MV, 576, RZ>), grid, dim3(256), sh, st, a)));
+    else
+      CHN_ROWS(a.rows, CHN_STAGED(T, m, hipLaunchKernelGGL((k_xpass<T, MV, 0, RZ>), grid, dim3(256), sh, st, a)));
     return hipGetLastError();
   }
   constexpr int QX = XrowCfg<T>::QX, XM = XrowCfg<T>::MV;
@@ -453,16 +472,19 @@ hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+int staging_for(const FftPlan& pl, int nlines, int bytes_per_value) {
+  return bytes_per_value == 8 ? pick_staging<float>(pl, nlines, 256) : pick_staging<double>(pl, nlines, 256);
+}
+
 template <typename T>
 hipError_t launch_plane_batch(const BatchPlan<T>& b, hipStream_t st) {
-  constexpr int MV = FftMaxv<T>::v;
-  hipLaunchKernelGGL((k_zinv_batch<T, MV>), dim3(b.nz), dim3(256), b.lds_z, st, b.zinv, b.wz);
+  CHN_STAGED(T, b.mz, hipLaunchKernelGGL((k_zinv_batch<T, MV>), dim3(b.nz), dim3(256), b.lds_z, st, b.zinv, b.wz));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_xpass_batch<T, MV>), dim3(b.nx), dim3(256), b.lds_x, st, b.xpass, b.wx);
+  CHN_ROWS(b.rz, CHN_STAGED(T, b.mx, hipLaunchKernelGGL((k_xpass_batch<T, MV, RZ>), dim3(b.nx), dim3(256), b.lds_x, st, b.xpass, b.wx)));
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_zfwd_batch<T, MV>), dim3(b.nz), dim3(256), b.lds_z, st, b.zfwd, b.wz);
+  CHN_STAGED(T, b.mz, hipLaunchKernelGGL((k_zfwd_batch<T, MV>), dim3(b.nz), dim3(256), b.lds_z, st, b.zfwd, b.wz));
   return hipGetLastError();
 }
 template hipError_t launch_plane_batch<double>(const BatchPlan<double>&, hipStream_t);
