@@ -211,6 +211,39 @@ def c3_run(reps=3):
             "pencils": pencils}
 
 
+def c5_run(reps=5, precision="mixed"):
+    """The low-storage stage on the 1536 x 385 x 1152 field (Re_tau ~ 950): cut-off
+    kc = (96, 72), filtered products and tau_ij on the 432 x 324 grid; median of reps."""
+    import torch
+
+    import synth
+    from paper_1808_06461_amd import Channel
+    c = synth.CASES["c5"]
+    v, om, U1, U3, y = synth.turbulent_field(c)
+    ch = Channel(c.n1, c.n2, c.n3, c.lx, c.lz, c.re_b, mass_flux=c.mass_flux, precision=precision, y=y)
+    ch.set_state(*(torch.from_numpy(a) for a in (v, om, U1, U3)))
+    del v, om
+    kcx, kcz, q1, q3 = c.n1 // 16, c.n3 // 16, 432, 324
+    ub, uu, tau = ch.filter_and_stress(kcx, kcz, q1, q3)  # warm-up, allocates the outputs
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ch.filter_and_stress(kcx, kcz, q1, q3)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ch.close()
+    del ub, uu, tau
+    torch.cuda.empty_cache()
+    times.sort()
+    G = c.n1 * c.n2 * c.n3
+    ms = times[len(times) // 2]
+    return {"workload": f"low-storage stage, {c.n1}x{c.n2}x{c.n3}, kc=({kcx},{kcz}), q=({q1},{q3})",
+            "precision": precision, "ms_median": round(ms, 3), "ms_min": round(times[0], 3),
+            "grid_points_per_s": G / (ms / 1e3)}
+
+
 def cpu_baseline(case, v, om, U1, U3, y):
     """The oracle on the host: one RK3 sub-step of the same workload, scaled to a step."""
     from oracle import kmm
@@ -234,6 +267,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the per-phase timing of the Re_tau 5300 share")
+    ap.add_argument("--no-c5", action="store_true", help="skip the timing of the low-storage stage")
     ap.add_argument("--plan", default=None, metavar="XROWS,ZLINES,YCHUNK[,FIXED]",
                     help="fixed plane-phase schedule instead of the autotuner (for profiling one schedule)")
     ap.add_argument("--source-hash", default=None, metavar="KIND",
@@ -329,6 +363,9 @@ def main():
     if not args.no_c3:
         print("[bench] Re_tau 5300 share: plane slab and pencil share", file=sys.stderr, flush=True)
         out["c3_share"] = c3_run()
+    if not args.no_c5:
+        print("[bench] low-storage stage, 1536x385x1152", file=sys.stderr, flush=True)
+        out["c5_filter"] = c5_run()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, one sub-step)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, v, om, U1, U3, y)

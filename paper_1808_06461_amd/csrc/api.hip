@@ -242,12 +242,16 @@ template <> struct Ty<double> { using c = double2; };
 template <> struct Ty<float> { using c = float2; };
 
 
+// LDS line stride (complex elements) of the plane kernels for lines of p
+// points: one slot skipped after every 8 elements (bank spreading).
+int plane_lds_stride(int p) { return p + p / 8 + 1; }
+
 // Largest number of z lines one workgroup can transform (staging registers and LDS).
 int z_lines_max(const chn_ctx* x) {
   const int maxv = x->mixed ? 48 : 24;
   const int cb = x->mixed ? 8 : 16;
   int K = maxv * 256 / x->p3;
-  const int byl = x->lds_max / ((x->p3 + 1) * cb);
+  const int byl = x->lds_max / (plane_lds_stride(x->p3) * cb);
   if (K > byl) K = byl;
   if (K > x->n1h) K = x->n1h;
   return K;
@@ -264,7 +268,8 @@ bool plan_fits(const chn_ctx* x, int xrows, int zK, int ych) {
   if (ych < 1 || ych > x->ychunk_max) return false;
   if (zK < 1 || zK > z_lines_max(x)) return false;
   if (xrows == 2 || xrows == 4 || xrows == 8)
-    return chn::staging_for(x->plan1, 3 * xrows, cb) > 0 && (size_t)3 * xrows * (x->p1 + 1) * cb <= (size_t)x->lds_max;
+    return chn::staging_for(x->plan1, 3 * xrows, cb) > 0 &&
+           (size_t)3 * xrows * plane_lds_stride(x->p1) * cb <= (size_t)x->lds_max;
   if (xrows == 1) return chn::xrow_threads(x->p1, cb) > 0 && (size_t)x->p1 * cb <= (size_t)x->lds_max;
   return false;
 }
@@ -283,7 +288,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   za.plan = x->plan3;
   za.d = x->dims;
   za.K = K;
-  za.lstride = x->p3 + 1;
+  za.lstride = plane_lds_stride(x->p3);
   za.nfields = 6;
   za.nslot = 6;
   za.y0 = 0;
@@ -294,7 +299,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   xa.tw = reinterpret_cast<const C*>(x->tw1);
   xa.plan = x->plan1;
   xa.d = x->dims;
-  xa.lstride = x->p1 + 1;
+  xa.lstride = plane_lds_stride(x->p1);
   xa.rowsum = x->rowsum;
   xa.rowcfl = x->rowcfl;
   xa.inv_dx = x->n1 / x->cfg.lx;
@@ -311,7 +316,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   fa.plan = x->plan3;
   fa.d = x->dims;
   fa.K = K;
-  fa.lstride = x->p3 + 1;
+  fa.lstride = plane_lds_stride(x->p3);
   fa.scale = 1.0 / ((double)x->p1 * x->p3);
   fa.y0 = 0;
   fa.ny = x->n2;
@@ -507,12 +512,13 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   za.plan = x->plan3;
   za.d = x->dims;
   za.K = lines(p3, n1h);
-  za.lstride = p3 + 1;
+  za.lstride = plane_lds_stride(p3);
   za.nfields = 3;
   za.nslot = nslot;
   za.zero_mean = 1;
   za.y0 = 0;
   za.ny = n2;
+  while (za.K > 1 && (size_t)za.K * za.lstride * 16 > (size_t)x->lds_max) --za.K;
   if ((size_t)za.K * za.lstride * 16 > (size_t)x->lds_max) return fail(x, CHN_EUNSUPPORTED, "z lines exceed LDS");
   HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_zinv<double>(za, x->stream); }));
   // 3. products and float64 forward in x
@@ -683,7 +689,7 @@ template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
     for (int i = 0; i < n && ok; ++i) {
       const int m = chn::staging_for(e->ctx[i]->plan1, 3 * rz, cb);
       ok = m > 0 && m <= (cb == 8 ? 16 : 8) &&
-           (size_t)3 * rz * (e->ctx[i]->p1 + 1) * cb <= (size_t)e->ctx[i]->lds_max;
+           (size_t)3 * rz * plane_lds_stride(e->ctx[i]->p1) * cb <= (size_t)e->ctx[i]->lds_max;
     }
     if (ok) {
       e->rz = rz;
@@ -1145,9 +1151,12 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
   struct Cand { int xr, K, ych, fx; };
   std::vector<Cand> cand;
   const int kmax = z_lines_max(x);
+  // planes per launch: the largest, and even splits of the planes into 2..12 launches
   std::vector<int> chunks;
-  for (int c : {x->ychunk_max, 64, 32, 16})
-    if (c >= 1 && c <= x->ychunk_max && std::find(chunks.begin(), chunks.end(), c) == chunks.end()) chunks.push_back(c);
+  for (int parts : {1, 2, 4, 8, 12}) {
+    const int c = std::min(x->ychunk_max, (x->n2 + parts - 1) / parts);
+    if (c >= 1 && std::find(chunks.begin(), chunks.end(), c) == chunks.end()) chunks.push_back(c);
+  }
   const bool has_fixed = chn::plan_is_576(x->plan1) || chn::plan_is_576(x->plan3);
   for (int fx = 0; fx <= (has_fixed ? 1 : 0); ++fx)
     for (int xr : {8, 4, 2, 1})

@@ -68,10 +68,15 @@ __device__ __forceinline__ unsigned qdiv(unsigned x, unsigned d, unsigned m) {
   return m == 0 ? x : __umulhi(x, m);
 }
 
+// LDS element index within a line: with PAD one slot is skipped after every 8
+// elements, which spreads the stride-R and stride-R Ns accesses of the
+// Stockham writes over the banks (lines are then lx(N - 1) + 1 long at least).
+template <bool PAD> __device__ __forceinline__ int lx(int i) { return PAD ? i + (i >> 3) : i; }
+
 // One radix-R pass over all lines.  NB = butterflies per thread (compile
 // time, so the staging array lives in registers); the caller guarantees
 // nlines * N / R <= NB * blockDim.x.
-template <typename T, int R, int NB>
+template <typename T, int R, int NB, bool PAD = false>
 __device__ __forceinline__ void stockham_pass(c2<T>* lds, int lstride, int nlines, int N, int Ns, unsigned mb,
                                               unsigned mk, const c2<T>* __restrict__ tw, int sgn) {
   const int nbl = N / R;
@@ -84,9 +89,9 @@ __device__ __forceinline__ void stockham_pass(c2<T>* lds, int lstride, int nline
     if (g < total) {
       const int line = (int)qdiv((unsigned)g, (unsigned)nbl, mb);
       const int j = g - line * nbl;
-      const c2<T>* src = lds + line * lstride + j;
+      const c2<T>* src = lds + line * lstride;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = src[r * nbl];
+      for (int r = 0; r < R; ++r) v[q][r] = src[lx<PAD>(j + r * nbl)];
     }
   }
   __syncthreads();
@@ -106,9 +111,10 @@ __device__ __forceinline__ void stockham_pass(c2<T>* lds, int lstride, int nline
         }
       }
       dft<T, R>(v[q], sgn);
-      c2<T>* dst = lds + line * lstride + (j - k) * R + k;
+      c2<T>* dst = lds + line * lstride;
+      const int d0 = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
+      for (int r = 0; r < R; ++r) dst[lx<PAD>(d0 + r * Ns)] = v[q][r];
     }
   }
   __syncthreads();
@@ -117,7 +123,7 @@ __device__ __forceinline__ void stockham_pass(c2<T>* lds, int lstride, int nline
 // The same pass with the line length and Ns known at compile time: divisions
 // by constants, LDS and twiddle offsets folded into the instructions.  Same
 // arithmetic, in the same order, as the runtime pass.
-template <typename T, int R, int NB, int N, int NS>
+template <typename T, int R, int NB, int N, int NS, bool PAD = false>
 __device__ __forceinline__ void stockham_pass_c(c2<T>* lds, int lstride, int nlines, const c2<T>* __restrict__ tw,
                                                 int sgn) {
   constexpr int nbl = N / R;
@@ -130,9 +136,15 @@ __device__ __forceinline__ void stockham_pass_c(c2<T>* lds, int lstride, int nli
     if (g < total) {
       const int line = (unsigned)g / (unsigned)nbl;
       const int j = g - line * nbl;
-      const c2<T>* src = lds + line * lstride + j;
+      if constexpr (!PAD || nbl % 8 == 0) {  // lx(j + r nbl) = lx(j) + r lx(nbl)
+        const c2<T>* src = lds + line * lstride + lx<PAD>(j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = src[r * nbl];
+        for (int r = 0; r < R; ++r) v[q][r] = src[r * (PAD ? nbl + nbl / 8 : nbl)];
+      } else {
+        const c2<T>* src = lds + line * lstride;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = src[lx<PAD>(j + r * nbl)];
+      }
     }
   }
   __syncthreads();
@@ -152,9 +164,20 @@ __device__ __forceinline__ void stockham_pass_c(c2<T>* lds, int lstride, int nli
         }
       }
       dft<T, R>(v[q], sgn);
-      c2<T>* dst = lds + line * lstride + (j - k) * R + k;
+      const int d0 = (j - k) * R + k;
+      if constexpr (!PAD || NS % 8 == 0) {  // lx(d0 + r NS) = lx(d0) + r lx(NS)
+        c2<T>* dst = lds + line * lstride + lx<PAD>(d0);
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * NS] = v[q][r];
+        for (int r = 0; r < R; ++r) dst[r * (PAD ? NS + NS / 8 : NS)] = v[q][r];
+      } else if constexpr (NS == 1 && R == 8) {  // d0 = 8 j: lx(d0 + r) = lx(d0) + r
+        c2<T>* dst = lds + line * lstride + lx<PAD>(d0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[r] = v[q][r];
+      } else {
+        c2<T>* dst = lds + line * lstride;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[lx<PAD>(d0 + r * NS)] = v[q][r];
+      }
     }
   }
   __syncthreads();
@@ -162,15 +185,15 @@ __device__ __forceinline__ void stockham_pass_c(c2<T>* lds, int lstride, int nli
 
 // Full transform of nlines lines of length pl.n.  MAXV = complex values
 // staged per thread (a multiple of 24); requires nlines * pl.n <= MAXV * blockDim.x.
-template <typename T, int MAXV, int FN = 0>
+template <typename T, int MAXV, int FN = 0, bool PAD = false>
 __device__ __forceinline__ void fft_lines(c2<T>* lds, int lstride, int nlines, const FftPlan& pl,
                           const c2<T>* __restrict__ tw, int sgn) {
   // 576 = 3/2 x 384 (the 384-mode directions): radices 8, 8, 3, 3 at compile time
   if constexpr (FN == 576) {
-    stockham_pass_c<T, 8, MAXV / 8, 576, 1>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
-    stockham_pass_c<T, 8, MAXV / 8, 576, 8>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
-    stockham_pass_c<T, 3, MAXV / 3, 576, 64>(lds, lstride, nlines, tw + pl.twoff[2], sgn);
-    stockham_pass_c<T, 3, MAXV / 3, 576, 192>(lds, lstride, nlines, tw + pl.twoff[3], sgn);
+    stockham_pass_c<T, 8, MAXV / 8, 576, 1, PAD>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
+    stockham_pass_c<T, 8, MAXV / 8, 576, 8, PAD>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
+    stockham_pass_c<T, 3, MAXV / 3, 576, 64, PAD>(lds, lstride, nlines, tw + pl.twoff[2], sgn);
+    stockham_pass_c<T, 3, MAXV / 3, 576, 192, PAD>(lds, lstride, nlines, tw + pl.twoff[3], sgn);
     return;
   } else {
   int Ns = 1;
@@ -179,10 +202,10 @@ __device__ __forceinline__ void fft_lines(c2<T>* lds, int lstride, int nlines, c
     const int R = pl.radix[p];
     const unsigned mb = qmagic((unsigned)(pl.n / R)), mk = qmagic((unsigned)Ns);
     switch (R) {
-      case 8: stockham_pass<T, 8, MAXV / 8>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
-      case 4: stockham_pass<T, 4, MAXV / 4>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
-      case 3: stockham_pass<T, 3, MAXV / 3>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
-      default: stockham_pass<T, 2, MAXV / 2>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
+      case 8: stockham_pass<T, 8, MAXV / 8, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
+      case 4: stockham_pass<T, 4, MAXV / 4, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
+      case 3: stockham_pass<T, 3, MAXV / 3, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
+      default: stockham_pass<T, 2, MAXV / 2, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
     }
     Ns *= R;
   }

@@ -20,6 +20,11 @@ namespace chn {
 
 static constexpr double kTwoPi = 6.283185307179586476925286766559;
 
+// The z passes and the x pass skip one LDS slot after every 8 elements of a
+// line (bank spreading, see lx in fft.hpp); their line stride on the host is
+// plane_lds_stride(p) = p + p / 8 + 1.
+constexpr bool kPad = true;
+
 template <typename T, int MAXV, int FN = 0>
 __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
@@ -51,19 +56,19 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
   for (int f = 0; f < a.nfields; ++f) {
     for (int e = threadIdx.x; e < K * npad; e += blockDim.x) {
       const int l = e / npad;
-      lds[l * LS + half + (e - l * npad)] = zero;
+      lds[l * LS + lx<kPad>(half + (e - l * npad))] = zero;
     }
     for (int e = threadIdx.x; e < K * n3; e += blockDim.x) {
       const int l = e / n3, s = e - l * n3;
       if (s == half) continue;
-      lds[l * LS + (s < half ? s : p3 - (n3 - s))] = value(f, l, s);
+      lds[l * LS + lx<kPad>(s < half ? s : p3 - (n3 - s))] = value(f, l, s);
     }
     __syncthreads();
-    fft_lines<T, MAXV, FN>(lds, LS, K, a.plan, a.tw, +1);
+    fft_lines<T, MAXV, FN, kPad>(lds, LS, K, a.plan, a.tw, +1);
     c2<T>* out = a.out + ((size_t)(by * a.nslot + f) * p3) * n1h + kx0;
     for (int e = threadIdx.x; e < nk * p3; e += blockDim.x) {
       const int z = e / nk, l = e - z * nk;
-      out[(size_t)z * n1h + l] = lds[l * LS + z];
+      out[(size_t)z * n1h + l] = lds[l * LS + lx<kPad>(z)];
     }
     __syncthreads();
   }
@@ -87,7 +92,7 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
   // --- load
   for (int e = threadIdx.x; e < 3 * RZ * npad; e += blockDim.x) {
     const int l = e / npad;
-    lds[l * LS + n1h + (e - l * npad)] = zero;
+    lds[l * LS + lx<kPad>(n1h + (e - l * npad))] = zero;
   }
   for (int e = threadIdx.x; e < 3 * RZ * n1h; e += blockDim.x) {
     const int l = e / n1h, k = e - l * n1h;
@@ -102,24 +107,25 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
     if (k == 0) {
       line[0] = mk<T>(X.x, Y.x);
     } else {
-      line[k] = mk<T>(X.x - Y.y, X.y + Y.x);
-      line[p1 - k] = mk<T>(X.x + Y.y, Y.x - X.y);
+      line[lx<kPad>(k)] = mk<T>(X.x - Y.y, X.y + Y.x);
+      line[lx<kPad>(p1 - k)] = mk<T>(X.x + Y.y, Y.x - X.y);
     }
   }
   __syncthreads();
-  fft_lines<T, MAXV, FN>(lds, LS, 3 * RZ, a.plan, a.tw, +1);
+  fft_lines<T, MAXV, FN, kPad>(lds, LS, 3 * RZ, a.plan, a.tw, +1);
   // --- products, row sums and CFL
   double s1[RZ], s3[RZ], cf[RZ];
 #pragma unroll
   for (int row = 0; row < RZ; ++row) s1[row] = s3[row] = cf[row] = 0.0;
   const double idy = a.inv_dy[yg];
   for (int x = threadIdx.x; x < p1; x += blockDim.x) {
+    const int px = lx<kPad>(x);
     T h3[RZ];
 #pragma unroll
     for (int row = 0; row < RZ; ++row) {
-      const c2<T> Z0 = lds[(3 * row + 0) * LS + x];
-      const c2<T> Z1 = lds[(3 * row + 1) * LS + x];
-      const c2<T> Z2 = lds[(3 * row + 2) * LS + x];
+      const c2<T> Z0 = lds[(3 * row + 0) * LS + px];
+      const c2<T> Z1 = lds[(3 * row + 1) * LS + px];
+      const c2<T> Z2 = lds[(3 * row + 2) * LS + px];
       const T u1 = Z0.x, u2 = Z0.y, u3 = Z1.x, o1 = Z1.y, o2 = Z2.x, o3 = Z2.y;
       const T H1 = u2 * o3 - u3 * o2;
       const T H2 = u3 * o1 - u1 * o3;
@@ -129,10 +135,10 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
       const double c = fabs((double)u1) * a.inv_dx + fabs((double)u2) * idy + fabs((double)u3) * a.inv_dz;
       cf[row] = fmax(cf[row], c);
       // line `row` belongs to row row / 3 <= row, already read at this x
-      lds[row * LS + x] = mk<T>(H1, H2);
+      lds[row * LS + px] = mk<T>(H1, H2);
     }
 #pragma unroll
-    for (int j = 0; j < RZ / 2; ++j) lds[(RZ + j) * LS + x] = mk<T>(h3[2 * j], h3[2 * j + 1]);
+    for (int j = 0; j < RZ / 2; ++j) lds[(RZ + j) * LS + px] = mk<T>(h3[2 * j], h3[2 * j + 1]);
   }
   // block reductions: wave64 shuffles, then across the waves through LDS
   __shared__ double red[3 * RZ][4];
@@ -162,12 +168,12 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
     a.rowsum[(size_t)a.d.n2 * p3 + o] = t3;
     a.rowcfl[o] = tc;
   }
-  fft_lines<T, MAXV, FN>(lds, LS, RZ + RZ / 2, a.plan, a.tw, -1);
+  fft_lines<T, MAXV, FN, kPad>(lds, LS, RZ + RZ / 2, a.plan, a.tw, -1);
   // --- unpack two real spectra per line, truncate, store in place over fields 0..2
   for (int e = threadIdx.x; e < (RZ + RZ / 2) * n1h; e += blockDim.x) {
     const int l = e / n1h, k = e - l * n1h;
-    const c2<T> W = lds[l * LS + k];
-    const c2<T> Wm = lds[l * LS + (k == 0 ? 0 : p1 - k)];
+    const c2<T> W = lds[l * LS + lx<kPad>(k)];
+    const c2<T> Wm = lds[l * LS + lx<kPad>(k == 0 ? 0 : p1 - k)];
     const c2<T> P = mk<T>(T(0.5) * (W.x + Wm.x), T(0.5) * (W.y - Wm.y));   // (W_k + conj W_m)/2
     const c2<T> Q = mk<T>(T(0.5) * (W.y + Wm.y), T(-0.5) * (W.x - Wm.x));  // (W_k - conj W_m)/(2i)
     if (l < RZ) {  // row l: H1 = P, H2 = Q
@@ -302,16 +308,16 @@ __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int 
     const c2<T>* in = a.buf + ((size_t)(y * 6 + f) * p3) * n1h + kx0;
     for (int e = threadIdx.x; e < K * p3; e += blockDim.x) {
       const int z = e / K, l = e - z * K;
-      lds[l * LS + z] = l < nk ? in[(size_t)z * n1h + l] : zero;
+      lds[l * LS + lx<kPad>(z)] = l < nk ? in[(size_t)z * n1h + l] : zero;
     }
     __syncthreads();
-    fft_lines<T, MAXV, FN>(lds, LS, K, a.plan, a.tw, -1);
+    fft_lines<T, MAXV, FN, kPad>(lds, LS, K, a.plan, a.tw, -1);
     c2<TO>* out = a.out[f] + ((size_t)(a.y0 + y) * n1h + kx0) * n3;
     for (int e = threadIdx.x; e < nk * n3; e += blockDim.x) {
       const int l = e / n3, s = e - l * n3;
       c2<TO> v = mk<TO>(TO(0), TO(0));
       if (s != half) {
-        const c2<T> w = lds[l * LS + (s < half ? s : p3 - (n3 - s))];
+        const c2<T> w = lds[l * LS + lx<kPad>(s < half ? s : p3 - (n3 - s))];
         v = mk<TO>(TO((double)w.x * a.scale), TO((double)w.y * a.scale));
       }
       out[(size_t)l * n3 + s] = v;
