@@ -337,8 +337,8 @@ __device__ __forceinline__ int2 z_tile() {
   const int t = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, n);
   return make_int2(t % gridDim.x, t / gridDim.x);
 }
-template <typename T, int MAXV, int FN>
-__global__ void __launch_bounds__(256) k_zinv(ZinvArgs<T> a) {
+template <typename T, int MAXV, int FN, int NT = 256>
+__global__ void __launch_bounds__(NT) k_zinv(ZinvArgs<T> a) {
   const int2 t = z_tile();
   zinv_body<T, MAXV, FN>(a, t.x, t.y);
 }
@@ -346,8 +346,8 @@ template <typename T, int MAXV, int FN, int RZ>
 __global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) { xpass_body<T, MAXV, FN, RZ>(a, blockIdx.x, blockIdx.y); }
 template <typename T, int NT, int QX, int MAXV>
 __global__ void __launch_bounds__(NT) k_xrow(XpassArgs<T> a) { xrow_body<T, NT, QX, MAXV>(a, blockIdx.x, blockIdx.y); }
-template <typename T, typename TO, int MAXV, int FN>
-__global__ void __launch_bounds__(256) k_zfwd(ZfwdArgs<T, TO> a) {
+template <typename T, typename TO, int MAXV, int FN, int NT = 256>
+__global__ void __launch_bounds__(NT) k_zfwd(ZfwdArgs<T, TO> a) {
   const int2 t = z_tile();
   zfwd_body<T, TO, MAXV, FN>(a, t.x, t.y);
 }
@@ -410,11 +410,20 @@ template <typename T> int pick_staging(const FftPlan& pl, int nlines, int nt) {
     }                                                            \
   } while (0)
 
+// Long z lines (one line per workgroup) get 1024 threads: LDS then admits
+// one workgroup per CU, and 16 waves keep it busy.
+inline int z_threads(const FftPlan& pl, int K) { return K == 1 && pl.n >= 4096 ? 1024 : 256; }
+
 template <typename T>
 hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st) {
-  const int m = pick_staging<T>(a.plan, a.K, 256);
   dim3 grid((a.d.n1h + a.K - 1) / a.K, a.ny);
   size_t sh = (size_t)a.K * a.lstride * sizeof(c2<T>);
+  if (z_threads(a.plan, a.K) == 1024) {
+    const int m = pick_staging<T>(a.plan, 1, 1024);
+    CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 0, 1024>), grid, dim3(1024), sh, st, a));
+    return hipGetLastError();
+  }
+  const int m = pick_staging<T>(a.plan, a.K, 256);
   if (a.fixed && plan_is_576(a.plan)) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 576>), grid, dim3(256), sh, st, a));
   else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 0>), grid, dim3(256), sh, st, a));
   return hipGetLastError();
@@ -470,9 +479,14 @@ hipError_t launch_xpass(const XpassArgs<T>& a, hipStream_t st) {
 
 template <typename T, typename TO>
 hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st) {
-  const int m = pick_staging<T>(a.plan, a.K, 256);
   dim3 grid((a.d.n1h + a.K - 1) / a.K, a.ny);
   size_t sh = (size_t)a.K * a.lstride * sizeof(c2<T>);
+  if (z_threads(a.plan, a.K) == 1024) {
+    const int m = pick_staging<T>(a.plan, 1, 1024);
+    CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 0, 1024>), grid, dim3(1024), sh, st, a));
+    return hipGetLastError();
+  }
+  const int m = pick_staging<T>(a.plan, a.K, 256);
   if (a.fixed && plan_is_576(a.plan)) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 576>), grid, dim3(256), sh, st, a));
   else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 0>), grid, dim3(256), sh, st, a));
   return hipGetLastError();
