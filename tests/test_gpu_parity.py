@@ -48,6 +48,8 @@ SMALL = synth.Case(n1=16, n2=33, n3=16, lx=2 * np.pi, lz=np.pi, re_b=2800.0, dt=
                    kmax=5, cfg=21)
 RAGGED = synth.Case(n1=24, n2=25, n3=12, lx=2 * np.pi, lz=np.pi / 2, re_b=1500.0, dt=0.004, amp=0.1,
                     kmax=None, cfg=22)
+# smallest accepted grid: n1 = n3 = 4 (6 x 6 padded plane), n2 = 9 (one interior compact stencil)
+TINY = synth.Case(n1=4, n2=9, n3=4, lx=2 * np.pi, lz=np.pi, re_b=500.0, dt=0.01, amp=0.1, kmax=None, cfg=25)
 
 
 @gpu
@@ -107,7 +109,7 @@ def test_set_state_and_recovery_parity(case):
 
 
 @gpu
-@pytest.mark.parametrize("case", [SMALL, RAGGED], ids=["small", "ragged"])
+@pytest.mark.parametrize("case", [SMALL, RAGGED, TINY], ids=["small", "ragged", "tiny"])
 def test_one_step_parity(case):
     v, om, U1, U3, y = synth.turbulent_field(case)
     S = _setup(case, y)
