@@ -64,12 +64,17 @@ struct chn_ctx {
   size_t inter_bytes = 0;
   double* S[8] = {};
   double* SU[8] = {};
+  double* junk = nullptr;  // one lane-indexed row that absorbs history writes nobody reads
   double* rowsum = nullptr;
   float* rowcfl = nullptr;
-  // homogeneous solutions of the three sub-steps for the time step htab_dt
+  // homogeneous solutions and Helmholtz factor tables of the three sub-steps
+  // for the time step htab_dt, and the Poisson factor table (SU[4..7]).  The
+  // tables of sub-steps 1 and 2 share S[3], S[4], S[6], S[7] with the filter
+  // stage and chn_get_fields, which reset htab_dt.
   double* hc[3] = {};
   double* hv[3] = {};
   double* hm[3] = {};
+  double* hu[3][4] = {};
   double htab_dt = 0.0;  // 0: not computed
   // tables
   double *A1, *B1, *A2, *B2, *L1d, *U1d, *L1u, *U1u, *L2d, *U2d, *clo, *chi_w, *quad, *inv_dy;
@@ -134,6 +139,7 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
   for (int k = 0; k < 8; ++k) S[k] = reinterpret_cast<double*>(cv.take(CB));
   double* SU[8];
   for (int k = 0; k < 8; ++k) SU[k] = D(NPb);
+  double* junk = D(po ? 0 : 2 * M);
   double* hc[3];
   double* hv[3];
   double* hm[3];
@@ -161,6 +167,14 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
     x->inter = inter;
     x->inter_bytes = ib;
     for (int k = 0; k < 8; ++k) { x->S[k] = S[k]; x->SU[k] = SU[k]; }
+    x->junk = junk;
+    // Helmholtz factor tables, NP doubles each: sub-step 0 in SU[0..3], 1 and
+    // 2 in the halves of S[3], S[4] and S[6], S[7] (2 NP doubles each)
+    for (int k = 0; k < 4; ++k) {
+      x->hu[0][k] = SU[k];
+      x->hu[1][k] = S[3 + k / 2] + (k % 2) * NPb;
+      x->hu[2][k] = S[6 + k / 2] + (k % 2) * NPb;
+    }
     x->rowsum = rowsum; x->rowcfl = rowcfl;
     for (int k = 0; k < 3; ++k) { x->hc[k] = hc[k]; x->hv[k] = hv[k]; x->hm[k] = hm[k]; }
     double* t = tabs;
@@ -380,9 +394,11 @@ chn_status homog_tables(chn_ctx* x, double dt, hipStream_t st) {
     h.hv[k] = x->hv[k];
     h.hm[k] = x->hm[k];
   }
-  h.S0 = x->S[3];
-  h.S1 = x->S[4];
+  h.S0 = x->S[0];
+  h.S1 = x->S[1];
   for (int k = 0; k < 8; ++k) h.SU[k] = x->SU[k];
+  for (int s = 0; s < 3; ++s)
+    for (int k = 0; k < 4; ++k) h.hu[s][k] = x->hu[s][k];
   HIPCHK(x, chn::launch_homog(h, st));
   x->htab_dt = dt;
   return CHN_OK;
@@ -417,8 +433,22 @@ template <typename T> void advance_args(chn_ctx* x, int s, double dt, chn::Advan
   for (int f = 0; f < 5; ++f) aa.ph[f] = po[f];
   for (int f = 0; f < 3; ++f) aa.H[f] = reinterpret_cast<const T*>(x->H[f]);
   aa.v = x->v; aa.chi = x->chi; aa.om2 = x->om2;
-  aa.nchi_old = x->nchi_old; aa.nom_old = x->nom_old;
-  for (int k = 0; k < 8; ++k) { aa.S[k] = x->S[k]; aa.SU[k] = x->SU[k]; }
+  // histories: sub-step s reads the previous one's N with weight zeta_s; the
+  // last sub-step's N is read next by sub-step 0 of the next step, with
+  // weight zeta_0.  A zero weight needs no data: the reads then stay on one
+  // (finite) row, the writes go to the junk row.
+  const size_t st = 2 * (size_t)x->M;
+  aa.nchi_rd = x->nchi_old; aa.nom_rd = x->nom_old;
+  aa.hist_rs = kZeta[s] == 0.0 ? 0 : st;
+  const bool dead = s == 2 && kZeta[0] == 0.0;
+  aa.nchi_wr = dead ? x->junk : x->nchi_old;
+  aa.nom_wr = dead ? x->junk : x->nom_old;
+  aa.hist_ws = dead ? 0 : st;
+  for (int k = 0; k < 8; ++k) aa.S[k] = x->S[k];
+  for (int k = 0; k < 4; ++k) {
+    aa.SU[k] = x->hu[s][k];
+    aa.SU[4 + k] = x->SU[4 + k];
+  }
   aa.U1 = x->U1; aa.U3 = x->U3; aa.nu_old = x->nu_old; aa.nw_old = x->nw_old;
   aa.rowsum = x->rowsum;
   aa.p3 = x->p3;
@@ -495,6 +525,7 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   // 1. float64 spectra of u1, u2, u3 (and the vorticities, unused here);
   //    mixed: rounded to float32 in place (the stored data of that path)
   double* su[5] = {x->S[3], x->S[4], x->S[5], x->S[6], x->S[7]};
+  x->htab_dt = 0.0;  // overwrites the factor tables of sub-steps 1 and 2
   if (chn_status st = recover<double>(x, su)) return st;
   if (x->mixed) {
     x->phase_valid = false;
@@ -1041,6 +1072,7 @@ chn_status chn_get_fields(chn_ctx* x, uint32_t mask, double* const* d_out) {
   const bool need_rec = mask & (CHN_F_U1 | CHN_F_U3 | CHN_F_OMEGA1 | CHN_F_OMEGA3);
   if (need_rec) {
     double* po[5] = {x->S[3], x->S[4], x->S[5], x->S[6], x->S[7]};
+    x->htab_dt = 0.0;  // overwrites the factor tables of sub-steps 1 and 2
     if (chn_status s = recover<double>(x, po)) return s;
   }
   int k = 0;

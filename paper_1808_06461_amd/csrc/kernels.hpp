@@ -144,10 +144,20 @@ template <typename TH, typename TP> struct AdvanceArgs {
   double* v;                  // state, updated
   double* chi;
   double* om2;
-  double* nchi_old;           // histories, updated
-  double* nom_old;
+  // histories N_chi, N_omega2 of the previous sub-step, lane-indexed: row i
+  // is read at *_rd + i hist_rs and the new one written at *_wr + i hist_ws.
+  // hist_rs = 0 where the history has weight zeta = 0 (one finite row is
+  // read); hist_ws = 0 where no later sub-step reads it (one junk row).
+  const double* nchi_rd;
+  const double* nom_rd;
+  double* nchi_wr;
+  double* nom_wr;
+  size_t hist_rs, hist_ws;
   double* S[8];               // lane-indexed scratch [n2][2M]
-  double* SU[8];              // mode-indexed scratch [n2][M]
+  // mode-indexed [n2][M] factor tables (k_homog): SU[0..3] the Helmholtz
+  // factor rows of this sub-step, SU[4..7] the Poisson ones, each
+  // {1/pivot, u1, u2, u3} of the upward / downward factorisation
+  const double* SU[8];
   // mean modes
   double* U1;
   double* U3;
@@ -178,7 +188,8 @@ struct HomogArgs {
   double* hm[3];              // per sub-step [M][4]
   double* S0;                 // lane-indexed scratch [n2][2M]
   double* S1;
-  double* SU[8];              // mode-indexed scratch [n2][M]
+  double* SU[8];              // SU[4..7]: Poisson factor table written here
+  double* hu[3][4];           // Helmholtz factor tables of the three sub-steps, written here
 };
 
 struct ChiArgs {

@@ -78,6 +78,55 @@ __device__ __forceinline__ void push_x(double (&xb)[3], double x) {
   xb[0] = x;
 }
 
+// Row r of the Helmholtz matrix (1 + cb k^2) A2 - cb B2 (hk = 1 + cb k^2),
+// and of the Poisson matrix B2 - k^2 A2; Dirichlet rows at the walls.  Band
+// order: m[3] diagonal, m[3 + d] the entry d columns to the right.
+__device__ __forceinline__ void helm_row(double (&m)[7], const double* __restrict__ A2r,
+                                         const double* __restrict__ B2r, bool wall, double hk, double cb) {
+#pragma unroll
+  for (int o = 0; o < 7; ++o) m[o] = wall ? (o == 3 ? 1.0 : 0.0) : hk * A2r[o] - cb * B2r[o];
+}
+__device__ __forceinline__ void pois_row(double (&m)[7], const double* __restrict__ A2r,
+                                         const double* __restrict__ B2r, bool wall, double k2) {
+#pragma unroll
+  for (int o = 0; o < 7; ++o) m[o] = wall ? (o == 3 ? 1.0 : 0.0) : B2r[o] - k2 * A2r[o];
+}
+// One row of an LU factorisation on the fly, upward (rows processed from
+// n - 1 to 0): eliminates the entries m[4..6] with the U rows uh[2], uh[1],
+// uh[0] of rows r + 1, r + 2, r + 3 (uh = {1/pivot, u1, u2, u3}, u_t the
+// entry at distance t towards row 0).  lm[3 - d] is the multiplier of the
+// row at distance d; the caller applies the same multipliers to its
+// right-hand sides.  The advance and homogeneous-solution kernels both
+// factor through these two functions, so their factors agree to the bit.
+__device__ __forceinline__ void factor_up(double (&m)[7], const double (&uh)[3][4], double (&lm)[3]) {
+#pragma unroll
+  for (int d = 3; d >= 1; --d) {
+    lm[3 - d] = m[3 + d] * uh[3 - d][0];
+    m[2 + d] -= lm[3 - d] * uh[3 - d][1];
+    m[1 + d] -= lm[3 - d] * uh[3 - d][2];
+    m[0 + d] -= lm[3 - d] * uh[3 - d][3];
+  }
+}
+// The same downward (rows 0 to n - 1): eliminates m[0..2].
+__device__ __forceinline__ void factor_down(double (&m)[7], const double (&uh)[3][4], double (&lm)[3]) {
+#pragma unroll
+  for (int d = 3; d >= 1; --d) {
+    lm[3 - d] = m[3 - d] * uh[3 - d][0];
+    m[4 - d] -= lm[3 - d] * uh[3 - d][1];
+    m[5 - d] -= lm[3 - d] * uh[3 - d][2];
+    m[6 - d] -= lm[3 - d] * uh[3 - d][3];
+  }
+}
+// shift the U-row history by one row
+__device__ __forceinline__ void push_u(double (&uh)[3][4], double u0, double u1, double u2, double u3) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uh[0][k] = uh[1][k];
+    uh[1][k] = uh[2][k];
+  }
+  uh[2][0] = u0; uh[2][1] = u1; uh[2][2] = u2; uh[2][3] = u3;
+}
+
 template <typename T> __device__ __forceinline__ double2 load_c(const T* p, size_t idx);
 template <> __device__ __forceinline__ double2 load_c<double>(const double* p, size_t idx) {
   return reinterpret_cast<const double2*>(p)[idx];
@@ -193,22 +242,28 @@ __global__ void __launch_bounds__(256) k_recover(RecoverArgs<TP> a) {
 // Software pipeline over T steps of a sweep: the loads of step t + D are
 // issued right after step t is processed, so D rows of loads are in flight
 // while the recurrence advances (the sweeps are otherwise latency-bound:
-// one dependent row per iteration).  load(t, buf) must accept t >= T.
+// one dependent row per iteration).  load(t, buf) must accept every t >= 0
+// (rows outside the line are clamped, their values unused) and load
+// unconditionally: a load under a branch makes the compiler wait for all
+// outstanding loads where the branch joins, which serialises the pipeline.
+// The steady state runs whole groups of D steps with no bounds test; the
+// last T mod D steps follow without loads.
 template <int D, typename B, typename LoadF, typename StepF>
 __device__ __forceinline__ void pipeline(int T, LoadF&& load, StepF&& step) {
   B buf[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) load(k, buf[k]);
-  for (int t0 = 0; t0 < T; t0 += D) {
+  int t0 = 0;
+  for (; t0 + D <= T; t0 += D) {
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const int t = t0 + k;
-      if (t < T) {
-        step(t, buf[k]);
-        load(t + D, buf[k]);
-      }
+      step(t0 + k, buf[k]);
+      load(t0 + k + D, buf[k]);
     }
   }
+#pragma unroll
+  for (int k = 0; k < D - 1; ++k)
+    if (t0 + k < T) step(t0 + k, buf[k]);
 }
 
 template <typename T> __device__ __forceinline__ void store_c(T* p, size_t idx, double x, double y);
@@ -409,6 +464,9 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
   auto LR = [&](auto* p, int i) { return p + (size_t)i * st; };       // lane-indexed [n2][2M]
   auto MR = [&](auto* p, int i) { return p + (size_t)i * M; };        // mode-indexed [n2][M]
   auto HR = [&](const TH* p, int i) { return p + 2 * (size_t)i * M; };
+  // histories N_old: rows read at stride hist_rs, written at hist_ws (0: one row)
+  auto HRD = [&](const double* p, int i) { return p + (size_t)i * a.hist_rs; };
+  auto HWR = [&](double* p, int i) { return p + (size_t)i * a.hist_ws; };
 
   // G = i(a H1 + b H3): lane c needs the other component (oc) of H1 and H3
   const double sg = L.c == 0 ? -1.0 : 1.0;
@@ -426,20 +484,17 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
     double w[7] = {0, 0, 0, 0, 0, 0, 0};
     double yb[3] = {0, 0, 0};
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    auto loadcol = [&](int j, B& b) {
-      if (j < n) {
-        b.h1 = (double)at(HR(a.H[0], j), hocol);
-        b.h3 = (double)at(HR(a.H[2], j), hocol);
-        b.om = at(LR(a.om2, j), bcol);
-        b.noo = at(LR(a.nom_old, j), bcol);
-      } else {
-        b.h1 = b.h3 = b.om = b.noo = 0.0;
-      }
+    auto loadcol = [&](int j, B& b) {  // rows j >= n are clamped (used only for j < n)
+      j = min(j, n - 1);
+      b.h1 = (double)at(HR(a.H[0], j), hocol);
+      b.h3 = (double)at(HR(a.H[2], j), hocol);
+      b.om = at(LR(a.om2, j), bcol);
+      b.noo = at(HRD(a.nom_rd, j), bcol);
     };
     auto column = [&](int j, int tb, const B& b) -> double {
       const double nom = L.live ? sg * (L.B * b.h1 - L.A * b.h3) : 0.0;  // i b H1 - i a H3
       const double q = f1 * b.om + dga * nom + dze * b.noo;
-      if (L.act) at(LR(a.nom_old, j), bcol) = nom;
+      if (L.act) at(HWR(a.nom_wr, j), bcol) = nom;
 #pragma unroll
       for (int k = 0; k < 7; ++k) {
         const int r = tb + k, o = j - r + 3;
@@ -479,16 +534,13 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
     double ycb[3] = {0, 0, 0}, yob[3] = {0, 0, 0};
     pipeline<D2, B>(
         n + 3,
-        [&](int t, B& b) {
-          const int i = n - 1 - t;
-          if (i >= 0) {
-            b.s0 = at(LR(a.S[0], i), bcol);
-            b.h2 = (double)at(HR(a.H[1], i), hcol);
-            b.chi = at(LR(a.chi, i), bcol);
-            b.nco = at(LR(a.nchi_old, i), bcol);
-          }
-          const int r = i + 3;
-          b.rom = (r <= n - 1 && t < n + 3) ? at(LR(a.S[2], r), bcol) : 0.0;
+        [&](int t, B& b) {  // rows clamped; the step uses them only inside the line
+          const int i = max(n - 1 - t, 0);
+          b.s0 = at(LR(a.S[0], i), bcol);
+          b.h2 = (double)at(HR(a.H[1], i), hcol);
+          b.chi = at(LR(a.chi, i), bcol);
+          b.nco = at(HRD(a.nchi_rd, i), bcol);
+          b.rom = at(LR(a.S[2], min(max(n + 2 - t, 0), n - 1)), bcol);
         },
         [&](int t, B& b) {
           const int i = n - 1 - t;
@@ -497,7 +549,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             push_x(xb, dG);
             const double nchi = L.live ? -dG - L.k2 * b.h2 : 0.0;
             const double q = f1 * b.chi + dga * nchi + dze * b.nco;
-            if (L.act) at(LR(a.nchi_old, i), bcol) = nchi;
+            if (L.act) at(HWR(a.nchi_wr, i), bcol) = nchi;
 #pragma unroll
             for (int k = 0; k < 7; ++k) {
               const int r = i + 3 - k;
@@ -506,40 +558,21 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           }
           const int r = i + 3;
           if (r <= n - 1) {
-            double m7[7], rc = acc[0], ro = b.rom;
-            if (r == 0 || r == n - 1) {
-#pragma unroll
-              for (int o = 0; o < 7; ++o) m7[o] = o == 3 ? 1.0 : 0.0;
-            } else {
-#pragma unroll
-              for (int o = 0; o < 7; ++o) m7[o] = hk * A2[r * 7 + o] - cb * B2[r * 7 + o];
-            }
+            // the factor rows themselves are tabulated per sub-step (k_homog)
+            double m7[7], lm[3], rc = acc[0], ro = b.rom;
+            helm_row(m7, A2 + r * 7, B2 + r * 7, r == 0 || r == n - 1, hk, cb);
+            factor_up(m7, uh, lm);
 #pragma unroll
             for (int d = 3; d >= 1; --d) {
-              const double lm = m7[3 + d] * uh[3 - d][0];
-              m7[2 + d] -= lm * uh[3 - d][1];
-              m7[1 + d] -= lm * uh[3 - d][2];
-              m7[0 + d] -= lm * uh[3 - d][3];
-              rc -= lm * ycb[3 - d];
-              ro -= lm * yob[3 - d];
+              rc -= lm[3 - d] * ycb[3 - d];
+              ro -= lm[3 - d] * yob[3 - d];
             }
             const double u0 = 1.0 / m7[3];
-            if (L.act && L.c == 0) {
-              at(MR(a.SU[0], r), bm) = u0;
-              at(MR(a.SU[1], r), bm) = m7[2];
-              at(MR(a.SU[2], r), bm) = m7[1];
-              at(MR(a.SU[3], r), bm) = m7[0];
-            }
             if (L.act) {
               at(LR(a.S[1], r), bcol) = rc;
               at(LR(a.S[2], r), bcol) = ro;
             }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              uh[0][k] = uh[1][k];
-              uh[1][k] = uh[2][k];
-            }
-            uh[2][0] = u0; uh[2][1] = m7[2]; uh[2][2] = m7[1]; uh[2][3] = m7[0];
+            push_u(uh, u0, m7[2], m7[1], m7[0]);
             ycb[0] = ycb[1]; ycb[1] = ycb[2]; ycb[2] = rc;
             yob[0] = yob[1]; yob[1] = yob[2]; yob[2] = ro;
           }
@@ -557,12 +590,11 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
     pipeline<D3, B>(
         n + 3,
         [&](int i, B& b) {
-          if (i < n) {
+          i = min(i, n - 1);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) b.u[k] = at(MR(a.SU[k], i), bm);
-            b.s1 = at(LR(a.S[1], i), bcol);
-            b.s2 = at(LR(a.S[2], i), bcol);
-          }
+          for (int k = 0; k < 4; ++k) b.u[k] = at(MR(a.SU[k], i), bm);
+          b.s1 = at(LR(a.S[1], i), bcol);
+          b.s2 = at(LR(a.S[2], i), bcol);
         },
         [&](int i, B& b) {
           double cp = 0.0;
@@ -579,41 +611,20 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           push_back(wcp, cp);
           const int r = i - 3;
           if (r >= 0) {
-            double p7[7], rv = 0.0;
-            if (r == 0 || r == n - 1) {
+            // the Poisson factor rows are tabulated once (k_homog)
+            const bool wall = r == 0 || r == n - 1;
+            double p7[7], lm[3], rv = 0.0;
+            if (!wall) {
 #pragma unroll
-              for (int o = 0; o < 7; ++o) p7[o] = o == 3 ? 1.0 : 0.0;
-            } else {
-              const double* A2r = A2 + r * 7;
-              const double* B2r = B2 + r * 7;
-#pragma unroll
-              for (int o = 0; o < 7; ++o) {
-                rv += A2r[o] * wcp[o];
-                p7[o] = B2r[o] - L.k2 * A2r[o];
-              }
+              for (int o = 0; o < 7; ++o) rv += A2[r * 7 + o] * wcp[o];
             }
+            pois_row(p7, A2 + r * 7, B2 + r * 7, wall, L.k2);
+            factor_down(p7, uh, lm);
 #pragma unroll
-            for (int d = 3; d >= 1; --d) {
-              const double lm = p7[3 - d] * uh[3 - d][0];
-              p7[4 - d] -= lm * uh[3 - d][1];
-              p7[5 - d] -= lm * uh[3 - d][2];
-              p7[6 - d] -= lm * uh[3 - d][3];
-              rv -= lm * yvb[3 - d];
-            }
+            for (int d = 3; d >= 1; --d) rv -= lm[3 - d] * yvb[3 - d];
             const double u0 = 1.0 / p7[3];
-            if (L.act && L.c == 0) {
-              at(MR(a.SU[4], r), bm) = u0;
-              at(MR(a.SU[5], r), bm) = p7[4];
-              at(MR(a.SU[6], r), bm) = p7[5];
-              at(MR(a.SU[7], r), bm) = p7[6];
-            }
             if (L.act) at(LR(a.S[5], r), bcol) = rv;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              uh[0][k] = uh[1][k];
-              uh[1][k] = uh[2][k];
-            }
-            uh[2][0] = u0; uh[2][1] = p7[4]; uh[2][2] = p7[5]; uh[2][3] = p7[6];
+            push_u(uh, u0, p7[4], p7[5], p7[6]);
             yvb[0] = yvb[1]; yvb[1] = yvb[2]; yvb[2] = rv;
           }
         });
@@ -628,12 +639,10 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
     pipeline<D, B>(
         n,
         [&](int t, B& b) {
-          const int r = n - 1 - t;
-          if (r >= 0) {
+          const int r = max(n - 1 - t, 0);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) b.u[k] = at(MR(a.SU[4 + k], r), bm);
-            b.s5 = at(LR(a.S[5], r), bcol);
-          }
+          for (int k = 0; k < 4; ++k) b.u[k] = at(MR(a.SU[4 + k], r), bm);
+          b.s5 = at(LR(a.S[5], r), bcol);
         },
         [&](int t, B& b) {
           const int r = n - 1 - t;
@@ -662,14 +671,11 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
     pipeline<D, B>(
         n + 3,
         [&](int i, B& b) {
-          if (i < n) {
-            b.vh = at(LR(a.hv, i), bcol);
-            b.ch = at(LR(a.hc, i), bcol);
-            b.vp = at(LR(a.v, i), bcol);
-            b.cp = at(LR(a.chi, i), bcol);
-          } else {
-            b.vh = b.ch = b.vp = b.cp = 0.0;
-          }
+          i = min(i, n - 1);
+          b.vh = at(LR(a.hv, i), bcol);
+          b.ch = at(LR(a.hc, i), bcol);
+          b.vp = at(LR(a.v, i), bcol);
+          b.cp = at(LR(a.chi, i), bcol);
         },
         [&](int i, B& b) {
           const double vho = __shfl_xor(b.vh, 1), cho = __shfl_xor(b.ch, 1);
@@ -706,14 +712,9 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
     pipeline<D, B>(
         n + 3,
         [&](int t, B& b) {
-          const int i = n - 1 - t;
-          if (i >= 0) {
-            b.s0 = at(LR(a.S[0], i), bcol);
-            b.om = at(LR(a.om2, i), bocol);
-          } else {
-            b.s0 = 0.0;
-            b.om = 0.0;
-          }
+          const int i = max(n - 1 - t, 0);
+          b.s0 = at(LR(a.S[0], i), bcol);
+          b.om = at(LR(a.om2, i), bocol);
         },
         [&](int t, B& b) {
           const int i = n - 1 - t;
@@ -756,11 +757,10 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
     pipeline<D, B>(
         n,
         [&](int r, B& b) {
-          if (r < n) {
-            b.s1 = at(LR(a.S[1], r), bcol);
-            b.s2 = at(LR(a.S[2], r), bcol);
-            b.v = at(LR(a.v, r), bocol);
-          }
+          r = min(r, n - 1);
+          b.s1 = at(LR(a.S[1], r), bcol);
+          b.s2 = at(LR(a.S[2], r), bcol);
+          b.v = at(LR(a.v, r), bocol);
         },
         [&](int r, B& b) {
           const double* U = U1u + r * 4;
@@ -830,37 +830,22 @@ __global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
       double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
       double yhb[3] = {0, 0, 0};
       for (int r = n - 1; r >= 0; --r) {
-        double m7[7], rh = 0.0;
-        if (r == 0 || r == n - 1) {
+        const bool wall = r == 0 || r == n - 1;
+        double m7[7], lm[3];
+        double rh = wall && (r == 0) == (L.c == 0) ? 1.0 : 0.0;
+        helm_row(m7, A2 + r * 7, B2 + r * 7, wall, hk, cb);
+        factor_up(m7, uh, lm);
 #pragma unroll
-          for (int o = 0; o < 7; ++o) m7[o] = o == 3 ? 1.0 : 0.0;
-          rh = (r == 0) == (L.c == 0) ? 1.0 : 0.0;
-        } else {
-#pragma unroll
-          for (int o = 0; o < 7; ++o) m7[o] = hk * A2[r * 7 + o] - cb * B2[r * 7 + o];
-        }
-#pragma unroll
-        for (int d = 3; d >= 1; --d) {
-          const double lm = m7[3 + d] * uh[3 - d][0];
-          m7[2 + d] -= lm * uh[3 - d][1];
-          m7[1 + d] -= lm * uh[3 - d][2];
-          m7[0 + d] -= lm * uh[3 - d][3];
-          rh -= lm * yhb[3 - d];
-        }
+        for (int d = 3; d >= 1; --d) rh -= lm[3 - d] * yhb[3 - d];
         const double u0 = 1.0 / m7[3];
-        if (L.act && L.c == 0) {
-          a.SU[0][r * M + m] = u0;
-          a.SU[1][r * M + m] = m7[2];
-          a.SU[2][r * M + m] = m7[1];
-          a.SU[3][r * M + m] = m7[0];
+        if (L.act && L.c == 0) {  // the factor table of sub-step s (read by k_advance)
+          a.hu[s][0][r * M + m] = u0;
+          a.hu[s][1][r * M + m] = m7[2];
+          a.hu[s][2][r * M + m] = m7[1];
+          a.hu[s][3][r * M + m] = m7[0];
         }
         if (L.act) a.S0[r * st + col] = rh;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          uh[0][k] = uh[1][k];
-          uh[1][k] = uh[2][k];
-        }
-        uh[2][0] = u0; uh[2][1] = m7[2]; uh[2][2] = m7[1]; uh[2][3] = m7[0];
+        push_u(uh, u0, m7[2], m7[1], m7[0]);
         yhb[0] = yhb[1]; yhb[1] = yhb[2]; yhb[2] = rh;
       }
     }
@@ -874,7 +859,8 @@ __global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
       for (int i = 0; i < n + 3; ++i) {
         double ch = 0.0;
         if (i < n) {
-          const double u[4] = {a.SU[0][i * M + m], a.SU[1][i * M + m], a.SU[2][i * M + m], a.SU[3][i * M + m]};
+          const double u[4] = {a.hu[s][0][i * M + m], a.hu[s][1][i * M + m], a.hu[s][2][i * M + m],
+                               a.hu[s][3][i * M + m]};
           ch = back3(a.S0[i * st + col], u, xhb);
           push_x(xhb, ch);
           if (L.act) a.hc[s][i * st + col] = ch;
@@ -882,41 +868,25 @@ __global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
         push_back(wch, ch);
         const int r = i - 3;
         if (r >= 0) {
-          double p7[7], rhv = 0.0;
-          if (r == 0 || r == n - 1) {
+          const bool wall = r == 0 || r == n - 1;
+          double p7[7], lm[3], rhv = 0.0;
+          if (!wall) {
 #pragma unroll
-            for (int o = 0; o < 7; ++o) p7[o] = o == 3 ? 1.0 : 0.0;
-          } else {
-            const double* A2r = A2 + r * 7;
-            const double* B2r = B2 + r * 7;
-#pragma unroll
-            for (int o = 0; o < 7; ++o) {
-              rhv += A2r[o] * wch[o];
-              p7[o] = B2r[o] - L.k2 * A2r[o];
-            }
+            for (int o = 0; o < 7; ++o) rhv += A2[r * 7 + o] * wch[o];
           }
+          pois_row(p7, A2 + r * 7, B2 + r * 7, wall, L.k2);
+          factor_down(p7, uh, lm);
 #pragma unroll
-          for (int d = 3; d >= 1; --d) {
-            const double lm = p7[3 - d] * uh[3 - d][0];
-            p7[4 - d] -= lm * uh[3 - d][1];
-            p7[5 - d] -= lm * uh[3 - d][2];
-            p7[6 - d] -= lm * uh[3 - d][3];
-            rhv -= lm * yhb[3 - d];
-          }
+          for (int d = 3; d >= 1; --d) rhv -= lm[3 - d] * yhb[3 - d];
           const double u0 = 1.0 / p7[3];
-          if (L.act && L.c == 0) {
+          if (L.act && L.c == 0) {  // the Poisson factor table (independent of dt)
             a.SU[4][r * M + m] = u0;
             a.SU[5][r * M + m] = p7[4];
             a.SU[6][r * M + m] = p7[5];
             a.SU[7][r * M + m] = p7[6];
           }
           if (L.act) a.S1[r * st + col] = rhv;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            uh[0][k] = uh[1][k];
-            uh[1][k] = uh[2][k];
-          }
-          uh[2][0] = u0; uh[2][1] = p7[4]; uh[2][2] = p7[5]; uh[2][3] = p7[6];
+          push_u(uh, u0, p7[4], p7[5], p7[6]);
           yhb[0] = yhb[1]; yhb[1] = yhb[2]; yhb[2] = rhv;
         }
       }
