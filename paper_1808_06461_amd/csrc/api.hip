@@ -72,7 +72,7 @@ struct chn_ctx {
   // tables of sub-steps 1 and 2 share S[3], S[4], S[6], S[7] with the filter
   // stage and chn_get_fields, which reset htab_dt.
   double* hc[3] = {};
-  double* hv[3] = {};
+  double* hw[3] = {};
   double* hm[3] = {};
   double* hu[3][4] = {};
   double htab_dt = 0.0;  // 0: not computed
@@ -141,11 +141,11 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
   for (int k = 0; k < 8; ++k) SU[k] = D(NPb);
   double* junk = D(po ? 0 : 2 * M);
   double* hc[3];
-  double* hv[3];
+  double* hw[3];
   double* hm[3];
   for (int k = 0; k < 3; ++k) {
     hc[k] = reinterpret_cast<double*>(cv.take(CB));
-    hv[k] = reinterpret_cast<double*>(cv.take(CB));
+    hw[k] = reinterpret_cast<double*>(cv.take(CB));
     hm[k] = D(po ? 0 : 4 * M);
   }
   double* rowsum = D(2 * (size_t)n2 * p3);
@@ -176,7 +176,7 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
       x->hu[2][k] = S[6 + k / 2] + (k % 2) * NPb;
     }
     x->rowsum = rowsum; x->rowcfl = rowcfl;
-    for (int k = 0; k < 3; ++k) { x->hc[k] = hc[k]; x->hv[k] = hv[k]; x->hm[k] = hm[k]; }
+    for (int k = 0; k < 3; ++k) { x->hc[k] = hc[k]; x->hw[k] = hw[k]; x->hm[k] = hm[k]; }
     double* t = tabs;
     x->A1 = t; t += 7 * n2; x->B1 = t; t += 7 * n2; x->A2 = t; t += 7 * n2; x->B2 = t; t += 7 * n2;
     x->L1d = t; t += 3 * n2; x->L1u = t; t += 3 * n2; x->L2d = t; t += 3 * n2;
@@ -270,12 +270,18 @@ int z_lines_max(const chn_ctx* x) {
   if (K > x->n1h) K = x->n1h;
   return K;
 }
-// Default schedule: 16 z lines per workgroup (capped), two x rows when six lines fit.
+// Default schedule, from the autotuner's choices on 384 x 193 x 384 and on
+// the 8192 x 6144 planes: z-pass workgroups of about 2304 (float) or 1152
+// (double) points, but at least 1024 of them per launch (small grids); two x
+// rows when six lines fit; compile-time radix schedules where they exist.
 bool plan_fits(const chn_ctx* x, int xrows, int zK, int ych);
 void default_plan(chn_ctx* x) {
-  x->zK = std::max(1, std::min(16, z_lines_max(x)));
   x->ychunk = x->planes_only || x->cfg.plane_chunk > 0 ? x->cfg.plane_chunk : x->n2;
+  int K = std::max(1, (x->mixed ? 2304 : 1152) / x->p3);
+  K = std::min(K, std::max(1, (int)((size_t)x->ychunk * x->n1h / 1024)));
+  x->zK = std::max(1, std::min(K, z_lines_max(x)));
   x->xrows = plan_fits(x, 2, x->zK, x->ychunk) ? 2 : 1;
+  x->ffix = 1;
 }
 bool plan_fits(const chn_ctx* x, int xrows, int zK, int ych) {
   const int cb = x->mixed ? 8 : 16;
@@ -391,11 +397,17 @@ chn_status homog_tables(chn_ctx* x, double dt, hipStream_t st) {
   for (int k = 0; k < 3; ++k) {
     h.be[k] = kBeta[k];
     h.hc[k] = x->hc[k];
-    h.hv[k] = x->hv[k];
+    h.hw[k] = x->hw[k];
     h.hm[k] = x->hm[k];
   }
   h.S0 = x->S[0];
   h.S1 = x->S[1];
+  h.T = x->S[2];
+  // four [n2][M] factor-row arrays for the transposed solves, in the plane
+  // intermediate (free between plane phases; it holds 9 n2 M doubles or more)
+  const size_t NP = (size_t)x->n2 * x->M;
+  if (x->inter_bytes < 4 * NP * sizeof(double)) return fail(x, CHN_EUNSUPPORTED, "intermediate too small for k_homog");
+  for (int k = 0; k < 4; ++k) h.Q[k] = reinterpret_cast<double*>(x->inter) + k * NP;
   for (int k = 0; k < 8; ++k) h.SU[k] = x->SU[k];
   for (int s = 0; s < 3; ++s)
     for (int k = 0; k < 4; ++k) h.hu[s][k] = x->hu[s][k];
@@ -459,7 +471,7 @@ template <typename T> void advance_args(chn_ctx* x, int s, double dt, chn::Advan
   aa.dt = dt; aa.nu = x->nu;
   aa.al = kAlpha[s]; aa.be = kBeta[s]; aa.ga = kGamma[s]; aa.ze = kZeta[s];
   aa.hc = x->hc[s];
-  aa.hv = x->hv[s];
+  aa.hw = x->hw[s];
   aa.hm = x->hm[s];
 }
 
@@ -731,6 +743,9 @@ template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
   e->mz = e->mx = 0;
   for (int i = 0; i < n; ++i) {
     chn_ctx* x = e->ctx[i];
+    // one launch covers every channel, so no channel needs a workgroup
+    // floor of its own: up to 16 z lines per workgroup
+    x->zK = std::max(1, std::min(16, z_lines_max(x)));
     plane_args<T, T>(x, x->ph, false, x->H, za[i], xa[i], fa[i]);
     xa[i].rows = e->rz;
     const int mz = chn::staging_for(x->plan3, za[i].K, cb);

@@ -173,8 +173,8 @@ template <typename TH, typename TP> struct AdvanceArgs {
   // homogeneous solutions of this sub-step (k_homog): lane c holds the one
   // with chi = 1 at wall c (c = 0 lower, 1 upper)
   const double* hc;           // chi_h, lane-indexed [n2][2M]
-  const double* hv;           // v_h, lane-indexed [n2][2M]
   const double* hm;           // [M][4]: D1 v_h at (lower, upper) wall for c = 0, then c = 1
+  const double* hw;           // lane-indexed [n2][2M]: lane c holds w_c, D1 v_p(wall c) = w_c . r_chi
 };
 
 // Homogeneous solutions of the three sub-steps for a time step dt: the
@@ -184,10 +184,12 @@ struct HomogArgs {
   PencilGeom g;
   double nu, dt, be[3];
   double* hc[3];              // per sub-step, lane-indexed [n2][2M]
-  double* hv[3];
+  double* hw[3];              // per sub-step, lane-indexed [n2][2M] (wall-derivative vectors w_c)
   double* hm[3];              // per sub-step [M][4]
   double* S0;                 // lane-indexed scratch [n2][2M]
   double* S1;
+  double* T;                  // lane-indexed scratch [n2][2M] (A2^T E P^-T d_c)
+  double* Q[4];               // mode-indexed scratch [n2][M] (factor rows of the transposed solves)
   double* SU[8];              // SU[4..7]: Poisson factor table written here
   double* hu[3][4];           // Helmholtz factor tables of the three sub-steps, written here
 };

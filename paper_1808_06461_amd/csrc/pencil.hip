@@ -424,15 +424,14 @@ __device__ void mean_block(const AdvanceArgs<TH, TP>& a) {
 // sub-step's velocities and vorticities:
 //   S1 down : G = i(a H1 + b H3); eliminate A1 (dG) = B1 G
 //   S2 up   : finish dG; N_chi, N_omega2; implicit right-hand sides (lag 3);
-//             Helmholtz factor on the fly; eliminate chi_p, omega2
-//   S3 down : finish chi_p, omega2; Poisson rhs (lag 3); P factor on the
-//             fly; eliminate v_p
-//   S4 up   : finish v_p; dense wall rows of D1; 2x2 influence system with
-//             the homogeneous solutions' wall derivatives (k_homog tables)
-//   S5 down : v, chi = particular + c_lo, c_hi homogeneous (tables);
-//             eliminate A1 (dv) = B1 v
-//   R2 up   : finish dv; u1, u3 by continuity; eliminate A1 (du) = B1 u
-//   R3 down : finish du1, du3; omega1 = du3 - i b v, omega3 = i a v - du1
+//             Helmholtz factor on the fly; eliminate chi_p, omega2; the
+//             wall values of D1 v_p as dot products with the chi right-hand
+//             side, then the 2x2 influence system (Appendix B)
+//   S3 down : finish chi_p, omega2; chi = chi_p + c_lo, c_hi homogeneous;
+//             Poisson rhs (lag 3); P factor on the fly; eliminate v
+//   S4 up   : finish v; eliminate A1 (dv) = B1 v
+//   R2 down : finish dv; u1, u3 by continuity; eliminate A1 (du) = B1 u
+//   R3 up   : finish du1, du3; omega1 = du3 - i b v, omega3 = i a v - du1
 template <typename TH, typename TP>
 __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int bx,
                                              // read-only tables as noalias parameters, so the wave-uniform
@@ -440,9 +439,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
                                              const double* __restrict__ B1, const double* __restrict__ A2,
                                              const double* __restrict__ B2, const double* __restrict__ L1d,
                                              const double* __restrict__ U1d, const double* __restrict__ L1u,
-                                             const double* __restrict__ U1u, const double* __restrict__ clo,
-                                             const double* __restrict__ chw) {
-  constexpr int D = 3, D2 = 3, D3 = 3;
+                                             const double* __restrict__ U1u) {
+  constexpr int D = 5, D2 = 3, D3 = 3;
   const PencilGeom& g = a.g;
   const Lane L = lane_setup(g, bx);
   const int n = g.n2;
@@ -525,22 +523,28 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
   }
   // ---- S2 (up): finish dG; N_chi = -dG - k^2 H2 and the chi right-hand side
   // (acc[k] is row i + 3 - k, complete when column i - ... arrives: lag 3);
-  // Helmholtz matrix factored on the fly; eliminate chi_p and omega2
+  // Helmholtz matrix factored on the fly; eliminate chi_p and omega2.  The
+  // wall values of D1 v_p are linear in the chi right-hand side r:
+  // D1 v_p(wall c) = w_c . r with w_c tabulated per sub-step (k_homog), so the
+  // influence coefficients c_lo, c_hi are known when this sweep ends.
+  double clo_c = 0.0, chi_c = 0.0;  // c_lo, c_hi of this lane's component
   {
-    struct B { double s0, h2, chi, nco, rom; };
+    struct B { double s0, h2, chi, nco, rom, w; };
     double xb[3] = {0, 0, 0};
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
     double ycb[3] = {0, 0, 0}, yob[3] = {0, 0, 0};
+    double glo = 0.0, ghi = 0.0;
     pipeline<D2, B>(
         n + 3,
         [&](int t, B& b) {  // rows clamped; the step uses them only inside the line
-          const int i = max(n - 1 - t, 0);
+          const int i = max(n - 1 - t, 0), r = min(max(n + 2 - t, 0), n - 1);
           b.s0 = at(LR(a.S[0], i), bcol);
           b.h2 = (double)at(HR(a.H[1], i), hcol);
           b.chi = at(LR(a.chi, i), bcol);
           b.nco = at(HRD(a.nchi_rd, i), bcol);
-          b.rom = at(LR(a.S[2], min(max(n + 2 - t, 0), n - 1)), bcol);
+          b.rom = at(LR(a.S[2], r), bcol);
+          b.w = at(LR(a.hw, r), bcol);
         },
         [&](int t, B& b) {
           const int i = n - 1 - t;
@@ -560,6 +564,9 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           if (r <= n - 1) {
             // the factor rows themselves are tabulated per sub-step (k_homog)
             double m7[7], lm[3], rc = acc[0], ro = b.rom;
+            const double wo = __shfl_xor(b.w, 1);  // lane c holds w of wall c
+            glo = fma(L.c == 0 ? b.w : wo, rc, glo);
+            ghi = fma(L.c == 0 ? wo : b.w, rc, ghi);
             helm_row(m7, A2 + r * 7, B2 + r * 7, r == 0 || r == n - 1, hk, cb);
             factor_up(m7, uh, lm);
 #pragma unroll
@@ -578,13 +585,27 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           }
           push_back(acc, 0.0);
         });
+    // 2x2 influence system: D1 v = 0 at both walls, with the wall derivatives
+    // of the homogeneous v (tabulated)
+    const double* hm = a.hm + 4 * (size_t)L.m;
+    const double m00 = hm[0];  // lower-wall homogeneous solution, D1 at the lower wall
+    const double m10 = hm[1];  // ... at the upper wall
+    const double m01 = hm[2];  // upper-wall homogeneous solution, lower wall
+    const double m11 = hm[3];
+    if (L.live) {
+      const double det = m00 * m11 - m01 * m10;
+      clo_c = (-glo * m11 + ghi * m01) / det;
+      chi_c = (-ghi * m00 + glo * m10) / det;
+    }
   }
-  // ---- S3 (down): finish chi_p and omega2; Poisson right-hand side A2 chi_p
-  // (lag 3), Poisson matrix factored on the fly; eliminate v_p
+  // ---- S3 (down): finish chi_p and omega2; chi = chi_p + c_lo chi_lo +
+  // c_hi chi_hi (homogeneous solutions tabulated); Poisson right-hand side
+  // A2 chi (lag 3), Poisson matrix factored on the fly; eliminate v.  The
+  // Poisson step is linear, so this v is v_p + c_lo v_lo + c_hi v_hi.
   {
-    struct B { double u[4]; double s1, s2; };
+    struct B { double u[4]; double s1, s2, hc; };
     double xcb[3] = {0, 0, 0}, xob[3] = {0, 0, 0};
-    double wcp[7] = {0, 0, 0, 0, 0, 0, 0};
+    double wch[7] = {0, 0, 0, 0, 0, 0, 0};
     double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
     double yvb[3] = {0, 0, 0};
     pipeline<D3, B>(
@@ -595,20 +616,24 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           for (int k = 0; k < 4; ++k) b.u[k] = at(MR(a.SU[k], i), bm);
           b.s1 = at(LR(a.S[1], i), bcol);
           b.s2 = at(LR(a.S[2], i), bcol);
+          b.hc = at(LR(a.hc, i), bcol);
         },
         [&](int i, B& b) {
-          double cp = 0.0;
+          double cn = 0.0;
           if (i < n) {
-            cp = back3(b.s1, b.u, xcb);
+            const double cp = back3(b.s1, b.u, xcb);
             const double om = back3(b.s2, b.u, xob);
             push_x(xcb, cp);
             push_x(xob, om);
+            const double hco = __shfl_xor(b.hc, 1);  // lane c holds chi_h of wall c
+            const double hlo = L.c == 0 ? b.hc : hco, hhi = L.c == 0 ? hco : b.hc;
+            cn = L.live ? cp + clo_c * hlo + chi_c * hhi : 0.0;
             if (L.act) {
               at(LR(a.om2, i), bcol) = L.live ? om : 0.0;
-              at(LR(a.chi, i), bcol) = cp;
+              at(LR(a.chi, i), bcol) = cn;
             }
           }
-          push_back(wcp, cp);
+          push_back(wch, cn);
           const int r = i - 3;
           if (r >= 0) {
             // the Poisson factor rows are tabulated once (k_homog)
@@ -616,7 +641,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             double p7[7], lm[3], rv = 0.0;
             if (!wall) {
 #pragma unroll
-              for (int o = 0; o < 7; ++o) rv += A2[r * 7 + o] * wcp[o];
+              for (int o = 0; o < 7; ++o) rv += A2[r * 7 + o] * wch[o];
             }
             pois_row(p7, A2 + r * 7, B2 + r * 7, wall, L.k2);
             factor_down(p7, uh, lm);
@@ -629,15 +654,14 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           }
         });
   }
-  // ---- S4 (up): finish v_p; dense wall rows of D1 on v_p; 2x2 influence
-  // system with the tabulated wall derivatives of the homogeneous v
-  double clo_c = 0.0, chi_c = 0.0;
+  // ---- S4 (up): finish v; eliminate A1 (dv) = B1 v upward (lag 3)
   {
     struct B { double u[4]; double s5; };
     double xvb[3] = {0, 0, 0};
-    double gplo = 0.0, gphi = 0.0;
+    double wv[7] = {0, 0, 0, 0, 0, 0, 0};
+    double yb[3] = {0, 0, 0};
     pipeline<D, B>(
-        n,
+        n + 3,
         [&](int t, B& b) {
           const int r = max(n - 1 - t, 0);
 #pragma unroll
@@ -645,57 +669,18 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           b.s5 = at(LR(a.S[5], r), bcol);
         },
         [&](int t, B& b) {
-          const int r = n - 1 - t;
-          const double vp = back3(b.s5, b.u, xvb);
-          push_x(xvb, vp);
-          if (L.act) at(LR(a.v, r), bcol) = vp;
-          gplo = fma(clo[r], vp, gplo);
-          gphi = fma(chw[r], vp, gphi);
-        });
-    const double* hm = a.hm + 4 * (size_t)L.m;
-    const double m00 = hm[0];  // lower-wall homogeneous solution, D1 at the lower wall
-    const double m10 = hm[1];  // ... at the upper wall
-    const double m01 = hm[2];  // upper-wall homogeneous solution, lower wall
-    const double m11 = hm[3];
-    if (L.live) {
-      const double det = m00 * m11 - m01 * m10;
-      clo_c = (-gplo * m11 + gphi * m01) / det;
-      chi_c = (-gphi * m00 + gplo * m10) / det;
-    }
-  }
-  // ---- S5 (+ R1)
-  {
-    struct B { double vh, ch, vp, cp; };
-    double w[7] = {0, 0, 0, 0, 0, 0, 0};
-    double yb[3] = {0, 0, 0};
-    pipeline<D, B>(
-        n + 3,
-        [&](int i, B& b) {
-          i = min(i, n - 1);
-          b.vh = at(LR(a.hv, i), bcol);
-          b.ch = at(LR(a.hc, i), bcol);
-          b.vp = at(LR(a.v, i), bcol);
-          b.cp = at(LR(a.chi, i), bcol);
-        },
-        [&](int i, B& b) {
-          const double vho = __shfl_xor(b.vh, 1), cho = __shfl_xor(b.ch, 1);
+          const int i = n - 1 - t;
           double vn = 0.0;
-          if (i < n) {
-            const int ixr = i;
-            const double vlo = L.c == 0 ? b.vh : vho, vhi = L.c == 0 ? vho : b.vh;
-            const double clo = L.c == 0 ? b.ch : cho, chh = L.c == 0 ? cho : b.ch;
-            vn = L.live ? b.vp + clo_c * vlo + chi_c * vhi : 0.0;
-            const double cn = L.live ? b.cp + clo_c * clo + chi_c * chh : 0.0;
-            if (L.act) {
-              at(LR(a.v, ixr), bcol) = vn;
-              at(LR(a.chi, ixr), bcol) = cn;
-            }
-            if (wph) at(LR(a.ph[1], ixr), pcol) = (TP)vn;
+          if (i >= 0) {
+            vn = back3(b.s5, b.u, xvb);
+            push_x(xvb, vn);
+            if (L.act) at(LR(a.v, i), bcol) = vn;
+            if (wph) at(LR(a.ph[1], i), pcol) = (TP)vn;
           }
-          push_back(w, vn);
-          const int r = i - 3;
-          if (r >= 0) {
-            const double yr = elim3(dot7(B1 + r * 7, w), L1d + r * 3, yb);
+          push_front(wv, vn);
+          const int r = i + 3;
+          if (r <= n - 1) {
+            const double yr = elim3(dot7(B1 + r * 7, wv), L1u + r * 3, yb);
             if (L.act) at(LR(a.S[0], r), bcol) = yr;
             yb[0] = yb[1];
             yb[1] = yb[2];
@@ -703,7 +688,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           }
         });
   }
-  // ---- R2
+  // ---- R2 (down): finish dv; u1, u3 by continuity; eliminate A1 (du) = B1 u
+  // downward (lag 3)
   {
     struct B { double s0, om; };  // om: the other component of omega2
     double xb[3] = {0, 0, 0};
@@ -711,18 +697,17 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
     double y1b[3] = {0, 0, 0}, y3b[3] = {0, 0, 0};
     pipeline<D, B>(
         n + 3,
-        [&](int t, B& b) {
-          const int i = max(n - 1 - t, 0);
+        [&](int i, B& b) {
+          i = min(i, n - 1);
           b.s0 = at(LR(a.S[0], i), bcol);
           b.om = at(LR(a.om2, i), bocol);
         },
-        [&](int t, B& b) {
-          const int i = n - 1 - t;
+        [&](int i, B& b) {
           double u1 = 0.0, u3 = 0.0;
-          const double dv = i >= 0 ? back3(b.s0, U1d + (i >= 0 ? i : 0) * 4, xb) : 0.0;
-          const double dvo = __shfl_xor(dv, 1);
-          if (i >= 0) {
+          if (i < n) {
+            const double dv = back3(b.s0, U1u + i * 4, xb);
             push_x(xb, dv);
+            const double dvo = __shfl_xor(dv, 1);
             if (L.live) {
               // u1 = i(a dv - b omega2)/k^2, u3 = i(b dv + a omega2)/k^2 (dvo, om: other component)
               u1 = sg * (L.A * dvo - L.B * b.om) * L.ik2;
@@ -733,12 +718,12 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
               at(LR(a.ph[2], i), pcol) = (TP)u3;
             }
           }
-          push_front(w1, u1);
-          push_front(w3, u3);
-          const int r = i + 3;
-          if (r <= n - 1) {
+          push_back(w1, u1);
+          push_back(w3, u3);
+          const int r = i - 3;
+          if (r >= 0) {
             const double* bb = B1 + r * 7;
-            const double* l = L1u + r * 3;
+            const double* l = L1d + r * 3;
             const double y1 = elim3(dot7(bb, w1), l, y1b);
             const double y3 = elim3(dot7(bb, w3), l, y3b);
             if (L.act) {
@@ -750,25 +735,25 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           }
         });
   }
-  // ---- R3
+  // ---- R3 (up): finish du1, du3; omega1 = du3 - i b v, omega3 = i a v - du1
   {
     struct B { double s1, s2, v; };  // v: the other component
     double x1[3] = {0, 0, 0}, x3[3] = {0, 0, 0};
     pipeline<D, B>(
         n,
-        [&](int r, B& b) {
-          r = min(r, n - 1);
+        [&](int t, B& b) {
+          const int r = max(n - 1 - t, 0);
           b.s1 = at(LR(a.S[1], r), bcol);
           b.s2 = at(LR(a.S[2], r), bcol);
           b.v = at(LR(a.v, r), bocol);
         },
-        [&](int r, B& b) {
-          const double* U = U1u + r * 4;
+        [&](int t, B& b) {
+          const int r = n - 1 - t;
+          const double* U = U1d + r * 4;
           const double du1 = back3(b.s1, U, x1);
           const double du3 = back3(b.s2, U, x3);
           push_x(x1, du1);
           push_x(x3, du3);
-          // omega1 = du3 - i b v, omega3 = i a v - du1
           const double o1 = du3 - sg * L.B * b.v;
           const double o3 = sg * L.A * b.v - du1;
           if (wph) {
@@ -785,13 +770,12 @@ template <typename TH, typename TP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
     k_advance(AdvanceArgs<TH, TP> a, const double* __restrict__ B1, const double* __restrict__ A2,
               const double* __restrict__ B2, const double* __restrict__ L1d, const double* __restrict__ U1d,
-              const double* __restrict__ L1u, const double* __restrict__ U1u, const double* __restrict__ clo,
-              const double* __restrict__ chw) {
+              const double* __restrict__ L1u, const double* __restrict__ U1u) {
   if (blockIdx.x == gridDim.x - 1) {
     mean_block(a);
     return;
   }
-  advance_body(a, blockIdx.x, B1, A2, B2, L1d, U1d, L1u, U1u, clo, chw);
+  advance_body(a, blockIdx.x, B1, A2, B2, L1d, U1d, L1u, U1u);
 }
 
 // Batched over contexts: work item (context, block, -, mean flag).
@@ -805,15 +789,67 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
     return;
   }
   const PencilGeom& g = a.g;
-  advance_body(a, q.y, g.B1, g.A2, g.B2, g.L1d, g.U1d, g.L1u, g.U1u, g.clo, g.chi);
+  advance_body(a, q.y, g.B1, g.A2, g.B2, g.L1d, g.U1d, g.L1u, g.U1u);
 }
 
 // ---------------------------------------------------------------- homogeneous solutions
+// Row i of the transpose of a 7-band matrix with Dirichlet rows 0 and n - 1,
+// in band order: mt[3 + d] = M[i + d][i]; ent(j, o) is entry o of interior row j.
+template <typename F>
+__device__ __forceinline__ void transposed_row(double (&mt)[7], int i, int n, F&& ent) {
+#pragma unroll
+  for (int d = -3; d <= 3; ++d) {
+    const int j = i + d;
+    mt[3 + d] = (j < 0 || j > n - 1) ? 0.0 : (j == 0 || j == n - 1) ? (d == 0 ? 1.0 : 0.0) : ent(j, 3 - d);
+  }
+}
+
+// Solve M^T x = b for a 7-band M given by rows mrow (transposed_row): LU
+// factored on the fly downward (U rows to the mode-indexed scratch Q, the
+// eliminated right-hand side to the lane-indexed Y), back-substitution
+// upward; out(i, x) receives x_i from row n - 1 to 0.
+template <typename RowF, typename RhsF, typename OutF>
+__device__ __forceinline__ void solve_transposed(const Lane& L, int n, size_t st, size_t M, double* const (&Q)[4],
+                                                 double* Y, RowF&& mrow, RhsF&& rhs, OutF&& out) {
+  const size_t col = L.col, m = L.m;
+  double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  double yb[3] = {0, 0, 0};
+  for (int i = 0; i < n; ++i) {
+    double mt[7], lm[3];
+    mrow(mt, i);
+    factor_down(mt, uh, lm);
+    double y = rhs(i);
+#pragma unroll
+    for (int d = 3; d >= 1; --d) y -= lm[3 - d] * yb[3 - d];
+    const double u0 = 1.0 / mt[3];
+    if (L.act && L.c == 0) {
+      Q[0][i * M + m] = u0;
+      Q[1][i * M + m] = mt[4];
+      Q[2][i * M + m] = mt[5];
+      Q[3][i * M + m] = mt[6];
+    }
+    if (L.act) Y[i * st + col] = y;
+    push_u(uh, u0, mt[4], mt[5], mt[6]);
+    yb[0] = yb[1]; yb[1] = yb[2]; yb[2] = y;
+  }
+  double xb[3] = {0, 0, 0};
+  for (int i = n - 1; i >= 0; --i) {
+    const double u[4] = {Q[0][i * M + m], Q[1][i * M + m], Q[2][i * M + m], Q[3][i * M + m]};
+    const double x = back3(Y[i * st + col], u, xb);
+    push_x(xb, x);
+    out(i, x);
+  }
+}
+
 // For each sub-step s of a time step dt, per mode: chi_h with chi = 1 at wall
 // c (lane c) and zero forcing from the Helmholtz step, v_h from the Poisson
 // step with right-hand side A2 chi_h, and D1 v_h at both walls.  The same
 // sweeps (directions, on-the-fly factorisation, operation order) as the
-// particular solutions in k_advance.
+// particular solutions in k_advance.  Also the vectors w_c that give the wall
+// derivatives of the particular v from the chi right-hand side r of
+// k_advance: D1 v_p(wall c) = d_c . P^-1 E A2 H^-1 r = w_c . r with
+// w_c = H^-T A2^T E P^-T d_c (d_c the compact D1 row at wall c, E zeroing the
+// Dirichlet rows of the Poisson right-hand side).
 __global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
   const PencilGeom& g = a.g;
   const Lane L = lane_setup(g, blockIdx.x);
@@ -822,6 +858,34 @@ __global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
   const size_t col = L.col, m = L.m;
   const double* A2 = g.A2;
   const double* B2 = g.B2;
+  // t_c = A2^T E P^-T d_c (independent of dt), to a.T; z_c = E P^-T d_c is
+  // consumed row by row (lag 3)
+  {
+    double wz[7] = {0, 0, 0, 0, 0, 0, 0};
+    auto emit_t = [&](int r) {  // t at row r from wz[o] = (E z) at row r - 3 + o
+      double tr = 0.0;
+#pragma unroll
+      for (int o = 0; o < 7; ++o) {
+        const int j = r - 3 + o;
+        if (j >= 1 && j <= n - 2) tr += A2[j * 7 + 6 - o] * wz[o];
+      }
+      if (L.act) a.T[r * st + col] = tr;
+    };
+    solve_transposed(
+        L, n, st, M, a.Q, a.S0,
+        [&](double(&mt)[7], int i) {
+          transposed_row(mt, i, n, [&](int j, int o) { return B2[j * 7 + o] - L.k2 * A2[j * 7 + o]; });
+        },
+        [&](int i) { return L.c == 0 ? g.clo[i] : g.chi[i]; },
+        [&](int i, double z) {
+          push_front(wz, (i == 0 || i == n - 1) ? 0.0 : z);
+          if (i + 3 <= n - 1) emit_t(i + 3);
+        });
+    for (int r = 2; r >= 0; --r) {
+      push_front(wz, 0.0);
+      emit_t(r);
+    }
+  }
   for (int s = 0; s < 3; ++s) {
     const double cb = a.dt * a.be[s] * a.nu;
     const double hk = 1.0 + cb * L.k2;
@@ -899,7 +963,6 @@ __global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
         const double u[4] = {a.SU[4][r * M + m], a.SU[5][r * M + m], a.SU[6][r * M + m], a.SU[7][r * M + m]};
         const double vh = back3(a.S1[r * st + col], u, xhb);
         push_x(xhb, vh);
-        if (L.act) a.hv[s][r * st + col] = vh;
         glo = fma(g.clo[r], vh, glo);
         ghi = fma(g.chi[r], vh, ghi);
       }
@@ -911,6 +974,19 @@ __global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
         hm[2] = olo;
         hm[3] = ohi;
       }
+    }
+    // w_c = H^-T t_c
+    {
+      const double* T = a.T;
+      double* W = a.hw[s];
+      solve_transposed(
+          L, n, st, M, a.Q, a.S0,
+          [&](double(&mt)[7], int i) {
+            transposed_row(mt, i, n, [&](int j, int o) { return hk * A2[j * 7 + o] - cb * B2[j * 7 + o]; });
+          },
+          [&](int i) { return T[i * st + col]; }, [&](int i, double w) {
+            if (L.act) W[i * st + col] = w;
+          });
     }
   }
 }
@@ -1019,7 +1095,7 @@ hipError_t launch_homog(const HomogArgs& a, hipStream_t st) {
 
 template <typename TH, typename TP> hipError_t launch_advance(const AdvanceArgs<TH, TP>& a, hipStream_t st) {
   hipLaunchKernelGGL((k_advance<TH, TP>), dim3(pencil_blocks(a.g.M) + 1), dim3(256), 0, st, a, a.g.B1, a.g.A2,
-                     a.g.B2, a.g.L1d, a.g.U1d, a.g.L1u, a.g.U1u, a.g.clo, a.g.chi);
+                     a.g.B2, a.g.L1d, a.g.U1d, a.g.L1u, a.g.U1u);
   return hipGetLastError();
 }
 hipError_t launch_chi_from_v(const ChiArgs& a, hipStream_t st) {
