@@ -1,4 +1,5 @@
-"""Low-storage database stage: sharp cut-off filter, filtered stresses, SGS tensor (oracle).
+"""Low-storage database stage: sharp cut-off filter, filtered stresses, SGS tensor,
+filtered enstrophy (oracle).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
@@ -20,6 +21,11 @@ tau_ij = F(u_i u_j) - F(u_i) F(u_j) follows.  Readings:
   tau is therefore evaluated from the fluctuations u_i - <u_i>, which avoids
   cancelling the large U_i U_j terms in rounding.  F(u_i u_j) itself is
   formed from the full fields.
+
+The tenth variable of the database is the filtered enstrophy
+F(omega_i omega_i): the sum of the squared vorticity components, formed from
+the full vorticity (mean shear included) on the 3/2 padded grid like the
+products u_i u_j, then cut off to K_c.
 
 Output layouts: retained modes ``[n2][kcx+1][2kcz+1]`` with kz in FFT slot
 order (0..kcz, then -kcz..-1); tau ``[6][n2][q3][q1]`` for the pairs
@@ -78,3 +84,14 @@ def filter_and_stress(u1, u2, u3, kcx, kcz, q1, q3):
     uuq = synth_plane(filtered_products(fl), q1, q3)
     tau = np.stack([uuq[p] - ubq[i] * ubq[j] for p, (i, j) in enumerate(PAIRS)])
     return ub, uu, tau
+
+
+def filtered_enstrophy(om1, om2, om3, kcx, kcz):
+    """F(omega_i omega_i) on K_c from the full vorticity fields om*[n2][n1/2][n3] (Section 3.1)."""
+    n2, n1h, n3 = om1.shape
+    n1 = 2 * n1h
+    p1, p3 = fourier.padded_size(n1), fourier.padded_size(n3)
+    e = np.zeros((n2, p3, p1))
+    for w in (om1, om2, om3):
+        e += fourier.to_physical(w, p1, p3) ** 2
+    return truncate(fourier.to_spectral(e, n1, n3), kcx, kcz)

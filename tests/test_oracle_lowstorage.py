@@ -8,7 +8,11 @@
 * a single mode u1 = A cos(k x) with k > kc has tau_11 = A^2/2;
 * tau is invariant to adding a plane-constant c(y) to the velocity;
 * tau equals the Germano decomposition -(1-G)(ub_i ub_j) + G(ub_i u''_j +
-  u''_i ub_j + u''_i u''_j), u'' = u - ub.
+  u''_i ub_j + u''_i u''_j), u'' = u - ub;
+* the filtered enstrophy F(omega_i omega_i) equals the exact self-convolution
+  of the three vorticity mode sets (no FFT), its (0,0) mode equals the plane
+  mean sum_i sum_k |omega_i(k)|^2 (Parseval, a direct sum), and a pure mean
+  shear W(y) gives W^2 in mode (0,0) and nothing else.
 """
 import numpy as np
 import pytest
@@ -115,3 +119,41 @@ def test_germano_decomposition():
         bb = ubf[i] * ubf[j]
         germ = -(ubq[i] * ubq[j] - G(bb)) + G(ubf[i] * upp[j] + upp[i] * ubf[j] + upp[i] * upp[j])
         assert np.abs(germ - tau[p]).max() < 1e-13 * np.abs(ubq[i] * ubq[j]).max()
+
+
+@pytest.mark.parametrize("kcx,kcz", [(2, 2), (3, 4)])
+def test_filtered_enstrophy_brute_force(kcx, kcz):
+    rng = np.random.default_rng(11)
+    w = [_field(rng) for _ in range(3)]
+    ens = lowstorage.filtered_enstrophy(*w, kcx, kcz)
+    slots = lowstorage.kc_slots(N3, kcz)
+    kzs = [s if s < N3 // 2 else s - N3 for s in slots]
+    for y in range(N2):
+        modes = [brute.full_modes(wi[y]) for wi in w]
+        prods = [brute.product_modes(m, m) for m in modes]
+        for kx in range(kcx + 1):
+            for c, kz in enumerate(kzs):
+                ref = sum(p.get((kx, kz), 0) for p in prods)
+                assert abs(ens[y, kx, c] - ref) < 1e-13 * (1 + abs(ref)), (y, kx, kz)
+
+
+def test_filtered_enstrophy_parseval():
+    rng = np.random.default_rng(12)
+    w = [_field(rng) for _ in range(3)]
+    ens = lowstorage.filtered_enstrophy(*w, 1, 1)
+    for y in range(N2):
+        ref = sum(sum(abs(c) ** 2 for c in brute.full_modes(wi[y]).values()) for wi in w)
+        assert abs(ens[y, 0, 0] - ref) < 1e-13 * ref
+        assert abs(ens[y, 0, 0].imag) < 1e-13 * ref
+
+
+def test_filtered_enstrophy_of_a_mean_shear():
+    W = 0.5 + np.arange(N2)
+    z = np.zeros((N2, N1 // 2, N3), complex)
+    w3 = z.copy()
+    w3[:, 0, 0] = W
+    ens = lowstorage.filtered_enstrophy(z, z, w3, 2, 2)
+    assert np.abs(ens[:, 0, 0] - W ** 2).max() < 1e-13 * W.max() ** 2
+    rest = ens.copy()
+    rest[:, 0, 0] = 0
+    assert np.abs(rest).max() < 1e-13 * W.max() ** 2
