@@ -95,3 +95,20 @@ def filtered_enstrophy(om1, om2, om3, kcx, kcz):
     for w in (om1, om2, om3):
         e += fourier.to_physical(w, p1, p3) ** 2
     return truncate(fourier.to_spectral(e, n1, n3), kcx, kcz)
+
+
+def spectra(u1, u2, u3):
+    """Two-dimensional spectra |u_i(kx, y, kz)|^2 of one sample (the paper's E_ii
+    before the ensemble average), on the stored half-plane of modes, with the
+    mean mode (0,0) set to zero (fluctuations only): [3][n2][n1/2][n3]."""
+    E = np.stack([np.abs(u) ** 2 for u in (u1, u2, u3)])
+    E[:, :, 0, 0] = 0.0
+    return E
+
+
+def rms_profiles(E):
+    """Plane-mean squared fluctuations <u'_i u'_i>(y) from spectra E[3][n2][n1/2][n3]
+    (Parseval: a stored kx > 0 mode stands for +kx and -kx)."""
+    w = np.full(E.shape[-2], 2.0)
+    w[0] = 1.0
+    return np.einsum("iykz,k->iy", E, w)

@@ -12,7 +12,9 @@
 * the filtered enstrophy F(omega_i omega_i) equals the exact self-convolution
   of the three vorticity mode sets (no FFT), its (0,0) mode equals the plane
   mean sum_i sum_k |omega_i(k)|^2 (Parseval, a direct sum), and a pure mean
-  shear W(y) gives W^2 in mode (0,0) and nothing else.
+  shear W(y) gives W^2 in mode (0,0) and nothing else;
+* the spectra summed with the Hermitian weights give the plane mean of the
+  squared fluctuation computed pointwise from a direct synthesis (no FFT).
 """
 import numpy as np
 import pytest
@@ -157,3 +159,19 @@ def test_filtered_enstrophy_of_a_mean_shear():
     rest = ens.copy()
     rest[:, 0, 0] = 0
     assert np.abs(rest).max() < 1e-13 * W.max() ** 2
+
+
+def test_spectra_parseval_against_direct_synthesis():
+    rng = np.random.default_rng(13)
+    u = [_field(rng) for _ in range(3)]
+    E = lowstorage.spectra(*u)
+    msq = lowstorage.rms_profiles(E)
+    x = np.arange(N1)[None, :] * LX / N1
+    z = np.arange(N3)[:, None] * LZ / N3
+    for y in range(N2):
+        for i in range(3):
+            modes = {k: c for k, c in brute.full_modes(u[i][y]).items() if k != (0, 0)}
+            f = brute.synth_points(modes, LX, LZ, x, z)
+            ref = float(np.mean(f ** 2))
+            assert abs(msq[i, y] - ref) < 1e-13 * ref, (i, y)
+    assert np.all(E[:, :, 0, 0] == 0)
