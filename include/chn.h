@@ -161,6 +161,34 @@ chn_status chn_nonlinear(chn_ctx *ctx, const double *const *d_in, double *const 
 chn_status chn_filter_and_stress(chn_ctx *ctx, int32_t kcx, int32_t kcz, int32_t q1, int32_t q3,
                                  double *d_ubar, double *d_uubar, double *d_tau);
 
+/* Filtered enstrophy of Section 3.1 (the tenth variable of the database):
+ * F(omega_i omega_i), the sharp cut-off (0 <= kx <= kcx, |kz| <= kcz) of
+ * omega_1^2 + omega_2^2 + omega_3^2 formed on the 3n1/2 x 3n3/2 grid of
+ * every plane from the vorticity of the current state (omega1, omega3 by
+ * continuity and compact D1, the mean vorticity D1 U3, -D1 U1 included).
+ * d_out: DEVICE, complex float64 [n2][kcx+1][2kcz+1], kz in slot order as
+ * for chn_filter_and_stress; owned by the caller.  Float64 transforms and
+ * products on both precisions.  CHN_EINVAL for a cut-off outside
+ * 0 <= kcx < n1/2, 0 <= kcz < n3/2 or a NULL pointer; CHN_ESTATE before
+ * chn_set_state; CHN_EUNSUPPORTED on a planes_only context or where the
+ * workspace cannot hold the retained products.  Uses the scratch of
+ * chn_filter_and_stress; the state is unchanged. */
+chn_status chn_filtered_enstrophy(chn_ctx *ctx, int32_t kcx, int32_t kcz, double *d_out);
+
+/* On-the-fly statistics (Section 3: the runs' one-point statistics and the
+ * two-dimensional spectra E_ii(kx, x2, kz) = <u_i u_i*>): adds, for the
+ * current state, |u_i(kx, y, kz)|^2 of every stored mode except the mean
+ * mode (0,0) to d_spec (DEVICE, float64 [3][n2][n1/2][n3], i = 1, 2, 3) and
+ * the mean profiles U1(y), U3(y) to d_mean (DEVICE, float64 [2][n2]).  Both
+ * buffers are owned by the caller, who zeroes them before the first call and
+ * divides by the number of calls.  A stored kx > 0 mode stands for +kx and
+ * -kx, so the plane-mean squared fluctuation is
+ * sum_kz (E(0, kz) + 2 sum_{kx>0} E(kx, kz)).  Read from the velocity fields
+ * the step already produces, in the context's transform precision (float32
+ * values on CHN_MIXED).  CHN_EINVAL for a NULL pointer; CHN_ESTATE before
+ * chn_set_state; CHN_EUNSUPPORTED on a planes_only context. */
+chn_status chn_accumulate_statistics(chn_ctx *ctx, double *d_spec, double *d_mean);
+
 /* Dealiased products of Section 2.1 on every plane (the plane phase of the
  * sub-step): d_in[0..5] = u1, u2, u3, omega1, omega2, omega3 and d_out[0..2] =
  * H1, H2, H3 of H = u x omega, DEVICE pointers in the layout

@@ -61,6 +61,8 @@ def lib():
         L.chn_get_fields.argtypes = [P, C.c_uint32, C.POINTER(P)]
         L.chn_nonlinear.argtypes = [P, C.POINTER(P), C.POINTER(P)]
         L.chn_filter_and_stress.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P]
+        L.chn_filtered_enstrophy.argtypes = [P, C.c_int32, C.c_int32, P]
+        L.chn_accumulate_statistics.argtypes = [P, P, P]
         L.chn_get_operators.argtypes = [P, P, P, P, P, P]
         L.chn_get_plan.argtypes = [P, C.POINTER(Plan)]
         L.chn_plane_products.argtypes = [P, C.POINTER(P), C.POINTER(P)]
@@ -80,9 +82,10 @@ def lib():
         L.chn_last_error.argtypes = [P]
         L.chn_last_error.restype = C.c_char_p
         for name in ("chn_create", "chn_destroy", "chn_set_state", "chn_step_rk3", "chn_get_fields",
-                     "chn_nonlinear", "chn_filter_and_stress", "chn_get_operators", "chn_timing_enable",
-                     "chn_timing_read", "chn_ens_create", "chn_ens_destroy", "chn_ens_step", "chn_get_plan",
-                     "chn_set_plan", "chn_autotune", "chn_plane_products"):
+                     "chn_nonlinear", "chn_filter_and_stress", "chn_filtered_enstrophy", "chn_accumulate_statistics",
+                     "chn_get_operators",
+                     "chn_timing_enable", "chn_timing_read", "chn_ens_create", "chn_ens_destroy", "chn_ens_step",
+                     "chn_get_plan", "chn_set_plan", "chn_autotune", "chn_plane_products"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -205,6 +208,22 @@ class Channel:
         self._check(self.L.chn_filter_and_stress(self.ctx, kcx, kcz, q1, q3, _ptr(ub), _ptr(uu), _ptr(tau)),
                     "chn_filter_and_stress")
         return ub, uu, tau
+
+    def filtered_enstrophy(self, kcx, kcz):
+        """F(omega_i omega_i) on 0 <= kx <= kcx, |kz| <= kcz: complex128 [n2][kcx+1][2kcz+1]."""
+        out = torch.empty((self.n2, kcx + 1, 2 * kcz + 1), dtype=torch.complex128, device=self.device)
+        self._check(self.L.chn_filtered_enstrophy(self.ctx, kcx, kcz, _ptr(out)), "chn_filtered_enstrophy")
+        return out
+
+    def accumulate_statistics(self, spec=None, mean=None):
+        """Adds |u_i|^2 per mode (mean mode excluded) to spec [3][n2][n1/2][n3] and U1, U3
+        to mean [2][n2] (float64 device tensors, zeroed here when not given)."""
+        if spec is None:
+            spec = torch.zeros((3, self.n2, self.n1h, self.n3), dtype=torch.float64, device=self.device)
+        if mean is None:
+            mean = torch.zeros((2, self.n2), dtype=torch.float64, device=self.device)
+        self._check(self.L.chn_accumulate_statistics(self.ctx, _ptr(spec), _ptr(mean)), "chn_accumulate_statistics")
+        return spec, mean
 
     def plan(self):
         p = Plan()

@@ -484,18 +484,22 @@ chn_status need_fields(chn_ctx* x);
 // float32 transforms reaches 1e-4 in tau.  The mixed path stores the
 // velocity coefficients in float32 (every term of tau then sees the same
 // rounded data) and keeps the transforms and products in float64.
+// With d_ens the same transforms run on the vorticity (omega1, omega2,
+// omega3) instead of the velocity, and only the trace F(omega_i omega_i), the
+// filtered enstrophy, is written (q1, q3, d_ubar, d_uubar, d_tau unused).
 chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_ubar, double* d_uubar,
-                        double* d_tau) {
+                        double* d_tau, double* d_ens = nullptr) {
   using C = double2;
+  const bool ens = d_ens != nullptr;
   const int n2 = x->n2, n1h = x->n1h, n3 = x->n3, p1 = x->p1, p3 = x->p3;
   const size_t te = sizeof(C);
   // slots of the intermediate per plane: float64 data in a float32-sized buffer on the mixed path
   const int nslot = x->mixed ? 3 : 6;
   const size_t plane_bytes = (size_t)(x->mixed ? 6 * 8 : 6 * 16) * p3 * n1h;
-  if (!d_ubar || !d_uubar) return fail(x, CHN_EINVAL, "NULL output pointer");
+  if (!ens && (!d_ubar || !d_uubar)) return fail(x, CHN_EINVAL, "NULL output pointer");
   if (kcx < 0 || kcz < 0 || kcx >= n1h || kcz >= n3 / 2) return fail(x, CHN_EINVAL, "need 0 <= kcx < n1/2, 0 <= kcz < n3/2");
-  if (q1 <= 2 * kcx || q3 <= 2 * kcz || (q1 % 2) || (q3 % 2) || !smooth23(q1) || !smooth23(q3) || q1 > kMaxQ ||
-      q3 > kMaxQ)
+  if (!ens && (q1 <= 2 * kcx || q3 <= 2 * kcz || (q1 % 2) || (q3 % 2) || !smooth23(q1) || !smooth23(q3) ||
+               q1 > kMaxQ || q3 > kMaxQ))
     return fail(x, CHN_EINVAL, "q1, q3 must be even, 2,3-smooth, <= 4096 and exceed 2 kcx, 2 kcz");
   const int kc1 = kcx + 1, nz = 2 * kcz + 1;
   const size_t NP = (size_t)n2 * x->M;
@@ -506,7 +510,7 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   if (!x->mixed && (size_t)6 * p3 * kc1 * 16 > (size_t)3 * p3 * n1h * te) return fail(x, CHN_EUNSUPPORTED, "kcx too large for the workspace");
   if (x->mixed && (size_t)6 * n2 * p3 * kc1 * 16 > 3 * 16 * NP) return fail(x, CHN_EUNSUPPORTED, "kcx too large for the workspace");
   if ((size_t)6 * n2 * kc1 * nz * 16 > hbytes) return fail(x, CHN_EUNSUPPORTED, "cut-off too large for the workspace");
-  if ((size_t)9 * n2 * q3 * kc1 * 16 > x->inter_bytes) return fail(x, CHN_EUNSUPPORTED, "q grid too large for the workspace");
+  if (!ens && (size_t)9 * n2 * q3 * kc1 * 16 > x->inter_bytes) return fail(x, CHN_EUNSUPPORTED, "q grid too large for the workspace");
   if (p1 > 12 * 256) return fail(x, CHN_EUNSUPPORTED, "3*n1/2 too large for the filter x-pass");
   const size_t lds_x = (size_t)3 * (p1 + 1) * 16;
   const size_t lds_t = (size_t)5 * (q1 + 1) * 16;
@@ -518,38 +522,48 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
     if (K > cap) K = cap;
     return K < 1 ? 1 : K;
   };
-  const int Kf = lines(p3, kc1), Kq = lines(q3, kc1);
+  const int Kf = lines(p3, kc1), Kq = ens ? 1 : lines(q3, kc1);
   if (lds_x > (size_t)x->lds_max || lds_t > (size_t)x->lds_max || (size_t)(p3 + 1) * 16 > (size_t)x->lds_max ||
       2 * p1 > 24 * 256 || p1 > 24 * 256 || p3 > 24 * 256 || 5 * q1 > 24 * 256 ||
       q3 > 24 * 256)
     return fail(x, CHN_EUNSUPPORTED, "plane too large for the filter kernels' LDS tiles on this device");
   // q-grid FFT tables
   FftPlan pq1{}, pq3{};
-  std::vector<double> t1, t3;
-  if (!chn::host::fft_plan(q1, &pq1, &t1) || !chn::host::fft_plan(q3, &pq3, &t3))
-    return fail(x, CHN_EINVAL, "q grid not supported");
-  x->twq_host.assign(t1.begin(), t1.end());
-  x->twq_host.resize(2 * kMaxQ, 0.0);
-  x->twq_host.insert(x->twq_host.end(), t3.begin(), t3.end());
-  HIPCHK(x, hipMemcpyAsync(x->twq, x->twq_host.data(), x->twq_host.size() * 8, hipMemcpyHostToDevice, x->stream));
+  if (!ens) {
+    std::vector<double> t1, t3;
+    if (!chn::host::fft_plan(q1, &pq1, &t1) || !chn::host::fft_plan(q3, &pq3, &t3))
+      return fail(x, CHN_EINVAL, "q grid not supported");
+    x->twq_host.assign(t1.begin(), t1.end());
+    x->twq_host.resize(2 * kMaxQ, 0.0);
+    x->twq_host.insert(x->twq_host.end(), t3.begin(), t3.end());
+    HIPCHK(x, hipMemcpyAsync(x->twq, x->twq_host.data(), x->twq_host.size() * 8, hipMemcpyHostToDevice, x->stream));
+  }
   const double2* twq1 = x->twq;
   const double2* twq3 = x->twq + kMaxQ;
-  // 1. float64 spectra of u1, u2, u3 (and the vorticities, unused here);
-  //    mixed: rounded to float32 in place (the stored data of that path)
+  // 1. float64 spectra of u1, u2, u3, omega1, omega3 (omega2 is the state);
+  //    mixed: the velocities rounded to float32 in place (the stored data of
+  //    that path; the enstrophy is formed from the float64 vorticity)
   double* su[5] = {x->S[3], x->S[4], x->S[5], x->S[6], x->S[7]};
   x->htab_dt = 0.0;  // overwrites the factor tables of sub-steps 1 and 2
   if (chn_status st = recover<double>(x, su)) return st;
-  if (x->mixed) {
-    x->phase_valid = false;
+  double* fin[3] = {x->S[3], x->S[4], x->S[5]};
+  if (ens) {
+    fin[0] = x->S[6];
+    fin[1] = x->om2;
+    fin[2] = x->S[7];
+  }
+  if (x->mixed && !ens) {
+    // the plane intermediate (9 n2 M float64 or more) is free until step 2;
+    // the phase fields stay valid for the next sub-step
     for (int f = 0; f < 3; ++f) {
-      float* tmp = reinterpret_cast<float*>(x->ph[f]);
+      float* tmp = reinterpret_cast<float*>(x->inter);
       HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_convert_d2f(x->S[3 + f], tmp, 2 * NP, x->stream); }));
       HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_convert_f2d(tmp, x->S[3 + f], 2 * NP, x->stream); }));
     }
   }
   // 2. z inverse of the fluctuations
   chn::ZinvArgs<double> za{};
-  for (int f = 0; f < 3; ++f) za.in[f] = reinterpret_cast<const C*>(x->S[3 + f]);
+  for (int f = 0; f < 3; ++f) za.in[f] = reinterpret_cast<const C*>(fin[f]);
   za.out = reinterpret_cast<C*>(x->inter);
   za.tw = x->tw3d;
   za.plan = x->plan3;
@@ -588,10 +602,11 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   chn::ZfilterArgs fa{};
   fa.xout = xa.out;
   fa.plane_stride = xa.plane_stride;
-  for (int f = 0; f < 3; ++f) fa.u[f] = x->S[3 + f];
+  for (int f = 0; f < 3; ++f) fa.u[f] = fin[f];
   fa.pp = reinterpret_cast<double2*>(x->H[0]);
-  fa.uubar = reinterpret_cast<double2*>(d_uubar);
-  fa.ubar = reinterpret_cast<double2*>(d_ubar);
+  fa.uubar = ens ? nullptr : reinterpret_cast<double2*>(d_uubar);
+  fa.ubar = ens ? nullptr : reinterpret_cast<double2*>(d_ubar);
+  fa.trace = ens ? reinterpret_cast<double2*>(d_ens) : nullptr;
   fa.tw = x->tw3d;
   fa.plan = x->plan3;
   fa.d = x->dims;
@@ -603,7 +618,7 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   HIPCHK(x, timed(x, CHN_K_FILTER, [&] {
     return chn::launch_zfilter(fa, (size_t)Kf * (p3 + 1) * 16, x->stream);
   }));
-  if (!d_tau) return CHN_OK;
+  if (ens || !d_tau) return CHN_OK;
   // 5. q grid: inverse in z, then in x with tau = pp - ub ub
   chn::ZinvQArgs qa{};
   qa.pp = fa.pp;
@@ -1157,6 +1172,46 @@ chn_status chn_filter_and_stress(chn_ctx* x, int32_t kcx, int32_t kcz, int32_t q
   if (chn_status s = check(x)) return s;
   if (!x->have_state) return fail(x, CHN_ESTATE, "chn_filter_and_stress before chn_set_state");
   return filter_stage(x, kcx, kcz, q1, q3, d_ubar, d_uubar, d_tau);
+}
+
+extern "C++" {
+namespace {
+template <typename T> chn_status stats_stage(chn_ctx* x, double* d_spec, double* d_mean) {
+  T* po[5];
+  phase_ptrs<T>(x, po);
+  if (!x->phase_valid) {  // the velocities of a new state (after a step they are current)
+    if (chn_status st = recover<T>(x, po)) return st;
+    x->phase_valid = true;
+  }
+  chn::StatsArgs<T> a{};
+  for (int i = 0; i < 3; ++i) a.u[i] = reinterpret_cast<const typename Ty<T>::c*>(po[i]);
+  a.spec = d_spec;
+  a.mean = d_mean;
+  a.U1 = x->U1;
+  a.U3 = x->U3;
+  a.M = x->M;
+  a.NP = (size_t)x->n2 * x->M;
+  a.n2 = x->n2;
+  HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_stats<T>(a, x->stream); }));
+  return CHN_OK;
+}
+}  // namespace
+}  // extern "C++"
+
+chn_status chn_accumulate_statistics(chn_ctx* x, double* d_spec, double* d_mean) {
+  if (chn_status s = check(x)) return s;
+  if (chn_status s = need_fields(x)) return s;
+  if (!x->have_state) return fail(x, CHN_ESTATE, "chn_accumulate_statistics before chn_set_state");
+  if (!d_spec || !d_mean) return fail(x, CHN_EINVAL, "NULL output pointer");
+  return x->mixed ? stats_stage<float>(x, d_spec, d_mean) : stats_stage<double>(x, d_spec, d_mean);
+}
+
+chn_status chn_filtered_enstrophy(chn_ctx* x, int32_t kcx, int32_t kcz, double* d_out) {
+  if (chn_status s = check(x)) return s;
+  if (chn_status s = need_fields(x)) return s;
+  if (!x->have_state) return fail(x, CHN_ESTATE, "chn_filtered_enstrophy before chn_set_state");
+  if (!d_out) return fail(x, CHN_EINVAL, "NULL output pointer");
+  return filter_stage(x, kcx, kcz, 0, 0, nullptr, nullptr, nullptr, d_out);
 }
 
 chn_status chn_get_operators(chn_ctx* x, double* a1, double* b1, double* a2, double* b2, double* quad) {

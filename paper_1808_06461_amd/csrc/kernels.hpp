@@ -80,8 +80,9 @@ struct ZfilterArgs {
   size_t plane_stride;
   const double* u[3];    // float64 spectral u1, u2, u3 (full mode set)
   double2* pp;           // [6][n2][kcx+1][2kcz+1] F(u'_i u'_j)
-  double2* uubar;        // [6][n2][kcx+1][2kcz+1] F(u_i u_j)
-  double2* ubar;         // [3][n2][kcx+1][2kcz+1] F(u_i)
+  double2* uubar;        // [6][n2][kcx+1][2kcz+1] F(u_i u_j), or nullptr
+  double2* ubar;         // [3][n2][kcx+1][2kcz+1] F(u_i), or nullptr
+  double2* trace;        // [n2][kcx+1][2kcz+1] F(u_i u_i) (sum over i), or nullptr
   const double2* tw;     // p3 plan, float64
   FftPlan plan;
   PlaneDims d;
@@ -105,6 +106,19 @@ struct XtauArgs {
   FftPlan plan;
   int n2, q1, q3, kcx, lstride;
 };
+
+// On-the-fly statistics: running sums of |u_i|^2 per mode (mean mode
+// excluded) and of the mean profiles
+template <typename TP> struct StatsArgs {
+  const c2<TP>* u[3];    // u1, u2, u3 spectral [n2][M] (the phase fields)
+  double* spec;          // [3][n2][M], += |u_i|^2
+  double* mean;          // [2][n2], += U1, U3
+  const double* U1;
+  const double* U3;
+  size_t NP, M;
+  int n2;
+};
+template <typename TP> hipError_t launch_stats(const StatsArgs<TP>& a, hipStream_t st);
 
 template <typename T> hipError_t launch_xfilter(const XfilterArgs<T>& a, size_t lds_bytes, hipStream_t st);
 hipError_t launch_zfilter(const ZfilterArgs& a, size_t lds_bytes, hipStream_t st);

@@ -100,7 +100,8 @@ __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
 
 // Per (y, tile of retained kx): forward z transform of the six products,
 // F(u'_i u'_j) on |kz| <= kcz -> pp; F(u_i u_j) with the mean terms -> uubar;
-// F(u_i) -> ubar.
+// F(u_i) -> ubar; the trace F(u_i u_i) -> trace (fed the vorticity, the
+// filtered enstrophy of Section 3.1).  Each output but pp is optional.
 __global__ void __launch_bounds__(256) k_zfilter(ZfilterArgs a) {
   extern __shared__ unsigned char smem_raw[];
   double2* lds = reinterpret_cast<double2*>(smem_raw);
@@ -117,7 +118,7 @@ __global__ void __launch_bounds__(256) k_zfilter(ZfilterArgs a) {
   const double2* uh[3] = {reinterpret_cast<const double2*>(a.u[0]), reinterpret_cast<const double2*>(a.u[1]),
                           reinterpret_cast<const double2*>(a.u[2])};
   // F(u_i) on the retained set
-  for (int e = threadIdx.x; e < 3 * nk * nz; e += blockDim.x) {
+  for (int e = threadIdx.x; a.ubar && e < 3 * nk * nz; e += blockDim.x) {
     const int i = e / (nk * nz), r = e - i * nk * nz, l = r / nz, s = r - l * nz;
     const double2 v = uh[i][(size_t)y * M + (size_t)(kx0 + l) * n3 + slot(s)];
     a.ubar[(((size_t)i * a.d.n2 + y) * kc1 + kx0 + l) * nz + s] = v;
@@ -148,7 +149,12 @@ __global__ void __launch_bounds__(256) k_zfilter(ZfilterArgs a) {
       }
       double2 uu = make_double2(pp.x + U[i] * uj.x + U[j] * ui.x, pp.y + U[i] * uj.y + U[j] * ui.y);
       if (k0) uu.x += U[i] * U[j];
-      a.uubar[o] = uu;
+      if (a.uubar) a.uubar[o] = uu;
+      if (a.trace && i == j) {  // pairs 11, 22, 33 in that order; this thread owns the entry
+        const size_t ot = ((size_t)y * kc1 + kx0 + l) * nz + s;
+        const double2 acc = f == 0 ? make_double2(0.0, 0.0) : a.trace[ot];
+        a.trace[ot] = make_double2(acc.x + uu.x, acc.y + uu.y);
+      }
     }
     __syncthreads();
   }
@@ -244,7 +250,35 @@ __global__ void __launch_bounds__(256) k_xtau(XtauArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- statistics
+// One thread per mode-point: the running sums of the two-dimensional spectra
+// E_ii(kx, y, kz) = |u_i|^2 (the mean mode (0,0) left out: fluctuations) and,
+// on the first mode of each plane, of the mean profiles U1(y), U3(y).
+template <typename TP>
+__global__ void __launch_bounds__(256) k_stats(StatsArgs<TP> a) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.NP) return;
+  const size_t y = idx / a.M, m = idx - y * a.M;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const c2<TP> u = a.u[i][idx];
+    const double re = (double)u.x, im = (double)u.y;
+    a.spec[(size_t)i * a.NP + idx] += m == 0 ? 0.0 : re * re + im * im;
+  }
+  if (m == 0) {
+    a.mean[y] += a.U1[y];
+    a.mean[a.n2 + y] += a.U3[y];
+  }
+}
+
 // ---------------------------------------------------------------- launchers
+template <typename TP> hipError_t launch_stats(const StatsArgs<TP>& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_stats<TP>, dim3((unsigned)((a.NP + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+template hipError_t launch_stats<double>(const StatsArgs<double>&, hipStream_t);
+template hipError_t launch_stats<float>(const StatsArgs<float>&, hipStream_t);
+
 template <typename T>
 hipError_t launch_xfilter(const XfilterArgs<T>& a, size_t lds_bytes, hipStream_t st) {
   constexpr int MV = sizeof(T) == 8 ? 24 : 48;

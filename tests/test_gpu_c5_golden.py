@@ -6,7 +6,9 @@ samples of F(u_i), F(u_i u_j) and tau_ij on the planes y_3, y_96 and y_192;
 the GPU computes every plane with the launch configuration of the full stage
 and is compared there: e(X) = ||X_gpu[s] - X_oracle[s]|| / ||X_oracle[s]||
 per component.  Bounds: float64 as for the small cases (F(u_i) 1e-13,
-F(u_i u_j) 1e-12, tau 1e-10); mixed 1e-5 on F(u_i u_j) and tau.
+F(u_i u_j) 1e-12, tau 1e-10); mixed 1e-5 on F(u_i u_j) and tau.  The
+filtered enstrophy F(omega_i omega_i) (float64 from the float64 vorticity on
+both paths) is compared on its own seeded samples and its (0,0) mode: 1e-12.
 """
 import os
 
@@ -58,5 +60,13 @@ def test_c5_filter_against_oracle_samples(field, precision):
             assert max(e_ub) <= t_ub, (p, e_ub)
             assert max(e_uu) <= t_uu, (p, e_uu)
             assert max(e_tau) <= t_tau, (p, e_tau)
+        ens = ch.filtered_enstrophy(kcx, kcz)
+        for p in (int(p) for p in g["planes"]):
+            ek, ez = torch.from_numpy(g[f"y{p}_ek"]), torch.from_numpy(g[f"y{p}_ez"])
+            got = ens[p].cpu()[ek, ez].numpy()
+            e_ens = rel(got, g[f"y{p}_ens"])
+            e_00 = abs(complex(ens[p, 0, 0].item()) - complex(g[f"y{p}_ens00"])) / abs(complex(g[f"y{p}_ens00"]))
+            print(f"[c5] {precision} y{p}: enstrophy {e_ens:.2e}, mode (0,0) {e_00:.2e}", flush=True)
+            assert e_ens <= 1e-12 and e_00 <= 1e-12, (p, e_ens, e_00)
     finally:
         ch.close()

@@ -1,9 +1,12 @@
-"""Parity of the low-storage stage (chn_filter_and_stress) with the oracle.
+"""Parity of the low-storage stage (chn_filter_and_stress, chn_filtered_enstrophy) with the oracle.
 
 Float64 path: 1e-12 relative per output component.  Mixed path (velocity
 coefficients stored in float32, transforms and products in float64): 1e-7
 on F(u_i) (the float32 rounding of the data) and 1e-5 relative on
-F(u_i u_j) and tau_ij, the bound the workload states.
+F(u_i u_j) and tau_ij, the bound the workload states.  The filtered
+enstrophy is formed from the float64 vorticity on both paths: 1e-12.
+Filter calls reuse pencil scratch that holds per-dt factor tables, so time
+stepping after them must match uninterrupted stepping bit for bit.
 """
 import numpy as np
 import pytest
@@ -76,3 +79,78 @@ def test_device_limits_report():
     print("device:", p.name, "LDS/block:", getattr(p, "shared_memory_per_block", None),
           "LDS/block optin:", getattr(p, "shared_memory_per_block_optin", None),
           "multiprocessors:", p.multi_processor_count)
+
+
+def _ens_case(name, kc=None):
+    case, kcx, kcz, _, _ = CASES[name]
+    if kc is not None:
+        kcx, kcz = kc
+    v, om, U1, U3, y = synth.turbulent_field(case)
+    S = kmm.Setup(n1=case.n1, n2=case.n2, n3=case.n3, lx=case.lx, lz=case.lz, nu=1 / case.re_b, dt=1e-3,
+                  mass_flux=2.0, y=y)
+    *_, o1, o2, o3 = kmm.recover(S, kmm.make_state(S, v, om, U1, U3))
+    return case, (v, om, U1, U3, y), kcx, kcz, lowstorage.filtered_enstrophy(o1, o2, o3, kcx, kcz)
+
+
+@gpu
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["small", "ragged", "mid"])
+def test_filtered_enstrophy(name, precision):
+    from paper_1808_06461_amd import Channel
+    case, (v, om, U1, U3, y), kcx, kcz, ref = _ens_case(name)
+    ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, precision=precision, y=y)
+    try:
+        ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+        got = ch.filtered_enstrophy(kcx, kcz).cpu().numpy()
+        e = rel(got, ref)
+        e0 = float(np.abs(got[:, 0, 0] - ref[:, 0, 0]).max() / np.abs(ref[:, 0, 0]).max())
+        print(f"{precision} {name}: enstrophy {e:.2e}, mode (0,0) {e0:.2e}")
+        assert e < 1e-12 and e0 < 1e-12, (e, e0)
+    finally:
+        ch.close()
+
+
+@gpu
+@pytest.mark.parametrize("kc", [(0, 0), (7, 11)])
+def test_filtered_enstrophy_extreme_cutoffs(kc):
+    """Only the (0,0) mode, and the largest cut-off the 32 x 24 context's
+    workspace holds (every kz; half the kx); beyond it CHN_EUNSUPPORTED."""
+    from paper_1808_06461_amd import Channel, ChnError
+    case, (v, om, U1, U3, y), kcx, kcz, ref = _ens_case("small", kc)
+    ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, precision="fp64", y=y)
+    try:
+        ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+        e = rel(ch.filtered_enstrophy(kcx, kcz).cpu().numpy(), ref)
+        print(f"kc={kc}: {e:.2e}")
+        assert e < 1e-12, e
+        with pytest.raises(ChnError, match="CHN_EUNSUPPORTED"):
+            ch.filtered_enstrophy(case.n1 // 2 - 1, kcz)
+    finally:
+        ch.close()
+
+
+@gpu
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_filter_calls_leave_time_stepping_intact(precision):
+    from paper_1808_06461_amd import Channel, ChnError
+    case, kcx, kcz, q1, q3 = CASES["small"]
+    v, om, U1, U3, y = synth.turbulent_field(case)
+    dt = 0.004
+    out = []
+    for interrupt in (False, True):
+        ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, precision=precision, y=y)
+        try:
+            ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+            ch.step(dt, 1)
+            if interrupt:
+                ch.filter_and_stress(kcx, kcz, q1, q3)
+                ch.filtered_enstrophy(kcx, kcz)
+                ch.get_fields("u1", "omega3")
+                with pytest.raises(ChnError, match="CHN_EINVAL"):
+                    ch.filtered_enstrophy(case.n1 // 2, kcz)
+            ch.step(dt, 2)
+            out.append({k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "chi").items()})
+        finally:
+            ch.close()
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
