@@ -35,6 +35,10 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
   const int nk = min(K, n1h - kx0);
   const int half = n3 / 2;
   const int npad = p3 - 2 * half + 1;
+  // element loops divide by multiply-high (exact: every index times its
+  // divisor stays below 2^32)
+  const unsigned mnp = qmagic(npad), mn3 = qmagic(n3), mnk = qmagic(nk);
+  const double tpx = kTwoPi / a.d.lx, tpz = kTwoPi / a.d.lz;
   const c2<T> zero = mk<T>(T(0), T(0));
   auto value = [&](int f, int l, int s) -> c2<T> {
     c2<T> v = zero;
@@ -43,7 +47,7 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
       if (f == 4 && a.in[4] == nullptr) {
         // omega2 = i (b u1 - a u3)
         const int kz = s < half ? s : s - n3;
-        const T ka = T(kTwoPi * (kx0 + l) / a.d.lx), kb = T(kTwoPi * kz / a.d.lz);
+        const T ka = T(tpx * (kx0 + l)), kb = T(tpz * kz);
         const c2<T> u1 = a.in[0][idx], u3 = a.in[2][idx];
         const c2<T> t = mk<T>(kb * u1.x - ka * u3.x, kb * u1.y - ka * u3.y);
         v = mk<T>(-t.y, t.x);
@@ -55,11 +59,11 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
   };
   for (int f = 0; f < a.nfields; ++f) {
     for (int e = threadIdx.x; e < K * npad; e += blockDim.x) {
-      const int l = e / npad;
+      const int l = (int)qdiv(e, npad, mnp);
       lds[l * LS + lx<kPad>(half + (e - l * npad))] = zero;
     }
     for (int e = threadIdx.x; e < K * n3; e += blockDim.x) {
-      const int l = e / n3, s = e - l * n3;
+      const int l = (int)qdiv(e, n3, mn3), s = e - l * n3;
       if (s == half) continue;
       lds[l * LS + lx<kPad>(s < half ? s : p3 - (n3 - s))] = value(f, l, s);
     }
@@ -67,7 +71,7 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
     fft_lines<T, MAXV, FN, kPad>(lds, LS, K, a.plan, a.tw, +1);
     c2<T>* out = a.out + ((size_t)(by * a.nslot + f) * p3) * n1h + kx0;
     for (int e = threadIdx.x; e < nk * p3; e += blockDim.x) {
-      const int z = e / nk, l = e - z * nk;
+      const int z = (int)qdiv(e, nk, mnk), l = e - z * nk;
       out[(size_t)z * n1h + l] = lds[l * LS + lx<kPad>(z)];
     }
     __syncthreads();
@@ -88,14 +92,15 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
   const int z0 = bx * RZ;
   const int n1h = a.d.n1h, p1 = a.d.p1, p3 = a.d.p3, LS = a.lstride;
   const int npad = p1 - 2 * n1h + 1;
+  const unsigned mnp = qmagic(npad), mnh = qmagic(n1h);  // exact multiply-high divisions
   const c2<T> zero = mk<T>(T(0), T(0));
   // --- load
   for (int e = threadIdx.x; e < 3 * RZ * npad; e += blockDim.x) {
-    const int l = e / npad;
+    const int l = (int)qdiv(e, npad, mnp);
     lds[l * LS + lx<kPad>(n1h + (e - l * npad))] = zero;
   }
   for (int e = threadIdx.x; e < 3 * RZ * n1h; e += blockDim.x) {
-    const int l = e / n1h, k = e - l * n1h;
+    const int l = (int)qdiv(e, n1h, mnh), k = e - l * n1h;
     const int row = l / 3, pr = l - row * 3;
     c2<T> X = zero, Y = zero;
     if (z0 + row < p3) {
@@ -114,10 +119,14 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
   __syncthreads();
   fft_lines<T, MAXV, FN, kPad>(lds, LS, 3 * RZ, a.plan, a.tw, +1);
   // --- products, row sums and CFL
-  double s1[RZ], s3[RZ], cf[RZ];
+  double s1[RZ], s3[RZ];
+  T cf[RZ];  // CFL numbers in the transform precision (they only report)
 #pragma unroll
-  for (int row = 0; row < RZ; ++row) s1[row] = s3[row] = cf[row] = 0.0;
-  const double idy = a.inv_dy[yg];
+  for (int row = 0; row < RZ; ++row) {
+    s1[row] = s3[row] = 0.0;
+    cf[row] = T(0);
+  }
+  const T idx_ = T(a.inv_dx), idy = T(a.inv_dy[yg]), idz = T(a.inv_dz);
   for (int x = threadIdx.x; x < p1; x += blockDim.x) {
     const int px = lx<kPad>(x);
     T h3[RZ];
@@ -132,7 +141,7 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
       h3[row] = u1 * o2 - u2 * o1;
       s1[row] += (double)H1;
       s3[row] += (double)h3[row];
-      const double c = fabs((double)u1) * a.inv_dx + fabs((double)u2) * idy + fabs((double)u3) * a.inv_dz;
+      const T c = fabs(u1) * idx_ + fabs(u2) * idy + fabs(u3) * idz;
       cf[row] = fmax(cf[row], c);
       // line `row` belongs to row row / 3 <= row, already read at this x
       lds[row * LS + px] = mk<T>(H1, H2);
@@ -146,7 +155,7 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
 #pragma unroll
   for (int q = 0; q < 3 * RZ; ++q) {
     const int row = q % RZ, kind = q / RZ;
-    double v = kind == 0 ? s1[row] : (kind == 1 ? s3[row] : cf[row]);
+    double v = kind == 0 ? s1[row] : (kind == 1 ? s3[row] : (double)cf[row]);
     for (int off = 32; off > 0; off >>= 1) {
       const double o = __shfl_xor(v, off);
       v = kind < 2 ? v + o : fmax(v, o);
@@ -171,7 +180,7 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
   fft_lines<T, MAXV, FN, kPad>(lds, LS, RZ + RZ / 2, a.plan, a.tw, -1);
   // --- unpack two real spectra per line, truncate, store in place over fields 0..2
   for (int e = threadIdx.x; e < (RZ + RZ / 2) * n1h; e += blockDim.x) {
-    const int l = e / n1h, k = e - l * n1h;
+    const int l = (int)qdiv(e, n1h, mnh), k = e - l * n1h;
     const c2<T> W = lds[l * LS + lx<kPad>(k)];
     const c2<T> Wm = lds[l * LS + lx<kPad>(k == 0 ? 0 : p1 - k)];
     const c2<T> P = mk<T>(T(0.5) * (W.x + Wm.x), T(0.5) * (W.y - Wm.y));   // (W_k + conj W_m)/2
@@ -302,23 +311,25 @@ __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int 
   const int n1h = a.d.n1h, n3 = a.d.n3, p3 = a.d.p3, K = a.K, LS = a.lstride;
   const int nk = min(K, n1h - kx0);
   const int half = n3 / 2;
+  const unsigned mK = qmagic(K), mn3 = qmagic(n3);  // exact multiply-high divisions
+  const T scale = T(a.scale);
   const c2<T> zero = mk<T>(T(0), T(0));
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const c2<T>* in = a.buf + ((size_t)(y * 6 + f) * p3) * n1h + kx0;
     for (int e = threadIdx.x; e < K * p3; e += blockDim.x) {
-      const int z = e / K, l = e - z * K;
+      const int z = (int)qdiv(e, K, mK), l = e - z * K;
       lds[l * LS + lx<kPad>(z)] = l < nk ? in[(size_t)z * n1h + l] : zero;
     }
     __syncthreads();
     fft_lines<T, MAXV, FN, kPad>(lds, LS, K, a.plan, a.tw, -1);
     c2<TO>* out = a.out[f] + ((size_t)(a.y0 + y) * n1h + kx0) * n3;
     for (int e = threadIdx.x; e < nk * n3; e += blockDim.x) {
-      const int l = e / n3, s = e - l * n3;
+      const int l = (int)qdiv(e, n3, mn3), s = e - l * n3;
       c2<TO> v = mk<TO>(TO(0), TO(0));
       if (s != half) {
         const c2<T> w = lds[l * LS + lx<kPad>(s < half ? s : p3 - (n3 - s))];
-        v = mk<TO>(TO((double)w.x * a.scale), TO((double)w.y * a.scale));
+        v = mk<TO>(TO(w.x * scale), TO(w.y * scale));
       }
       out[(size_t)l * n3 + s] = v;
     }
