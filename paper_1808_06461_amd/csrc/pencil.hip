@@ -807,37 +807,55 @@ __device__ __forceinline__ void transposed_row(double (&mt)[7], int i, int n, F&
 // Solve M^T x = b for a 7-band M given by rows mrow (transposed_row): LU
 // factored on the fly downward (U rows to the mode-indexed scratch Q, the
 // eliminated right-hand side to the lane-indexed Y), back-substitution
-// upward; out(i, x) receives x_i from row n - 1 to 0.
+// upward; out(i, x) receives x_i from row n - 1 to 0.  rhs(i) must accept
+// every row of the line (it is read ahead by the pipeline).
 template <typename RowF, typename RhsF, typename OutF>
 __device__ __forceinline__ void solve_transposed(const Lane& L, int n, size_t st, size_t M, double* const (&Q)[4],
                                                  double* Y, RowF&& mrow, RhsF&& rhs, OutF&& out) {
+  constexpr int D = 4;
   const size_t col = L.col, m = L.m;
-  double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-  double yb[3] = {0, 0, 0};
-  for (int i = 0; i < n; ++i) {
-    double mt[7], lm[3];
-    mrow(mt, i);
-    factor_down(mt, uh, lm);
-    double y = rhs(i);
+  {
+    struct B { double b; };
+    double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    double yb[3] = {0, 0, 0};
+    pipeline<D, B>(
+        n, [&](int i, B& b) { b.b = rhs(min(i, n - 1)); },
+        [&](int i, B& b) {
+          double mt[7], lm[3];
+          mrow(mt, i);
+          factor_down(mt, uh, lm);
+          double y = b.b;
 #pragma unroll
-    for (int d = 3; d >= 1; --d) y -= lm[3 - d] * yb[3 - d];
-    const double u0 = 1.0 / mt[3];
-    if (L.act && L.c == 0) {
-      Q[0][i * M + m] = u0;
-      Q[1][i * M + m] = mt[4];
-      Q[2][i * M + m] = mt[5];
-      Q[3][i * M + m] = mt[6];
-    }
-    if (L.act) Y[i * st + col] = y;
-    push_u(uh, u0, mt[4], mt[5], mt[6]);
-    yb[0] = yb[1]; yb[1] = yb[2]; yb[2] = y;
+          for (int d = 3; d >= 1; --d) y -= lm[3 - d] * yb[3 - d];
+          const double u0 = 1.0 / mt[3];
+          if (L.act && L.c == 0) {
+            Q[0][i * M + m] = u0;
+            Q[1][i * M + m] = mt[4];
+            Q[2][i * M + m] = mt[5];
+            Q[3][i * M + m] = mt[6];
+          }
+          if (L.act) Y[i * st + col] = y;
+          push_u(uh, u0, mt[4], mt[5], mt[6]);
+          yb[0] = yb[1]; yb[1] = yb[2]; yb[2] = y;
+        });
   }
-  double xb[3] = {0, 0, 0};
-  for (int i = n - 1; i >= 0; --i) {
-    const double u[4] = {Q[0][i * M + m], Q[1][i * M + m], Q[2][i * M + m], Q[3][i * M + m]};
-    const double x = back3(Y[i * st + col], u, xb);
-    push_x(xb, x);
-    out(i, x);
+  {
+    struct B { double u[4]; double y; };
+    double xb[3] = {0, 0, 0};
+    pipeline<D, B>(
+        n,
+        [&](int t, B& b) {
+          const int i = max(n - 1 - t, 0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) b.u[k] = Q[k][i * M + m];
+          b.y = Y[i * st + col];
+        },
+        [&](int t, B& b) {
+          const int i = n - 1 - t;
+          const double x = back3(b.y, b.u, xb);
+          push_x(xb, x);
+          out(i, x);
+        });
   }
 }
 
@@ -850,14 +868,16 @@ __device__ __forceinline__ void solve_transposed(const Lane& L, int n, size_t st
 // k_advance: D1 v_p(wall c) = d_c . P^-1 E A2 H^-1 r = w_c . r with
 // w_c = H^-T A2^T E P^-T d_c (d_c the compact D1 row at wall c, E zeroing the
 // Dirichlet rows of the Poisson right-hand side).
-__global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
+// Read-only tables as noalias parameters: wave-uniform row reads through the
+// scalar cache, and no ordering against the kernel's stores.
+__device__ __forceinline__ void homog_body(const HomogArgs& a, const double* __restrict__ A2,
+                                           const double* __restrict__ B2, const double* __restrict__ dlo,
+                                           const double* __restrict__ dhi) {
   const PencilGeom& g = a.g;
   const Lane L = lane_setup(g, blockIdx.x);
   const int n = g.n2;
   const size_t st = 2 * (size_t)g.M, M = g.M;
   const size_t col = L.col, m = L.m;
-  const double* A2 = g.A2;
-  const double* B2 = g.B2;
   // t_c = A2^T E P^-T d_c (independent of dt), to a.T; z_c = E P^-T d_c is
   // consumed row by row (lag 3)
   {
@@ -876,7 +896,7 @@ __global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
         [&](double(&mt)[7], int i) {
           transposed_row(mt, i, n, [&](int j, int o) { return B2[j * 7 + o] - L.k2 * A2[j * 7 + o]; });
         },
-        [&](int i) { return L.c == 0 ? g.clo[i] : g.chi[i]; },
+        [&](int i) { return L.c == 0 ? dlo[i] : dhi[i]; },
         [&](int i, double z) {
           push_front(wz, (i == 0 || i == n - 1) ? 0.0 : z);
           if (i + 3 <= n - 1) emit_t(i + 3);
@@ -916,16 +936,23 @@ __global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
     // Helmholtz back-substitution, downward: chi_h; Poisson right-hand side
     // A2 chi_h (lag 3), Poisson rows factored, eliminated
     {
+      struct B { double u[4]; double s0; };
       double xhb[3] = {0, 0, 0};
       double wch[7] = {0, 0, 0, 0, 0, 0, 0};
       double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
       double yhb[3] = {0, 0, 0};
-      for (int i = 0; i < n + 3; ++i) {
+      pipeline<4, B>(
+          n + 3,
+          [&](int i, B& b) {
+            i = min(i, n - 1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) b.u[k] = a.hu[s][k][i * M + m];
+            b.s0 = a.S0[i * st + col];
+          },
+          [&](int i, B& b) {
         double ch = 0.0;
         if (i < n) {
-          const double u[4] = {a.hu[s][0][i * M + m], a.hu[s][1][i * M + m], a.hu[s][2][i * M + m],
-                               a.hu[s][3][i * M + m]};
-          ch = back3(a.S0[i * st + col], u, xhb);
+          ch = back3(b.s0, b.u, xhb);
           push_x(xhb, ch);
           if (L.act) a.hc[s][i * st + col] = ch;
         }
@@ -953,19 +980,28 @@ __global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
           push_u(uh, u0, p7[4], p7[5], p7[6]);
           yhb[0] = yhb[1]; yhb[1] = yhb[2]; yhb[2] = rhv;
         }
-      }
+          });
     }
     // Poisson back-substitution, upward: v_h and D1 v_h at both walls
     {
+      struct B { double u[4]; double s1; };
       double xhb[3] = {0, 0, 0};
       double glo = 0.0, ghi = 0.0;
-      for (int r = n - 1; r >= 0; --r) {
-        const double u[4] = {a.SU[4][r * M + m], a.SU[5][r * M + m], a.SU[6][r * M + m], a.SU[7][r * M + m]};
-        const double vh = back3(a.S1[r * st + col], u, xhb);
-        push_x(xhb, vh);
-        glo = fma(g.clo[r], vh, glo);
-        ghi = fma(g.chi[r], vh, ghi);
-      }
+      pipeline<4, B>(
+          n,
+          [&](int t, B& b) {
+            const int r = max(n - 1 - t, 0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) b.u[k] = a.SU[4 + k][r * M + m];
+            b.s1 = a.S1[r * st + col];
+          },
+          [&](int t, B& b) {
+            const int r = n - 1 - t;
+            const double vh = back3(b.s1, b.u, xhb);
+            push_x(xhb, vh);
+            glo = fma(dlo[r], vh, glo);
+            ghi = fma(dhi[r], vh, ghi);
+          });
       const double olo = __shfl_xor(glo, 1), ohi = __shfl_xor(ghi, 1);
       if (L.act && L.c == 0) {
         double* hm = a.hm[s] + 4 * m;
@@ -989,6 +1025,12 @@ __global__ void __launch_bounds__(256) k_homog(HomogArgs a) {
           });
     }
   }
+}
+
+__global__ void __launch_bounds__(256) k_homog(HomogArgs a, const double* __restrict__ A2,
+                                               const double* __restrict__ B2, const double* __restrict__ dlo,
+                                               const double* __restrict__ dhi) {
+  homog_body(a, A2, B2, dlo, dhi);
 }
 
 // ---------------------------------------------------------------- set state
@@ -1089,7 +1131,7 @@ template <typename TP> hipError_t launch_recover(const RecoverArgs<TP>& a, hipSt
   return hipGetLastError();
 }
 hipError_t launch_homog(const HomogArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_homog, dim3(pencil_blocks(a.g.M)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_homog, dim3(pencil_blocks(a.g.M)), dim3(256), 0, st, a, a.g.A2, a.g.B2, a.g.clo, a.g.chi);
   return hipGetLastError();
 }
 
