@@ -35,7 +35,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fourier
+from . import compact, fourier
 
 PAIRS = ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))
 
@@ -112,3 +112,41 @@ def rms_profiles(E):
     w = np.full(E.shape[-2], 2.0)
     w[0] = 1.0
     return np.einsum("iykz,k->iy", E, w)
+
+
+def filtered_pressure(S, uu, ub, kcx, kcz):
+    """Filtered pressure on K_c from F(u_i u_j) uu[6][n2][kcx+1][2kcz+1] (pairs 11, 12,
+    13, 22, 23, 33) and F(u_i) ub[3][...] (Section 3.1: d_kk p = -d_i d_j F(u_i u_j)).
+
+    Readings (the paper states the Poisson equation only):
+    * per retained mode (kx, kz) != (0, 0) the interior rows take the A-form of
+      the implicit steps, (B2 - k^2 A2) p = A2 r with r = -d_i d_j F(u_i u_j),
+      d_x -> i a, d_z -> i b, d_y -> the compact D1 (D2 for the 22 term);
+    * the wall rows are the wall-normal filtered momentum equation at a wall,
+      where the velocity and hence F(u_2 u_j) and its wall-parallel derivatives
+      vanish: D1 p = nu D2 F(v), with the full compact rows of D1 and D2;
+    * mode (0, 0): the mean wall-normal momentum balance, P = -F(u_2 u_2)(0, 0)
+      (the additive constant chosen so that P = 0 at the walls).
+    Dense linear algebra, one mode at a time.  Returns p[n2][kcx+1][2kcz+1]."""
+    A1, B1 = compact.band_to_dense(S.A1), compact.band_to_dense(S.B1)
+    A2, B2 = compact.band_to_dense(S.A2), compact.band_to_dense(S.B2)
+    D1 = np.linalg.solve(A1, B1)
+    D2 = np.linalg.solve(A2, B2)
+    kzs = list(range(0, kcz + 1)) + list(range(-kcz, 0))
+    p = np.zeros(uu.shape[1:], dtype=np.complex128)
+    for ix in range(kcx + 1):
+        for iz, kz in enumerate(kzs):
+            u11, u12, u13, u22, u23, u33 = (uu[q][:, ix, iz] for q in range(6))
+            if ix == 0 and kz == 0:
+                p[:, 0, 0] = -u22.real
+                continue
+            a, b = 2 * np.pi * ix / S.lx, 2 * np.pi * kz / S.lz
+            r = -((1j * a) ** 2 * u11 + 2 * (1j * a) * (D1 @ u12) + 2 * (1j * a) * (1j * b) * u13
+                  + D2 @ u22 + 2 * (1j * b) * (D1 @ u23) + (1j * b) ** 2 * u33)
+            M = B2 - (a * a + b * b) * A2
+            M[0], M[-1] = D1[0], D1[-1]
+            rhs = A2 @ r
+            g = S.nu * (D2 @ ub[1][:, ix, iz])
+            rhs[0], rhs[-1] = g[0], g[-1]
+            p[:, ix, iz] = np.linalg.solve(M, rhs)
+    return p
