@@ -189,6 +189,21 @@ chn_status chn_filtered_enstrophy(chn_ctx *ctx, int32_t kcx, int32_t kcz, double
  * chn_set_state; CHN_EUNSUPPORTED on a planes_only context. */
 chn_status chn_accumulate_statistics(chn_ctx *ctx, double *d_spec, double *d_mean);
 
+/* Filtered pressure of Section 3.1 from the database variables: on every
+ * retained mode (0 <= kx <= kcx, |kz| <= kcz) the Poisson equation
+ * d_kk p = -d_i d_j F(u_i u_j), in the A-form of the implicit steps
+ * ((B2 - k^2 A2) p = A2 r in the interior rows, r = -d_i d_j F(u_i u_j) with
+ * the compact D1, D2 in y), with the wall rows D1 p = nu D2 F(v) (the filtered
+ * wall-normal momentum equation at a wall; full compact wall rows of D1 and
+ * D2); the mean mode P(y) = -F(u_2 u_2)(0, 0).  d_uubar, d_ubar: DEVICE, as
+ * written by chn_filter_and_stress for the same kcx, kcz; d_p: DEVICE,
+ * complex float64 [n2][kcx+1][2kcz+1] (kz in slot order), owned by the
+ * caller.  Float64 on both precisions; uses the context's tables and scratch,
+ * not its state.  CHN_EINVAL for a NULL pointer or a cut-off outside
+ * 0 <= kcx < n1/2, 0 <= kcz < n3/2; CHN_EUNSUPPORTED on a planes_only context. */
+chn_status chn_filtered_pressure(chn_ctx *ctx, int32_t kcx, int32_t kcz, const double *d_uubar,
+                                 const double *d_ubar, double *d_p);
+
 /* Dealiased products of Section 2.1 on every plane (the plane phase of the
  * sub-step): d_in[0..5] = u1, u2, u3, omega1, omega2, omega3 and d_out[0..2] =
  * H1, H2, H3 of H = u x omega, DEVICE pointers in the layout

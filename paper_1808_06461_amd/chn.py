@@ -63,6 +63,7 @@ def lib():
         L.chn_filter_and_stress.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P]
         L.chn_filtered_enstrophy.argtypes = [P, C.c_int32, C.c_int32, P]
         L.chn_accumulate_statistics.argtypes = [P, P, P]
+        L.chn_filtered_pressure.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
         L.chn_get_operators.argtypes = [P, P, P, P, P, P]
         L.chn_get_plan.argtypes = [P, C.POINTER(Plan)]
         L.chn_plane_products.argtypes = [P, C.POINTER(P), C.POINTER(P)]
@@ -83,6 +84,7 @@ def lib():
         L.chn_last_error.restype = C.c_char_p
         for name in ("chn_create", "chn_destroy", "chn_set_state", "chn_step_rk3", "chn_get_fields",
                      "chn_nonlinear", "chn_filter_and_stress", "chn_filtered_enstrophy", "chn_accumulate_statistics",
+                     "chn_filtered_pressure",
                      "chn_get_operators",
                      "chn_timing_enable", "chn_timing_read", "chn_ens_create", "chn_ens_destroy", "chn_ens_step",
                      "chn_get_plan", "chn_set_plan", "chn_autotune", "chn_plane_products"):
@@ -213,6 +215,18 @@ class Channel:
         """F(omega_i omega_i) on 0 <= kx <= kcx, |kz| <= kcz: complex128 [n2][kcx+1][2kcz+1]."""
         out = torch.empty((self.n2, kcx + 1, 2 * kcz + 1), dtype=torch.complex128, device=self.device)
         self._check(self.L.chn_filtered_enstrophy(self.ctx, kcx, kcz, _ptr(out)), "chn_filtered_enstrophy")
+        return out
+
+    def filtered_pressure(self, kcx, kcz, uubar, ubar):
+        """Filtered pressure [n2][kcx+1][2kcz+1] (complex128) from the outputs of filter_and_stress."""
+        nk = (self.n2, kcx + 1, 2 * kcz + 1)
+        for t, lead in ((uubar, 6), (ubar, 3)):
+            if (t.dtype != torch.complex128 or tuple(t.shape) != (lead,) + nk or not t.is_contiguous()
+                    or t.device != self.device):
+                raise ValueError("uubar / ubar must be contiguous complex128 device tensors from filter_and_stress")
+        out = torch.empty(nk, dtype=torch.complex128, device=self.device)
+        self._check(self.L.chn_filtered_pressure(self.ctx, kcx, kcz, _ptr(uubar), _ptr(ubar), _ptr(out)),
+                    "chn_filtered_pressure")
         return out
 
     def accumulate_statistics(self, spec=None, mean=None):

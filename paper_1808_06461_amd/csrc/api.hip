@@ -1206,6 +1206,32 @@ chn_status chn_accumulate_statistics(chn_ctx* x, double* d_spec, double* d_mean)
   return x->mixed ? stats_stage<float>(x, d_spec, d_mean) : stats_stage<double>(x, d_spec, d_mean);
 }
 
+chn_status chn_filtered_pressure(chn_ctx* x, int32_t kcx, int32_t kcz, const double* d_uubar, const double* d_ubar,
+                                 double* d_p) {
+  if (chn_status s = check(x)) return s;
+  if (chn_status s = need_fields(x)) return s;
+  if (!d_uubar || !d_ubar || !d_p) return fail(x, CHN_EINVAL, "NULL pointer");
+  if (kcx < 0 || kcz < 0 || kcx >= x->n1h || kcz >= x->n3 / 2)
+    return fail(x, CHN_EINVAL, "need 0 <= kcx < n1/2, 0 <= kcz < n3/2");
+  const size_t R = (size_t)(kcx + 1) * (2 * kcz + 1);  // <= M: the scratch below always fits
+  chn::PressureArgs a{};
+  a.g = x->geom;
+  a.uu = d_uubar;
+  a.vb = d_ubar + 2 * (size_t)x->n2 * R;  // F(u_2)
+  a.p = d_p;
+  a.T[0] = x->S[0];
+  a.T[1] = x->S[1];
+  a.T[2] = x->S[2];
+  a.T[3] = x->S[5];
+  for (int k = 0; k < 4; ++k) a.Q[k] = reinterpret_cast<double*>(x->inter) + k * (size_t)x->n2 * R;
+  a.R = (int)R;
+  a.nz = 2 * kcz + 1;
+  a.kcz = kcz;
+  a.nu = x->nu;
+  HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_pressure(a, x->stream); }));
+  return CHN_OK;
+}
+
 chn_status chn_filtered_enstrophy(chn_ctx* x, int32_t kcx, int32_t kcz, double* d_out) {
   if (chn_status s = check(x)) return s;
   if (chn_status s = need_fields(x)) return s;

@@ -139,6 +139,20 @@ struct PencilGeom {
   const double *quad;         // mass-flux weights
 };
 
+// Filtered pressure on the retained modes (Section 3.1): R = (kcx + 1)(2 kcz + 1)
+// modes per plane, lane-indexed columns [n2][2R] (two lanes per mode)
+struct PressureArgs {
+  PencilGeom g;          // compact tables (n2, ka, kb used; M unused)
+  const double* uu;      // [6][n2][R] complex F(u_i u_j), pairs 11, 12, 13, 22, 23, 33
+  const double* vb;      // [n2][R] complex F(v)
+  double* p;             // [n2][R] complex out
+  double* T[4];          // lane-indexed scratch [n2][2R]
+  double* Q[4];          // mode-indexed scratch [n2][R] (factor rows)
+  int R, nz, kcz;
+  double nu;
+};
+hipError_t launch_pressure(const PressureArgs& a, hipStream_t st);
+
 template <typename TP> struct RecoverArgs {
   PencilGeom g;
   const double* v;            // state u2, complex [n2][M]

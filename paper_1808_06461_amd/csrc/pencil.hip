@@ -1033,6 +1033,194 @@ __global__ void __launch_bounds__(256) k_homog(HomogArgs a, const double* __rest
   homog_body(a, A2, B2, dlo, dhi);
 }
 
+// ---------------------------------------------------------------- filtered pressure
+// Section 3.1: d_kk p = -d_i d_j F(u_i u_j) on every retained mode, from the
+// filtered stresses and the filtered wall-normal velocity.  Per mode: the
+// right-hand side in the A-form of the implicit steps (B2 - k^2 A2) p = A2 r,
+// the wall rows D1 p = nu D2 F(v) (full compact rows) through the influence
+// matrix (particular solution with p = 0 at the walls, plus the homogeneous
+// ones with p = 1 at one wall, tabulated nowhere: computed alongside), mode
+// (0,0) as P = -F(u_2 u_2).  Lanes as in the pencil kernels: two per mode
+// (real, imaginary part); lane c also carries the homogeneous solution of
+// wall c.
+//   S1 down : eliminate A1 d = B1 F(u1u2), A1 d = B1 F(u2u3), A2 d = B2 F(v)
+//   S2 up   : finish them (D2 F(v) only at the walls)
+//   S3 down : A2 r (lag 3); factor B2 - k^2 A2 on the fly; eliminate p_0, p_h
+//   S4 up   : finish p_0, p_h; wall rows of D1; 2x2 influence system
+//   S5      : p = p_0 + c_lo p_lo + c_hi p_hi
+__device__ __forceinline__ void pressure_body(const PressureArgs& a, const double* __restrict__ A2,
+                                              const double* __restrict__ B2, const double* __restrict__ B1,
+                                              const double* __restrict__ L1d, const double* __restrict__ U1d,
+                                              const double* __restrict__ L2d, const double* __restrict__ U2d,
+                                              const double* __restrict__ dlo, const double* __restrict__ dhi) {
+  const int n = a.g.n2;
+  const int gl = blockIdx.x * blockDim.x + threadIdx.x;
+  int r = gl >> 1;
+  const int c = gl & 1;
+  const bool act = r < a.R;
+  if (!act) r = a.R - 1;
+  const int kx = r / a.nz, s = r - kx * a.nz;
+  const int kz = s <= a.kcz ? s : s - a.nz;
+  const double A = a.g.ka * kx, B = a.g.kb * kz, k2 = A * A + B * B;
+  const bool mean = r == 0;
+  const double sg = c == 0 ? -1.0 : 1.0;  // (i z)_c = sg z_other
+  const size_t st = 2 * (size_t)a.R, R = a.R;
+  const size_t col = 2 * (size_t)r + c;
+  const size_t fs = (size_t)n * st;      // one field of uu
+  auto U = [&](int q, int i) { return a.uu[q * fs + (size_t)i * st + col]; };
+  double* T0 = a.T[0];
+  double* T1 = a.T[1];
+  double* T2 = a.T[2];
+  double* T3 = a.T[3];
+  // ---- S1 (down)
+  {
+    double w12[7] = {0, 0, 0, 0, 0, 0, 0}, w23[7] = {0, 0, 0, 0, 0, 0, 0}, wv[7] = {0, 0, 0, 0, 0, 0, 0};
+    double y12[3] = {0, 0, 0}, y23[3] = {0, 0, 0}, yv[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+      w12[3 + k] = U(1, k);
+      w23[3 + k] = U(4, k);
+      wv[3 + k] = a.vb[(size_t)k * st + col];
+    }
+    for (int i = 0; i < n; ++i) {
+      const bool more = i + 3 < n;
+      w12[6] = more ? U(1, i + 3) : 0.0;
+      w23[6] = more ? U(4, i + 3) : 0.0;
+      wv[6] = more ? a.vb[(size_t)(i + 3) * st + col] : 0.0;
+      const double e12 = elim3(dot7(B1 + i * 7, w12), L1d + i * 3, y12);
+      const double e23 = elim3(dot7(B1 + i * 7, w23), L1d + i * 3, y23);
+      const double ev = elim3(dot7(B2 + i * 7, wv), L2d + i * 3, yv);
+      if (act) {
+        T0[i * st + col] = e12;
+        T1[i * st + col] = e23;
+        T2[i * st + col] = ev;
+      }
+      y12[0] = y12[1]; y12[1] = y12[2]; y12[2] = e12;
+      y23[0] = y23[1]; y23[1] = y23[2]; y23[2] = e23;
+      yv[0] = yv[1]; yv[1] = yv[2]; yv[2] = ev;
+      push_back(w12, 0.0);
+      push_back(w23, 0.0);
+      push_back(wv, 0.0);
+    }
+  }
+  // ---- S2 (up): D1 F(u1u2), D1 F(u2u3) in place; nu D2 F(v) at the walls
+  double g_lo = 0.0, g_hi = 0.0;
+  {
+    double x12[3] = {0, 0, 0}, x23[3] = {0, 0, 0}, xv[3] = {0, 0, 0};
+    for (int i = n - 1; i >= 0; --i) {
+      const double d12 = back3(T0[i * st + col], U1d + i * 4, x12);
+      const double d23 = back3(T1[i * st + col], U1d + i * 4, x23);
+      const double dv = back3(T2[i * st + col], U2d + i * 4, xv);
+      push_x(x12, d12);
+      push_x(x23, d23);
+      push_x(xv, dv);
+      if (act) {
+        T0[i * st + col] = d12;
+        T1[i * st + col] = d23;
+      }
+      if (i == n - 1) g_hi = a.nu * dv;
+      if (i == 0) g_lo = a.nu * dv;
+    }
+  }
+  // ---- S3 (down): rhs = -(A2 q + B2 F(u2u2)) on interior rows, q = -a^2 u11
+  // + 2a (i d12) - 2ab u13 + 2b (i d23) - b^2 u33; Dirichlet rows: 0 for p_0,
+  // 1 at wall c for p_h
+  {
+    double wq[7] = {0, 0, 0, 0, 0, 0, 0}, wu[7] = {0, 0, 0, 0, 0, 0, 0};
+    double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    double y0[3] = {0, 0, 0}, yh[3] = {0, 0, 0};
+    for (int i = 0; i < n + 3; ++i) {
+      double q = 0.0, u22 = 0.0;
+      if (i < n) {
+        const double d12 = T0[i * st + col], d23 = T1[i * st + col];
+        const double d12o = __shfl_xor(d12, 1), d23o = __shfl_xor(d23, 1);
+        q = -A * A * U(0, i) + 2.0 * A * sg * d12o - 2.0 * A * B * U(2, i) + 2.0 * B * sg * d23o - B * B * U(5, i);
+        u22 = U(3, i);
+      }
+      push_back(wq, q);
+      push_back(wu, u22);
+      const int rr = i - 3;
+      if (rr >= 0) {
+        const bool wall = rr == 0 || rr == n - 1;
+        double rhs = 0.0, rh = 0.0;
+        if (!wall) {
+#pragma unroll
+          for (int o = 0; o < 7; ++o) rhs -= A2[rr * 7 + o] * wq[o] + B2[rr * 7 + o] * wu[o];
+        } else {
+          rh = (rr == 0) == (c == 0) ? 1.0 : 0.0;
+        }
+        double p7[7], lm[3];
+        pois_row(p7, A2 + rr * 7, B2 + rr * 7, wall, k2);
+        factor_down(p7, uh, lm);
+#pragma unroll
+        for (int d = 3; d >= 1; --d) {
+          rhs -= lm[3 - d] * y0[3 - d];
+          rh -= lm[3 - d] * yh[3 - d];
+        }
+        const double u0 = 1.0 / p7[3];
+        if (act && c == 0) {
+          a.Q[0][rr * R + r] = u0;
+          a.Q[1][rr * R + r] = p7[4];
+          a.Q[2][rr * R + r] = p7[5];
+          a.Q[3][rr * R + r] = p7[6];
+        }
+        if (act) {
+          T2[rr * st + col] = rhs;
+          T3[rr * st + col] = rh;
+        }
+        push_u(uh, u0, p7[4], p7[5], p7[6]);
+        y0[0] = y0[1]; y0[1] = y0[2]; y0[2] = rhs;
+        yh[0] = yh[1]; yh[1] = yh[2]; yh[2] = rh;
+      }
+    }
+  }
+  // ---- S4 (up): p_0, p_h; D1 at the walls (full compact rows)
+  double c_lo = 0.0, c_hi = 0.0;
+  {
+    double x0[3] = {0, 0, 0}, xh[3] = {0, 0, 0};
+    double l0 = 0.0, h0 = 0.0, lh = 0.0, hh = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+      const double u[4] = {a.Q[0][i * R + r], a.Q[1][i * R + r], a.Q[2][i * R + r], a.Q[3][i * R + r]};
+      const double p0 = back3(T2[i * st + col], u, x0);
+      const double ph = back3(T3[i * st + col], u, xh);
+      push_x(x0, p0);
+      push_x(xh, ph);
+      if (act) {
+        T2[i * st + col] = p0;
+        T3[i * st + col] = ph;
+      }
+      l0 = fma(dlo[i], p0, l0);
+      h0 = fma(dhi[i], p0, h0);
+      lh = fma(dlo[i], ph, lh);
+      hh = fma(dhi[i], ph, hh);
+    }
+    // lane c holds D1 p_h of wall c at (lower, upper); the other lane the other wall's
+    const double lo_ = __shfl_xor(lh, 1), ho_ = __shfl_xor(hh, 1);
+    const double m00 = c == 0 ? lh : lo_, m10 = c == 0 ? hh : ho_;  // p_lo at the lower, upper wall
+    const double m01 = c == 0 ? lo_ : lh, m11 = c == 0 ? ho_ : hh;  // p_hi
+    if (!mean) {
+      const double f0 = g_lo - l0, f1 = g_hi - h0;
+      const double det = m00 * m11 - m01 * m10;
+      c_lo = (f0 * m11 - f1 * m01) / det;
+      c_hi = (f1 * m00 - f0 * m10) / det;
+    }
+  }
+  // ---- S5: combine and write
+  for (int i = 0; i < n; ++i) {
+    const double ph = T3[i * st + col], pho = __shfl_xor(ph, 1);
+    const double plo = c == 0 ? ph : pho, phi = c == 0 ? pho : ph;
+    const double v = mean ? (c == 0 ? -U(3, i) : 0.0) : T2[i * st + col] + c_lo * plo + c_hi * phi;
+    if (act) a.p[(size_t)i * st + col] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_pressure(PressureArgs a, const double* __restrict__ A2,
+                                                  const double* __restrict__ B2, const double* __restrict__ B1,
+                                                  const double* __restrict__ L1d, const double* __restrict__ U1d,
+                                                  const double* __restrict__ L2d, const double* __restrict__ U2d,
+                                                  const double* __restrict__ dlo, const double* __restrict__ dhi) {
+  pressure_body(a, A2, B2, B1, L1d, U1d, L2d, U2d, dlo, dhi);
+}
+
 // ---------------------------------------------------------------- set state
 __global__ void __launch_bounds__(256) k_chi_from_v(ChiArgs a) {
   const PencilGeom& g = a.g;
@@ -1138,6 +1326,13 @@ hipError_t launch_homog(const HomogArgs& a, hipStream_t st) {
 template <typename TH, typename TP> hipError_t launch_advance(const AdvanceArgs<TH, TP>& a, hipStream_t st) {
   hipLaunchKernelGGL((k_advance<TH, TP>), dim3(pencil_blocks(a.g.M) + 1), dim3(256), 0, st, a, a.g.B1, a.g.A2,
                      a.g.B2, a.g.L1d, a.g.U1d, a.g.L1u, a.g.U1u);
+  return hipGetLastError();
+}
+hipError_t launch_pressure(const PressureArgs& a, hipStream_t st) {
+  const unsigned nb = (unsigned)((2 * (size_t)a.R + 255) / 256);
+  const PencilGeom& g = a.g;
+  hipLaunchKernelGGL(k_pressure, dim3(nb), dim3(256), 0, st, a, g.A2, g.B2, g.B1, g.L1d, g.U1d, g.L2d, g.U2d, g.clo,
+                     g.chi);
   return hipGetLastError();
 }
 hipError_t launch_chi_from_v(const ChiArgs& a, hipStream_t st) {
