@@ -136,12 +136,16 @@ template <> __device__ __forceinline__ double2 load_c<float>(const float* p, siz
   return make_double2((double)f.x, (double)f.y);
 }
 
-// element at a byte offset from a (wave-uniform) base
-template <typename T> __device__ __forceinline__ T& at(T* base, unsigned boff) {
-  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff);
+
+// Element at a byte offset from a (wave-uniform) base.  These are the
+// streaming accesses of the sweeps: every field row a sweep touches is used
+// again only a whole sweep later, far beyond the caches, so loads and stores
+// carry the non-temporal hint.
+template <typename T> __device__ __forceinline__ T ldn(const T* base, unsigned boff) {
+  return __builtin_nontemporal_load(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff));
 }
-template <typename T> __device__ __forceinline__ const T& at(const T* base, unsigned boff) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+template <typename T> __device__ __forceinline__ void stn(T* base, unsigned boff, T v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff));
 }
 
 // one real component (c = 0: real part, 1: imaginary part) of a complex entry
@@ -484,15 +488,15 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     auto loadcol = [&](int j, B& b) {  // rows j >= n are clamped (used only for j < n)
       j = min(j, n - 1);
-      b.h1 = (double)at(HR(a.H[0], j), hocol);
-      b.h3 = (double)at(HR(a.H[2], j), hocol);
-      b.om = at(LR(a.om2, j), bcol);
-      b.noo = at(HRD(a.nom_rd, j), bcol);
+      b.h1 = (double)ldn(HR(a.H[0], j), hocol);
+      b.h3 = (double)ldn(HR(a.H[2], j), hocol);
+      b.om = ldn(LR(a.om2, j), bcol);
+      b.noo = ldn(HRD(a.nom_rd, j), bcol);
     };
     auto column = [&](int j, int tb, const B& b) -> double {
       const double nom = L.live ? sg * (L.B * b.h1 - L.A * b.h3) : 0.0;  // i b H1 - i a H3
       const double q = f1 * b.om + dga * nom + dze * b.noo;
-      if (L.act) at(HWR(a.nom_wr, j), bcol) = nom;
+      if (L.act) stn(HWR(a.nom_wr, j), bcol, nom);
 #pragma unroll
       for (int k = 0; k < 7; ++k) {
         const int r = tb + k, o = j - r + 3;
@@ -511,8 +515,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           w[6] = (t + 3 < n) ? column(t + 3, t, b) : 0.0;
           const double yi = elim3(dot7(B1 + t * 7, w), L1d + t * 3, yb);
           if (L.act) {
-            at(LR(a.S[0], t), bcol) = yi;
-            at(LR(a.S[2], t), bcol) = acc[0];  // omega2 rhs of row t (0 on the wall rows)
+            stn(LR(a.S[0], t), bcol, yi);
+            stn(LR(a.S[2], t), bcol, acc[0]);  // omega2 rhs of row t (0 on the wall rows)
           }
           yb[0] = yb[1];
           yb[1] = yb[2];
@@ -539,12 +543,12 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
         n + 3,
         [&](int t, B& b) {  // rows clamped; the step uses them only inside the line
           const int i = max(n - 1 - t, 0), r = min(max(n + 2 - t, 0), n - 1);
-          b.s0 = at(LR(a.S[0], i), bcol);
-          b.h2 = (double)at(HR(a.H[1], i), hcol);
-          b.chi = at(LR(a.chi, i), bcol);
-          b.nco = at(HRD(a.nchi_rd, i), bcol);
-          b.rom = at(LR(a.S[2], r), bcol);
-          b.w = at(LR(a.hw, r), bcol);
+          b.s0 = ldn(LR(a.S[0], i), bcol);
+          b.h2 = (double)ldn(HR(a.H[1], i), hcol);
+          b.chi = ldn(LR(a.chi, i), bcol);
+          b.nco = ldn(HRD(a.nchi_rd, i), bcol);
+          b.rom = ldn(LR(a.S[2], r), bcol);
+          b.w = ldn(LR(a.hw, r), bcol);
         },
         [&](int t, B& b) {
           const int i = n - 1 - t;
@@ -553,7 +557,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             push_x(xb, dG);
             const double nchi = L.live ? -dG - L.k2 * b.h2 : 0.0;
             const double q = f1 * b.chi + dga * nchi + dze * b.nco;
-            if (L.act) at(HWR(a.nchi_wr, i), bcol) = nchi;
+            if (L.act) stn(HWR(a.nchi_wr, i), bcol, nchi);
 #pragma unroll
             for (int k = 0; k < 7; ++k) {
               const int r = i + 3 - k;
@@ -576,8 +580,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             }
             const double u0 = 1.0 / m7[3];
             if (L.act) {
-              at(LR(a.S[1], r), bcol) = rc;
-              at(LR(a.S[2], r), bcol) = ro;
+              stn(LR(a.S[1], r), bcol, rc);
+              stn(LR(a.S[2], r), bcol, ro);
             }
             push_u(uh, u0, m7[2], m7[1], m7[0]);
             ycb[0] = ycb[1]; ycb[1] = ycb[2]; ycb[2] = rc;
@@ -613,10 +617,10 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
         [&](int i, B& b) {
           i = min(i, n - 1);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) b.u[k] = at(MR(a.SU[k], i), bm);
-          b.s1 = at(LR(a.S[1], i), bcol);
-          b.s2 = at(LR(a.S[2], i), bcol);
-          b.hc = at(LR(a.hc, i), bcol);
+          for (int k = 0; k < 4; ++k) b.u[k] = ldn(MR(a.SU[k], i), bm);
+          b.s1 = ldn(LR(a.S[1], i), bcol);
+          b.s2 = ldn(LR(a.S[2], i), bcol);
+          b.hc = ldn(LR(a.hc, i), bcol);
         },
         [&](int i, B& b) {
           double cn = 0.0;
@@ -629,8 +633,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             const double hlo = L.c == 0 ? b.hc : hco, hhi = L.c == 0 ? hco : b.hc;
             cn = L.live ? cp + clo_c * hlo + chi_c * hhi : 0.0;
             if (L.act) {
-              at(LR(a.om2, i), bcol) = L.live ? om : 0.0;
-              at(LR(a.chi, i), bcol) = cn;
+              stn(LR(a.om2, i), bcol, L.live ? om : 0.0);
+              stn(LR(a.chi, i), bcol, cn);
             }
           }
           push_back(wch, cn);
@@ -648,7 +652,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
 #pragma unroll
             for (int d = 3; d >= 1; --d) rv -= lm[3 - d] * yvb[3 - d];
             const double u0 = 1.0 / p7[3];
-            if (L.act) at(LR(a.S[5], r), bcol) = rv;
+            if (L.act) stn(LR(a.S[5], r), bcol, rv);
             push_u(uh, u0, p7[4], p7[5], p7[6]);
             yvb[0] = yvb[1]; yvb[1] = yvb[2]; yvb[2] = rv;
           }
@@ -665,8 +669,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
         [&](int t, B& b) {
           const int r = max(n - 1 - t, 0);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) b.u[k] = at(MR(a.SU[4 + k], r), bm);
-          b.s5 = at(LR(a.S[5], r), bcol);
+          for (int k = 0; k < 4; ++k) b.u[k] = ldn(MR(a.SU[4 + k], r), bm);
+          b.s5 = ldn(LR(a.S[5], r), bcol);
         },
         [&](int t, B& b) {
           const int i = n - 1 - t;
@@ -674,14 +678,14 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           if (i >= 0) {
             vn = back3(b.s5, b.u, xvb);
             push_x(xvb, vn);
-            if (L.act) at(LR(a.v, i), bcol) = vn;
-            if (wph) at(LR(a.ph[1], i), pcol) = (TP)vn;
+            if (L.act) stn(LR(a.v, i), bcol, vn);
+            if (wph) stn(LR(a.ph[1], i), pcol, (TP)vn);
           }
           push_front(wv, vn);
           const int r = i + 3;
           if (r <= n - 1) {
             const double yr = elim3(dot7(B1 + r * 7, wv), L1u + r * 3, yb);
-            if (L.act) at(LR(a.S[0], r), bcol) = yr;
+            if (L.act) stn(LR(a.S[0], r), bcol, yr);
             yb[0] = yb[1];
             yb[1] = yb[2];
             yb[2] = yr;
@@ -699,8 +703,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
         n + 3,
         [&](int i, B& b) {
           i = min(i, n - 1);
-          b.s0 = at(LR(a.S[0], i), bcol);
-          b.om = at(LR(a.om2, i), bocol);
+          b.s0 = ldn(LR(a.S[0], i), bcol);
+          b.om = ldn(LR(a.om2, i), bocol);
         },
         [&](int i, B& b) {
           double u1 = 0.0, u3 = 0.0;
@@ -714,8 +718,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
               u3 = sg * (L.B * dvo + L.A * b.om) * L.ik2;
             }
             if (wph) {
-              at(LR(a.ph[0], i), pcol) = (TP)u1;
-              at(LR(a.ph[2], i), pcol) = (TP)u3;
+              stn(LR(a.ph[0], i), pcol, (TP)u1);
+              stn(LR(a.ph[2], i), pcol, (TP)u3);
             }
           }
           push_back(w1, u1);
@@ -727,8 +731,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             const double y1 = elim3(dot7(bb, w1), l, y1b);
             const double y3 = elim3(dot7(bb, w3), l, y3b);
             if (L.act) {
-              at(LR(a.S[1], r), bcol) = y1;
-              at(LR(a.S[2], r), bcol) = y3;
+              stn(LR(a.S[1], r), bcol, y1);
+              stn(LR(a.S[2], r), bcol, y3);
             }
             y1b[0] = y1b[1]; y1b[1] = y1b[2]; y1b[2] = y1;
             y3b[0] = y3b[1]; y3b[1] = y3b[2]; y3b[2] = y3;
@@ -743,9 +747,9 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
         n,
         [&](int t, B& b) {
           const int r = max(n - 1 - t, 0);
-          b.s1 = at(LR(a.S[1], r), bcol);
-          b.s2 = at(LR(a.S[2], r), bcol);
-          b.v = at(LR(a.v, r), bocol);
+          b.s1 = ldn(LR(a.S[1], r), bcol);
+          b.s2 = ldn(LR(a.S[2], r), bcol);
+          b.v = ldn(LR(a.v, r), bocol);
         },
         [&](int t, B& b) {
           const int r = n - 1 - t;
@@ -757,8 +761,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           const double o1 = du3 - sg * L.B * b.v;
           const double o3 = sg * L.A * b.v - du1;
           if (wph) {
-            at(LR(a.ph[3], r), pcol) = (TP)o1;
-            at(LR(a.ph[4], r), pcol) = (TP)o3;
+            stn(LR(a.ph[3], r), pcol, (TP)o1);
+            stn(LR(a.ph[4], r), pcol, (TP)o3);
           }
         });
   }
