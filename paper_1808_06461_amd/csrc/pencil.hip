@@ -15,7 +15,11 @@
 //               implicit Helmholtz steps for omega2 and chi, Poisson step for v,
 //               influence-matrix combination enforcing dv/dy = 0 at the walls
 //               (Appendix A eqs. for chi and omega2, Appendix B), plus one
-//               extra workgroup for the mean profiles with constant mass flux.
+//               extra workgroup for the mean profiles with constant mass flux;
+//               fused with the recovery of the next sub-step's fields.
+//   k_homog   : per time step size, the factor tables, homogeneous solutions
+//               and wall-derivative vectors k_advance reads.
+//   k_pressure : the filtered pressure of the low-storage database (Section 3.1).
 //   k_chi_from_v : chi = (D2 - k^2) v for a new state.
 #include "kernels.hpp"
 
