@@ -288,6 +288,8 @@ def main():
                     help="also run five plain device copies of BYTES bytes (calibrates HBM byte counters)")
     ap.add_argument("--only", choices=("fp64", "mixed"), default=None,
                     help="run one precision only (for profiling; the JSON then lacks the comparison)")
+    ap.add_argument("--leg", choices=("ensemble", "c3", "c5"), default=None,
+                    help="run one of the other workloads only (for profiling) and print its JSON object")
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash(args.source_hash))
@@ -309,6 +311,11 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] copy probe: 5 copies of {args.copy_probe} bytes", file=sys.stderr, flush=True)
         del src, dst
+
+    if args.leg:
+        leg = {"ensemble": ensemble_run, "c3": c3_run, "c5": c5_run}[args.leg]
+        print(json.dumps({args.leg: leg()}))
+        return
 
     import synth
     case = synth.CASES["c2"]
