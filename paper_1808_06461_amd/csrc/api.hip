@@ -512,7 +512,7 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   if ((size_t)6 * n2 * kc1 * nz * 16 > hbytes) return fail(x, CHN_EUNSUPPORTED, "cut-off too large for the workspace");
   if (!ens && (size_t)9 * n2 * q3 * kc1 * 16 > x->inter_bytes) return fail(x, CHN_EUNSUPPORTED, "q grid too large for the workspace");
   if (p1 > 12 * 256) return fail(x, CHN_EUNSUPPORTED, "3*n1/2 too large for the filter x-pass");
-  const size_t lds_x = (size_t)3 * (p1 + 1) * 16;
+  const size_t lds_x = (size_t)(p1 + 1) * 16;  // one line at a time
   const size_t lds_t = (size_t)5 * (q1 + 1) * 16;
   auto lines = [&](int len, int cap) {
     int K = 24 * 256 / len;

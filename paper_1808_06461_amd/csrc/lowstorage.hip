@@ -23,78 +23,77 @@ namespace chn {
 __device__ __constant__ int kPairI[6] = {0, 0, 0, 1, 1, 2};
 __device__ __constant__ int kPairJ[6] = {0, 1, 2, 1, 2, 2};
 
-template <typename T, int MAXV>
+// Per (y, z row): inverse x transforms of u1 + i u2 and u3, the six
+// products, forward float64 transforms of (11, 22), (12, 13), (23, 33) as two
+// real signals per complex line, kx <= kcx kept.  One line in LDS at a time
+// (the physical values stay in registers), so several workgroups share a CU.
+template <typename T, int MAXV, int NQ>
 __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
-  c2<T>* lt = reinterpret_cast<c2<T>*>(smem_raw);   // 2 lines: u1 + i u2, u3
-  double2* ld = reinterpret_cast<double2*>(smem_raw);  // 3 lines of products (reuses the space)
+  c2<T>* lt = reinterpret_cast<c2<T>*>(smem_raw);      // one context-precision line
+  double2* ld = reinterpret_cast<double2*>(smem_raw);  // one float64 line (the same space)
   const int y = blockIdx.y, z = blockIdx.x;
-  const int n1h = a.d.n1h, p1 = a.d.p1, p3 = a.d.p3, LT = a.lst, LD = a.lsd;
-  const int npad = p1 - 2 * n1h + 1;
+  const int n1h = a.d.n1h, p1 = a.d.p1, p3 = a.d.p3;
   const c2<T> zero = mk<T>(T(0), T(0));
-  for (int e = threadIdx.x; e < 2 * npad; e += blockDim.x) {
-    const int l = e / npad;
-    lt[l * LT + n1h + (e - l * npad)] = zero;
-  }
-  for (int e = threadIdx.x; e < 2 * n1h; e += blockDim.x) {
-    const int l = e / n1h, k = e - l * n1h;
-    const size_t base = ((size_t)(y * a.nslot + 2 * l) * p3 + z) * n1h + k;
-    const c2<T> X = a.buf[base];
-    const c2<T> Y = l == 0 ? a.buf[base + (size_t)p3 * n1h] : zero;
-    c2<T>* line = lt + l * LT;
-    if (k == 0) {
-      line[0] = mk<T>(X.x, Y.x);
-    } else {
-      line[k] = mk<T>(X.x - Y.y, X.y + Y.x);
-      line[p1 - k] = mk<T>(X.x + Y.y, Y.x - X.y);
-    }
-  }
-  __syncthreads();
-  fft_lines<T, MAXV>(lt, LT, 2, a.plan, a.tw, +1);
-  // products in the context precision, staged in registers, then stored as
-  // float64 lines (pp11 + i pp22, pp12 + i pp13, pp23 + i pp33)
-  constexpr int NQ = 12;  // points per thread (p1 <= 12 * 256)
-  double pr[NQ][6];
+  T ph[3][NQ];            // NQ points per thread: p1 <= NQ * 256            // u1, u2, u3 at x = threadIdx.x + q * blockDim.x
+  // inverse transforms: line 0 = u1 + i u2 (two real signals), line 1 = u3
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int x = threadIdx.x + q * blockDim.x;
-    if (x < p1) {
-      const c2<T> A = lt[x], B = lt[LT + x];
-      const T u1 = A.x, u2 = A.y, u3 = B.x;
-      pr[q][0] = (double)(u1 * u1);
-      pr[q][1] = (double)(u1 * u2);
-      pr[q][2] = (double)(u1 * u3);
-      pr[q][3] = (double)(u2 * u2);
-      pr[q][4] = (double)(u2 * u3);
-      pr[q][5] = (double)(u3 * u3);
+  for (int l = 0; l < 2; ++l) {
+    for (int e = threadIdx.x; e < p1; e += blockDim.x) lt[e] = zero;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n1h; k += blockDim.x) {
+      const size_t base = ((size_t)(y * a.nslot + 2 * l) * p3 + z) * n1h + k;
+      const c2<T> X = a.buf[base];
+      const c2<T> Y = l == 0 ? a.buf[base + (size_t)p3 * n1h] : zero;
+      if (k == 0) {
+        lt[0] = mk<T>(X.x, Y.x);
+      } else {
+        lt[k] = mk<T>(X.x - Y.y, X.y + Y.x);
+        lt[p1 - k] = mk<T>(X.x + Y.y, Y.x - X.y);
+      }
     }
-  }
-  __syncthreads();
+    __syncthreads();
+    fft_lines<T, MAXV>(lt, a.lst, 1, a.plan, a.tw, +1);
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int x = threadIdx.x + q * blockDim.x;
-    if (x < p1) {
-      ld[0 * LD + x] = make_double2(pr[q][0], pr[q][3]);
-      ld[1 * LD + x] = make_double2(pr[q][1], pr[q][2]);
-      ld[2 * LD + x] = make_double2(pr[q][4], pr[q][5]);
+    for (int q = 0; q < NQ; ++q) {
+      const int x = threadIdx.x + q * blockDim.x;
+      const c2<T> v = x < p1 ? lt[x] : zero;
+      if (l == 0) {
+        ph[0][q] = v.x;
+        ph[1][q] = v.y;
+      } else {
+        ph[2][q] = v.x;
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int l = 0; l < 3; ++l) fft_lines<double, 24>(ld + l * LD, LD, 1, a.plan_d, a.tw_d, -1);
-  // unpack the two real spectra of each line, keep kx <= kcx
+  // products in the context precision, one float64 line of two of them at a
+  // time: (11, 22), (12, 13), (23, 33); then kx <= kcx of both spectra
   const int kc1 = a.kcx + 1;
   double2* out = a.out + ((size_t)y * a.plane_stride) + (size_t)z * kc1;
-  for (int e = threadIdx.x; e < 3 * kc1; e += blockDim.x) {
-    const int l = e / kc1, k = e - l * kc1;
-    const double2 W = ld[l * LD + k];
-    const double2 Wm = ld[l * LD + (k == 0 ? 0 : p1 - k)];
-    const double2 P = make_double2(0.5 * (W.x + Wm.x), 0.5 * (W.y - Wm.y));   // (W_k + conj W_m)/2
-    const double2 Q = make_double2(0.5 * (W.y + Wm.y), -0.5 * (W.x - Wm.x));  // (W_k - conj W_m)/(2i)
-    // line 0: pairs 0 (11), 3 (22); line 1: 1 (12), 2 (13); line 2: 4 (23), 5 (33)
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const int ia = l == 0 ? 0 : (l == 1 ? 0 : 1), ja = l == 0 ? 0 : (l == 1 ? 1 : 2);
+    const int ib = l == 0 ? 1 : (l == 1 ? 0 : 2), jb = l == 0 ? 1 : (l == 1 ? 2 : 2);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int x = threadIdx.x + q * blockDim.x;
+      if (x < p1) ld[x] = make_double2((double)(ph[ia][q] * ph[ja][q]), (double)(ph[ib][q] * ph[jb][q]));
+    }
+    __syncthreads();
+    fft_lines<double, 16>(ld, a.lsd, 1, a.plan_d, a.tw_d, -1);
+    // pairs of the line: 0 (11) and 3 (22); 1 (12) and 2 (13); 4 (23) and 5 (33)
     const int pa = l == 0 ? 0 : (l == 1 ? 1 : 4);
     const int pb = l == 0 ? 3 : (l == 1 ? 2 : 5);
-    out[(size_t)pa * p3 * kc1 + k] = P;
-    out[(size_t)pb * p3 * kc1 + k] = Q;
+    for (int k = threadIdx.x; k < kc1; k += blockDim.x) {
+      const double2 W = ld[k];
+      const double2 Wm = ld[k == 0 ? 0 : p1 - k];
+      const double2 P = make_double2(0.5 * (W.x + Wm.x), 0.5 * (W.y - Wm.y));   // (W_k + conj W_m)/2
+      const double2 Q = make_double2(0.5 * (W.y + Wm.y), -0.5 * (W.x - Wm.x));  // (W_k - conj W_m)/(2i)
+      out[(size_t)pa * p3 * kc1 + k] = P;
+      out[(size_t)pb * p3 * kc1 + k] = Q;
+    }
+    __syncthreads();
   }
 }
 
@@ -281,8 +280,15 @@ template hipError_t launch_stats<float>(const StatsArgs<float>&, hipStream_t);
 
 template <typename T>
 hipError_t launch_xfilter(const XfilterArgs<T>& a, size_t lds_bytes, hipStream_t st) {
-  constexpr int MV = sizeof(T) == 8 ? 24 : 48;
-  hipLaunchKernelGGL((k_xfilter<T, MV>), dim3(a.d.p3, a.d.n2), dim3(256), lds_bytes, st, a);
+  // one line of p1 <= 3072 points per transform: 16 staged values per thread
+  // hold every radix pass (radix 8: 2 butterflies, 4: 4, 3: 5, 2: 8 per thread)
+  // physical values per thread: the fewest of 3, 6, 9, 12 that cover p1 <= 3072
+  const dim3 grid(a.d.p3, a.d.n2);
+  if (a.d.p1 <= 3 * 256) hipLaunchKernelGGL((k_xfilter<T, 16, 3>), grid, dim3(256), lds_bytes, st, a);
+  else if (a.d.p1 <= 6 * 256) hipLaunchKernelGGL((k_xfilter<T, 16, 6>), grid, dim3(256), lds_bytes, st, a);
+  else if (a.d.p1 <= 9 * 256) hipLaunchKernelGGL((k_xfilter<T, 16, 9>), grid, dim3(256), lds_bytes, st, a);
+  else if (a.d.p1 <= 12 * 256) hipLaunchKernelGGL((k_xfilter<T, 16, 12>), grid, dim3(256), lds_bytes, st, a);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 hipError_t launch_zfilter(const ZfilterArgs& a, size_t lds_bytes, hipStream_t st) {
