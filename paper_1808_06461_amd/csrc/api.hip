@@ -361,8 +361,10 @@ chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, voi
   return CHN_OK;
 }
 
-template <typename TP> chn_status recover(chn_ctx* x, TP* const* out) {
+// omega = false: u1, u2, u3 only (out[3], out[4] untouched)
+template <typename TP> chn_status recover(chn_ctx* x, TP* const* out, bool omega = true) {
   chn::RecoverArgs<TP> ra{};
+  ra.omega = omega ? 1 : 0;
   ra.g = x->geom;
   ra.v = x->v;
   ra.om2 = x->om2;
@@ -545,7 +547,7 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   //    that path; the enstrophy is formed from the float64 vorticity)
   double* su[5] = {x->S[3], x->S[4], x->S[5], x->S[6], x->S[7]};
   x->htab_dt = 0.0;  // overwrites the factor tables of sub-steps 1 and 2
-  if (chn_status st = recover<double>(x, su)) return st;
+  if (chn_status st = recover<double>(x, su, ens)) return st;  // the stresses need the velocities only
   double* fin[3] = {x->S[3], x->S[4], x->S[5]};
   if (ens) {
     fin[0] = x->S[6];
@@ -568,8 +570,9 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   za.tw = x->tw3d;
   za.plan = x->plan3;
   za.d = x->dims;
-  za.K = lines(p3, n1h);
   za.lstride = plane_lds_stride(p3);
+  // lines per workgroup: at most what leaves room for three workgroups per CU
+  za.K = std::max(1, std::min(lines(p3, n1h), (int)((size_t)x->lds_max / 3 / ((size_t)za.lstride * 16))));
   za.nfields = 3;
   za.nslot = nslot;
   za.zero_mean = 1;

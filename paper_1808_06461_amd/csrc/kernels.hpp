@@ -163,6 +163,7 @@ template <typename TP> struct RecoverArgs {
   double* S0;                 // lane-indexed scratch, 3 arrays of [n2][2M]
   double* S1;
   double* S2;
+  int omega;                  // nonzero: also omega1, omega3 (else out[3], out[4] untouched)
 };
 
 template <typename TH, typename TP> struct AdvanceArgs {

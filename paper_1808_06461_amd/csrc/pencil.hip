@@ -159,7 +159,10 @@ template <typename T> __device__ __forceinline__ double load_r(const T* p, size_
 
 // ---------------------------------------------------------------- recovery
 template <typename TP>
-__global__ void __launch_bounds__(256) k_recover(RecoverArgs<TP> a) {
+__global__ void __launch_bounds__(256) k_recover(RecoverArgs<TP> a, const double* __restrict__ B1,
+                                                 const double* __restrict__ L1d, const double* __restrict__ U1d,
+                                                 const double* __restrict__ L1u, const double* __restrict__ U1u) {
+  // tables as noalias parameters: wave-uniform row reads through the scalar cache
   const PencilGeom& g = a.g;
   const Lane L = lane_setup(g, blockIdx.x);
   const int n = g.n2;
@@ -173,7 +176,7 @@ __global__ void __launch_bounds__(256) k_recover(RecoverArgs<TP> a) {
     for (int k = 0; k < 3; ++k) w[3 + k] = a.v[k * st + col];
     for (int i = 0; i < n; ++i) {
       w[6] = (i + 3 < n) ? a.v[(i + 3) * st + col] : 0.0;
-      const double yi = elim3(dot7(g.B1 + i * 7, w), g.L1d + i * 3, yb);
+      const double yi = elim3(dot7(B1 + i * 7, w), L1d + i * 3, yb);
       if (L.act) {
         a.S0[i * st + col] = yi;
         a.out[1][i * st + col] = (TP)w[3];
@@ -192,7 +195,7 @@ __global__ void __launch_bounds__(256) k_recover(RecoverArgs<TP> a) {
     for (int i = n - 1; i >= -3; --i) {
       double u1 = 0.0, u3 = 0.0;
       if (i >= 0) {
-        const double dv = back3(a.S0[i * st + col], g.U1d + i * 4, xb);
+        const double dv = back3(a.S0[i * st + col], U1d + i * 4, xb);
         push_x(xb, dv);
         const double dvo = __shfl_xor(dv, 1);
         const double dre = L.c ? dvo : dv, dim = L.c ? dv : dvo;
@@ -209,12 +212,13 @@ __global__ void __launch_bounds__(256) k_recover(RecoverArgs<TP> a) {
           a.out[2][i * st + col] = (TP)u3;
         }
       }
+      if (!a.omega) continue;  // velocities only
       push_front(w1, u1);
       push_front(w3, u3);
       const int r = i + 3;
       if (r <= n - 1) {
-        const double* b = g.B1 + r * 7;
-        const double* l = g.L1u + r * 3;
+        const double* b = B1 + r * 7;
+        const double* l = L1u + r * 3;
         const double y1 = elim3(dot7(b, w1), l, y1b);
         const double y3 = elim3(dot7(b, w3), l, y3b);
         if (L.act) {
@@ -227,10 +231,10 @@ __global__ void __launch_bounds__(256) k_recover(RecoverArgs<TP> a) {
     }
   }
   // R3, downward: finish du1, du3; omega1 = du3 - i b v, omega3 = i a v - du1
-  {
+  if (a.omega) {
     double x1[3] = {0, 0, 0}, x3[3] = {0, 0, 0};
     for (int r = 0; r < n; ++r) {
-      const double* U = g.U1u + r * 4;
+      const double* U = U1u + r * 4;
       const double du1 = back3(a.S1[r * st + col], U, x1);
       const double du3 = back3(a.S2[r * st + col], U, x3);
       push_x(x1, du1);
@@ -1323,7 +1327,8 @@ __global__ void k_f2d(const float* __restrict__ in, double* __restrict__ out, si
 static inline unsigned pencil_blocks(int M) { return (unsigned)((2 * (size_t)M + 255) / 256); }
 
 template <typename TP> hipError_t launch_recover(const RecoverArgs<TP>& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_recover<TP>), dim3(pencil_blocks(a.g.M)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_recover<TP>), dim3(pencil_blocks(a.g.M)), dim3(256), 0, st, a, a.g.B1, a.g.L1d, a.g.U1d,
+                     a.g.L1u, a.g.U1u);
   return hipGetLastError();
 }
 hipError_t launch_homog(const HomogArgs& a, hipStream_t st) {
