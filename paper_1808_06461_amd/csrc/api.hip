@@ -1288,7 +1288,8 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
     const int c = std::min(x->ychunk_max, (x->n2 + parts - 1) / parts);
     if (c >= 1 && std::find(chunks.begin(), chunks.end(), c) == chunks.end()) chunks.push_back(c);
   }
-  const bool has_fixed = chn::plan_is_576(x->plan1) || chn::plan_is_576(x->plan3);
+  const bool has_fixed = chn::plan_is_576(x->plan1) || chn::plan_is_576(x->plan3) || chn::plan_is_9216(x->plan3) ||
+                         chn::plan_is_12288(x->plan1);
   for (int fx = 0; fx <= (has_fixed ? 1 : 0); ++fx)
     for (int xr : {8, 4, 2, 1})
       for (int K : {1, 2, 4, 8, 12, 16, kmax})

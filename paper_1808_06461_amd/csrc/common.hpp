@@ -30,6 +30,22 @@ __host__ __device__ inline bool plan_is_576(const FftPlan& pl) {
   return pl.n == 576 && pl.npass == 4 && pl.radix[0] == 8 && pl.radix[1] == 8 && pl.radix[2] == 3 &&
          pl.radix[3] == 3;
 }
+// The long lines of the 8192 x 6144 planes: 9216 points (radices 8, 8, 8, 2,
+// 3, 3) and 12288 points (8, 8, 8, 8, 3), compile-time schedules like 576.
+__host__ __device__ inline bool plan_has(const FftPlan& pl, int n, int np, const int* r) {
+  if (pl.n != n || pl.npass != np) return false;
+  for (int p = 0; p < np; ++p)
+    if (pl.radix[p] != r[p]) return false;
+  return true;
+}
+__host__ __device__ inline bool plan_is_9216(const FftPlan& pl) {
+  const int r[6] = {8, 8, 8, 2, 3, 3};
+  return plan_has(pl, 9216, 6, r);
+}
+__host__ __device__ inline bool plan_is_12288(const FftPlan& pl) {
+  const int r[5] = {8, 8, 8, 8, 3};
+  return plan_has(pl, 12288, 5, r);
+}
 
 // XCD-aware order of a launch's n workgroups.  The dispatcher deals
 // workgroup w to XCD w % 8, and each XCD has its own L2; this gives XCD x the

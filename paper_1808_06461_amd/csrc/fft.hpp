@@ -195,6 +195,21 @@ __device__ __forceinline__ void fft_lines(c2<T>* lds, int lstride, int nlines, c
     stockham_pass_c<T, 3, MAXV / 3, 576, 64, PAD>(lds, lstride, nlines, tw + pl.twoff[2], sgn);
     stockham_pass_c<T, 3, MAXV / 3, 576, 192, PAD>(lds, lstride, nlines, tw + pl.twoff[3], sgn);
     return;
+  } else if constexpr (FN == 9216) {  // 3/2 x 6144: radices 8, 8, 8, 2, 3, 3
+    stockham_pass_c<T, 8, MAXV / 8, 9216, 1, PAD>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
+    stockham_pass_c<T, 8, MAXV / 8, 9216, 8, PAD>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
+    stockham_pass_c<T, 8, MAXV / 8, 9216, 64, PAD>(lds, lstride, nlines, tw + pl.twoff[2], sgn);
+    stockham_pass_c<T, 2, MAXV / 2, 9216, 512, PAD>(lds, lstride, nlines, tw + pl.twoff[3], sgn);
+    stockham_pass_c<T, 3, MAXV / 3, 9216, 1024, PAD>(lds, lstride, nlines, tw + pl.twoff[4], sgn);
+    stockham_pass_c<T, 3, MAXV / 3, 9216, 3072, PAD>(lds, lstride, nlines, tw + pl.twoff[5], sgn);
+    return;
+  } else if constexpr (FN == 12288) {  // 3/2 x 8192: radices 8, 8, 8, 8, 3
+    stockham_pass_c<T, 8, MAXV / 8, 12288, 1, PAD>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
+    stockham_pass_c<T, 8, MAXV / 8, 12288, 8, PAD>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
+    stockham_pass_c<T, 8, MAXV / 8, 12288, 64, PAD>(lds, lstride, nlines, tw + pl.twoff[2], sgn);
+    stockham_pass_c<T, 8, MAXV / 8, 12288, 512, PAD>(lds, lstride, nlines, tw + pl.twoff[3], sgn);
+    stockham_pass_c<T, 3, MAXV / 3, 12288, 4096, PAD>(lds, lstride, nlines, tw + pl.twoff[4], sgn);
+    return;
   } else {
   int Ns = 1;
   for (int p = 0; p < pl.npass; ++p) {

@@ -203,8 +203,9 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
 // (thread t owns x = t + NT q, q < QX); the products are formed in registers,
 // then H1 + i H2 and H3 are transformed forward one line at a time.  Used
 // when six lines of the row do not fit the two-row kernel.
-template <typename T, int NT, int QX, int MAXV>
+template <typename T, int NT, int QX, int MAXV, int FN = 0>
 __device__ __forceinline__ void xrow_body(const XpassArgs<T>& a, int z, int y) {
+  static_assert(FN == 0 || FN == 12288, "compile-time schedules of long rows: 12288 points");
   extern __shared__ unsigned char smem_raw[];
   c2<T>* line = reinterpret_cast<c2<T>*>(smem_raw);
   const int n1h = a.d.n1h, p1 = a.d.p1, p3 = a.d.p3;
@@ -224,7 +225,7 @@ __device__ __forceinline__ void xrow_body(const XpassArgs<T>& a, int z, int y) {
       }
     }
     __syncthreads();
-    fft_lines<T, MAXV>(line, p1, 1, a.plan, a.tw, +1);
+    fft_lines<T, MAXV, FN>(line, p1, 1, a.plan, a.tw, +1);
 #pragma unroll
     for (int q = 0; q < QX; ++q) {
       const int x = threadIdx.x + q * NT;
@@ -285,7 +286,7 @@ __device__ __forceinline__ void xrow_body(const XpassArgs<T>& a, int z, int y) {
       a.rowsum[(size_t)a.d.n2 * p3 + o] = t3;
       a.rowcfl[o] = tc;
     }
-    fft_lines<T, MAXV>(line, p1, 1, a.plan, a.tw, -1);
+    fft_lines<T, MAXV, FN>(line, p1, 1, a.plan, a.tw, -1);
     for (int k = threadIdx.x; k < n1h; k += NT) {
       const c2<T> W = line[k];
       if (l == 0) {
@@ -355,8 +356,8 @@ __global__ void __launch_bounds__(NT) k_zinv(ZinvArgs<T> a) {
 }
 template <typename T, int MAXV, int FN, int RZ>
 __global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) { xpass_body<T, MAXV, FN, RZ>(a, blockIdx.x, blockIdx.y); }
-template <typename T, int NT, int QX, int MAXV>
-__global__ void __launch_bounds__(NT) k_xrow(XpassArgs<T> a) { xrow_body<T, NT, QX, MAXV>(a, blockIdx.x, blockIdx.y); }
+template <typename T, int NT, int QX, int MAXV, int FN = 0>
+__global__ void __launch_bounds__(NT) k_xrow(XpassArgs<T> a) { xrow_body<T, NT, QX, MAXV, FN>(a, blockIdx.x, blockIdx.y); }
 template <typename T, typename TO, int MAXV, int FN, int NT = 256>
 __global__ void __launch_bounds__(NT) k_zfwd(ZfwdArgs<T, TO> a) {
   const int2 t = z_tile();
@@ -430,6 +431,8 @@ hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st) {
   dim3 grid((a.d.n1h + a.K - 1) / a.K, a.ny);
   size_t sh = (size_t)a.K * a.lstride * sizeof(c2<T>);
   if (z_threads(a.plan, a.K) == 1024) {
+    // runtime schedule: the compile-time 9216-point one spills at 1024 threads
+    // (128 VGPRs) and is slower here; the forward pass below keeps it
     const int m = pick_staging<T>(a.plan, 1, 1024);
     CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 0, 1024>), grid, dim3(1024), sh, st, a));
     return hipGetLastError();
@@ -483,6 +486,8 @@ hipError_t launch_xpass(const XpassArgs<T>& a, hipStream_t st) {
   const size_t sh = (size_t)a.d.p1 * sizeof(c2<T>);
   if (nt == 256) hipLaunchKernelGGL((k_xrow<T, 256, QX, XM>), grid, dim3(256), sh, st, a);
   else if (nt == 512) hipLaunchKernelGGL((k_xrow<T, 512, QX, XM>), grid, dim3(512), sh, st, a);
+  else if (nt == 1024 && a.fixed && plan_is_12288(a.plan))
+    hipLaunchKernelGGL((k_xrow<T, 1024, QX, XM, 12288>), grid, dim3(1024), sh, st, a);
   else if (nt == 1024) hipLaunchKernelGGL((k_xrow<T, 1024, QX, XM>), grid, dim3(1024), sh, st, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
@@ -494,7 +499,10 @@ hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st) {
   size_t sh = (size_t)a.K * a.lstride * sizeof(c2<T>);
   if (z_threads(a.plan, a.K) == 1024) {
     const int m = pick_staging<T>(a.plan, 1, 1024);
-    CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 0, 1024>), grid, dim3(1024), sh, st, a));
+    if (a.fixed && plan_is_9216(a.plan))
+      CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 9216, 1024>), grid, dim3(1024), sh, st, a));
+    else
+      CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 0, 1024>), grid, dim3(1024), sh, st, a));
     return hipGetLastError();
   }
   const int m = pick_staging<T>(a.plan, a.K, 256);
