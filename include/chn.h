@@ -220,6 +220,38 @@ chn_status chn_plane_products(chn_ctx *ctx, const void *const *d_in, void *const
 chn_status chn_get_operators(chn_ctx *ctx, double *a1, double *b1, double *a2, double *b2,
                              double *quad);
 
+/* Near-wall mesh optimisation of Appendix B (a host routine: no context, no
+ * GPU).  The homogeneous problem of the implicit steps, (B2 - k* A2) g = 0
+ * in the interior rows with g = 1 at y = -1 and g = 0 at y = 1, has the
+ * analytic solution sinh(q (1 - y)) / sinh(2 q), q = sqrt(k*); for layers
+ * thinner than the first cells the compact solution departs from it near
+ * the wall.  The first m interior nodes y_1..y_m (and their mirror images
+ * y_{n2-2}..y_{n2-1-m}) are moved to minimise
+ *   L = ||g - g_ana||_2 + penalty ||(y_1..y_m) - (y_ref_1..y_ref_m)||_2
+ * by steepest descent in spacing-scaled coordinates: central-difference
+ * gradient (step 1e-6 of the local spacing), step length halved from twice
+ * the last accepted one until the mesh is strictly increasing, L strictly
+ * decreases, the Armijo condition with 1e-4 holds and the trial mesh's A2
+ * has a 1-norm condition number at most 10 times the reference mesh's (so
+ * the compact operator stays well posed); at most max_iter
+ * steps, fewer when the step length falls below 1e-30.  The compact rows
+ * are the quad-precision ones of the library's operators.
+ *   y_ref:      HOST, n2 nodes, strictly increasing, y_ref[0] = -1,
+ *               y_ref[n2-1] = 1, exactly symmetric (y[n2-1-i] = -y[i]).
+ *   m:          free nodes per wall, 1 <= m, 2 m + 2 <= n2 (the paper moves
+ *               20, with the wall node 21).
+ *   kstar:      modified wavenumber k^2 + 1/(beta nu dt) of the layer, > 0.
+ *   penalty:    C >= 0 (the paper uses about 1e-3).
+ *   y_out:      HOST, n2 nodes, written on CHN_OK (may alias nothing).
+ *   err_ref, err_opt, iterations: HOST scalars (each may be NULL):
+ *               ||g - g_ana||_2 on y_ref and on y_out, accepted steps.
+ * Errors: CHN_EINVAL for invalid arguments (nothing written), CHN_EUNSTABLE
+ * if a banded solve breaks down or gives a non-finite error.  Thread-safe
+ * (no global state).  Runs on the calling thread. */
+chn_status chn_optimise_mesh(const double *y_ref, int n2, int m, double kstar, double penalty,
+                             int max_iter, double *y_out, double *err_ref, double *err_opt,
+                             int *iterations);
+
 /* ---------------------------------------------------------------- ensembles
  * An ensemble advances n independent channels of uneven sizes together:
  * every phase of the RK3 sub-step is one batched launch over all channels

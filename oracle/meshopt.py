@@ -30,6 +30,12 @@ Readings (where the paper is silent):
   L(new) <= L + 1e-4 t (grad . d) holds (strict decrease rejects a step that
   rounds to no move at all); the descent stops after max_iter iterations,
   or when t falls below 1e-30.
+- A trial mesh must also keep the compact operator well posed: its A2 may
+  have a 1-norm condition number at most 10 times that of the reference
+  mesh's A2.  The paper's functional only sees B2 - k* A2, and without this
+  guard the descent can reach meshes on which A2 itself is singular (the
+  maximum-order stencils degenerate for some local stretchings) while the
+  homogeneous error keeps falling.
 
 The compact rows come from ``compact.row_coefficients`` (exact rationals);
 only the rows whose stencils contain a moved node are recomputed.
@@ -43,6 +49,13 @@ from . import compact
 FD_REL = 1e-6       # central-difference step, relative to the local spacing
 ARMIJO = 1e-4
 T_MIN = 1e-30
+COND_GROWTH = 10.0  # allowed growth of cond_1(A2) over the reference mesh
+
+
+def cond1(A):
+    """1-norm condition number of the banded matrix A (dense inverse)."""
+    M = compact.band_to_dense(A)
+    return float(np.linalg.norm(M, 1) * np.linalg.norm(np.linalg.inv(M), 1))
 
 
 def g_analytic(y, kstar):
@@ -95,6 +108,7 @@ class _Problem:
         self.s = y_ref[2:m + 2] - y_ref[1:m + 1]
         A, B = compact.operators(y_ref, 2)
         self.A0, self.B0 = A.copy(), B.copy()
+        self.cond_max = COND_GROWTH * cond1(A)
 
     def mesh(self, x):
         y = self.y_ref.copy()
@@ -159,7 +173,7 @@ def optimise_mesh(y_ref, m=20, kstar=1e10, penalty=1e-3, max_iter=60, history=No
             if np.all(np.diff(yn) > 0):
                 An, Bn = P.operators(yn)
                 fn = P.L_from(xn, yn, An, Bn)[0]
-                if fn < f and fn <= f + ARMIJO * t * slope:
+                if fn < f and fn <= f + ARMIJO * t * slope and cond1(An) <= P.cond_max:
                     accepted = True
                     break
             t *= 0.5

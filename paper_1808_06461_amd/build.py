@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchn.so")
 HIP_SOURCES = ["api.hip", "plane.hip", "pencil.hip", "lowstorage.hip"]
-HOST_SOURCES = ["coeffs.cpp"]
+HOST_SOURCES = ["coeffs.cpp", "meshopt.cpp"]
 ARCH = os.environ.get("CHN_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -82,12 +82,16 @@ def lib():
         L.chn_ens_last_error.restype = C.c_char_p
         L.chn_last_error.argtypes = [P]
         L.chn_last_error.restype = C.c_char_p
+        D = C.POINTER(C.c_double)
+        L.chn_optimise_mesh.argtypes = [D, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, D, D, D,
+                                        C.POINTER(C.c_int)]
         for name in ("chn_create", "chn_destroy", "chn_set_state", "chn_step_rk3", "chn_get_fields",
                      "chn_nonlinear", "chn_filter_and_stress", "chn_filtered_enstrophy", "chn_accumulate_statistics",
                      "chn_filtered_pressure",
                      "chn_get_operators",
                      "chn_timing_enable", "chn_timing_read", "chn_ens_create", "chn_ens_destroy", "chn_ens_step",
-                     "chn_get_plan", "chn_set_plan", "chn_autotune", "chn_plane_products"):
+                     "chn_get_plan", "chn_set_plan", "chn_autotune", "chn_plane_products",
+                     "chn_optimise_mesh"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -97,6 +101,25 @@ def header_symbols():
     """Names of the functions declared in include/chn.h."""
     text = open(HEADER).read()
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(chn_\w+)\s*\(", text, re.M)))
+
+
+def optimise_mesh(y_ref, m=20, kstar=1e10, penalty=1e-3, max_iter=60):
+    """Near-wall mesh optimisation (``chn_optimise_mesh``, a host routine).
+
+    Returns (y_opt, err_ref, err_opt, iterations); raises ChnError on a
+    non-OK status."""
+    import numpy as np
+    y_ref = np.ascontiguousarray(y_ref, dtype=np.float64)
+    n2 = len(y_ref)
+    y_out = np.empty(n2)
+    e0, e1, it = C.c_double(), C.c_double(), C.c_int()
+    D = C.POINTER(C.c_double)
+    st = lib().chn_optimise_mesh(y_ref.ctypes.data_as(D), n2, int(m), float(kstar), float(penalty),
+                                 int(max_iter), y_out.ctypes.data_as(D), C.byref(e0), C.byref(e1),
+                                 C.byref(it))
+    if st != 0:
+        raise ChnError(f"chn_optimise_mesh: {STATUS.get(st, st)}")
+    return y_out, e0.value, e1.value, it.value
 
 
 def _ptr(t):

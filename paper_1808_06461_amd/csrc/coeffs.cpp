@@ -54,10 +54,9 @@ static bool solve_dense(int n, q* M, q* r) {
   return true;
 }
 
-bool compact_bands(int n2, const double* y, int p, double* A, double* B) {
-  std::memset(A, 0, sizeof(double) * 7 * n2);
-  std::memset(B, 0, sizeof(double) * 7 * n2);
-  for (int i = 0; i < n2; ++i) {
+bool compact_row(int n2, const double* y, int i, int p, double* Ar, double* Br) {
+  for (int o = 0; o < 7; ++o) Ar[o] = Br[o] = 0.0;
+  {
     const int lo = i - 3 < 0 ? 0 : i - 3;
     const int hi = i + 3 > n2 - 1 ? n2 - 1 : i + 3;
     const int w = hi - lo + 1;
@@ -87,10 +86,16 @@ bool compact_bands(int n2, const double* y, int p, double* A, double* B) {
     q hp = p == 2 ? h * h : h;
     for (int j = 0; j < w; ++j) {
       const int o = lo + j - i + 3;
-      B[i * 7 + o] = (double)(r[j] / hp);
-      A[i * 7 + o] = (double)r[w + j];
+      Br[o] = (double)(r[j] / hp);
+      Ar[o] = (double)r[w + j];
     }
   }
+  return true;
+}
+
+bool compact_bands(int n2, const double* y, int p, double* A, double* B) {
+  for (int i = 0; i < n2; ++i)
+    if (!compact_row(n2, y, i, p, A + 7 * i, B + 7 * i)) return false;
   return true;
 }
 

@@ -18,6 +18,8 @@ constexpr int kMaxPass = 16;
 #endif
 
 namespace host {
+// row i of the banded (A, B) pair: Ar[3 + o] = A[i][i + o], o = -3..3
+bool compact_row(int n2, const double* y, int i, int p, double* Ar, double* Br);
 bool compact_bands(int n2, const double* y, int p, double* A, double* B);
 void quadrature(int n2, const double* y, double* w);
 bool band_lu(int n, const double* band, int dir, double* L, double* U);

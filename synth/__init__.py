@@ -107,7 +107,7 @@ def _leg(n=96):
     return x, w
 
 
-def turbulent_field(case: Case, seed_i: int = 0):
+def turbulent_field(case: Case, seed_i: int = 0, y: np.ndarray | None = None):
     """Divergence-free random perturbation + mean profile.
 
     Per retained mode m != (0,0):
@@ -117,9 +117,12 @@ def turbulent_field(case: Case, seed_i: int = 0):
     is proportional to k_h**spectrum, then globally so that the volume RMS of
     |u'| equals ``case.amp``.  kx=0 modes are made Hermitian in kz.
     Returns (v, omega2, U1, U3, y) with v/omega2 complex [n2][n1/2][n3].
+    ``y`` (n2 nodes) replaces the default tanh mesh; the profiles are the
+    same functions of y, so only the sampling changes.
     """
     n1, n2, n3 = case.n1, case.n2, case.n3
-    y = mesh_tanh(n2)
+    y = mesh_tanh(n2) if y is None else np.asarray(y, dtype=np.float64)
+    assert y.shape == (n2,)
     kxi, kzi, a, b = wavenumbers(n1, n3, case.lx, case.lz)
     g = rng(case.cfg, seed_i)
     nk = n1 // 2

@@ -1,0 +1,120 @@
+"""Near-wall mesh optimisation (Appendix B) through the C ABI, against the oracle.
+
+``chn_optimise_mesh`` is a host routine; these tests run with the GPU tests
+because they call the library, and the last one steps the channel on the
+optimised mesh.
+
+* Parity with the oracle's descent on small meshes: the reference error
+  ||g - g_ana|| to 1e-13 relative (one banded solve against a dense one),
+  the same number of accepted steps, and after them the meshes to 1e-5 of
+  the smallest moved spacing and the errors to 1e-5 relative.  The
+  gradient is a central difference (step 1e-6 of the spacing), so rounding
+  differences of the two solves (1e-16) reach the gradient at about 1e-10
+  and grow over the steps; 1e-5 leaves room for that and would still catch
+  a wrong row, sign or norm (those change the first step at O(1)).
+* At the size of the 384 x 193 x 384 workload (193 nodes, its critical
+  modified wavenumber, 20 free nodes per wall, the paper's C = 1e-3): the
+  error the library reports for its mesh is what the oracle computes on
+  that mesh, the mesh is symmetric and increasing, and the error drops.
+* The 64 x 65 x 64 workload stepped for 10 RK3 steps on its optimised mesh
+  matches the oracle on the same mesh to the float64 bound of the step
+  parity tests (1e-11), scaled by the growth of cond_1(A2) over the
+  reference mesh: both sides round at 1e-16, and the compact solves amplify
+  that by the operator's conditioning, which the descent lets grow up to
+  tenfold.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import kmm, meshopt
+
+torch = pytest.importorskip("torch")
+gpu = pytest.mark.gpu
+
+
+def critical_kstar(case):
+    """Largest k^2 + 1/(beta nu dt) of the retained modes (beta_min = 1/6)."""
+    kx = 2 * math.pi / case.lx * (case.n1 // 2 - 1)
+    kz = 2 * math.pi / case.lz * (case.n3 // 2 - 1)
+    return kx * kx + kz * kz + 6.0 * case.re_b / case.dt
+
+
+def _rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+@gpu
+@pytest.mark.parametrize("n2,m,iters,kstar", [(33, 6, 5, 1e10), (49, 10, 4, 1e6)])
+def test_descent_matches_oracle(n2, m, iters, kstar):
+    from paper_1808_06461_amd import chn
+    y_ref = synth.mesh_tanh(n2)
+    yp, p0, p1, pk = chn.optimise_mesh(y_ref, m=m, kstar=kstar, max_iter=iters)
+    yo, o0, o1, ok = meshopt.optimise_mesh(y_ref, m=m, kstar=kstar, max_iter=iters)
+    s = np.diff(y_ref)[:m + 1].min()
+    print(f"n2={n2} m={m}: e_ref {p0:.6e}/{o0:.6e}, e_opt {p1:.6e}/{o1:.6e}, "
+          f"mesh {np.abs(yp - yo).max() / s:.2e} of the spacing")
+    assert pk == ok == iters
+    assert _rel(p0, o0) < 1e-13
+    assert _rel(p1, o1) < 1e-5
+    assert np.abs(yp - yo).max() < 1e-5 * s
+
+
+@gpu
+def test_workload_mesh_properties():
+    from paper_1808_06461_amd import chn
+    case = synth.CASES["c2"]
+    y_ref = synth.mesh_tanh(case.n2)
+    ks = critical_kstar(case)
+    y, e0, e1, it = chn.optimise_mesh(y_ref, m=20, kstar=ks, penalty=1e-3, max_iter=60)
+    print(f"193 nodes, k* = {ks:.4e}: {e0:.3e} -> {e1:.3e} in {it} steps")
+    assert it >= 1 and e1 < e0
+    assert np.all(np.diff(y) > 0)
+    np.testing.assert_array_equal(y, -y[::-1])
+    np.testing.assert_array_equal(y[21:case.n2 - 21], y_ref[21:case.n2 - 21])
+    assert _rel(e1, meshopt.homogeneous_error(y, ks)) < 1e-10
+    assert _rel(e0, meshopt.homogeneous_error(y_ref, ks)) < 1e-12
+
+
+@gpu
+def test_invalid_arguments():
+    from paper_1808_06461_amd import chn
+    y = synth.mesh_tanh(33)
+    bad = y.copy()
+    bad[3] += 1e-9  # breaks the mirror symmetry
+    for args in ((bad, 6), (y, 16), (y, 0)):
+        with pytest.raises(chn.ChnError, match="CHN_EINVAL"):
+            chn.optimise_mesh(args[0], m=args[1], kstar=1e6, max_iter=1)
+    with pytest.raises(chn.ChnError, match="CHN_EINVAL"):
+        chn.optimise_mesh(y, m=6, kstar=-1.0, max_iter=1)
+
+
+@gpu
+def test_c1_steps_on_optimised_mesh():
+    from paper_1808_06461_amd import Channel, chn
+    case = synth.CASES["c1"]
+    y0 = synth.mesh_tanh(case.n2)
+    y, e0, e1, it = chn.optimise_mesh(y0, m=20, kstar=critical_kstar(case), max_iter=30)
+    from oracle import compact
+    growth = meshopt.cond1(compact.operators(y, 2)[0]) / meshopt.cond1(compact.operators(y0, 2)[0])
+    print(f"65 nodes: {e0:.3e} -> {e1:.3e} in {it} steps, cond_1(A2) x {growth:.2f}")
+    assert e1 < e0 and growth <= meshopt.COND_GROWTH * (1 + 1e-9)
+    tol = 1e-11 * max(1.0, growth)
+    v, om, U1, U3, _ = synth.turbulent_field(case, y=y)
+    S = kmm.Setup(n1=case.n1, n2=case.n2, n3=case.n3, lx=case.lx, lz=case.lz, nu=1 / case.re_b,
+                  dt=case.dt, mass_flux=case.mass_flux, y=y)
+    ref, _ = kmm.step(S, kmm.make_state(S, v, om, U1, U3), 10)
+    ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, mass_flux=case.mass_flux,
+                 precision="fp64", y=y)
+    try:
+        ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+        ch.step(case.dt, 10)
+        got = {k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "chi", "u1mean").items()}
+    finally:
+        ch.close()
+    for name, r in (("v", ref.v), ("omega2", ref.om2), ("chi", ref.chi), ("u1mean", ref.U1)):
+        e = float(np.linalg.norm(got[name] - r) / np.linalg.norm(r))
+        print(f"optimised mesh {name}: {e:.2e}")
+        assert e < tol, (name, e)
