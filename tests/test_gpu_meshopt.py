@@ -21,7 +21,10 @@ optimised mesh.
   parity tests (1e-11), scaled by the growth of cond_1(A2) over the
   reference mesh: both sides round at 1e-16, and the compact solves amplify
   that by the operator's conditioning, which the descent lets grow up to
-  tenfold.
+  tenfold.  chi's wall values come out of the influence-matrix cancellation
+  (the step parity tests allow it 1e-9 on coarse meshes), so chi as a whole
+  gets 1e-9 times the same growth, and A2 chi in the interior rows, the form
+  the Poisson step uses, the tight bound.
 """
 import math
 
@@ -114,7 +117,16 @@ def test_c1_steps_on_optimised_mesh():
         got = {k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "chi", "u1mean").items()}
     finally:
         ch.close()
-    for name, r in (("v", ref.v), ("omega2", ref.om2), ("chi", ref.chi), ("u1mean", ref.U1)):
+    for name, r in (("v", ref.v), ("omega2", ref.om2), ("u1mean", ref.U1)):
         e = float(np.linalg.norm(got[name] - r) / np.linalg.norm(r))
         print(f"optimised mesh {name}: {e:.2e}")
         assert e < tol, (name, e)
+    e = float(np.linalg.norm(got["chi"] - ref.chi) / np.linalg.norm(ref.chi))
+    print(f"optimised mesh chi: {e:.2e}")
+    assert e < 1e-9 * max(1.0, growth), ("chi", e)
+    A2 = compact.band_to_dense(compact.operators(y, 2)[0])[1:-1]
+    ca = np.tensordot(A2, got["chi"], axes=1)
+    cb = np.tensordot(A2, ref.chi, axes=1)
+    e = float(np.linalg.norm(ca - cb) / np.linalg.norm(cb))
+    print(f"optimised mesh A2 chi (interior rows): {e:.2e}")
+    assert e < tol, ("A2 chi", e)
