@@ -211,6 +211,32 @@ def c3_run(reps=3):
             "pencils": pencils}
 
 
+def meshopt_run():
+    """Near-wall mesh optimisation (a host routine, run once before a simulation):
+    the 193-node mesh of the 384 x 193 x 384 workload at its critical modified
+    wavenumber k^2_max + 1/(beta_min nu dt), and the 1537-node mesh of the
+    Re_tau 5300 channel at k* = 1e10 (the unresolved-layer regime, where the
+    homogeneous error has saturated); 20 free nodes per wall, C = 1e-3, at
+    most 60 descent steps; wall time of the call on the host."""
+    import math
+
+    import synth
+    from paper_1808_06461_amd import chn
+    c = synth.CASES["c2"]
+    kx = 2 * math.pi / c.lx * (c.n1 // 2 - 1)
+    kz = 2 * math.pi / c.lz * (c.n3 // 2 - 1)
+    out = {}
+    for name, n2, ks in (("mesh_193", c.n2, kx * kx + kz * kz + 6.0 * c.re_b / c.dt), ("mesh_1537", 1537, 1e10)):
+        y = synth.mesh_tanh(n2)
+        t0 = time.perf_counter()
+        yo, e0, e1, it = chn.optimise_mesh(y, m=20, kstar=ks, penalty=1e-3, max_iter=60)
+        ms = (time.perf_counter() - t0) * 1e3
+        s = np.diff(y)[1:21]
+        out[name] = {"kstar": ks, "err_ref": e0, "err_opt": e1, "reduction": e0 / e1, "steps": it,
+                     "max_shift_in_spacings": float((np.abs(yo - y)[1:21] / s).max()), "host_ms": round(ms, 1)}
+    return out
+
+
 def c5_run(reps=5, precision="mixed"):
     """The low-storage stage on the 1536 x 385 x 1152 field (Re_tau ~ 950): cut-off
     kc = (96, 72), filtered products and tau_ij on the 432 x 324 grid, the
@@ -280,6 +306,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the per-phase timing of the Re_tau 5300 share")
     ap.add_argument("--no-c5", action="store_true", help="skip the timing of the low-storage stage")
+    ap.add_argument("--no-meshopt", action="store_true", help="skip the near-wall mesh optimisation leg")
     ap.add_argument("--plan", default=None, metavar="XROWS,ZLINES,YCHUNK[,FIXED]",
                     help="fixed plane-phase schedule instead of the autotuner (for profiling one schedule)")
     ap.add_argument("--source-hash", default=None, metavar="KIND",
@@ -288,7 +315,7 @@ def main():
                     help="also run five plain device copies of BYTES bytes (calibrates HBM byte counters)")
     ap.add_argument("--only", choices=("fp64", "mixed"), default=None,
                     help="run one precision only (for profiling; the JSON then lacks the comparison)")
-    ap.add_argument("--leg", choices=("ensemble", "c3", "c5"), default=None,
+    ap.add_argument("--leg", choices=("ensemble", "c3", "c5", "meshopt"), default=None,
                     help="run one of the other workloads only (for profiling) and print its JSON object")
     args = ap.parse_args()
     if args.source_hash:
@@ -313,7 +340,7 @@ def main():
         del src, dst
 
     if args.leg:
-        leg = {"ensemble": ensemble_run, "c3": c3_run, "c5": c5_run}[args.leg]
+        leg = {"ensemble": ensemble_run, "c3": c3_run, "c5": c5_run, "meshopt": meshopt_run}[args.leg]
         print(json.dumps({args.leg: leg()}))
         return
 
@@ -385,6 +412,9 @@ def main():
     if not args.no_c5:
         print("[bench] low-storage stage, 1536x385x1152", file=sys.stderr, flush=True)
         out["c5_filter"] = c5_run()
+    if not args.no_meshopt:
+        print("[bench] near-wall mesh optimisation (host)", file=sys.stderr, flush=True)
+        out["mesh_opt"] = meshopt_run()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, one sub-step)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, v, om, U1, U3, y)
