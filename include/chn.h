@@ -276,6 +276,11 @@ chn_status chn_ens_destroy(chn_ens *ens);
  * chn_filter_and_stress, ...); owned by the ensemble. */
 chn_ctx *chn_ens_context(chn_ens *ens, int32_t i);
 
+/* chn_set_state on channel i of the ensemble (same arguments, layouts and
+ * errors; CHN_EINVAL for i outside 0..n-1, with chn_ens_last_error set). */
+chn_status chn_ens_set_state(chn_ens *ens, int32_t i, const double *d_v, const double *d_omega2,
+                             const double *d_u1mean, const double *d_u3mean);
+
 /* Advances every channel nsteps RK3 steps; dt is a HOST array of n step
  * sizes.  Every channel must have a state (chn_set_state). */
 chn_status chn_ens_step(chn_ens *ens, const double *dt, int32_t nsteps);

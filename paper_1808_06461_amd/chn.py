@@ -78,6 +78,7 @@ def lib():
         L.chn_ens_context.argtypes = [P, C.c_int32]
         L.chn_ens_context.restype = P
         L.chn_ens_step.argtypes = [P, C.POINTER(C.c_double), C.c_int32]
+        L.chn_ens_set_state.argtypes = [P, C.c_int32, P, P, P, P]
         L.chn_ens_last_error.argtypes = [P]
         L.chn_ens_last_error.restype = C.c_char_p
         L.chn_last_error.argtypes = [P]
@@ -91,7 +92,7 @@ def lib():
                      "chn_get_operators",
                      "chn_timing_enable", "chn_timing_read", "chn_ens_create", "chn_ens_destroy", "chn_ens_step",
                      "chn_get_plan", "chn_set_plan", "chn_autotune", "chn_plane_products",
-                     "chn_optimise_mesh"):
+                     "chn_optimise_mesh", "chn_ens_set_state"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -319,6 +320,15 @@ class _EnsChannel(Channel):
         self.n1h = cfg.n1 // 2
         self.ctx = C.c_void_p(self.L.chn_ens_context(ens.ens, i))
         self._owner = ens
+        self._i = i
+
+    def set_state(self, v, omega2, u1mean, u3mean):
+        self._keep = [self._dev(v, torch.complex128), self._dev(omega2, torch.complex128),
+                      self._dev(u1mean, torch.float64), self._dev(u3mean, torch.float64)]
+        s = self.L.chn_ens_set_state(self._owner.ens, self._i, *[_ptr(t) for t in self._keep])
+        if s != 0:
+            raise ChnError(f"chn_ens_set_state: {STATUS.get(s, s)}: "
+                           f"{self.L.chn_ens_last_error(self._owner.ens).decode()}")
 
     def close(self):
         self.ctx = None

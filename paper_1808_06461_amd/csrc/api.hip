@@ -1423,6 +1423,18 @@ chn_status chn_ens_destroy(chn_ens* e) {
 
 chn_ctx* chn_ens_context(chn_ens* e, int32_t i) { return (e && i >= 0 && i < e->n) ? e->ctx[i] : nullptr; }
 
+chn_status chn_ens_set_state(chn_ens* e, int32_t i, const double* d_v, const double* d_omega2,
+                             const double* d_u1mean, const double* d_u3mean) {
+  if (!e) return CHN_EINVAL;
+  if (i < 0 || i >= e->n) {
+    e->err = "channel index out of range";
+    return CHN_EINVAL;
+  }
+  const chn_status s = chn_set_state(e->ctx[i], d_v, d_omega2, d_u1mean, d_u3mean);
+  if (s != CHN_OK) e->err = "channel " + std::to_string(i) + ": " + e->ctx[i]->err;
+  return s;
+}
+
 chn_status chn_ens_step(chn_ens* e, const double* dt, int32_t nsteps) {
   if (!e || !dt || nsteps < 0) return CHN_EINVAL;
   return e->mixed ? ens_step<float>(e, dt, nsteps) : ens_step<double>(e, dt, nsteps);

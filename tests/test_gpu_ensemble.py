@@ -113,3 +113,27 @@ def test_c4_ensemble_fifty_steps():
             assert torch.equal(got[n], ref[n]), (k, n)
         single.close()
     ens.close()
+
+
+@gpu
+def test_ens_set_state_index_checked():
+    """chn_ens_set_state sets channel i like chn_set_state on its context and
+    rejects an index outside the ensemble without touching any channel."""
+    from paper_1808_06461_amd import chn
+    from paper_1808_06461_amd.chn import Ensemble
+    c = SPECS[0]
+    v, om, U1, U3, y = synth.turbulent_field(c)
+    ens = Ensemble([_spec(c, y)], precision="fp64")
+    try:
+        ch = ens.channels[0]
+        ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+        got = ch.get_fields("v")["v"].cpu().numpy()
+        assert rel(got, v) < 1e-15
+        keep = [t.to("cuda") for t in (torch.from_numpy(v), torch.from_numpy(om),
+                                       torch.from_numpy(U1), torch.from_numpy(U3))]
+        ptrs = [chn._ptr(t) for t in keep]
+        for bad in (-1, 1):
+            assert ens.L.chn_ens_set_state(ens.ens, bad, *ptrs) == 1  # CHN_EINVAL
+        assert b"out of range" in ens.L.chn_ens_last_error(ens.ens)
+    finally:
+        ens.close()
