@@ -14,7 +14,10 @@
   mean sum_i sum_k |omega_i(k)|^2 (Parseval, a direct sum), and a pure mean
   shear W(y) gives W^2 in mode (0,0) and nothing else;
 * the spectra summed with the Hermitian weights give the plane mean of the
-  squared fluctuation computed pointwise from a direct synthesis (no FFT).
+  squared fluctuation computed pointwise from a direct synthesis (no FFT);
+* the filter equals the physical-space convolution with the sharp cut-off
+  kernel (inclusive cut-off, no FFT), and it commutes with the compact
+  wall-normal D1 and D2 (it acts on x and z only).
 """
 import numpy as np
 import pytest
@@ -175,3 +178,41 @@ def test_spectra_parseval_against_direct_synthesis():
             ref = float(np.mean(f ** 2))
             assert abs(msq[i, y] - ref) < 1e-13 * ref, (i, y)
     assert np.all(E[:, :, 0, 0] == 0)
+
+
+def test_filter_is_the_sharp_kernel_convolution():
+    """Section 3.1's cut-off filter as a physical-space convolution, no FFT:
+    F u(x_p, z_q) = (1/(N1 N3)) sum_{j,l} u(x_j, z_l) D_kcx(x_p - x_j) D_kcz(z_q - z_l)
+    with D_K(t) = 1 + 2 sum_{k=1..K} cos(k t) (in units of the box wavenumber),
+    against the oracle's truncation synthesised on the same grid."""
+    rng = np.random.default_rng(71)
+    uh = _field(rng)[2]
+    kcx, kcz = 3, 2
+    x = np.arange(N1) * LX / N1
+    z = np.arange(N3) * LZ / N3
+    X, Z = np.meshgrid(x, z)
+    u = brute.synth_points(brute.full_modes(uh), LX, LZ, X, Z)          # [N3][N1]
+    tx = 2 * np.pi / LX * (x[:, None] - x[None, :])
+    tz = 2 * np.pi / LZ * (z[:, None] - z[None, :])
+    Dx = 1 + 2 * sum(np.cos(k * tx) for k in range(1, kcx + 1))
+    Dz = 1 + 2 * sum(np.cos(k * tz) for k in range(1, kcz + 1))
+    Fu = Dz @ u @ Dx.T / (N1 * N3)
+    got = lowstorage.synth_plane(lowstorage.truncate(uh[None], kcx, kcz), N1, N3)[0]
+    np.testing.assert_allclose(got, Fu, rtol=0, atol=1e-13 * np.abs(Fu).max())
+
+
+def test_filter_commutes_with_the_wall_normal_derivative():
+    """The filter acts on x and z only, so it commutes with the compact D1 and
+    D2 of the wall-normal direction (the property the a-posteriori filtered
+    pressure rests on): F(D u) = D F(u) mode by mode."""
+    import synth
+    from oracle import kmm
+    n2 = 17
+    y = synth.mesh_tanh(n2)
+    S = kmm.Setup(n1=N1, n2=n2, n3=N3, lx=LX, lz=LZ, nu=1e-3, dt=1e-3, mass_flux=0.0, y=y)
+    rng = np.random.default_rng(72)
+    uh = rng.standard_normal((n2, N1 // 2, N3)) + 1j * rng.standard_normal((n2, N1 // 2, N3))
+    for d in (kmm.d1, kmm.d2):
+        lhs = lowstorage.truncate(d(S, uh), 3, 2)
+        rhs = d(S, lowstorage.truncate(uh, 3, 2))
+        np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-13 * np.abs(lhs).max())
