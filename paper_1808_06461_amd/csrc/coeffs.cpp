@@ -56,39 +56,37 @@ static bool solve_dense(int n, q* M, q* r) {
 
 bool compact_row(int n2, const double* y, int i, int p, double* Ar, double* Br) {
   for (int o = 0; o < 7; ++o) Ar[o] = Br[o] = 0.0;
-  {
-    const int lo = i - 3 < 0 ? 0 : i - 3;
-    const int hi = i + 3 > n2 - 1 ? n2 - 1 : i + 3;
-    const int w = hi - lo + 1;
-    const int nu = 2 * w;
-    const q h = (i + 2 < n2) ? qabs((q)y[i + 2] - (q)y[i]) : qabs((q)y[i] - (q)y[i - 2]);
-    q d[7];
-    for (int j = 0; j < w; ++j) d[j] = ((q)y[lo + j] - (q)y[i]) / h;
-    q M[14 * 14], r[14];
-    for (int e = 0; e < nu * nu; ++e) M[e] = 0;
-    for (int k = 0; k < nu - 1; ++k) {
-      r[k] = 0;
-      for (int j = 0; j < w; ++j) {
-        q dk = 1;
-        for (int e = 0; e < k; ++e) dk *= d[j];
-        M[k * nu + j] = dk;
-        if (k >= p) {
-          q dkp = 1;
-          for (int e = 0; e < k - p; ++e) dkp *= d[j];
-          const q fac = p == 2 ? (q)(k * (k - 1)) : (q)k;
-          M[k * nu + w + j] = -fac * dkp;
-        }
+  const int lo = i - 3 < 0 ? 0 : i - 3;
+  const int hi = i + 3 > n2 - 1 ? n2 - 1 : i + 3;
+  const int w = hi - lo + 1;
+  const int nu = 2 * w;
+  const q h = (i + 2 < n2) ? qabs((q)y[i + 2] - (q)y[i]) : qabs((q)y[i] - (q)y[i - 2]);
+  q d[7];
+  for (int j = 0; j < w; ++j) d[j] = ((q)y[lo + j] - (q)y[i]) / h;
+  q M[14 * 14], r[14];
+  for (int e = 0; e < nu * nu; ++e) M[e] = 0;
+  for (int k = 0; k < nu - 1; ++k) {
+    r[k] = 0;
+    for (int j = 0; j < w; ++j) {
+      q dk = 1;
+      for (int e = 0; e < k; ++e) dk *= d[j];
+      M[k * nu + j] = dk;
+      if (k >= p) {
+        q dkp = 1;
+        for (int e = 0; e < k - p; ++e) dkp *= d[j];
+        const q fac = p == 2 ? (q)(k * (k - 1)) : (q)k;
+        M[k * nu + w + j] = -fac * dkp;
       }
     }
-    M[(nu - 1) * nu + w + (i - lo)] = 1;
-    r[nu - 1] = 1;
-    if (!solve_dense(nu, M, r)) return false;
-    q hp = p == 2 ? h * h : h;
-    for (int j = 0; j < w; ++j) {
-      const int o = lo + j - i + 3;
-      Br[o] = (double)(r[j] / hp);
-      Ar[o] = (double)r[w + j];
-    }
+  }
+  M[(nu - 1) * nu + w + (i - lo)] = 1;
+  r[nu - 1] = 1;
+  if (!solve_dense(nu, M, r)) return false;
+  q hp = p == 2 ? h * h : h;
+  for (int j = 0; j < w; ++j) {
+    const int o = lo + j - i + 3;
+    Br[o] = (double)(r[j] / hp);
+    Ar[o] = (double)r[w + j];
   }
   return true;
 }
