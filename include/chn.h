@@ -242,7 +242,8 @@ chn_status chn_get_operators(chn_ctx *ctx, double *a1, double *b1, double *a2, d
  *               20, with the wall node 21).
  *   kstar:      modified wavenumber k^2 + 1/(beta nu dt) of the layer, > 0.
  *   penalty:    C >= 0 (the paper uses about 1e-3).
- *   y_out:      HOST, n2 nodes, written on CHN_OK (may alias nothing).
+ *   y_out:      HOST, n2 nodes, written on CHN_OK (may be y_ref itself:
+ *               y_ref is copied before anything is written).
  *   err_ref, err_opt, iterations: HOST scalars (each may be NULL):
  *               ||g - g_ana||_2 on y_ref and on y_out, accepted steps.
  * Errors: CHN_EINVAL for invalid arguments (nothing written), CHN_EUNSTABLE

@@ -43,7 +43,7 @@ struct MeshProblem {
   double ks, C;
   std::vector<double> yref, xref, s;
   std::vector<double> A, B;  // [n][7] operators at the current mesh
-  std::vector<double> rhs, g;
+  std::vector<double> M7, g;  // Dirichlet-row matrix [n][7], solution
   double cond_max;
 };
 
@@ -107,7 +107,7 @@ struct BandLU {
 // ||g - g_ana||_2 for mesh y and operators A, B.
 bool homogeneous_error(MeshProblem& P, const double* y, const double* A, const double* B, double* err) {
   const int n = P.n;
-  std::vector<double>& M = P.rhs;  // [n][7] Dirichlet-row matrix, then reused
+  std::vector<double>& M = P.M7;
   M.assign((size_t)n * 7, 0.0);
   M[3] = 1.0;
   M[(size_t)(n - 1) * 7 + 3] = 1.0;
