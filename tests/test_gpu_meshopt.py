@@ -130,3 +130,21 @@ def test_c1_steps_on_optimised_mesh():
     e = float(np.linalg.norm(ca - cb) / np.linalg.norm(cb))
     print(f"optimised mesh A2 chi (interior rows): {e:.2e}")
     assert e < tol, ("A2 chi", e)
+
+
+@gpu
+def test_output_may_be_the_input():
+    """y_out may be y_ref itself: the result equals a call with separate buffers."""
+    import ctypes as C
+    from paper_1808_06461_amd import chn
+    y = synth.mesh_tanh(33)
+    ref = chn.optimise_mesh(y.copy(), m=6, kstar=1e10, max_iter=3)
+    yy = y.copy()
+    D = C.POINTER(C.c_double)
+    e0, e1, it = C.c_double(), C.c_int(), C.c_int()
+    e1 = C.c_double()
+    st = chn.lib().chn_optimise_mesh(yy.ctypes.data_as(D), 33, 6, 1e10, 1e-3, 3, yy.ctypes.data_as(D),
+                                     C.byref(e0), C.byref(e1), C.byref(it))
+    assert st == 0
+    np.testing.assert_array_equal(yy, ref[0])
+    assert (e0.value, e1.value, it.value) == (ref[1], ref[2], ref[3])
