@@ -56,11 +56,21 @@ def test_c3_plane_slab_against_oracle_samples():
 
 
 @pytest.mark.gpu
-def test_c3_pencil_share_invariants():
-    from paper_1808_06461_amd import Channel
+@pytest.mark.parametrize("mesh", ["tanh", "optimised"])
+def test_c3_pencil_share_invariants(mesh):
+    """One mixed RK3 step of the 1537-node pencil share: finite, walls and mass
+    flux exact; on the tanh mesh and on that mesh after the near-wall
+    optimisation (k* = 1e10, 20 nodes per wall), the mesh the optimisation is
+    meant to make safe for this Reynolds number."""
+    from paper_1808_06461_amd import Channel, chn
     case = synth.c3_pencil_case()
-    print(f"[c3] pencil share {case.n1 // 2 * case.n3} modes x {case.n2}", flush=True)
-    v, om, U1, U3, y = synth.turbulent_field(case)
+    print(f"[c3] pencil share {case.n1 // 2 * case.n3} modes x {case.n2}, {mesh} mesh", flush=True)
+    y = synth.mesh_tanh(case.n2)
+    if mesh == "optimised":
+        y, e0, e1, it = chn.optimise_mesh(y, m=20, kstar=1e10, max_iter=60)
+        print(f"[c3] optimised mesh: {e0:.3e} -> {e1:.3e} in {it} steps", flush=True)
+        assert e1 < e0
+    v, om, U1, U3, y = synth.turbulent_field(case, y=y)
     ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, mass_flux=case.mass_flux,
                  precision="mixed", y=y)
     try:
