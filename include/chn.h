@@ -32,7 +32,8 @@
  *   - Errors: CHN_EINVAL for invalid sizes or pointers (the context is left
  *     unchanged), CHN_EDEVICE for a HIP runtime error (sticky: every later
  *     call on that context returns it), CHN_ESTATE for a call made before
- *     chn_set_state, CHN_EUNSTABLE when a step produced NaN/Inf.
+ *     chn_set_state, CHN_EUNSTABLE when a sub-step's CFL number was not
+ *     finite or above CHN_CFL_LIMIT (see chn_step_rk3).
  *     chn_last_error gives a message for the last failing call.
  *   - A context is bound to one stream and is not thread-safe.
  */
@@ -74,8 +75,11 @@ typedef struct {
   double mass_flux;     /* target integral of U1 over y (2 for unit bulk velocity) */
   int32_t precision;    /* chn_precision */
   const double *y;      /* HOST pointer to n2 ascending nodes, y[0] = -1,
-                           y[n2-1] = 1; NULL selects y_j = tanh(2 s_j)/tanh(2),
-                           s_j uniform on [-1, 1] */
+                           y[n2-1] = 1; NULL selects y_j = tanh(g s_j)/tanh(g),
+                           s_j uniform on [-1, 1], with the largest g in
+                           {2, 1.75, ..., 0.5} whose compact operators have
+                           cond_1(A2, Dirichlet rows) <= 1e4 and
+                           cond_1(A1) <= 1e5 (chn_get_mesh returns it) */
   void *stream;         /* hipStream_t the context runs on (NULL = default stream) */
   int32_t planes_only;  /* nonzero: a plane-phase context (one GPU's slab of x-z
                            planes): only chn_plane_products, the schedule and
@@ -89,10 +93,25 @@ typedef struct {
 typedef struct {
   double f_mean;        /* mean pressure gradient of the last sub-step (Section 2.1) */
   double mass_flux;     /* integral of U1 over y after the step */
-  double cfl_max;       /* dt * max(|u1|/dx + |u2|/dy_j + |u3|/dz) on the padded grid,
-                           from the velocities of the step's last sub-step */
-  double utau_lo, utau_hi; /* sqrt(nu |dU1/dy|) at the two walls */
+  double cfl_max;       /* dt * max(|u1|/dx + |u2|/dy_j + |u3|/dz) on the padded grid
+                           (dx = lx/n1, dz = lz/n3, dy_j the smaller gap next to node
+                           j), from the velocities entering the step's last sub-step;
+                           on CHN_EUNSTABLE the value that tripped the guard */
+  double utau_lo, utau_hi; /* sqrt(nu |dU1/dy|) at the two walls after the step */
+  double max_abs_div;   /* max over modes and nodes of |i a u1 + D1 u2 + i b u3| of the
+                           velocity fields the next sub-step's transforms read (float32
+                           on CHN_MIXED, so about 1e-7 of the velocities there; they are
+                           formed from continuity, so rounding only on CHN_FP64) */
+  float ms_phase[5];    /* milliseconds of the last step per phase (HIP events on the
+                           context's stream): z inverse, x pass, z forward, pencil
+                           kernel, other launches (velocity recovery, per-dt tables) */
+  int32_t fail_step;    /* -1, or the step (0-based, within the call) ... */
+  int32_t fail_substep; /* ... and sub-step whose CFL tripped the guard */
 } chn_step_info;
+
+/* Stability limit of the guard: a sub-step whose CFL number (as in
+ * chn_step_info) is above it or not finite is not applied. */
+#define CHN_CFL_LIMIT 2.0
 
 /* Bytes of device workspace needed for cfg (0 if cfg is invalid). */
 size_t chn_workspace_bytes(const chn_config *cfg);
@@ -100,7 +119,14 @@ size_t chn_workspace_bytes(const chn_config *cfg);
 /* Builds the compact operators of Appendix B on the mesh (rows solved in
  * extended precision, maximum order, stencils truncated at the walls), the
  * quadrature weights of the mass flux, and the FFT tables, and uploads them
- * into d_workspace.  Synchronises.  *out receives the context. */
+ * into d_workspace.  Synchronises.  *out receives the context.
+ * The wall-normal systems are factored without pivoting, so the mesh is
+ * checked first (Appendix B notes that the compact rows need care near the
+ * walls): CHN_EINVAL, with the two numbers in chn_last_error(NULL), if the
+ * 1-norm condition number of A1 or of A2 with Dirichlet end rows exceeds
+ * 1e6 (the maximum-order seven-point stencils degenerate for some local
+ * stretchings, e.g. the tanh mesh with g = 2 on 33 to 65 nodes; well-posed
+ * meshes give 1e2 to 1e4).  Not checked for planes_only contexts. */
 chn_status chn_create(const chn_config *cfg, void *d_workspace, size_t ws_bytes, chn_ctx **out);
 
 /* Frees host-side state; the workspace stays the caller's. */
@@ -117,9 +143,17 @@ chn_status chn_set_state(chn_ctx *ctx, const double *d_v, const double *d_omega2
  * paper's Appendix A/C sequence: velocities and vorticities, dealiased
  * u x omega, non-linear forcings, explicit viscous terms, implicit
  * Helmholtz steps with the influence-matrix treatment of u2, mean modes with
- * constant mass flux).  If info is not NULL the call synchronises and fills
- * it for the last step; it returns CHN_EUNSTABLE if that step's CFL number is
- * not finite. */
+ * constant mass flux).  Synchronises once, at the end of the call.
+ * Instability guard, on every sub-step whether or not info is given: the
+ * x pass gathers the sub-step's CFL number on the device; if it is not
+ * finite (a NaN or Inf anywhere in the velocities) or above CHN_CFL_LIMIT,
+ * that sub-step and every later one of the call leave the state untouched
+ * and the call returns CHN_EUNSTABLE, with the step and sub-step in
+ * chn_last_error (and in info).  The state is then as at the start of the
+ * failing sub-step: for sub-step 0 that is the start of the failing step;
+ * for sub-steps 1 and 2 it is the state between two sub-steps of that step
+ * (no copy of the state is kept per step).  If info is not NULL it is
+ * filled for the last step. */
 chn_status chn_step_rk3(chn_ctx *ctx, double dt, int32_t nsteps, chn_step_info *info);
 
 /* Field selectors for chn_get_fields. */
@@ -214,6 +248,10 @@ chn_status chn_filtered_pressure(chn_ctx *ctx, int32_t kcx, int32_t kcz, const d
  * Works on every context; the only compute call of a planes_only context. */
 chn_status chn_plane_products(chn_ctx *ctx, const void *const *d_in, void *const *d_out);
 
+/* Copies the context's n2 wall-normal nodes (the configured mesh, or the
+ * default one) to the HOST array y. */
+chn_status chn_get_mesh(chn_ctx *ctx, double *y);
+
 /* Copies the library's compact-difference tables to host arrays (each
  * n2 x 7, row i holding M[i][i-3..i+3]) and the mass-flux quadrature weights
  * (n2).  Any pointer may be NULL.  Synchronises. */
@@ -231,9 +269,10 @@ chn_status chn_get_operators(chn_ctx *ctx, double *a1, double *b1, double *a2, d
  * by steepest descent in spacing-scaled coordinates: central-difference
  * gradient (step 1e-6 of the local spacing), step length halved from twice
  * the last accepted one until the mesh is strictly increasing, L strictly
- * decreases, the Armijo condition with 1e-4 holds and the trial mesh's A2
- * has a 1-norm condition number at most 10 times the reference mesh's (so
- * the compact operator stays well posed); at most max_iter
+ * decreases, the Armijo condition with 1e-4 holds, every ratio of adjacent
+ * spacings lies in [1/2, 2], and the trial mesh's A2 and A1 each have a
+ * 1-norm condition number at most 10 times the reference mesh's (so the
+ * compact operators stay well posed); at most max_iter
  * steps, fewer when the step length falls below 1e-30.  The compact rows
  * are the quad-precision ones of the library's operators.
  *   y_ref:      HOST, n2 nodes, strictly increasing, y_ref[0] = -1,
@@ -283,7 +322,11 @@ chn_status chn_ens_set_state(chn_ens *ens, int32_t i, const double *d_v, const d
                              const double *d_u1mean, const double *d_u3mean);
 
 /* Advances every channel nsteps RK3 steps; dt is a HOST array of n step
- * sizes.  Every channel must have a state (chn_set_state). */
+ * sizes.  Every channel must have a state (chn_set_state).  Synchronises at
+ * the end; the instability guard of chn_step_rk3 runs per channel (a
+ * channel whose sub-step trips it stops there, the others go on), and the
+ * call then returns CHN_EUNSTABLE naming the first such channel in
+ * chn_ens_last_error. */
 chn_status chn_ens_step(chn_ens *ens, const double *dt, int32_t nsteps);
 
 const char *chn_ens_last_error(const chn_ens *ens);

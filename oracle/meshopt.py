@@ -25,17 +25,24 @@ Readings (where the paper is silent):
 - Steepest descent in the spacing-scaled coordinates xi_j = y_j / s_j
   (s_j = y_ref[j+1] - y_ref[j]), i.e. the step in y_j is -t s_j^2 dL/dy_j;
   the gradient by central differences with step 1e-6 s_j; the step length
-  by halving from twice the last accepted one (first trial 1) until the mesh
+  by halving from twice the last accepted one (t starts at 1, so the first
+  trial is 2) until the mesh
   is strictly increasing, L strictly decreases and the Armijo condition
   L(new) <= L + 1e-4 t (grad . d) holds (strict decrease rejects a step that
   rounds to no move at all); the descent stops after max_iter iterations,
   or when t falls below 1e-30.
-- A trial mesh must also keep the compact operator well posed: its A2 may
-  have a 1-norm condition number at most 10 times that of the reference
-  mesh's A2.  The paper's functional only sees B2 - k* A2, and without this
-  guard the descent can reach meshes on which A2 itself is singular (the
-  maximum-order stencils degenerate for some local stretchings) while the
-  homogeneous error keeps falling.
+- A trial mesh must also keep the compact operators well posed: its A2 and
+  its A1 may each have a 1-norm condition number at most 10 times that of
+  the reference mesh's.  The paper's functional only sees B2 - k* A2, and
+  without this guard the descent can reach meshes on which A2 itself is
+  singular (the maximum-order stencils degenerate for some local
+  stretchings) while the homogeneous error keeps falling; A1 (the first
+  derivative of the velocity recovery and of the non-linear forcing) is
+  bounded the same way.
+- The paper moves the nodes without changing much the individual grid
+  spacings; read as: every ratio of adjacent spacings of a trial mesh lies
+  in [1/2, 2].  (The displacement penalty, measured in absolute y, is far
+  too small against the error to enforce this by itself.)
 
 The compact rows come from ``compact.row_coefficients`` (exact rationals);
 only the rows whose stencils contain a moved node are recomputed.
@@ -49,7 +56,8 @@ from . import compact
 FD_REL = 1e-6       # central-difference step, relative to the local spacing
 ARMIJO = 1e-4
 T_MIN = 1e-30
-COND_GROWTH = 10.0  # allowed growth of cond_1(A2) over the reference mesh
+COND_GROWTH = 10.0  # allowed growth of cond_1(A2) and cond_1(A1) over the reference mesh
+SPACING_RATIO = 2.0  # adjacent spacings of a trial mesh within a factor 2 of each other
 
 
 def cond1(A):
@@ -65,10 +73,17 @@ def g_analytic(y, kstar):
     return np.exp(-q * (1.0 + y)) * (-np.expm1(-2.0 * q * (1.0 - y))) / (-np.expm1(-4.0 * q))
 
 
-def _rows(y, rows, A, B):
-    """Recompute the compact second-derivative rows ``rows`` of (A, B) in place."""
+def spacing_ratio_ok(y):
+    """Every ratio of adjacent spacings of mesh y within [1/SPACING_RATIO, SPACING_RATIO]."""
+    h = np.diff(y)
+    r = h[1:] / h[:-1]
+    return bool(np.all(r <= SPACING_RATIO) and np.all(r >= 1.0 / SPACING_RATIO))
+
+
+def _rows(y, rows, A, B, p=2):
+    """Recompute the compact rows ``rows`` of the order-p pair (A, B) in place."""
     for i in rows:
-        S, a, b = compact.row_coefficients(y, i, 2)
+        S, a, b = compact.row_coefficients(y, i, p)
         A[i] = 0.0
         B[i] = 0.0
         for j, aj, bj in zip(S, a, b):
@@ -109,6 +124,9 @@ class _Problem:
         A, B = compact.operators(y_ref, 2)
         self.A0, self.B0 = A.copy(), B.copy()
         self.cond_max = COND_GROWTH * cond1(A)
+        A1, B1 = compact.operators(y_ref, 1)
+        self.A10, self.B10 = A1, B1
+        self.cond1_max = COND_GROWTH * cond1(A1)
 
     def mesh(self, x):
         y = self.y_ref.copy()
@@ -116,13 +134,26 @@ class _Problem:
         y[self.n - 1 - self.m:self.n - 1] = -x[::-1]
         return y
 
+    def _touched(self):
+        n, m = self.n, self.m
+        return [i for i in range(n) if i <= m + compact.HALF or i >= n - 1 - m - compact.HALF]
+
     def operators(self, y):
         """(A2, B2) of mesh y: the rows whose stencils hold a moved node recomputed."""
-        n, m = self.n, self.m
-        touched = [i for i in range(n) if i <= m + compact.HALF or i >= n - 1 - m - compact.HALF]
         A, B = self.A0.copy(), self.B0.copy()
-        _rows(y, touched, A, B)
+        _rows(y, self._touched(), A, B)
         return A, B
+
+    def a1(self, y):
+        """A1 of mesh y (rows recomputed as for A2)."""
+        A, B = self.A10.copy(), self.B10.copy()
+        _rows(y, self._touched(), A, B, p=1)
+        return A
+
+    def admissible(self, y, A2):
+        """The trial-mesh conditions besides the descent: spacing ratios and conditioning."""
+        return (spacing_ratio_ok(y) and cond1(A2) <= self.cond_max
+                and cond1(self.a1(y)) <= self.cond1_max)
 
     def L_from(self, x, y, A, B):
         e = homogeneous_error(y, self.kstar, A, B)
@@ -173,7 +204,7 @@ def optimise_mesh(y_ref, m=20, kstar=1e10, penalty=1e-3, max_iter=60, history=No
             if np.all(np.diff(yn) > 0):
                 An, Bn = P.operators(yn)
                 fn = P.L_from(xn, yn, An, Bn)[0]
-                if fn < f and fn <= f + ARMIJO * t * slope and cond1(An) <= P.cond_max:
+                if fn < f and fn <= f + ARMIJO * t * slope and P.admissible(yn, An):
                     accepted = True
                     break
             t *= 0.5

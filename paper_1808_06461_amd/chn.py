@@ -38,7 +38,13 @@ class Plan(C.Structure):
 
 class StepInfo(C.Structure):
     _fields_ = [("f_mean", C.c_double), ("mass_flux", C.c_double), ("cfl_max", C.c_double),
-                ("utau_lo", C.c_double), ("utau_hi", C.c_double)]
+                ("utau_lo", C.c_double), ("utau_hi", C.c_double), ("max_abs_div", C.c_double),
+                ("ms_phase", C.c_float * 5), ("fail_step", C.c_int32), ("fail_substep", C.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["ms_phase"] = list(self.ms_phase)
+        return d
 
 
 _lib = None
@@ -65,6 +71,7 @@ def lib():
         L.chn_accumulate_statistics.argtypes = [P, P, P]
         L.chn_filtered_pressure.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
         L.chn_get_operators.argtypes = [P, P, P, P, P, P]
+        L.chn_get_mesh.argtypes = [P, P]
         L.chn_get_plan.argtypes = [P, C.POINTER(Plan)]
         L.chn_plane_products.argtypes = [P, C.POINTER(P), C.POINTER(P)]
         L.chn_set_plan.argtypes = [P, C.POINTER(Plan)]
@@ -89,7 +96,7 @@ def lib():
         for name in ("chn_create", "chn_destroy", "chn_set_state", "chn_step_rk3", "chn_get_fields",
                      "chn_nonlinear", "chn_filter_and_stress", "chn_filtered_enstrophy", "chn_accumulate_statistics",
                      "chn_filtered_pressure",
-                     "chn_get_operators",
+                     "chn_get_operators", "chn_get_mesh",
                      "chn_timing_enable", "chn_timing_read", "chn_ens_create", "chn_ens_destroy", "chn_ens_step",
                      "chn_get_plan", "chn_set_plan", "chn_autotune", "chn_plane_products",
                      "chn_optimise_mesh", "chn_ens_set_state"):
@@ -184,8 +191,15 @@ class Channel:
         self._check(self.L.chn_step_rk3(self.ctx, float(dt), int(nsteps), C.byref(si) if info else None),
                     "chn_step_rk3")
         if info:
-            return {k: getattr(si, k) for k, _ in StepInfo._fields_}
+            return si.as_dict()
         return None
+
+    def step_status(self, dt, nsteps=1):
+        """chn_step_rk3 with a step record; returns (status name, record, message) without raising."""
+        si = StepInfo()
+        s = self.L.chn_step_rk3(self.ctx, float(dt), int(nsteps), C.byref(si))
+        msg = self.L.chn_last_error(self.ctx).decode() if s else ""
+        return STATUS.get(s, s), si.as_dict(), msg
 
     def get_fields(self, *names):
         mask = 0
@@ -283,6 +297,13 @@ class Channel:
         self._check(self.L.chn_get_operators(self.ctx, *[C.c_void_p(a.ctypes.data) for a in arrs]),
                     "chn_get_operators")
         return arrs
+
+    def mesh(self):
+        """The context's wall-normal nodes (numpy float64[n2])."""
+        import numpy as np
+        y = np.zeros(self.n2)
+        self._check(self.L.chn_get_mesh(self.ctx, C.c_void_p(y.ctypes.data)), "chn_get_mesh")
+        return y
 
     KERNELS = ("recover", "zinv", "xpass", "zfwd", "advance", "filter")
 

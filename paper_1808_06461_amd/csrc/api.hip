@@ -22,6 +22,15 @@ const double kZeta[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 
 std::string g_create_error;
 
+// A sub-step whose CFL number dt max(|u1|/dx + |u2|/dy_j + |u3|/dz) is above
+// this (or not finite) leaves the state untouched and the call returns
+// CHN_EUNSTABLE.
+constexpr double kCflLimit = 2.0;
+
+// chn_create refuses a mesh on which cond_1(A1) or cond_1(A2 with Dirichlet
+// end rows) exceeds this.
+constexpr double kCondMax = 1e6;
+
 constexpr int kMaxQ = 4096;  // largest q1, q3 of the filter stage's output grid
 
 bool smooth23(int n) {
@@ -83,6 +92,9 @@ struct chn_ctx {
   std::vector<double> twq_host;
   FftPlan plan1{}, plan3{};
   double *mean_scr = nullptr, *mean_out = nullptr, *info_dev = nullptr;
+  unsigned* guard = nullptr;  // instability guard, four words (common.hpp)
+  // per-phase times of the last step of chn_step_rk3 when info is requested
+  bool phase_rec = false;
   std::vector<double> hA1, hB1, hA2, hB2, hquad;
   chn::PencilGeom geom{};
   chn::PlaneDims dims{};
@@ -98,6 +110,7 @@ struct chn_ctx {
   bool timing = false;
   struct Timed { int kind; hipEvent_t a, b; };
   std::vector<Timed> timed;
+  std::vector<Timed> phase_timed;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
   ~chn_ctx() {
@@ -159,6 +172,7 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
   double* mean_scr = D(3 * (size_t)n2 * 5 + 4 * (size_t)n2);
   double* mean_out = D(8);
   double* info = D(8);
+  unsigned* guard = reinterpret_cast<unsigned*>(cv.take(4 * sizeof(unsigned)));
   if (x) {
     x->v = v; x->chi = chi; x->om2 = om2; x->nchi_old = nco; x->nom_old = noo;
     x->U1 = U1; x->U3 = U3; x->nu_old = nuo; x->nw_old = nwo;
@@ -187,6 +201,7 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
     x->tw3d = reinterpret_cast<double2*>(tw3d);
     x->twq = reinterpret_cast<double2*>(twq);
     x->mean_scr = mean_scr; x->mean_out = mean_out; x->info_dev = info;
+    x->guard = guard;
   }
   return cv.off + 256;
 }
@@ -241,13 +256,14 @@ hipEvent_t pool_event(chn_ctx* x) {
 
 // Runs one kernel launch; with timing on, brackets it with events on the context's stream.
 template <typename F> hipError_t timed(chn_ctx* x, int kind, F&& launch) {
-  if (!x->timing) return launch();
+  if (!x->timing && !x->phase_rec) return launch();
   hipEvent_t a = pool_event(x), b = pool_event(x);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, x->stream);
   if (e == hipSuccess) e = launch();
   if (e == hipSuccess) e = hipEventRecord(b, x->stream);
-  if (e == hipSuccess) x->timed.push_back({kind, a, b});
+  if (e == hipSuccess && x->timing) x->timed.push_back({kind, a, b});
+  if (e == hipSuccess && x->phase_rec) x->phase_timed.push_back({kind, a, b});
   return e;
 }
 
@@ -295,9 +311,10 @@ bool plan_fits(const chn_ctx* x, int xrows, int zK, int ych) {
 }
 template <typename T> int z_lines(const chn_ctx* x) { return x->zK; }
 
+// guard: the context's instability guard inside the time step, else nullptr
 template <typename T, typename TO>
 void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* const* out, chn::ZinvArgs<T>& za,
-                chn::XpassArgs<T>& xa, chn::ZfwdArgs<T, TO>& fa) {
+                chn::XpassArgs<T>& xa, chn::ZfwdArgs<T, TO>& fa, unsigned* guard = nullptr) {
   using C = typename Ty<T>::c;
   const int K = z_lines<T>(x);
   za = {};
@@ -314,6 +331,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   za.y0 = 0;
   za.ny = x->n2;
   za.fixed = x->ffix;
+  za.guard = guard;
   xa = {};
   xa.buf = reinterpret_cast<C*>(x->inter);
   xa.tw = reinterpret_cast<const C*>(x->tw1);
@@ -329,6 +347,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   xa.y0 = 0;
   xa.ny = x->n2;
   xa.fixed = x->ffix;
+  xa.guard = guard;
   fa = {};
   fa.buf = reinterpret_cast<const C*>(x->inter);
   for (int f = 0; f < 3; ++f) fa.out[f] = reinterpret_cast<typename Ty<TO>::c*>(out[f]);
@@ -345,11 +364,12 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
 
 // plane phase: ph (6 slots) -> H (3 slots) through the intermediate
 template <typename T, typename TO>
-chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, void* const* out) {
+chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, void* const* out,
+                       unsigned* guard = nullptr) {
   chn::ZinvArgs<T> za;
   chn::XpassArgs<T> xa;
   chn::ZfwdArgs<T, TO> fa;
-  plane_args<T, TO>(x, in, omega2_given, out, za, xa, fa);
+  plane_args<T, TO>(x, in, omega2_given, out, za, xa, fa, guard);
   // chunks of planes: the intermediate holds the chunk from its plane 0
   for (int y0 = 0; y0 < x->n2; y0 += x->ychunk) {
     za.y0 = xa.y0 = fa.y0 = y0;
@@ -428,8 +448,8 @@ template <typename T> chn_status substep(chn_ctx* x, int s, double dt) {
     if (st != CHN_OK) return st;
     x->phase_valid = true;
   }
-  // 2. dealiased u x omega
-  chn_status st = plane_phase<T, T>(x, x->ph, false, x->H);
+  // 2. dealiased u x omega (the x pass also gathers the CFL number for the guard)
+  chn_status st = plane_phase<T, T>(x, x->ph, false, x->H, x->guard);
   if (st != CHN_OK) return st;
   // 3. pencils + mean modes + next sub-step's velocities and vorticities
   if (chn_status hs = homog_tables(x, dt, x->stream)) return hs;
@@ -475,6 +495,26 @@ template <typename T> void advance_args(chn_ctx* x, int s, double dt, chn::Advan
   aa.hc = x->hc[s];
   aa.hw = x->hw[s];
   aa.hm = x->hm[s];
+  aa.guard = x->guard;
+  aa.cfl_limit = kCflLimit;
+  aa.substep = s;
+}
+
+// Divergence of the phase velocities (the step record), raised into *maxbits.
+template <typename T> chn_status divergence(chn_ctx* x, unsigned long long* maxbits) {
+  T* po[5];
+  phase_ptrs<T>(x, po);
+  if (!x->phase_valid) {
+    if (chn_status st = recover<T>(x, po)) return st;
+    x->phase_valid = true;
+  }
+  chn::DivArgs<T> da{};
+  da.g = x->geom;
+  for (int f = 0; f < 3; ++f) da.u[f] = po[f];
+  da.S0 = x->S[0];
+  da.maxbits = maxbits;
+  HIPCHK(x, chn::launch_div<T>(da, x->stream));
+  return CHN_OK;
 }
 
 chn_status check(chn_ctx* x);
@@ -671,6 +711,7 @@ struct chn_ens {
   void* d_xpass = nullptr;
   void* d_zfwd = nullptr;
   void* d_adv = nullptr;      // [3][n] advance argument blocks
+  unsigned* d_guard = nullptr;  // [n][4] instability guards of the channels
   int4 *d_wz = nullptr, *d_wx = nullptr, *d_wa = nullptr;
   int nz = 0, nx = 0, na = 0;
   size_t lds_z = 0, lds_x = 0;
@@ -724,7 +765,8 @@ bool ens_layout(int n, const chn_config* cfgs, EnsLayout* L) {
   }
   off = (off + 255) & ~(size_t)255;
   L->tables = off;
-  L->total = off + (size_t)n * arg_bytes(cfgs[0].precision == CHN_MIXED) + 256 * 4 + items * sizeof(int4) * 2 + 4096;
+  L->total = off + (size_t)n * arg_bytes(cfgs[0].precision == CHN_MIXED) + 256 * 5 + items * sizeof(int4) * 2 +
+             16 * (size_t)n + 4096;
   return true;
 }
 
@@ -759,12 +801,22 @@ template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
   }
   e->lds_z = e->lds_x = 0;
   e->mz = e->mx = 0;
+  // device placement of the tables
+  char* p = tables;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += (bytes + 255) & ~(size_t)255;
+    return q;
+  };
+  // the channels' guards side by side, so one copy reads them all
+  e->d_guard = reinterpret_cast<unsigned*>(take(16 * (size_t)n));
+  for (int i = 0; i < n; ++i) e->ctx[i]->guard = e->d_guard + 4 * i;
   for (int i = 0; i < n; ++i) {
     chn_ctx* x = e->ctx[i];
     // one launch covers every channel, so no channel needs a workgroup
     // floor of its own: up to 16 z lines per workgroup
     x->zK = std::max(1, std::min(16, z_lines_max(x)));
-    plane_args<T, T>(x, x->ph, false, x->H, za[i], xa[i], fa[i]);
+    plane_args<T, T>(x, x->ph, false, x->H, za[i], xa[i], fa[i], x->guard);
     xa[i].rows = e->rz;
     const int mz = chn::staging_for(x->plan3, za[i].K, cb);
     const int mx = chn::staging_for(x->plan1, 3 * e->rz, cb);
@@ -788,13 +840,6 @@ template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
     wa.push_back(make_int4(c, 0, 0, 1));  // mean-mode workgroup
     for (int b = 0; b < nb; ++b) wa.push_back(make_int4(c, b, 0, 0));
   }
-  // device placement
-  char* p = tables;
-  auto take = [&](size_t bytes) {
-    char* q = p;
-    p += (bytes + 255) & ~(size_t)255;
-    return q;
-  };
   e->d_zinv = take(sizeof(za[0]) * n);
   e->d_xpass = take(sizeof(xa[0]) * n);
   e->d_zfwd = take(sizeof(fa[0]) * n);
@@ -811,6 +856,7 @@ template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
   if (r == hipSuccess) r = hipMemcpyAsync(e->d_wz, wz.data(), sizeof(int4) * wz.size(), hipMemcpyHostToDevice, e->user);
   if (r == hipSuccess) r = hipMemcpyAsync(e->d_wx, wx.data(), sizeof(int4) * wx.size(), hipMemcpyHostToDevice, e->user);
   if (r == hipSuccess) r = hipMemcpyAsync(e->d_wa, wa.data(), sizeof(int4) * wa.size(), hipMemcpyHostToDevice, e->user);
+  if (r == hipSuccess) r = hipMemsetAsync(e->d_guard, 0, 16 * (size_t)n, e->user);
   if (r == hipSuccess) r = hipStreamSynchronize(e->user);
   if (r != hipSuccess) {
     e->err = std::string("uploading ensemble tables: ") + hipGetErrorString(r);
@@ -869,6 +915,7 @@ template <typename T> chn_status ens_step(chn_ens* e, const double* dt, int nste
     ENSCHK(e, hipMemcpyAsync(e->d_adv, e->h_adv.data(), e->h_adv.size(), hipMemcpyHostToDevice, e->user));
     e->last_dt.assign(dt, dt + n);
   }
+  ENSCHK(e, hipMemsetAsync(e->d_guard, 0, 16 * (size_t)n, e->user));
   ENSCHK(e, hipEventRecord(e->ev_in, e->user));
   ENSCHK(e, hipStreamWaitEvent(e->own, e->ev_in, 0));
   chn::BatchPlan<T> bp{};
@@ -909,6 +956,17 @@ template <typename T> chn_status ens_step(chn_ens* e, const double* dt, int nste
   for (int k = 0; k < nsteps; ++k) ENSCHK(e, hipGraphLaunch(e->exec, e->own));
   ENSCHK(e, hipEventRecord(e->ev_out, e->own));
   ENSCHK(e, hipStreamWaitEvent(e->user, e->ev_out, 0));
+  std::vector<unsigned> gw(4 * (size_t)n);
+  ENSCHK(e, hipMemcpyAsync(gw.data(), e->d_guard, 16 * (size_t)n, hipMemcpyDeviceToHost, e->user));
+  ENSCHK(e, hipStreamSynchronize(e->user));
+  for (int i = 0; i < n; ++i)
+    if (gw[4 * i + 1]) {
+      const unsigned c = gw[4 * i + 1] - 1;
+      e->err = "channel " + std::to_string(i) + ": step " + std::to_string(c / 3) + ", sub-step " +
+               std::to_string(c % 3) + ": CFL not finite or above the limit; that channel's state is as at the "
+               "start of that sub-step";
+      return CHN_EUNSTABLE;
+    }
   return CHN_OK;
 }
 
@@ -951,6 +1009,22 @@ chn_status chn_create(const chn_config* cfg, void* d_ws, size_t ws_bytes, chn_ct
   else chn::host::default_mesh(x->n2, x->y.data());
   x->cfg.y = nullptr;
   const int n2 = x->n2;
+  // The banded LUs are unpivoted; refuse meshes on which the compact
+  // operators are close to singular (the maximum-order stencils degenerate
+  // for some local stretchings, Appendix B).  A plane-phase context uses the
+  // mesh for the CFL number only.
+  if (!x->planes_only) {
+    double c1 = INFINITY, c2 = INFINITY;
+    const bool ok = chn::host::operator_conditioning(n2, x->y.data(), &c1, &c2);
+    if (!ok || !(c1 <= kCondMax) || !(c2 <= kCondMax)) {
+      char msg[200];
+      std::snprintf(msg, sizeof(msg),
+                    "compact operators ill-conditioned on this mesh: cond_1(A1) = %.3g, cond_1(A2 with Dirichlet "
+                    "rows) = %.3g, bound %.0e (a milder wall stretching helps)", c1, c2, kCondMax);
+      delete x;
+      return fail(nullptr, CHN_EINVAL, msg);
+    }
+  }
   // tables
   x->hA1.resize(7 * n2); x->hB1.resize(7 * n2); x->hA2.resize(7 * n2); x->hB2.resize(7 * n2);
   x->hquad.resize(n2);
@@ -1057,6 +1131,7 @@ chn_status chn_set_state(chn_ctx* x, const double* d_v, const double* d_om2, con
   HIPCHK(x, hipMemsetAsync(x->nom_old, 0, CB, x->stream));
   HIPCHK(x, hipMemsetAsync(x->nu_old, 0, n2b, x->stream));
   HIPCHK(x, hipMemsetAsync(x->nw_old, 0, n2b, x->stream));
+  HIPCHK(x, hipMemsetAsync(x->guard, 0, 4 * sizeof(unsigned), x->stream));
   x->have_state = true;
   x->phase_valid = false;
   return CHN_OK;
@@ -1067,12 +1142,29 @@ chn_status chn_step_rk3(chn_ctx* x, double dt, int32_t nsteps, chn_step_info* in
   if (chn_status s = need_fields(x)) return s;
   if (!x->have_state) return fail(x, CHN_ESTATE, "chn_step_rk3 before chn_set_state");
   if (!(dt > 0) || nsteps < 0) return fail(x, CHN_EINVAL, "dt must be positive and nsteps >= 0");
-  for (int k = 0; k < nsteps; ++k)
+  // the guard's CFL word, fail code and step count start from zero
+  HIPCHK(x, hipMemsetAsync(x->guard, 0, 4 * sizeof(unsigned), x->stream));
+  const size_t pool_mark = x->pool_used;
+  for (int k = 0; k < nsteps; ++k) {
+    if (info && k == nsteps - 1) {  // per-phase times of the last step
+      x->phase_rec = true;
+      x->phase_timed.clear();
+    }
     for (int s = 0; s < 3; ++s) {
       const chn_status st = x->mixed ? substep<float>(x, s, dt) : substep<double>(x, s, dt);
-      if (st != CHN_OK) return st;
+      if (st != CHN_OK) {
+        x->phase_rec = false;
+        return st;
+      }
     }
+  }
+  x->phase_rec = false;
   if (info) {
+    double* div = x->info_dev + 6;
+    HIPCHK(x, hipMemsetAsync(div, 0, sizeof(double), x->stream));
+    const chn_status ds = x->mixed ? divergence<float>(x, reinterpret_cast<unsigned long long*>(div))
+                                   : divergence<double>(x, reinterpret_cast<unsigned long long*>(div));
+    if (ds != CHN_OK) return ds;
     chn::InfoArgs ia{};
     ia.g = x->geom;
     ia.rowcfl = x->rowcfl;
@@ -1083,16 +1175,42 @@ chn_status chn_step_rk3(chn_ctx* x, double dt, int32_t nsteps, chn_step_info* in
     ia.out = x->info_dev;
     ia.mean_out = x->mean_out;
     HIPCHK(x, chn::launch_info(ia, x->stream));
-    double h[8] = {0};
-    HIPCHK(x, hipMemcpyAsync(h, x->info_dev, sizeof(h), hipMemcpyDeviceToHost, x->stream));
-    HIPCHK(x, hipStreamSynchronize(x->stream));
+  }
+  double h[8] = {0};
+  unsigned gw[4] = {0, 0, 0, 0};
+  if (info) HIPCHK(x, hipMemcpyAsync(h, x->info_dev, sizeof(h), hipMemcpyDeviceToHost, x->stream));
+  HIPCHK(x, hipMemcpyAsync(gw, x->guard, sizeof(gw), hipMemcpyDeviceToHost, x->stream));
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  const int fstep = gw[1] ? (int)((gw[1] - 1) / 3) : -1, fsub = gw[1] ? (int)((gw[1] - 1) % 3) : -1;
+  if (info) {
     info->cfl_max = h[0];
     info->mass_flux = h[1];
     info->utau_lo = h[2];
     info->utau_hi = h[3];
     info->f_mean = h[4];
-    if (h[5] != 0.0 || !std::isfinite(h[0])) return fail(x, CHN_EUNSTABLE, "non-finite values after the step");
+    info->max_abs_div = h[6];
+    for (int p = 0; p < 5; ++p) info->ms_phase[p] = 0.0f;
+    for (const auto& r : x->phase_timed) {
+      float ms = 0.0f;
+      HIPCHK(x, hipEventElapsedTime(&ms, r.a, r.b));
+      const int ph = r.kind == CHN_K_ZINV ? 0 : r.kind == CHN_K_XPASS ? 1 : r.kind == CHN_K_ZFWD ? 2
+                   : r.kind == CHN_K_ADVANCE ? 3 : 4;
+      info->ms_phase[ph] += ms;
+    }
+    info->fail_step = fstep;
+    info->fail_substep = fsub;
+    if (fstep >= 0) info->cfl_max = (double)reinterpret_cast<const float&>(gw[0]) * dt;
   }
+  x->phase_timed.clear();
+  if (!x->timing) x->pool_used = pool_mark;  // the last step's events are free again
+  if (fstep >= 0) {
+    const float c = reinterpret_cast<const float&>(gw[0]);
+    char msg[160];
+    std::snprintf(msg, sizeof(msg), "step %d, sub-step %d: CFL %.4g %s; the state is as at the start of that sub-step",
+                  fstep, fsub, (double)c * dt, std::isfinite(c) ? "above the limit" : "not finite");
+    return fail(x, CHN_EUNSTABLE, msg);
+  }
+  if (info && (h[5] != 0.0 || !std::isfinite(h[0]))) return fail(x, CHN_EUNSTABLE, "non-finite values after the step");
   return CHN_OK;
 }
 
@@ -1251,6 +1369,13 @@ chn_status chn_get_operators(chn_ctx* x, double* a1, double* b1, double* a2, dou
   if (a2) std::memcpy(a2, x->hA2.data(), nb);
   if (b2) std::memcpy(b2, x->hB2.data(), nb);
   if (quad) std::memcpy(quad, x->hquad.data(), sizeof(double) * x->n2);
+  return CHN_OK;
+}
+
+chn_status chn_get_mesh(chn_ctx* x, double* y) {
+  if (!x) return CHN_EINVAL;
+  if (!y) return fail(x, CHN_EINVAL, "y is NULL");
+  std::memcpy(y, x->y.data(), sizeof(double) * x->n2);
   return CHN_OK;
 }
 

@@ -231,14 +231,42 @@ bool fft_plan(int n, FftPlan* pl, std::vector<double>* tw) {
   return true;
 }
 
-void default_mesh(int n2, double* y) {
-  const long double t2 = tanhl(2.0L);
+bool operator_conditioning(int n2, const double* y, double* c1, double* c2) {
+  std::vector<double> A((size_t)n2 * 7), B((size_t)n2 * 7);
+  if (!compact_bands(n2, y, 1, A.data(), B.data())) return false;
+  *c1 = band_cond1(n2, A.data());
+  if (!compact_bands(n2, y, 2, A.data(), B.data())) return false;
+  for (int o = 0; o < 7; ++o) {
+    A[o] = o == 3 ? 1.0 : 0.0;
+    A[(size_t)(n2 - 1) * 7 + o] = o == 3 ? 1.0 : 0.0;
+  }
+  *c2 = band_cond1(n2, A.data());
+  return std::isfinite(*c1) && std::isfinite(*c2);
+}
+
+static void tanh_mesh(int n2, long double g, double* y) {
+  const long double tg = tanhl(g);
   for (int j = 0; j < n2; ++j) {
     const long double s = -1.0L + 2.0L * j / (n2 - 1);
-    y[j] = (double)(tanhl(2.0L * s) / t2);
+    y[j] = (double)(tanhl(g * s) / tg);
   }
+  // exact mirror symmetry, walls at -1 and 1
+  for (int j = 0; j < n2 / 2; ++j) y[n2 - 1 - j] = -y[j];
+  if (n2 % 2) y[n2 / 2] = 0.0;
   y[0] = -1.0;
   y[n2 - 1] = 1.0;
+}
+
+void default_mesh(int n2, double* y, double* gamma) {
+  for (int k = 0; k < 7; ++k) {
+    const double g = 2.0 - 0.25 * k;
+    tanh_mesh(n2, g, y);
+    double c1, c2;
+    if (g == 0.5 || (operator_conditioning(n2, y, &c1, &c2) && c2 <= 1e4 && c1 <= 1e5)) {
+      if (gamma) *gamma = g;
+      return;
+    }
+  }
 }
 
 }  // namespace host

@@ -25,6 +25,21 @@ template <typename T> __device__ __forceinline__ c2<T> cmuli(c2<T> a, int sgn) {
 }
 template <typename T> __device__ __forceinline__ c2<T> cconj(c2<T> a) { return mk<T>(a.x, -a.y); }
 
+// Maximum that propagates NaN from either argument (fmax drops a NaN
+// operand), for the CFL reductions that guard against blown-up states.
+template <typename T> __device__ __forceinline__ T nanmax(T a, T b) { return (b > a || b != b) ? b : a; }
+
+// Instability guard of a context, four words in device memory:
+//   [0] CFL maximum of the current sub-step as the bits of a non-negative
+//       float (reset by the z inverse, raised by atomicMax in the x pass; as
+//       unsigned integers the bits order like the values, +inf and NaN
+//       above every finite one),
+//   [1] fail code: 0, or 1 + 3 step + sub-step of the first sub-step whose
+//       CFL was not finite or above the limit (set by the pencil kernel),
+//   [2] steps completed since the host cleared the guard,
+//   [3] unused.
+constexpr unsigned kGuardNonFinite = 0x7f800000u;  // bits of +inf
+
 // Plans with a compile-time radix schedule (FN template argument of the plane kernels).
 __host__ __device__ inline bool plan_is_576(const FftPlan& pl) {
   return pl.n == 576 && pl.npass == 4 && pl.radix[0] == 8 && pl.radix[1] == 8 && pl.radix[2] == 3 &&

@@ -25,6 +25,15 @@ void quadrature(int n2, const double* y, double* w);
 bool band_lu(int n, const double* band, int dir, double* L, double* U);
 bool wall_rows(int n, const double* A1, const double* B1, double* clo, double* chi);
 bool fft_plan(int n, FftPlan* pl, std::vector<double>* tw);
-void default_mesh(int n2, double* y);
+// 1-norm condition number ||A||_1 ||A^-1||_1 of a [n][7] band (inf if singular)
+double band_cond1(int n, const double* A);
+// cond_1 of A1 and of A2 with its end rows replaced by Dirichlet rows (the
+// implicit steps' matrix at vanishing time step); false if a band is singular
+bool operator_conditioning(int n2, const double* y, double* c1, double* c2);
+// Default wall-normal mesh: y_j = tanh(g s_j) / tanh(g), s_j uniform on
+// [-1, 1], with the largest g in {2, 1.75, ..., 0.5} whose compact operators
+// have cond_1(A2, Dirichlet rows) <= 1e4 and cond_1(A1) <= 1e5 (g = 0.5 if
+// none); *gamma receives g
+void default_mesh(int n2, double* y, double* gamma = nullptr);
 }  // namespace host
 }  // namespace chn

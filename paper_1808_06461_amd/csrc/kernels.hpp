@@ -23,6 +23,8 @@ template <typename T> struct ZinvArgs {
   int zero_mean;       // nonzero: the (0,0) coefficient of every input is taken as 0
   int y0, ny;          // planes y0 .. y0 + ny - 1 of the inputs; `out` holds them from plane 0
   int fixed;           // nonzero: compile-time radix schedule where one exists for the plan
+  unsigned* guard;     // instability guard (common.hpp) whose CFL word the launch
+                       // with y0 == 0 resets; nullptr outside the time step
 };
 
 template <typename T> struct XpassArgs {
@@ -38,6 +40,8 @@ template <typename T> struct XpassArgs {
   int rows;              // rows per workgroup: 2, 4, 8 (3 rows lines in LDS) or 1 (long rows)
   int y0, ny;            // buf holds planes y0 .. y0 + ny - 1 (from its plane 0)
   int fixed;             // nonzero: compile-time radix schedule where one exists for the plan
+  unsigned* guard;       // instability guard: every workgroup raises word 0 to its
+                         // CFL maximum (nullptr outside the time step)
 };
 
 template <typename T, typename TO> struct ZfwdArgs {
@@ -204,6 +208,12 @@ template <typename TH, typename TP> struct AdvanceArgs {
   const double* hc;           // chi_h, lane-indexed [n2][2M]
   const double* hm;           // [M][4]: D1 v_h at (lower, upper) wall for c = 0, then c = 1
   const double* hw;           // lane-indexed [n2][2M]: lane c holds w_c, D1 v_p(wall c) = w_c . r_chi
+  // instability guard (common.hpp): every workgroup leaves the state untouched
+  // when the fail word is set or the sub-step's CFL (word 0 times dt) is not
+  // finite or above cfl_limit; the mean workgroup then records the sub-step
+  unsigned* guard;
+  double cfl_limit;
+  int substep;                // s, for the fail code
 };
 
 // Homogeneous solutions of the three sub-steps for a time step dt: the
@@ -239,9 +249,22 @@ struct InfoArgs {
   int p3;
   const double* U1;
   double dt, nu;
-  double* out;                // cfl, mass flux, utau_lo, utau_hi, f (copied), nonfinite flag
+  double* out;                // cfl, mass flux, utau_lo, utau_hi, f (copied), nonfinite flag,
+                              // max |divergence| (out[6], as the bits of a non-negative double)
   const double* mean_out;
 };
+
+// Divergence of the velocity fields the transforms consume: per mode
+// i a u1 + D1 u2 + i b u3 (compact D1 of u2 through the LU of A1); the
+// maximum modulus over all modes and nodes is raised into *maxbits (bits of
+// a non-negative double, atomicMax).
+template <typename TP> struct DivArgs {
+  PencilGeom g;
+  const TP* u[3];             // u1, u2, u3 interleaved complex [n2][M]
+  double* S0;                 // lane-indexed scratch [n2][2M]
+  unsigned long long* maxbits;
+};
+template <typename TP> hipError_t launch_div(const DivArgs<TP>& a, hipStream_t st);
 
 // batched plane phase: descriptors and work lists (context, bx, by, -) in device memory
 template <typename T> struct BatchPlan {

@@ -12,13 +12,16 @@
 // by steepest descent in spacing-scaled coordinates (the step in y_j is
 // -t s_j^2 dL/dy_j, s_j = y_ref[j+1] - y_ref[j]); the gradient by central
 // differences with step 1e-6 s_j; the step length by halving from twice the
-// last accepted one (first trial 1) until the mesh is strictly increasing,
-// L strictly decreases, the Armijo condition L_new <= L + 1e-4 t (grad . d)
-// holds and the trial mesh's A2 has a 1-norm condition number at most ten
-// times the reference mesh's (the functional sees only B2 - k* A2; without
-// the bound the descent can reach stretchings on which the maximum-order
-// stencils make A2 singular).  It stops after max_iter steps or when
-// t < 1e-30.
+// last accepted one (t starts at 1, so the first trial is 2) until the mesh
+// is strictly increasing, L strictly decreases, the Armijo condition
+// L_new <= L + 1e-4 t (grad . d) holds, every ratio of adjacent spacings of
+// the trial mesh lies in [1/2, 2] (the nodes move without changing much the
+// individual spacings), and the trial mesh's A2 and A1 each have a 1-norm
+// condition number at most ten times the reference mesh's (the functional
+// sees only B2 - k* A2; without the bound the descent can reach
+// stretchings on which the maximum-order stencils make A2 singular, and A1,
+// which the velocity recovery and the forcing use, degrades the same way).
+// It stops after max_iter steps or when t < 1e-30.
 //
 // A moved node changes only the compact rows whose stencils hold it, so a
 // gradient component recomputes 14 rows (quad precision, compact_row) and
@@ -44,8 +47,19 @@ struct MeshProblem {
   std::vector<double> yref, xref, s;
   std::vector<double> A, B;  // [n][7] operators at the current mesh
   std::vector<double> M7, g;  // Dirichlet-row matrix [n][7], solution
-  double cond_max;
+  std::vector<double> A1, B1;  // first-derivative operators (conditioning check)
+  double cond_max, cond1_max;  // bounds on cond_1(A2), cond_1(A1)
 };
+
+constexpr double kSpacingRatio = 2.0;
+
+bool spacing_ratio_ok(int n, const double* y) {
+  for (int i = 1; i + 1 < n; ++i) {
+    const double r = (y[i + 1] - y[i]) / (y[i] - y[i - 1]);
+    if (!(r <= kSpacingRatio && r >= 1.0 / kSpacingRatio)) return false;
+  }
+  return true;
+}
 
 double g_analytic(double y, double ks) {
   const double qk = std::sqrt(ks);
@@ -169,15 +183,26 @@ double penalty_term(const MeshProblem& P, const double* x) {
   return P.C * std::sqrt(ss);
 }
 
-// Operators of mesh y: the rows within reach of a moved node recomputed.
-bool near_wall_rows(const MeshProblem& P, const double* y, double* A, double* B) {
+// Operators of order p of mesh y: the rows within reach of a moved node recomputed.
+bool near_wall_rows(const MeshProblem& P, const double* y, double* A, double* B, int p = 2) {
   for (int i = 0; i < P.n; ++i)
     if (i <= P.m + 3 || i >= P.n - 1 - P.m - 3)
-      if (!compact_row(P.n, y, i, 2, A + 7 * i, B + 7 * i)) return false;
+      if (!compact_row(P.n, y, i, p, A + 7 * i, B + 7 * i)) return false;
   return true;
 }
 
+// The trial-mesh conditions besides the descent: spacing ratios, and the
+// conditioning of A2 (given) and of A1 (recomputed near the walls).
+bool admissible(const MeshProblem& P, const double* y, const double* A2) {
+  if (!spacing_ratio_ok(P.n, y) || !(cond1(P.n, A2) <= P.cond_max)) return false;
+  std::vector<double> A1(P.A1), B1(P.B1);
+  return near_wall_rows(P, y, A1.data(), B1.data(), 1) && cond1(P.n, A1.data()) <= P.cond1_max;
+}
+
 }  // namespace
+
+double band_cond1(int n, const double* A) { return cond1(n, A); }
+
 }  // namespace host
 }  // namespace chn
 
@@ -209,6 +234,11 @@ extern "C" chn_status chn_optimise_mesh(const double* y_ref, int n2, int m, doub
   if (!compact_bands(n2, y_ref, 2, P.A.data(), P.B.data())) return CHN_EINVAL;
   P.cond_max = 10.0 * cond1(n2, P.A.data());
   if (!std::isfinite(P.cond_max)) return CHN_EINVAL;
+  P.A1.resize((size_t)n2 * 7);
+  P.B1.resize((size_t)n2 * 7);
+  if (!compact_bands(n2, y_ref, 1, P.A1.data(), P.B1.data())) return CHN_EINVAL;
+  P.cond1_max = 10.0 * cond1(n2, P.A1.data());
+  if (!std::isfinite(P.cond1_max)) return CHN_EINVAL;
 
   std::vector<double> x = P.xref, yt(n2), xt(m), grad(m), d(m);
   std::vector<double> At(P.A), Bt(P.B), An(P.A), Bn(P.B);
@@ -272,7 +302,7 @@ extern "C" chn_status chn_optimise_mesh(const double* y_ref, int n2, int m, doub
         if (near_wall_rows(P, yt.data(), An.data(), Bn.data()) &&
             homogeneous_error(P, yt.data(), An.data(), Bn.data(), &err)) {
           fn = err + penalty_term(P, xt.data());
-          if (fn < f && fn <= f + 1e-4 * t * slope && cond1(n2, An.data()) <= P.cond_max) {
+          if (fn < f && fn <= f + 1e-4 * t * slope && admissible(P, yt.data(), An.data())) {
             en = err;
             accepted = true;
             break;

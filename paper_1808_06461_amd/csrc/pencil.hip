@@ -286,14 +286,32 @@ template <> __device__ __forceinline__ void store_c<float>(float* p, size_t idx,
   reinterpret_cast<float2*>(p)[idx] = make_float2((float)x, (float)y);
 }
 
+// ---------------------------------------------------------------- guard
+// True when the sub-step must leave the state untouched: an earlier sub-step
+// failed, or this one's CFL number (the x pass's maximum times dt) is not
+// finite or above the limit.  Uniform over the launch.
+template <typename TH, typename TP> __device__ __forceinline__ bool unstable(const AdvanceArgs<TH, TP>& a) {
+  if (!a.guard) return false;
+  const unsigned bits = __hip_atomic_load(a.guard, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned fail = __hip_atomic_load(a.guard + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return fail != 0u || bits >= kGuardNonFinite || (double)__uint_as_float(bits) * a.dt > a.cfl_limit;
+}
+
 // ---------------------------------------------------------------- mean modes
 // One workgroup: U1 with constant mass flux and U3 (float64, Section 2.1),
 // then the (0,0) entries of the next sub-step's velocity/vorticity fields.
+// It also keeps the guard's books: the fail code of an unstable sub-step,
+// the count of completed steps.
 template <typename TH, typename TP>
 __device__ void mean_block(const AdvanceArgs<TH, TP>& a) {
   const PencilGeom& g = a.g;
   const int n = g.n2;
   const int t = threadIdx.x;
+  if (unstable(a)) {
+    if (t == 0 && a.guard[1] == 0u) a.guard[1] = 1u + 3u * a.guard[2] + (unsigned)a.substep;
+    return;
+  }
+  if (a.guard && t == 0 && a.substep == 2) a.guard[2] += 1u;
   double* NU = a.mean_scr + 3 * (size_t)n * 5;
   double* NW = NU + n;
   double* DU = NW + n;  // D1 U1, D1 U3
@@ -453,6 +471,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
                                              const double* __restrict__ U1d, const double* __restrict__ L1u,
                                              const double* __restrict__ U1u) {
   constexpr int D = 5, D2 = 3, D3 = 3;
+  if (unstable(a)) return;
   const PencilGeom& g = a.g;
   const Lane L = lane_setup(g, bx);
   const int n = g.n2;
@@ -1266,6 +1285,47 @@ __global__ void __launch_bounds__(256) k_chi_from_v(ChiArgs a) {
 }
 
 // ---------------------------------------------------------------- diagnostics
+// Divergence i a u1 + D1 u2 + i b u3 of the phase velocities, per mode and
+// node: A1 (D1 u2) = B1 u2 eliminated downward, finished upward; the lane
+// pair of a mode forms the complex divergence and its modulus.
+template <typename TP>
+__global__ void __launch_bounds__(256) k_div(DivArgs<TP> a, const double* __restrict__ B1,
+                                             const double* __restrict__ L1d, const double* __restrict__ U1d) {
+  const PencilGeom& g = a.g;
+  const Lane L = lane_setup(g, blockIdx.x);
+  const int n = g.n2;
+  const size_t st = 2 * (size_t)g.M, col = L.col;
+  auto u = [&](int f, int i) { return (double)a.u[f][(size_t)i * st + col]; };
+  {
+    double w[7] = {0, 0, 0, 0, 0, 0, 0};
+    double yb[3] = {0, 0, 0};
+    for (int k = 0; k < 3 && k < n; ++k) w[3 + k] = u(1, k);
+    for (int i = 0; i < n; ++i) {
+      w[6] = (i + 3 < n) ? u(1, i + 3) : 0.0;
+      const double yi = elim3(dot7(B1 + i * 7, w), L1d + i * 3, yb);
+      if (L.act) a.S0[i * st + col] = yi;
+      yb[0] = yb[1];
+      yb[1] = yb[2];
+      yb[2] = yi;
+      push_back(w, 0.0);
+    }
+  }
+  double dmax = 0.0;
+  double xb[3] = {0, 0, 0};
+  const double sg = L.c == 0 ? -1.0 : 1.0;  // component c of i z is sg times the other component of z
+  for (int i = n - 1; i >= 0; --i) {
+    const double dv = back3(a.S0[i * st + col], U1d + i * 4, xb);
+    push_x(xb, dv);
+    const double u1o = __shfl_xor(u(0, i), 1), u3o = __shfl_xor(u(2, i), 1);
+    const double dc = dv + sg * (L.A * u1o + L.B * u3o);
+    const double m2 = dc * dc + __shfl_xor(dc * dc, 1);
+    if (L.act) dmax = nanmax(dmax, sqrt(m2));
+  }
+  for (int off = 32; off > 0; off >>= 1) dmax = nanmax(dmax, __shfl_xor(dmax, off));
+  if ((threadIdx.x & 63) == 0)
+    atomicMax(a.maxbits, (unsigned long long)__double_as_longlong(dmax != dmax ? __longlong_as_double(0x7ff8000000000000ll) : dmax));
+}
+
 __global__ void __launch_bounds__(256) k_info(InfoArgs a) {
   __shared__ double red[3][4];
   const int n = a.g.n2;
@@ -1274,7 +1334,7 @@ __global__ void __launch_bounds__(256) k_info(InfoArgs a) {
   for (size_t e = threadIdx.x; e < (size_t)n * a.p3; e += blockDim.x) {
     const float c = a.rowcfl[e];
     if (!isfinite(c)) bad = true;
-    cm = fmax(cm, (double)c);
+    cm = nanmax(cm, (double)c);
   }
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
     wm += a.g.quad[r] * a.U1[r];
@@ -1282,7 +1342,7 @@ __global__ void __launch_bounds__(256) k_info(InfoArgs a) {
   }
   double b = bad ? 1.0 : 0.0;
   for (int off = 32; off > 0; off >>= 1) {
-    cm = fmax(cm, __shfl_xor(cm, off));
+    cm = nanmax(cm, __shfl_xor(cm, off));
     wm += __shfl_xor(wm, off);
     b = fmax(b, __shfl_xor(b, off));
   }
@@ -1296,7 +1356,7 @@ __global__ void __launch_bounds__(256) k_info(InfoArgs a) {
   if (threadIdx.x == 0) {
     double c = 0.0, m = 0.0, bb = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      c = fmax(c, red[0][w]);
+      c = nanmax(c, red[0][w]);
       m += red[1][w];
       bb = fmax(bb, red[2][w]);
     }
@@ -1352,6 +1412,12 @@ hipError_t launch_chi_from_v(const ChiArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_chi_from_v, dim3(pencil_blocks(a.g.M)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
+template <typename TP> hipError_t launch_div(const DivArgs<TP>& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_div<TP>), dim3(pencil_blocks(a.g.M)), dim3(256), 0, st, a, a.g.B1, a.g.L1d, a.g.U1d);
+  return hipGetLastError();
+}
+template hipError_t launch_div<double>(const DivArgs<double>&, hipStream_t);
+template hipError_t launch_div<float>(const DivArgs<float>&, hipStream_t);
 hipError_t launch_info(const InfoArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_info, dim3(1), dim3(256), 0, st, a);
   return hipGetLastError();

@@ -57,6 +57,8 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
     }
     return v;
   };
+  // the first launch of a sub-step's plane phase starts the CFL maximum
+  if (a.guard && a.y0 == 0 && bx == 0 && by == 0 && threadIdx.x == 0) a.guard[0] = 0u;
   for (int f = 0; f < a.nfields; ++f) {
     for (int e = threadIdx.x; e < K * npad; e += blockDim.x) {
       const int l = (int)qdiv(e, npad, mnp);
@@ -142,7 +144,7 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
       s1[row] += (double)H1;
       s3[row] += (double)h3[row];
       const T c = fabs(u1) * idx_ + fabs(u2) * idy + fabs(u3) * idz;
-      cf[row] = fmax(cf[row], c);
+      cf[row] = nanmax(cf[row], c);
       // line `row` belongs to row row / 3 <= row, already read at this x
       lds[row * LS + px] = mk<T>(H1, H2);
     }
@@ -158,7 +160,7 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
     double v = kind == 0 ? s1[row] : (kind == 1 ? s3[row] : (double)cf[row]);
     for (int off = 32; off > 0; off >>= 1) {
       const double o = __shfl_xor(v, off);
-      v = kind < 2 ? v + o : fmax(v, o);
+      v = kind < 2 ? v + o : nanmax(v, o);
     }
     if ((threadIdx.x & 63) == 0) red[q][wid] = v;
   }
@@ -170,12 +172,13 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
     for (int w = 0; w < nw; ++w) {
       t1 += red[row][w];
       t3 += red[RZ + row][w];
-      tc = fmax(tc, red[2 * RZ + row][w]);
+      tc = nanmax(tc, red[2 * RZ + row][w]);
     }
     const size_t o = (size_t)yg * p3 + z0 + row;
     a.rowsum[o] = t1;
     a.rowsum[(size_t)a.d.n2 * p3 + o] = t3;
     a.rowcfl[o] = tc;
+    if (a.guard) atomicMax(a.guard, __float_as_uint(fabsf((float)tc)) | (tc != tc ? kGuardNonFinite : 0u));
   }
   fft_lines<T, MAXV, FN, kPad>(lds, LS, RZ + RZ / 2, a.plan, a.tw, -1);
   // --- unpack two real spectra per line, truncate, store in place over fields 0..2
@@ -249,7 +252,7 @@ __device__ __forceinline__ void xrow_body(const XpassArgs<T>& a, int z, int y) {
     if (threadIdx.x + q * NT < p1) {
       s1 += (double)H1;
       s3 += (double)H3;
-      cf = fmax(cf, fabs((double)u1) * a.inv_dx + fabs((double)u2) * idy + fabs((double)u3) * a.inv_dz);
+      cf = nanmax(cf, fabs((double)u1) * a.inv_dx + fabs((double)u2) * idy + fabs((double)u3) * a.inv_dz);
     }
     r0[q] = mk<T>(H1, H2);
     r1[q] = mk<T>(H3, T(0));
@@ -257,7 +260,7 @@ __device__ __forceinline__ void xrow_body(const XpassArgs<T>& a, int z, int y) {
   for (int off = 32; off > 0; off >>= 1) {
     s1 += __shfl_xor(s1, off);
     s3 += __shfl_xor(s3, off);
-    cf = fmax(cf, __shfl_xor(cf, off));
+    cf = nanmax(cf, __shfl_xor(cf, off));
   }
   __shared__ double red[3][NT / 64];
   const int wid = threadIdx.x >> 6;
@@ -279,12 +282,13 @@ __device__ __forceinline__ void xrow_body(const XpassArgs<T>& a, int z, int y) {
       for (int w = 0; w < NT / 64; ++w) {
         t1 += red[0][w];
         t3 += red[1][w];
-        tc = fmax(tc, red[2][w]);
+        tc = nanmax(tc, red[2][w]);
       }
       const size_t o = (size_t)(a.y0 + y) * p3 + z;
       a.rowsum[o] = t1;
       a.rowsum[(size_t)a.d.n2 * p3 + o] = t3;
       a.rowcfl[o] = tc;
+      if (a.guard) atomicMax(a.guard, __float_as_uint(fabsf((float)tc)) | (tc != tc ? kGuardNonFinite : 0u));
     }
     fft_lines<T, MAXV, FN>(line, p1, 1, a.plan, a.tw, -1);
     for (int k = threadIdx.x; k < n1h; k += NT) {

@@ -22,6 +22,37 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+def rel_max(a, b):
+    """Element-wise bound: max |a - b| / max |b| (a localized error cannot hide in the norm)."""
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+def worst_mode(a, b, floor=1e-6):
+    """Largest per-(kx, kz) pencil error ||a - b|| / ||b|| over the modes whose
+    energy is above `floor` times the most energetic mode's; and that mode."""
+    e = np.sum(np.abs(b) ** 2, axis=0)
+    worst, where = 0.0, None
+    for kx, kz in zip(*np.nonzero(e > floor * e.max())):
+        r = np.linalg.norm(a[:, kx, kz] - b[:, kx, kz]) / np.sqrt(e[kx, kz])
+        if r > worst:
+            worst, where = float(r), (int(kx), int(kz))
+    return worst, where
+
+
+def run_oracle_with_diagnostics(S, st, nsteps):
+    """nsteps oracle RK3 steps; also the CFL number of the velocities entering
+    the last sub-step (what the library's step record reports) and u_tau."""
+    f, cfl = 0.0, None
+    for k in range(nsteps):
+        hist = kmm.zero_history(S)
+        for s in range(3):
+            if k == nsteps - 1 and s == 2:
+                cfl = kmm.cfl(S, st, S.dt)
+            st, hist, f = kmm.substep(S, st, hist, s)
+    dU = kmm.d1(S, st.U1)
+    return st, f, cfl, np.sqrt(S.nu * abs(dU[0])), np.sqrt(S.nu * abs(dU[-1]))
+
+
 def test_library_exports_every_declared_symbol():
     from paper_1808_06461_amd import chn
     if not os.path.exists(chn.LIB_PATH):
@@ -119,36 +150,87 @@ def test_one_step_parity(case):
     info = ch.step(case.dt, 1, info=True)
     got = {k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "chi", "u1mean", "u3mean").items()}
     for name, r in (("v", ref.v), ("omega2", ref.om2), ("chi", ref.chi), ("u1mean", ref.U1)):
-        e = rel(got[name], r)
-        print(f"{name}: {e:.2e}")
+        e, em = rel(got[name], r), rel_max(got[name], r)
+        print(f"{name}: {e:.2e} max {em:.2e}")
         # chi's wall rows are set by the influence-matrix cancellation; on these
         # coarse test meshes the oracle's own sensitivity to 2 ulp noise in H is ~1e-10
-        assert e < (1e-9 if name == "chi" else 1e-11), (name, e)
+        t = 1e-9 if name == "chi" else 1e-11
+        assert e < t and em < t, (name, e, em)
     assert np.abs(got["u3mean"] - ref.U3).max() < 1e-13
     assert abs(info["f_mean"] - f) < 1e-9 * abs(f)
     assert abs(info["mass_flux"] - case.mass_flux) < 1e-13
     ch.close()
 
 
-@gpu
-def test_c1_ten_steps_fp64():
-    """The 64 x 65 x 64, Re_tau ~ 180 workload: 10 RK3 steps at dt = 0.005."""
+@pytest.fixture(scope="module")
+def c1_oracle():
+    """The 64 x 65 x 64, Re_tau ~ 180 workload after 10 oracle RK3 steps at dt = 0.005."""
     case = synth.CASES["c1"]
     v, om, U1, U3, y = synth.turbulent_field(case)
     S = _setup(case, y)
-    ref, f = kmm.step(S, kmm.make_state(S, v, om, U1, U3), 10)
+    ref, f, cfl, ulo, uhi = run_oracle_with_diagnostics(S, kmm.make_state(S, v, om, U1, U3), 10)
     ru = kmm.recover(S, ref)
-    ch = _channel(case, y)
+    refs = dict(v=ref.v, omega2=ref.om2, u1=ru[0], u3=ru[2], omega1=ru[3], omega3=ru[5], u1mean=ref.U1,
+                chi=ref.chi)
+    return case, (v, om, U1, U3, y), refs, ref.U3, dict(f_mean=f, cfl_max=cfl, utau_lo=ulo, utau_hi=uhi)
+
+
+# float64: 1e-11 per field in the L2 and the max norm; mixed: 1e-5 on the
+# velocities and means, the vorticities and chi (one derivative further from
+# the float32 products) 1e-4.  chi's wall rows hold the influence-matrix
+# coefficients, which amplify rounding: the oracle itself moves them by 1.5e-10
+# of max|chi| (interior 1.2e-11) when its input changes by one ulp
+# (test_oracle_physics.test_chi_wall_rows_amplify_rounding), so chi's
+# element-wise bound is 5x the field bound inside and 50x at the wall rows.
+# Per mode (pencils of the modes above 1e-6 of the peak energy): float32
+# products carry errors of ~1e-7 of the largest mode into every mode, so a
+# weak mode's relative error is larger by its amplitude ratio; the per-mode
+# bounds (1e-9 float64; 1e-3 velocities, 3e-2 vorticities and chi mixed)
+# still fail for any mode that is wrong as a whole.
+# Step diagnostics: 1e-12 (float64; the mean pressure gradient is a small
+# difference of O(1) integrals: 1e-9) and 1e-6 (mixed, CFL from float32
+# velocities).
+C1_TOL = {"fp64": dict(field=1e-11, vort=1e-11, mode=1e-9, vmode=1e-9, diag=1e-12, f=1e-9),
+          "mixed": dict(field=1e-5, vort=1e-4, mode=1e-3, vmode=3e-2, diag=1e-6, f=1e-4)}
+VORT = ("omega1", "omega2", "omega3", "chi")
+
+
+@gpu
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c1_ten_steps(c1_oracle, precision):
+    """The 64 x 65 x 64, Re_tau ~ 180 workload: 10 RK3 steps at dt = 0.005,
+    every field element-wise and per mode, and the step record."""
+    case, (v, om, U1, U3, y), refs, ref_U3, diag = c1_oracle
+    tol = C1_TOL[precision]
+    ch = _channel(case, y, precision)
     ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
-    ch.step(case.dt, 10)
+    info = ch.step(case.dt, 10, info=True)
     got = {k: t.cpu().numpy() for k, t in ch.get_fields(
         "v", "omega2", "chi", "u1", "u3", "omega1", "omega3", "u1mean", "u3mean").items()}
-    errs = {}
-    for name, r in (("v", ref.v), ("omega2", ref.om2), ("u1", ru[0]), ("u3", ru[2]), ("omega1", ru[3]),
-                    ("omega3", ru[5]), ("u1mean", ref.U1), ("chi", ref.chi)):
-        errs[name] = rel(got[name], r)
-        print(f"{name}: {errs[name]:.2e}")
-    for name, e in errs.items():
-        assert e < 1e-11, (name, e)
-    assert np.abs(got["u3mean"] - ref.U3).max() < 1e-13
+    for name, r in refs.items():
+        t = tol["vort"] if name in VORT else tol["field"]
+        g = got[name]
+        e2 = rel(g, r)
+        if name == "chi":
+            scale = np.abs(r).max()
+            em = np.abs(g[1:-1] - r[1:-1]).max() / scale
+            ew = np.abs(g[[0, -1]] - r[[0, -1]]).max() / scale
+            line = f"{precision} {name}: L2 {e2:.2e} max interior {em:.2e} walls {ew:.2e}"
+            assert em < 5 * t and ew < 50 * t, (name, em, ew)
+        else:
+            em = rel_max(g, r)
+            line = f"{precision} {name}: L2 {e2:.2e} max {em:.2e}"
+            assert em < t, (name, em)
+        if r.ndim == 3:
+            wm, where = worst_mode(g, r)
+            line += f" worst mode {wm:.2e} at {where}"
+            assert wm < tol["vmode" if name in VORT else "mode"], (name, wm, where)
+        print(line)
+        assert e2 < t, (name, e2)
+    assert np.abs(got["u3mean"] - ref_U3).max() < (1e-13 if precision == "fp64" else 1e-9)
+    for k in ("cfl_max", "utau_lo", "utau_hi"):
+        e = abs(info[k] / diag[k] - 1)
+        print(f"{precision} {k}: {info[k]:.10e} oracle {diag[k]:.10e} rel {e:.2e}")
+        assert e < tol["diag"], (k, info[k], diag[k])
+    assert abs(info["f_mean"] / diag["f_mean"] - 1) < tol["f"]
     ch.close()

@@ -72,6 +72,24 @@ def test_numeric_unresolved_limit_is_A2_nullspace():
     assert abs(g[1]) > 1e-2
 
 
+def _assert_admissible(y, y_ref):
+    """cond_1 of A2 and of A1 within COND_GROWTH of the reference mesh's, spacing ratios in [1/2, 2]."""
+    for p in (2, 1):
+        A_opt, _ = compact.operators(y, p)
+        A_ref, _ = compact.operators(y_ref, p)
+        assert meshopt.cond1(A_opt) <= meshopt.COND_GROWTH * meshopt.cond1(A_ref), p
+    h = np.diff(y)
+    r = h[1:] / h[:-1]
+    assert r.max() <= 2.0 and r.min() >= 0.5, (r.min(), r.max())
+
+
+def test_spacing_ratio_bound():
+    y = np.cumsum([0.0, 1.0, 2.0, 4.0, 2.0, 1.0])
+    assert meshopt.spacing_ratio_ok(y)          # ratios 2, 2, 1/2, 1/2: on the bound
+    assert not meshopt.spacing_ratio_ok(np.cumsum([0.0, 1.0, 2.5, 2.5]))
+    assert not meshopt.spacing_ratio_ok(np.cumsum([0.0, 1.0, 1.0, 0.3]))
+
+
 def test_descent_lowers_the_error():
     n2, m = 33, 6
     y_ref = synth.mesh_tanh(n2)
@@ -80,9 +98,7 @@ def test_descent_lowers_the_error():
     assert it == 5 and len(hist) == 5
     assert all(b < a for a, b in zip(hist, hist[1:]))
     assert e1 < 0.8 * e0, (e0, e1)
-    A_opt, _ = compact.operators(y, 2)
-    A_ref, _ = compact.operators(y_ref, 2)
-    assert meshopt.cond1(A_opt) <= meshopt.COND_GROWTH * meshopt.cond1(A_ref)
+    _assert_admissible(y, y_ref)
     assert np.all(np.diff(y) > 0)
     np.testing.assert_array_equal(y, -y[::-1])
     assert y[0] == -1.0 and y[-1] == 1.0
@@ -118,6 +134,4 @@ def test_guard_bounds_the_stretching():
     y_ref = synth.mesh_tanh(65)
     y, e0, e1, it = meshopt.optimise_mesh(y_ref, m=20, kstar=3364805.0, max_iter=2)
     assert it == 2 and e1 < e0
-    A_opt, _ = compact.operators(y, 2)
-    A_ref, _ = compact.operators(y_ref, 2)
-    assert meshopt.cond1(A_opt) <= meshopt.COND_GROWTH * meshopt.cond1(A_ref)
+    _assert_admissible(y, y_ref)

@@ -178,3 +178,33 @@ def test_z_reflection_symmetry_preserved():
     assert rel(st.om2[:, :, sl] + st.om2[:, :, mir], st.om2) < 1e-12
     assert rel(st.om2[:, :, 0], st.om2) < 1e-12
     assert np.abs(st.U3).max() < 1e-14
+
+
+@pytest.mark.slow
+def test_chi_wall_rows_amplify_rounding():
+    """The conditioning that sets the element-wise parity bounds of chi.
+
+    chi's wall values are the influence-matrix coefficients c = -D1 v_p / D1 v_h
+    at the walls, a quotient of two small numbers (the homogeneous layers are
+    far thinner than the first cell), so they amplify rounding.  The oracle's
+    own 10-step run of the 64 x 65 x 64 workload, restarted from a state
+    perturbed by one ulp, moves chi by 1e-11 (L2) and ~1e-10 of max|chi| at the
+    wall rows, ~1e-11 inside, while v and omega2 stay at 1e-15."""
+    case = synth.CASES["c1"]
+    v, om, U1, U3, y = synth.turbulent_field(case)
+    S = kmm.Setup(n1=case.n1, n2=case.n2, n3=case.n3, lx=case.lx, lz=case.lz, nu=1 / case.re_b, dt=case.dt,
+                  mass_flux=2.0, y=y)
+    a, _ = kmm.step(S, kmm.make_state(S, v, om, U1, U3), 10)
+    g = np.random.default_rng(1)
+    vp = v * (1 + 2.2e-16 * g.standard_normal(v.shape))
+    op = om * (1 + 2.2e-16 * g.standard_normal(om.shape))
+    b, _ = kmm.step(S, kmm.make_state(S, vp, op, U1, U3), 10)
+    d = np.abs(a.chi - b.chi)
+    scale = np.abs(a.chi).max()
+    wall, inner = d[[0, -1]].max() / scale, d[1:-1].max() / scale
+    l2 = np.linalg.norm(a.chi - b.chi) / np.linalg.norm(a.chi)
+    print(f"chi: L2 {l2:.2e}, wall rows {wall:.2e}, interior {inner:.2e}")
+    assert 3e-11 < wall < 1e-9 and inner < 5e-11 and l2 < 3e-11
+    for f in ("v", "om2"):
+        x, z = getattr(a, f), getattr(b, f)
+        assert np.abs(x - z).max() < 1e-14 * np.abs(x).max(), f
