@@ -38,9 +38,33 @@ def algorithmic_bytes(kind, n1, n2, n3, elem):
         "zinv": 5 * elem * NP + 6 * elem * IP,    # 5 spectral fields -> 6 padded lines
         "xpass": 6 * elem * IP + 3 * elem * IP,   # 6 fields in, H1 H2 H3 out
         "zfwd": 3 * elem * IP + 3 * elem * NP,    # 3 padded fields -> 3 spectral
-        # H, chi, om2, 2 histories -> chi, om2, v, 2 histories, next sub-step's u1 u2 u3 o1 o3
-        "advance": (3 * elem + 64 + 80 + 5 * elem) * NP,
+        # the pencil phase's compulsory bytes: H in, chi, omega2 and two
+        # histories in and out (float64 state), the next sub-step's five
+        # velocity/vorticity fields out (192 B per mode-point mixed, 256 float64)
+        "advance": (3 * elem + 64 + 64 + 5 * elem) * NP,
     }[kind]
+
+
+# float64 store of v, which the state keeps besides chi and omega2 (it is
+# recomputable from chi, so it is not in the compulsory count above)
+V_STORE_BYTES = 16
+
+# Nominal floating-point operations per sub-step (for the FLOP/s figure):
+# 2.5 n log2 n per real two-dimensional transform of n points (six inverse,
+# three forward per plane), 20 per padded point for the products, the CFL
+# terms and the plane sums, and 560 per mode-point for the pencil sweeps (the
+# compact derivatives, the right-hand sides, the factorisations and the
+# substitutions of the six sweeps, counted without the lane pair's duplicate
+# factorisation).
+PENCIL_FLOPS_PER_MODE_POINT = 560
+
+
+def nominal_flops_per_substep(n1, n2, n3):
+    import math
+    p1, p3 = 3 * n1 // 2, 3 * n3 // 2
+    n = p1 * p3
+    fft = 9 * n2 * 2.5 * n * math.log2(n)
+    return fft + 20 * n2 * n + PENCIL_FLOPS_PER_MODE_POINT * n2 * (n1 // 2) * n3
 
 
 # Source files that make up each kernel kind; the HBM traffic measured with
@@ -98,9 +122,9 @@ def run_path(case, v, om, U1, U3, y, precision, steps, warmup):
     print(f"[bench] {precision}: plane schedule {plan}", file=sys.stderr, flush=True)
     if warmup:
         ch.step(case.dt, warmup)
-    ch.timing(True)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # the timed steps run exactly as a user's would: no per-kernel events
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
@@ -109,9 +133,17 @@ def run_path(case, v, om, U1, U3, y, precision, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
+    fields = {k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "u1", "u3", "u1mean").items()}
+    # then the same number of steps with every kernel bracketed by HIP events
+    # on the context's stream: the per-kernel durations and the roofline
+    ch.timing(True)
+    e0.record(stream)
+    ch.step(case.dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
     kern = ch.timing_read()
     ch.timing(False)
-    fields = {k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "u1", "u3", "u1mean").items()}
+    kern["_instrumented_ms"] = e0.elapsed_time(e1)
     ch.close()
     kern["_plan"] = plan
     return ms, wall, kern, fields
@@ -274,27 +306,72 @@ def c5_run(reps=5, precision="mixed"):
     del ub, uu, tau, ens, pr
     torch.cuda.empty_cache()
     G = c.n1 * c.n2 * c.n3
+    # algorithmic bytes: the three velocity coefficient fields in (float32
+    # complex on the mixed path), F(u_i) and F(u_i u_j) out (complex128 on the
+    # retained set), tau_ij out (float64 on the q grid); nominal flops: the
+    # inverse transforms of u_i to the 3/2 grid and the forward transforms of
+    # the six products (2.5 n log2 n each), the tau grid's transforms ignored
+    NP = c.n2 * (c.n1 // 2) * c.n3
+    R = (kcx + 1) * (2 * kcz + 1)
+    alg = 3 * NP * (8 if precision == "mixed" else 16) + 9 * c.n2 * R * 16 + 6 * c.n2 * q1 * q3 * 8
+    import math
+    n = (3 * c.n1 // 2) * (3 * c.n3 // 2)
+    fl = 9 * c.n2 * 2.5 * n * math.log2(n)
+    roof = {"bound": "hbm", "achieved": round(alg / (ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": alg,
+            "nominal_flop": fl, "TFLOPs": round(fl / (ms / 1e3) / 1e12, 2)}
     return {"workload": f"low-storage stage, {c.n1}x{c.n2}x{c.n3}, kc=({kcx},{kcz}), q=({q1},{q3})",
             "precision": precision, "ms_median": round(ms, 3), "ms_min": round(ms_min, 3),
+            "roofline": roof,
             "grid_points_per_s": G / (ms / 1e3),
             "enstrophy": {"ms_median": round(ms_e, 3), "ms_min": round(ms_e_min, 3),
                           "grid_points_per_s": G / (ms_e / 1e3)},
             "pressure": {"ms_median": round(ms_p, 3), "ms_min": round(ms_p_min, 3)}}
 
 
+def host_cpu():
+    """Model name of the host CPU and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count(), usable
+
+
 def cpu_baseline(case, v, om, U1, U3, y):
-    """The oracle on the host: one RK3 sub-step of the same workload, scaled to a step."""
-    from oracle import kmm
+    """The oracle on the host: one RK3 sub-step of the same workload, scaled to a
+    step, once on one thread and once with the FFTs on every usable core (the
+    banded solves are numpy array sweeps over all modes, one thread either way)."""
+    from oracle import fourier, kmm
     S = kmm.Setup(n1=case.n1, n2=case.n2, n3=case.n3, lx=case.lx, lz=case.lz, nu=1 / case.re_b,
                   dt=case.dt, mass_flux=case.mass_flux, y=y)
     st = kmm.make_state(S, v, om, U1, U3)
-    t0 = time.perf_counter()
-    kmm.substep(S, st, kmm.zero_history(S), 0)
-    t = time.perf_counter() - t0
     G = case.n1 * case.n2 * case.n3
-    return {"value": G / (3 * t), "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"one RK3 sub-step (of 3) of the {case.n1}x{case.n2}x{case.n3} workload, "
-                      f"{t:.1f} s, numpy/pocketfft single thread, scaled x3 to a step"}
+    model, ncpu, usable = host_cpu()
+    runs = {}
+    for workers in (1, usable):
+        fourier.WORKERS = workers
+        t0 = time.perf_counter()
+        kmm.substep(S, st, kmm.zero_history(S), 0)
+        runs[workers] = time.perf_counter() - t0
+    fourier.WORKERS = 1
+    t1, tn = runs[1], runs[usable]
+    sample = (f"one RK3 sub-step (of 3) of the {case.n1}x{case.n2}x{case.n3} workload, scaled x3 to a step; "
+              f"host: {model}, os.cpu_count() = {ncpu}, {usable} usable")
+    return {"value": G / (3 * tn), "unit": UNIT, "cores": usable, "kind": "oracle",
+            "sample": f"{sample}; {tn:.1f} s with the FFTs on {usable} threads",
+            "cpu_model": model, "cpu_count": ncpu,
+            "single_thread": {"value": G / (3 * t1), "cores": 1, "seconds_per_substep": round(t1, 2)},
+            "all_cores": {"value": G / (3 * tn), "cores": usable, "seconds_per_substep": round(tn, 2)}}
 
 
 def main():
@@ -367,6 +444,7 @@ def main():
     errs = {k: float(np.linalg.norm(fm[k] - f64[k]) / np.linalg.norm(f64[k])) for k in fm}
 
     plan_mixed, plan64 = kern.pop("_plan"), kern64.pop("_plan")
+    inst_ms, inst_ms64 = kern.pop("_instrumented_ms"), kern64.pop("_instrumented_ms")
     nsub = 3 * args.steps  # sub-steps in the timed region; a kernel kind may launch once per plane chunk
     # roofline of the dominant kernel of the mixed path
     dom = max(kern, key=lambda k: kern[k][0])
@@ -378,6 +456,16 @@ def main():
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
             "algorithmic_bytes_per_launch": alg * nsub // cnt, "avg_launch_ms": round(tot / cnt, 4)}
+    if dom == "advance":
+        NP = case.n2 * (case.n1 // 2) * case.n3
+        withv = (alg + V_STORE_BYTES * NP) / avg_s / 1e9
+        roof["frac_with_v_store"] = round(withv / HBM_PEAK_GBS, 4)
+    fl = nominal_flops_per_substep(case.n1, case.n2, case.n3) * 3  # per RK3 step
+    flops = {"nominal_flop_per_step": fl,
+             "mixed": {"TFLOPs": round(fl / step_ms / 1e9, 2), "peak_fp32_vector": 157.3,
+                       "frac": round(fl / step_ms / 1e9 / 157.3, 4)},
+             "fp64": {"TFLOPs": round(fl / (ms_fp64 / args.steps) / 1e9, 2), "peak_fp64_vector": 78.6,
+                      "frac": round(fl / (ms_fp64 / args.steps) / 1e9 / 78.6, 4)}}
 
     def table(kk, e):
         out = {}
@@ -396,7 +484,9 @@ def main():
                                "k^-5/3 perturbations on a Reichardt mean, dt at CFL 0.5, mixed precision",
                    "grid_points": G, "dt": case.dt},
         "fp64": {"value": G * args.steps / (ms_fp64 / 1e3), "ms_per_step": ms_fp64 / args.steps,
-                 "kernels": per_kernel64},
+                 "kernels": per_kernel64, "instrumented_ms_per_step": inst_ms64 / args.steps},
+        "instrumented_ms_per_step": inst_ms / args.steps,
+        "flops": flops,
         "plane_schedule": {"mixed": plan_mixed, "fp64": plan64},
         "mixed_vs_fp64_rel_err": errs,
         "speedup_mixed_over_fp64": ms_fp64 / ms_mixed,

@@ -14,12 +14,18 @@ back.  Conventions (readings of the paper, which does not state them):
   mode set of uh e^{i(a x_p + b z_q)}, x_p = p L1/P1, z_q = q L3/P3.
 * forward (analysis) is scaled by 1/(P1 P3) and keeps |kz| < n3/2, kx < n1/2.
 
-numpy's FFTs are the library steps; the tests pin them to brute-force DFT sums.
-Physical planes are ``f[z, x]`` (P3 rows of P1 points).
+scipy's FFTs (pocketfft) are the library steps; the tests pin them to
+brute-force DFT sums.  ``WORKERS`` threads split a batch of planes (1 unless
+a caller, such as the benchmark's all-cores CPU baseline, raises it; the
+results do not depend on it).  Physical planes are ``f[z, x]`` (P3 rows of
+P1 points).
 """
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft
+
+WORKERS = 1
 
 
 def padded_size(n):
@@ -41,13 +47,13 @@ def to_physical(uh, p1, p3):
     F = np.zeros(uh.shape[:-2] + (p3, p1 // 2 + 1), dtype=np.complex128)
     F[..., dst, :n1h] = np.swapaxes(uh, -1, -2)[..., src, :]
     # kx = 0 column: the real-signal synthesis uses its Hermitian part only
-    return np.fft.irfft2(F, s=(p3, p1)) * (p1 * p3)
+    return scipy.fft.irfft2(F, s=(p3, p1), workers=WORKERS) * (p1 * p3)
 
 
 def to_spectral(f, n1, n3):
     """Real f[..., z, x] -> uh[..., kx, kz] (kx < n1/2, |kz| < n3/2), scaled 1/(P1 P3)."""
     p3, p1 = f.shape[-2], f.shape[-1]
-    F = np.fft.rfft2(f) / (p1 * p3)
+    F = scipy.fft.rfft2(f, workers=WORKERS) / (p1 * p3)
     src, dst = _zslots(n3, p3)
     out = np.zeros(f.shape[:-2] + (n1 // 2, n3), dtype=np.complex128)
     out[..., :, src] = np.swapaxes(F[..., dst, : n1 // 2], -1, -2)
