@@ -75,7 +75,7 @@ struct chn_ctx {
   double* SU[8] = {};
   double* junk = nullptr;  // one lane-indexed row that absorbs history writes nobody reads
   double* rowsum = nullptr;
-  float* rowcfl = nullptr;
+  double* rowcfl = nullptr;
   // homogeneous solutions and Helmholtz factor tables of the three sub-steps
   // for the time step htab_dt, and the Poisson factor table (SU[4..7]).  The
   // tables of sub-steps 1 and 2 share S[3], S[4], S[6], S[7] with the filter
@@ -162,7 +162,7 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
     hm[k] = D(po ? 0 : 4 * M);
   }
   double* rowsum = D(2 * (size_t)n2 * p3);
-  float* rowcfl = reinterpret_cast<float*>(cv.take(sizeof(float) * (size_t)n2 * p3));
+  double* rowcfl = D((size_t)n2 * p3);
   double* tabs = D((size_t)n2 * (4 * 7 + 3 * 3 + 3 * 4 + 4));
   void* tw1 = cv.take(te * (size_t)p1);
   void* tw3 = cv.take(te * (size_t)p3);
@@ -836,7 +836,7 @@ template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
       for (int b = 0; b < nbz; ++b) wz.push_back(make_int4(c, b, y, 0));
     for (int y = 0; y < x->n2; ++y)
       for (int b = 0; b < (x->p3 + e->rz - 1) / e->rz; ++b) wx.push_back(make_int4(c, b, y, 0));
-    const int nb = (int)((2 * (size_t)x->M + 255) / 256);
+    const int nb = chn::advance_blocks(x->M);
     wa.push_back(make_int4(c, 0, 0, 1));  // mean-mode workgroup
     for (int b = 0; b < nb; ++b) wa.push_back(make_int4(c, b, 0, 0));
   }

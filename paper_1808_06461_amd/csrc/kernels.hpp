@@ -34,7 +34,7 @@ template <typename T> struct XpassArgs {
   PlaneDims d;
   int lstride;
   double* rowsum;      // [2][n2][p3] sums over x of H1 and H3
-  float* rowcfl;       // [n2][p3] max over x of |u1|/dx + |u2|/dy + |u3|/dz
+  double* rowcfl;      // [n2][p3] max over x of |u1|/dx + |u2|/dy + |u3|/dz
   double inv_dx, inv_dz;
   const double* inv_dy;  // [n2]
   int rows;              // rows per workgroup: 2, 4, 8 (3 rows lines in LDS) or 1 (long rows)
@@ -186,8 +186,8 @@ template <typename TH, typename TP> struct AdvanceArgs {
   double* nchi_wr;
   double* nom_wr;
   size_t hist_rs, hist_ws;
-  double* S[8];               // lane-indexed scratch [n2][2M]
-  // mode-indexed [n2][M] factor tables (k_homog): SU[0..3] the Helmholtz
+  double* S[8];               // scratch, complex [n2][M] (the lane pairs of k_homog: [n2][2 M/2])
+  // per-pair [n2][Q] factor tables (k_homog): SU[0..3] the Helmholtz
   // factor rows of this sub-step, SU[4..7] the Poisson ones, each
   // {1/pivot, u1, u2, u3} of the upward / downward factorisation
   const double* SU[8];
@@ -203,11 +203,13 @@ template <typename TH, typename TP> struct AdvanceArgs {
   double* mean_out;           // [0]: mean pressure gradient of the sub-step
   double mass_flux;
   double dt, nu, al, be, ga, ze;
-  // homogeneous solutions of this sub-step (k_homog): lane c holds the one
-  // with chi = 1 at wall c (c = 0 lower, 1 upper)
-  const double* hc;           // chi_h, lane-indexed [n2][2M]
-  const double* hm;           // [M][4]: D1 v_h at (lower, upper) wall for c = 0, then c = 1
-  const double* hw;           // lane-indexed [n2][2M]: lane c holds w_c, D1 v_p(wall c) = w_c . r_chi
+  // per-dt tables of this sub-step (k_homog), one entry per (kx, +-kz) pair
+  // q = kx n3/2 + |kz| (Q = M/2 pairs): the SU factor rows are [n2][Q];
+  // the homogeneous solution with chi = 1 at wall c is entry c of a (lower,
+  // upper) pair
+  const double* hc;           // chi_h, [n2][Q][2]
+  const double* hm;           // [Q][4]: D1 v_h at (lower, upper) wall for c = 0, then c = 1
+  const double* hw;           // [n2][Q][2]: w_c, D1 v_p(wall c) = w_c . r_chi
   // instability guard (common.hpp): every workgroup leaves the state untouched
   // when the fail word is set or the sub-step's CFL (word 0 times dt) is not
   // finite or above cfl_limit; the mean workgroup then records the sub-step
@@ -222,9 +224,10 @@ template <typename TH, typename TP> struct AdvanceArgs {
 struct HomogArgs {
   PencilGeom g;
   double nu, dt, be[3];
-  double* hc[3];              // per sub-step, lane-indexed [n2][2M]
-  double* hw[3];              // per sub-step, lane-indexed [n2][2M] (wall-derivative vectors w_c)
-  double* hm[3];              // per sub-step [M][4]
+  // tables per (kx, +-kz) pair, Q = M/2 of them (see AdvanceArgs)
+  double* hc[3];              // per sub-step, [n2][Q][2]
+  double* hw[3];              // per sub-step, [n2][Q][2] (wall-derivative vectors w_c)
+  double* hm[3];              // per sub-step [Q][4]
   double* S0;                 // lane-indexed scratch [n2][2M]
   double* S1;
   double* T;                  // lane-indexed scratch [n2][2M] (A2^T E P^-T d_c)
@@ -245,7 +248,7 @@ struct ChiArgs {
 
 struct InfoArgs {
   PencilGeom g;
-  const float* rowcfl;        // [n2][p3]
+  const double* rowcfl;       // [n2][p3]
   int p3;
   const double* U1;
   double dt, nu;
@@ -285,6 +288,8 @@ template <typename T> hipError_t launch_plane_batch(const BatchPlan<T>& b, hipSt
 template <typename T>
 hipError_t launch_advance_batch(const AdvanceArgs<T, T>* d, const int4* w, int nblocks, hipStream_t st);
 
+// workgroups of k_advance for M modes per plane (the mean workgroup not counted)
+int advance_blocks(int M);
 template <typename TP> hipError_t launch_recover(const RecoverArgs<TP>& a, hipStream_t st);
 template <typename TH, typename TP> hipError_t launch_advance(const AdvanceArgs<TH, TP>& a, hipStream_t st);
 hipError_t launch_homog(const HomogArgs& a, hipStream_t st);

@@ -52,12 +52,12 @@ __device__ __forceinline__ Lane lane_setup(const PencilGeom& g, int bx) {
   return L;
 }
 
-template <int N> __device__ __forceinline__ void push_back(double (&w)[N], double v) {
+template <typename T, int N> __device__ __forceinline__ void push_back(T (&w)[N], T v) {
 #pragma unroll
   for (int k = 0; k < N - 1; ++k) w[k] = w[k + 1];
   w[N - 1] = v;
 }
-template <int N> __device__ __forceinline__ void push_front(double (&w)[N], double v) {
+template <typename T, int N> __device__ __forceinline__ void push_front(T (&w)[N], T v) {
 #pragma unroll
   for (int k = N - 1; k > 0; --k) w[k] = w[k - 1];
   w[0] = v;
@@ -450,18 +450,113 @@ __device__ void mean_block(const AdvanceArgs<TH, TP>& a) {
 }
 
 // ---------------------------------------------------------------- advance
+// One Fourier mode per lane, its real and imaginary parts together (the
+// banded matrices are real, so both go through the same factorisations):
+// every wall-normal row of a field is one 16-byte access per lane, 1 KB
+// contiguous per wave.  Lanes l and l + 32 of a wave hold the modes (kx, kz)
+// and (kx, -kz) of one pair; they share k^2, so every per-dt table (factor
+// rows, homogeneous solutions, wall-derivative vectors) is stored per pair
+// and the two lanes read the same entries.  Pair q = kx n3/2 + p,
+// p = 0 .. n3/2 - 1, holds kz = +p (slot p) and kz = -p (slot n3 - p; for
+// p = 0 the Nyquist slot n3/2, which carries no mode).
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ dv2 zi(dv2 z) { return (dv2){-z.y, z.x}; }  // i z
+__device__ __forceinline__ dv2 zz() { return (dv2){0.0, 0.0}; }
+
+// complex element at a byte offset from a wave-uniform row base
+// (non-temporal, like the real accesses of the sweeps)
+__device__ __forceinline__ dv2 ldz(const double* base, unsigned boff) {
+  return __builtin_nontemporal_load(reinterpret_cast<const dv2*>(reinterpret_cast<const char*>(base) + boff));
+}
+__device__ __forceinline__ dv2 ldz(const float* base, unsigned boff) {
+  const fv2 f = __builtin_nontemporal_load(reinterpret_cast<const fv2*>(reinterpret_cast<const char*>(base) + boff));
+  return __builtin_convertvector(f, dv2);
+}
+__device__ __forceinline__ void stz(double* base, unsigned boff, dv2 v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<dv2*>(reinterpret_cast<char*>(base) + boff));
+}
+__device__ __forceinline__ void stz(float* base, unsigned boff, dv2 v) {
+  __builtin_nontemporal_store(__builtin_convertvector(v, fv2),
+                              reinterpret_cast<fv2*>(reinterpret_cast<char*>(base) + boff));
+}
+// complex element in its stored precision (converted where it is used)
+template <typename T> struct NV2;
+template <> struct NV2<double> { using t = dv2; };
+template <> struct NV2<float> { using t = fv2; };
+template <typename T> __device__ __forceinline__ typename NV2<T>::t ldr(const T* base, unsigned boff) {
+  using V = typename NV2<T>::t;
+  return __builtin_nontemporal_load(reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + boff));
+}
+__device__ __forceinline__ dv2 cvt(dv2 v) { return v; }
+__device__ __forceinline__ dv2 cvt(fv2 v) { return __builtin_convertvector(v, dv2); }
+__device__ __forceinline__ dv2 dot7z(const double* __restrict__ b, const dv2 (&w)[7]) {
+  dv2 r = zz();
+#pragma unroll
+  for (int o = 0; o < 7; ++o) r += b[o] * w[o];
+  return r;
+}
+__device__ __forceinline__ dv2 elim3z(dv2 r, const double* __restrict__ l, const dv2 (&yb)[3]) {
+  return r - l[0] * yb[0] - l[1] * yb[1] - l[2] * yb[2];
+}
+__device__ __forceinline__ dv2 back3z(dv2 y, const double* __restrict__ U, const dv2 (&xb)[3]) {
+  return (y - U[1] * xb[0] - U[2] * xb[1] - U[3] * xb[2]) * U[0];
+}
+__device__ __forceinline__ void shift3(dv2 (&b)[3], dv2 x) {
+  b[0] = b[1];
+  b[1] = b[2];
+  b[2] = x;
+}
+__device__ __forceinline__ void push_xz(dv2 (&xb)[3], dv2 x) {
+  xb[2] = xb[1];
+  xb[1] = xb[0];
+  xb[0] = x;
+}
+
+struct PairLane {
+  unsigned m, q;     // mode slot in [n2][M] arrays, pair in [n2][Q] tables
+  bool act, live, wph;
+  double A, B, k2, ik2;
+};
+// Lane gl of the launch: wave gl / 64 holds pairs 32 (gl / 64) .. + 31;
+// lanes 0..31 of the wave the +kz modes, 32..63 the -kz ones.
+__device__ __forceinline__ PairLane pair_lane(const PencilGeom& g, int bx) {
+  PairLane L;
+  const int gl = bx * blockDim.x + threadIdx.x;
+  const int n3h = g.n3 >> 1, Q = g.n1h * n3h;
+  int q = 32 * (gl >> 6) + (gl & 31);
+  const bool neg = (gl >> 5) & 1;
+  L.act = q < Q;
+  if (!L.act) q = Q - 1;  // in-bounds reads; nothing is written
+  const int kx = q / n3h, p = q - kx * n3h;
+  const int slot = neg ? (p == 0 ? n3h : g.n3 - p) : p;
+  L.q = q;
+  L.m = kx * g.n3 + slot;
+  L.A = g.ka * kx;
+  L.B = g.kb * (neg ? -p : p);
+  L.k2 = L.A * L.A + L.B * L.B;
+  L.live = L.act && slot != n3h && L.m != 0;
+  L.wph = L.act && L.m != 0;  // the (0,0) phase entries come from the mean block
+  L.ik2 = L.live ? 1.0 / L.k2 : 0.0;
+  return L;
+}
+
 // One sub-step of the pencil phase, fused with the recovery of the next
 // sub-step's velocities and vorticities:
 //   S1 down : G = i(a H1 + b H3); eliminate A1 (dG) = B1 G
-//   S2 up   : finish dG; N_chi, N_omega2; implicit right-hand sides (lag 3);
-//             Helmholtz factor on the fly; eliminate chi_p, omega2; the
-//             wall values of D1 v_p as dot products with the chi right-hand
-//             side, then the 2x2 influence system (Appendix B)
+//   S2 up   : finish dG; N_chi, N_omega2, histories; implicit right-hand
+//             sides of chi and omega2 (lag 3); Helmholtz factor on the fly;
+//             eliminate chi_p, omega2; the wall values of D1 v_p as dot
+//             products with the chi right-hand side, then the 2x2 influence
+//             system (Appendix B)
 //   S3 down : finish chi_p, omega2; chi = chi_p + c_lo, c_hi homogeneous;
 //             Poisson rhs (lag 3); P factor on the fly; eliminate v
 //   S4 up   : finish v; eliminate A1 (dv) = B1 v
 //   R2 down : finish dv; u1, u3 by continuity; eliminate A1 (du) = B1 u
 //   R3 up   : finish du1, du3; omega1 = du3 - i b v, omega3 = i a v - du1
+// Scratch rows between sweeps are float64; the histories N_old are stored in
+// the phase precision TP (float32 on the mixed path: they are products of
+// the float32 transforms, rounded once after their float64 assembly).
 template <typename TH, typename TP>
 __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int bx,
                                              // read-only tables as noalias parameters, so the wave-uniform
@@ -470,134 +565,137 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
                                              const double* __restrict__ B2, const double* __restrict__ L1d,
                                              const double* __restrict__ U1d, const double* __restrict__ L1u,
                                              const double* __restrict__ U1u) {
-  constexpr int D = 5, D2 = 3, D3 = 3;
+  constexpr int D = 5, DS1 = 8, D2 = 2, D3 = 3;
   if (unstable(a)) return;
   const PencilGeom& g = a.g;
-  const Lane L = lane_setup(g, bx);
+  const PairLane L = pair_lane(g, bx);
   const int n = g.n2;
-  const size_t st = 2 * (size_t)g.M;
-  const size_t M = g.M;
-  const size_t col = L.col;
+  const size_t M = g.M, Q = M / 2;
   const double cb = a.dt * a.be * a.nu;
   const double f1 = 1.0 - a.al * a.dt * a.nu * L.k2;
   const double f2 = a.al * a.dt * a.nu;
   const double dga = a.dt * a.ga, dze = a.dt * a.ze;
   const double hk = 1.0 + cb * L.k2;
-  const bool wph = L.act && L.m != 0;  // the (0,0) phase entries come from the mean block
   // Row bases are wave-uniform (scalar registers); per-lane offsets are
   // 32-bit byte offsets, so every access is one scalar base + one shared VGPR.
-  const unsigned ocol = 2u * (unsigned)L.m + (1u - (unsigned)L.c);  // the other component
-  const unsigned bcol = 8u * (unsigned)col, bocol = 8u * ocol, bm = 8u * (unsigned)L.m;
-  const unsigned hcol = (unsigned)sizeof(TH) * (unsigned)col, hocol = (unsigned)sizeof(TH) * ocol;
-  const unsigned pcol = (unsigned)sizeof(TP) * (unsigned)col;
-  auto LR = [&](auto* p, int i) { return p + (size_t)i * st; };       // lane-indexed [n2][2M]
-  auto MR = [&](auto* p, int i) { return p + (size_t)i * M; };        // mode-indexed [n2][M]
-  auto HR = [&](const TH* p, int i) { return p + 2 * (size_t)i * M; };
-  // histories N_old: rows read at stride hist_rs, written at hist_ws (0: one row)
-  auto HRD = [&](const double* p, int i) { return p + (size_t)i * a.hist_rs; };
-  auto HWR = [&](double* p, int i) { return p + (size_t)i * a.hist_ws; };
+  const unsigned zo = 16u * L.m;                                 // complex float64 rows [n2][M]
+  const unsigned ho = 2u * (unsigned)sizeof(TH) * L.m;           // complex TH rows
+  const unsigned po = 2u * (unsigned)sizeof(TP) * L.m;           // complex TP rows
+  const unsigned qo = 8u * L.q, qo2 = 16u * L.q;                 // pair tables: one value, (lo, hi)
+  auto ZR = [&](auto* p, int i) { return p + 2 * (size_t)i * M; };   // row i of a complex [n2][M] array
+  auto QR = [&](const double* p, int i) { return p + (size_t)i * Q; };       // [n2][Q]
+  auto Q2R = [&](const double* p, int i) { return p + 2 * (size_t)i * Q; };  // [n2][Q][2]
+  // histories N_old (phase precision): rows read at stride hist_rs, written
+  // at hist_ws (0: one row)
+  auto HRD = [&](const TP* p, int i) { return p + (size_t)i * a.hist_rs; };
+  auto HWR = [&](TP* p, int i) { return p + (size_t)i * a.hist_ws; };
+  const TP* nchi_rd = reinterpret_cast<const TP*>(a.nchi_rd);
+  const TP* nom_rd = reinterpret_cast<const TP*>(a.nom_rd);
+  TP* nchi_wr = reinterpret_cast<TP*>(a.nchi_wr);
+  TP* nom_wr = reinterpret_cast<TP*>(a.nom_wr);
+  // Scratch rows between sweeps stay float64 on both paths: an eliminated
+  // right-hand side of the A1 solves rounded to float32 loses about four
+  // digits in the back-substitution (cond(A1) ~ 1e4), and the influence
+  // coefficients amplify that error much further at the wall rows of chi.
+  double* S0r = a.S[0];
+  double* S1r = a.S[1];
+  double* S2r = a.S[2];
 
-  // G = i(a H1 + b H3): lane c needs the other component (oc) of H1 and H3
-  const double sg = L.c == 0 ? -1.0 : 1.0;
-  auto gval = [&](double h1o, double h3o) -> double {
-    if (!L.live) return 0.0;
-    return sg * (L.A * h1o + L.B * h3o);
-  };
-
-  // ---- S1 (down): G = i(a H1 + b H3), eliminate A1 (dG) = B1 G (look-ahead 3);
-  // N_omega2 = i b H1 - i a H3 and the omega2 right-hand side
-  // A2 q + f2 B2 omega2, q = f1 omega2 + dt (gamma N + zeta N_old), accumulated
-  // as columns arrive (acc[k] is row t + k); history N_omega2
+  // ---- S1 (down): G = i(a H1 + b H3), eliminate A1 (dG) = B1 G (look-ahead 3)
   {
-    struct B { double h1, h3, om, noo; };
-    double w[7] = {0, 0, 0, 0, 0, 0, 0};
-    double yb[3] = {0, 0, 0};
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    struct B { typename NV2<TH>::t h1, h3; };
+    dv2 w[7], yb[3];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) w[k] = zz();
+    yb[0] = yb[1] = yb[2] = zz();
     auto loadcol = [&](int j, B& b) {  // rows j >= n are clamped (used only for j < n)
       j = min(j, n - 1);
-      b.h1 = (double)ldn(HR(a.H[0], j), hocol);
-      b.h3 = (double)ldn(HR(a.H[2], j), hocol);
-      b.om = ldn(LR(a.om2, j), bcol);
-      b.noo = ldn(HRD(a.nom_rd, j), bcol);
+      b.h1 = ldr(ZR(a.H[0], j), ho);
+      b.h3 = ldr(ZR(a.H[2], j), ho);
     };
-    auto column = [&](int j, int tb, const B& b) -> double {
-      const double nom = L.live ? sg * (L.B * b.h1 - L.A * b.h3) : 0.0;  // i b H1 - i a H3
-      const double q = f1 * b.om + dga * nom + dze * b.noo;
-      if (L.act) stn(HWR(a.nom_wr, j), bcol, nom);
-#pragma unroll
-      for (int k = 0; k < 7; ++k) {
-        const int r = tb + k, o = j - r + 3;
-        if (o >= 0 && o <= 6 && r >= 1 && r <= n - 2) acc[k] += A2[r * 7 + o] * q + f2 * B2[r * 7 + o] * b.om;
-      }
-      return gval(b.h1, b.h3);
-    };
+    auto gval = [&](const B& b) -> dv2 { return L.live ? zi(L.A * cvt(b.h1) + L.B * cvt(b.h3)) : zz(); };
     for (int j = 0; j < 3; ++j) {
       B b;
       loadcol(j, b);
-      w[3 + j] = column(j, 0, b);
+      w[3 + j] = gval(b);
     }
-    pipeline<D, B>(
+    pipeline<DS1, B>(
         n, [&](int t, B& b) { loadcol(t + 3, b); },
         [&](int t, B& b) {
-          w[6] = (t + 3 < n) ? column(t + 3, t, b) : 0.0;
-          const double yi = elim3(dot7(B1 + t * 7, w), L1d + t * 3, yb);
-          if (L.act) {
-            stn(LR(a.S[0], t), bcol, yi);
-            stn(LR(a.S[2], t), bcol, acc[0]);  // omega2 rhs of row t (0 on the wall rows)
-          }
-          yb[0] = yb[1];
-          yb[1] = yb[2];
-          yb[2] = yi;
-          push_back(w, 0.0);
-          push_back(acc, 0.0);
+          w[6] = (t + 3 < n) ? gval(b) : zz();
+          const dv2 yi = elim3z(dot7z(B1 + t * 7, w), L1d + t * 3, yb);
+          if (L.act) stz(ZR(S0r, t), zo, yi);
+          shift3(yb, yi);
+          push_back(w, zz());
         });
   }
-  // ---- S2 (up): finish dG; N_chi = -dG - k^2 H2 and the chi right-hand side
-  // (acc[k] is row i + 3 - k, complete when column i - ... arrives: lag 3);
-  // Helmholtz matrix factored on the fly; eliminate chi_p and omega2.  The
-  // wall values of D1 v_p are linear in the chi right-hand side r:
-  // D1 v_p(wall c) = w_c . r with w_c tabulated per sub-step (k_homog), so the
-  // influence coefficients c_lo, c_hi are known when this sweep ends.
-  double clo_c = 0.0, chi_c = 0.0;  // c_lo, c_hi of this lane's component
+  // ---- S2 (up): finish dG; N_chi = -dG - k^2 H2 and N_omega2 = i b H1 - i a H3;
+  // the right-hand sides A2 q + f2 B2 x, q = f1 x + dt (gamma N + zeta N_old),
+  // of chi and omega2 accumulated as columns arrive (acc[k] is row i + 3 - k,
+  // complete at lag 3; zero on the wall rows); histories; Helmholtz matrix
+  // factored on the fly; eliminate chi_p and omega2.  The wall values of
+  // D1 v_p are linear in the chi right-hand side r: D1 v_p(wall c) = w_c . r
+  // with w_c tabulated per sub-step (k_homog), so the influence coefficients
+  // c_lo, c_hi are known when this sweep ends.
+  dv2 clo_c = zz(), chi_c = zz();
   {
-    struct B { double s0, h2, chi, nco, rom, w; };
-    double xb[3] = {0, 0, 0};
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    struct B {
+      typename NV2<TP>::t nco, noo;
+      typename NV2<TH>::t h1, h2, h3;
+      dv2 s0, chi, om, w;
+    };
+    dv2 xb[3], ac[7], ao[7], ycb[3], yob[3];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) ac[k] = ao[k] = zz();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xb[k] = ycb[k] = yob[k] = zz();
     double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    double ycb[3] = {0, 0, 0}, yob[3] = {0, 0, 0};
-    double glo = 0.0, ghi = 0.0;
+    dv2 glo = zz(), ghi = zz();
     pipeline<D2, B>(
         n + 3,
         [&](int t, B& b) {  // rows clamped; the step uses them only inside the line
           const int i = max(n - 1 - t, 0), r = min(max(n + 2 - t, 0), n - 1);
-          b.s0 = ldn(LR(a.S[0], i), bcol);
-          b.h2 = (double)ldn(HR(a.H[1], i), hcol);
-          b.chi = ldn(LR(a.chi, i), bcol);
-          b.nco = ldn(HRD(a.nchi_rd, i), bcol);
-          b.rom = ldn(LR(a.S[2], r), bcol);
-          b.w = ldn(LR(a.hw, r), bcol);
+          b.s0 = ldz(ZR(S0r, i), zo);
+          b.h1 = ldr(ZR(a.H[0], i), ho);
+          b.h2 = ldr(ZR(a.H[1], i), ho);
+          b.h3 = ldr(ZR(a.H[2], i), ho);
+          b.chi = ldz(ZR(a.chi, i), zo);
+          b.om = ldz(ZR(a.om2, i), zo);
+          b.nco = ldr(HRD(nchi_rd, i), po);
+          b.noo = ldr(HRD(nom_rd, i), po);
+          b.w = ldz(Q2R(a.hw, r), qo2);
         },
         [&](int t, B& b) {
           const int i = n - 1 - t;
           if (i >= 0) {
-            const double dG = back3(b.s0, U1d + i * 4, xb);
-            push_x(xb, dG);
-            const double nchi = L.live ? -dG - L.k2 * b.h2 : 0.0;
-            const double q = f1 * b.chi + dga * nchi + dze * b.nco;
-            if (L.act) stn(HWR(a.nchi_wr, i), bcol, nchi);
+            const dv2 dG = back3z(b.s0, U1d + i * 4, xb);
+            push_xz(xb, dG);
+            const dv2 h1 = cvt(b.h1), h3 = cvt(b.h3);
+            const dv2 nchi = L.live ? -dG - L.k2 * cvt(b.h2) : zz();
+            const dv2 nom = L.live ? zi(L.B * h1 - L.A * h3) : zz();
+            const dv2 qc = f1 * b.chi + dga * nchi + dze * cvt(b.nco);
+            const dv2 qo = f1 * b.om + dga * nom + dze * cvt(b.noo);
+            if (L.act) {
+              stz(HWR(nchi_wr, i), po, nchi);
+              stz(HWR(nom_wr, i), po, nom);
+            }
 #pragma unroll
             for (int k = 0; k < 7; ++k) {
               const int r = i + 3 - k;
-              if (r >= 1 && r <= n - 2) acc[k] += A2[r * 7 + k] * q + f2 * B2[r * 7 + k] * b.chi;
+              if (r >= 1 && r <= n - 2) {
+                const double a2 = A2[r * 7 + k], b2 = f2 * B2[r * 7 + k];
+                ac[k] += a2 * qc + b2 * b.chi;
+                ao[k] += a2 * qo + b2 * b.om;
+              }
             }
           }
           const int r = i + 3;
           if (r <= n - 1) {
             // the factor rows themselves are tabulated per sub-step (k_homog)
-            double m7[7], lm[3], rc = acc[0], ro = b.rom;
-            const double wo = __shfl_xor(b.w, 1);  // lane c holds w of wall c
-            glo = fma(L.c == 0 ? b.w : wo, rc, glo);
-            ghi = fma(L.c == 0 ? wo : b.w, rc, ghi);
+            double m7[7], lm[3];
+            dv2 rc = ac[0], ro = ao[0];
+            glo += b.w.x * rc;  // (w_lo, w_hi) of row r
+            ghi += b.w.y * rc;
             helm_row(m7, A2 + r * 7, B2 + r * 7, r == 0 || r == n - 1, hk, cb);
             factor_up(m7, uh, lm);
 #pragma unroll
@@ -607,26 +705,27 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             }
             const double u0 = 1.0 / m7[3];
             if (L.act) {
-              stn(LR(a.S[1], r), bcol, rc);
-              stn(LR(a.S[2], r), bcol, ro);
+              stz(ZR(a.S[1], r), zo, rc);
+              stz(ZR(a.S[2], r), zo, ro);
             }
             push_u(uh, u0, m7[2], m7[1], m7[0]);
-            ycb[0] = ycb[1]; ycb[1] = ycb[2]; ycb[2] = rc;
-            yob[0] = yob[1]; yob[1] = yob[2]; yob[2] = ro;
+            shift3(ycb, rc);
+            shift3(yob, ro);
           }
-          push_back(acc, 0.0);
+          push_back(ac, zz());
+          push_back(ao, zz());
         });
     // 2x2 influence system: D1 v = 0 at both walls, with the wall derivatives
     // of the homogeneous v (tabulated)
-    const double* hm = a.hm + 4 * (size_t)L.m;
+    const double* hm = a.hm + 4 * (size_t)L.q;
     const double m00 = hm[0];  // lower-wall homogeneous solution, D1 at the lower wall
     const double m10 = hm[1];  // ... at the upper wall
     const double m01 = hm[2];  // upper-wall homogeneous solution, lower wall
     const double m11 = hm[3];
     if (L.live) {
       const double det = m00 * m11 - m01 * m10;
-      clo_c = (-glo * m11 + ghi * m01) / det;
-      chi_c = (-ghi * m00 + glo * m10) / det;
+      clo_c = (m01 * ghi - m11 * glo) / det;
+      chi_c = (m10 * glo - m00 * ghi) / det;
     }
   }
   // ---- S3 (down): finish chi_p and omega2; chi = chi_p + c_lo chi_lo +
@@ -634,34 +733,34 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
   // A2 chi (lag 3), Poisson matrix factored on the fly; eliminate v.  The
   // Poisson step is linear, so this v is v_p + c_lo v_lo + c_hi v_hi.
   {
-    struct B { double u[4]; double s1, s2, hc; };
-    double xcb[3] = {0, 0, 0}, xob[3] = {0, 0, 0};
-    double wch[7] = {0, 0, 0, 0, 0, 0, 0};
+    struct B { double u[4]; dv2 s1, s2, hc; };
+    dv2 xcb[3], xob[3], wch[7], yvb[3];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) wch[k] = zz();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xcb[k] = xob[k] = yvb[k] = zz();
     double uh[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-    double yvb[3] = {0, 0, 0};
     pipeline<D3, B>(
         n + 3,
         [&](int i, B& b) {
           i = min(i, n - 1);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) b.u[k] = ldn(MR(a.SU[k], i), bm);
-          b.s1 = ldn(LR(a.S[1], i), bcol);
-          b.s2 = ldn(LR(a.S[2], i), bcol);
-          b.hc = ldn(LR(a.hc, i), bcol);
+          for (int k = 0; k < 4; ++k) b.u[k] = ldn(QR(a.SU[k], i), qo);
+          b.s1 = ldz(ZR(a.S[1], i), zo);
+          b.s2 = ldz(ZR(a.S[2], i), zo);
+          b.hc = ldz(Q2R(a.hc, i), qo2);
         },
         [&](int i, B& b) {
-          double cn = 0.0;
+          dv2 cn = zz();
           if (i < n) {
-            const double cp = back3(b.s1, b.u, xcb);
-            const double om = back3(b.s2, b.u, xob);
-            push_x(xcb, cp);
-            push_x(xob, om);
-            const double hco = __shfl_xor(b.hc, 1);  // lane c holds chi_h of wall c
-            const double hlo = L.c == 0 ? b.hc : hco, hhi = L.c == 0 ? hco : b.hc;
-            cn = L.live ? cp + clo_c * hlo + chi_c * hhi : 0.0;
+            const dv2 cp = back3z(b.s1, b.u, xcb);
+            const dv2 om = back3z(b.s2, b.u, xob);
+            push_xz(xcb, cp);
+            push_xz(xob, om);
+            cn = L.live ? cp + b.hc.x * clo_c + b.hc.y * chi_c : zz();  // hc = (chi_lo, chi_hi) of row i
             if (L.act) {
-              stn(LR(a.om2, i), bcol, L.live ? om : 0.0);
-              stn(LR(a.chi, i), bcol, cn);
+              stz(ZR(a.om2, i), zo, L.live ? om : zz());
+              stz(ZR(a.chi, i), zo, cn);
             }
           }
           push_back(wch, cn);
@@ -669,84 +768,83 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           if (r >= 0) {
             // the Poisson factor rows are tabulated once (k_homog)
             const bool wall = r == 0 || r == n - 1;
-            double p7[7], lm[3], rv = 0.0;
-            if (!wall) {
-#pragma unroll
-              for (int o = 0; o < 7; ++o) rv += A2[r * 7 + o] * wch[o];
-            }
+            double p7[7], lm[3];
+            dv2 rv = zz();
+            if (!wall) rv = dot7z(A2 + r * 7, wch);
             pois_row(p7, A2 + r * 7, B2 + r * 7, wall, L.k2);
             factor_down(p7, uh, lm);
 #pragma unroll
             for (int d = 3; d >= 1; --d) rv -= lm[3 - d] * yvb[3 - d];
             const double u0 = 1.0 / p7[3];
-            if (L.act) stn(LR(a.S[5], r), bcol, rv);
+            if (L.act) stz(ZR(a.S[5], r), zo, rv);
             push_u(uh, u0, p7[4], p7[5], p7[6]);
-            yvb[0] = yvb[1]; yvb[1] = yvb[2]; yvb[2] = rv;
+            shift3(yvb, rv);
           }
         });
   }
   // ---- S4 (up): finish v; eliminate A1 (dv) = B1 v upward (lag 3)
   {
-    struct B { double u[4]; double s5; };
-    double xvb[3] = {0, 0, 0};
-    double wv[7] = {0, 0, 0, 0, 0, 0, 0};
-    double yb[3] = {0, 0, 0};
+    struct B { double u[4]; dv2 s5; };
+    dv2 xvb[3], wv[7], yb[3];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) wv[k] = zz();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xvb[k] = yb[k] = zz();
     pipeline<D, B>(
         n + 3,
         [&](int t, B& b) {
           const int r = max(n - 1 - t, 0);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) b.u[k] = ldn(MR(a.SU[4 + k], r), bm);
-          b.s5 = ldn(LR(a.S[5], r), bcol);
+          for (int k = 0; k < 4; ++k) b.u[k] = ldn(QR(a.SU[4 + k], r), qo);
+          b.s5 = ldz(ZR(a.S[5], r), zo);
         },
         [&](int t, B& b) {
           const int i = n - 1 - t;
-          double vn = 0.0;
+          dv2 vn = zz();
           if (i >= 0) {
-            vn = back3(b.s5, b.u, xvb);
-            push_x(xvb, vn);
-            if (L.act) stn(LR(a.v, i), bcol, vn);
-            if (wph) stn(LR(a.ph[1], i), pcol, (TP)vn);
+            vn = back3z(b.s5, b.u, xvb);
+            push_xz(xvb, vn);
+            if (L.act) stz(ZR(a.v, i), zo, vn);
+            if (L.wph) stz(ZR(a.ph[1], i), po, vn);
           }
           push_front(wv, vn);
           const int r = i + 3;
           if (r <= n - 1) {
-            const double yr = elim3(dot7(B1 + r * 7, wv), L1u + r * 3, yb);
-            if (L.act) stn(LR(a.S[0], r), bcol, yr);
-            yb[0] = yb[1];
-            yb[1] = yb[2];
-            yb[2] = yr;
+            const dv2 yr = elim3z(dot7z(B1 + r * 7, wv), L1u + r * 3, yb);
+            if (L.act) stz(ZR(S0r, r), zo, yr);
+            shift3(yb, yr);
           }
         });
   }
   // ---- R2 (down): finish dv; u1, u3 by continuity; eliminate A1 (du) = B1 u
   // downward (lag 3)
   {
-    struct B { double s0, om; };  // om: the other component of omega2
-    double xb[3] = {0, 0, 0};
-    double w1[7] = {0, 0, 0, 0, 0, 0, 0}, w3[7] = {0, 0, 0, 0, 0, 0, 0};
-    double y1b[3] = {0, 0, 0}, y3b[3] = {0, 0, 0};
+    struct B { dv2 s0, om; };
+    dv2 xb[3], w1[7], w3[7], y1b[3], y3b[3];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) w1[k] = w3[k] = zz();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xb[k] = y1b[k] = y3b[k] = zz();
     pipeline<D, B>(
         n + 3,
         [&](int i, B& b) {
           i = min(i, n - 1);
-          b.s0 = ldn(LR(a.S[0], i), bcol);
-          b.om = ldn(LR(a.om2, i), bocol);
+          b.s0 = ldz(ZR(S0r, i), zo);
+          b.om = ldz(ZR(a.om2, i), zo);
         },
         [&](int i, B& b) {
-          double u1 = 0.0, u3 = 0.0;
+          dv2 u1 = zz(), u3 = zz();
           if (i < n) {
-            const double dv = back3(b.s0, U1u + i * 4, xb);
-            push_x(xb, dv);
-            const double dvo = __shfl_xor(dv, 1);
+            const dv2 dv = back3z(b.s0, U1u + i * 4, xb);
+            push_xz(xb, dv);
             if (L.live) {
-              // u1 = i(a dv - b omega2)/k^2, u3 = i(b dv + a omega2)/k^2 (dvo, om: other component)
-              u1 = sg * (L.A * dvo - L.B * b.om) * L.ik2;
-              u3 = sg * (L.B * dvo + L.A * b.om) * L.ik2;
+              // u1 = i(a dv - b omega2)/k^2, u3 = i(b dv + a omega2)/k^2
+              u1 = zi(L.A * dv - L.B * b.om) * L.ik2;
+              u3 = zi(L.B * dv + L.A * b.om) * L.ik2;
             }
-            if (wph) {
-              stn(LR(a.ph[0], i), pcol, (TP)u1);
-              stn(LR(a.ph[2], i), pcol, (TP)u3);
+            if (L.wph) {
+              stz(ZR(a.ph[0], i), po, u1);
+              stz(ZR(a.ph[2], i), po, u3);
             }
           }
           push_back(w1, u1);
@@ -755,50 +853,50 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           if (r >= 0) {
             const double* bb = B1 + r * 7;
             const double* l = L1d + r * 3;
-            const double y1 = elim3(dot7(bb, w1), l, y1b);
-            const double y3 = elim3(dot7(bb, w3), l, y3b);
+            const dv2 y1 = elim3z(dot7z(bb, w1), l, y1b);
+            const dv2 y3 = elim3z(dot7z(bb, w3), l, y3b);
             if (L.act) {
-              stn(LR(a.S[1], r), bcol, y1);
-              stn(LR(a.S[2], r), bcol, y3);
+              stz(ZR(S1r, r), zo, y1);
+              stz(ZR(S2r, r), zo, y3);
             }
-            y1b[0] = y1b[1]; y1b[1] = y1b[2]; y1b[2] = y1;
-            y3b[0] = y3b[1]; y3b[1] = y3b[2]; y3b[2] = y3;
+            shift3(y1b, y1);
+            shift3(y3b, y3);
           }
         });
   }
   // ---- R3 (up): finish du1, du3; omega1 = du3 - i b v, omega3 = i a v - du1
   {
-    struct B { double s1, s2, v; };  // v: the other component
-    double x1[3] = {0, 0, 0}, x3[3] = {0, 0, 0};
+    struct B { dv2 s1, s2, v; };
+    dv2 x1[3], x3[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x1[k] = x3[k] = zz();
     pipeline<D, B>(
         n,
         [&](int t, B& b) {
           const int r = max(n - 1 - t, 0);
-          b.s1 = ldn(LR(a.S[1], r), bcol);
-          b.s2 = ldn(LR(a.S[2], r), bcol);
-          b.v = ldn(LR(a.v, r), bocol);
+          b.s1 = ldz(ZR(S1r, r), zo);
+          b.s2 = ldz(ZR(S2r, r), zo);
+          b.v = ldz(ZR(a.v, r), zo);
         },
         [&](int t, B& b) {
           const int r = n - 1 - t;
           const double* U = U1d + r * 4;
-          const double du1 = back3(b.s1, U, x1);
-          const double du3 = back3(b.s2, U, x3);
-          push_x(x1, du1);
-          push_x(x3, du3);
-          const double o1 = du3 - sg * L.B * b.v;
-          const double o3 = sg * L.A * b.v - du1;
-          if (wph) {
-            stn(LR(a.ph[3], r), pcol, (TP)o1);
-            stn(LR(a.ph[4], r), pcol, (TP)o3);
+          const dv2 du1 = back3z(b.s1, U, x1);
+          const dv2 du3 = back3z(b.s2, U, x3);
+          push_xz(x1, du1);
+          push_xz(x3, du3);
+          if (L.wph) {
+            stz(ZR(a.ph[3], r), po, du3 - zi(L.B * b.v));
+            stz(ZR(a.ph[4], r), po, zi(L.A * b.v) - du1);
           }
         });
   }
 }
 
-// At most 168 VGPRs (three waves per SIMD): a 384 x 384 mode plane gives
-// 577 workgroups, which then fit the 768 resident slots in one round.
+// Workgroups of 128 pairs (256 modes); at most 256 VGPRs (two waves per
+// SIMD): the 384 x 384 mode plane gives 289 workgroups, resident in one round.
 template <typename TH, typename TP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
     k_advance(AdvanceArgs<TH, TP> a, const double* __restrict__ B1, const double* __restrict__ A2,
               const double* __restrict__ B2, const double* __restrict__ L1d, const double* __restrict__ U1d,
               const double* __restrict__ L1u, const double* __restrict__ U1u) {
@@ -811,7 +909,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
 
 // Batched over contexts: work item (context, block, -, mean flag).
 template <typename TH, typename TP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) k_advance_batch(const AdvanceArgs<TH, TP>* __restrict__ d,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_advance_batch(const AdvanceArgs<TH, TP>* __restrict__ d,
                                                        const int4* __restrict__ w) {
   const int4 q = w[blockIdx.x];
   const AdvanceArgs<TH, TP>& a = d[q.x];
@@ -901,13 +999,36 @@ __device__ __forceinline__ void solve_transposed(const Lane& L, int n, size_t st
 // Dirichlet rows of the Poisson right-hand side).
 // Read-only tables as noalias parameters: wave-uniform row reads through the
 // scalar cache, and no ordering against the kernel's stores.
+// Lane pair of a (kx, +-kz) pair of modes for the per-pair tables: lane c
+// carries the homogeneous solution of wall c; k^2 from kz = p >= 0.
+__device__ __forceinline__ Lane pair_wall_lane(const PencilGeom& g, int bx) {
+  Lane L;
+  const int gl = bx * blockDim.x + threadIdx.x;
+  const int n3h = g.n3 >> 1, Q = g.n1h * n3h;
+  int q = gl >> 1;
+  L.c = gl & 1;
+  L.act = q < Q;
+  if (!L.act) q = Q - 1;
+  L.m = q;
+  L.col = 2 * (size_t)q + L.c;
+  const int kx = q / n3h, p = q - kx * n3h;
+  L.A = g.ka * kx;
+  L.B = g.kb * p;
+  L.k2 = L.A * L.A + L.B * L.B;
+  L.mean = L.act && q == 0;
+  L.live = L.act && q != 0;
+  L.ik2 = L.live ? 1.0 / L.k2 : 0.0;
+  return L;
+}
+
 __device__ __forceinline__ void homog_body(const HomogArgs& a, const double* __restrict__ A2,
                                            const double* __restrict__ B2, const double* __restrict__ dlo,
                                            const double* __restrict__ dhi) {
   const PencilGeom& g = a.g;
-  const Lane L = lane_setup(g, blockIdx.x);
+  const Lane L = pair_wall_lane(g, blockIdx.x);
   const int n = g.n2;
-  const size_t st = 2 * (size_t)g.M, M = g.M;
+  // per-pair tables: [n2][2Q] lane-indexed (lane c: wall c), [n2][Q] pair-indexed
+  const size_t M = g.M / 2, st = 2 * M;
   const size_t col = L.col, m = L.m;
   // t_c = A2^T E P^-T d_c (independent of dt), to a.T; z_c = E P^-T d_c is
   // consumed row by row (lag 3)
@@ -1332,9 +1453,9 @@ __global__ void __launch_bounds__(256) k_info(InfoArgs a) {
   double cm = 0.0, wm = 0.0;
   bool bad = false;
   for (size_t e = threadIdx.x; e < (size_t)n * a.p3; e += blockDim.x) {
-    const float c = a.rowcfl[e];
+    const double c = a.rowcfl[e];
     if (!isfinite(c)) bad = true;
-    cm = nanmax(cm, (double)c);
+    cm = nanmax(cm, c);
   }
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
     wm += a.g.quad[r] * a.U1[r];
@@ -1385,6 +1506,8 @@ __global__ void k_f2d(const float* __restrict__ in, double* __restrict__ out, si
 
 // ---------------------------------------------------------------- launchers
 static inline unsigned pencil_blocks(int M) { return (unsigned)((2 * (size_t)M + 255) / 256); }
+// k_advance: 128 (kx, +-kz) pairs (256 modes) per workgroup, plus the mean workgroup
+int advance_blocks(int M) { return (int)(((size_t)M / 2 + 127) / 128); }
 
 template <typename TP> hipError_t launch_recover(const RecoverArgs<TP>& a, hipStream_t st) {
   hipLaunchKernelGGL((k_recover<TP>), dim3(pencil_blocks(a.g.M)), dim3(256), 0, st, a, a.g.B1, a.g.L1d, a.g.U1d,
@@ -1392,12 +1515,13 @@ template <typename TP> hipError_t launch_recover(const RecoverArgs<TP>& a, hipSt
   return hipGetLastError();
 }
 hipError_t launch_homog(const HomogArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_homog, dim3(pencil_blocks(a.g.M)), dim3(256), 0, st, a, a.g.A2, a.g.B2, a.g.clo, a.g.chi);
+  hipLaunchKernelGGL(k_homog, dim3(pencil_blocks(a.g.M / 2)), dim3(256), 0, st, a, a.g.A2, a.g.B2, a.g.clo,
+                     a.g.chi);
   return hipGetLastError();
 }
 
 template <typename TH, typename TP> hipError_t launch_advance(const AdvanceArgs<TH, TP>& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_advance<TH, TP>), dim3(pencil_blocks(a.g.M) + 1), dim3(256), 0, st, a, a.g.B1, a.g.A2,
+  hipLaunchKernelGGL((k_advance<TH, TP>), dim3(advance_blocks(a.g.M) + 1), dim3(256), 0, st, a, a.g.B1, a.g.A2,
                      a.g.B2, a.g.L1d, a.g.U1d, a.g.L1u, a.g.U1u);
   return hipGetLastError();
 }

@@ -12,10 +12,13 @@ steps, on two meshes:
   - that mesh after the oracle's near-wall optimisation (Appendix B) at
     k* = 1e10 with 20 free nodes per wall, 60 descent steps.
 Stored (tests/golden/c3_narrow.npz): both meshes; per mesh dt, whole pencils
-(all 1537 nodes) of v, omega2, chi, u1, u3, omega1, omega3 for the modes of
-PENCIL_MODES, 4096 seeded mode-point samples of the same fields, U1, U3, the
+(all 1537 nodes) of v, omega2, chi, u1, u3 for the modes of PENCIL_MODES,
+4096 seeded mode-point samples of those fields and of omega1, omega3, U1, U3, the
 mean pressure gradient of the last sub-step, the CFL number entering the
-last sub-step and u_tau at both walls.
+last sub-step, u_tau at both walls, and per field the oracle's own
+sensitivity to rounding (the relative change of the samples when the
+initial v and omega2 change by one ulp), which sets the parity bound of
+the fields whose near-wall derivatives amplify rounding on this mesh.
 Run: python tests/golden/make_c3_narrow.py   (about 20 min; the optimisation
 with dense 1537-point solves dominates)
 """
@@ -33,8 +36,8 @@ from oracle import kmm, meshopt  # noqa: E402
 
 NSTEPS = 3
 NSAMPLE = 4096
-PENCIL_MODES = [(0, 1), (0, 3), (1, 0), (1, 1), (1, -1), (2, 5), (3, -7), (4, 2), (5, -3), (6, 7),
-                (7, -7), (7, 1)]
+PENCIL_MODES = [(0, 1), (1, 0), (1, -1), (2, 5), (3, -7), (5, -3), (6, 7), (7, -7)]
+PENCIL_FIELDS = ("v", "omega2", "chi", "u1", "u3")
 
 
 def case():
@@ -57,14 +60,26 @@ def run(y, tag, out):
             st, hist, f = kmm.substep(S, st, hist, s)
     u1, _, u3, o1, _, o3 = kmm.recover(S, st)
     dU = kmm.d1(S, st.U1)
+    # the oracle's own sensitivity to rounding: the same run from a state
+    # perturbed by one ulp (relative 2.2e-16 normal noise on v and omega2)
+    r = np.random.default_rng(1537)
+    vp = v * (1 + 2.2e-16 * r.standard_normal(v.shape))
+    op = om * (1 + 2.2e-16 * r.standard_normal(om.shape))
+    sp = kmm.make_state(S, vp, op, U1, U3)
+    for k in range(NSTEPS):
+        sp, _ = kmm.step(S, sp, 1)
+    pu1, _, pu3, po1, _, po3 = kmm.recover(S, sp)
     g = np.random.default_rng(5300)
     idx = (g.integers(0, c.n2, NSAMPLE), g.integers(0, c.n1 // 2, NSAMPLE), g.integers(0, c.n3, NSAMPLE))
     pkx = np.array([m[0] for m in PENCIL_MODES])
     pkz = np.array([m[1] % c.n3 for m in PENCIL_MODES])
     fields = dict(v=st.v, omega2=st.om2, chi=st.chi, u1=u1, u3=u3, omega1=o1, omega3=o3)
+    perturbed = dict(v=sp.v, omega2=sp.om2, chi=sp.chi, u1=pu1, u3=pu3, omega1=po1, omega3=po3)
     for k, a in fields.items():
         out[f"{tag}_{k}"] = a[idx]
-        out[f"{tag}_pen_{k}"] = a[:, pkx, pkz]
+        out[f"{tag}_sens_{k}"] = np.linalg.norm(perturbed[k][idx] - a[idx]) / np.linalg.norm(a[idx])
+        if k in PENCIL_FIELDS:
+            out[f"{tag}_pen_{k}"] = a[:, pkx, pkz]
     out.update({f"{tag}_y": y, f"{tag}_dt": S.dt, f"{tag}_U1": st.U1, f"{tag}_U3": st.U3, f"{tag}_f": f,
                 f"{tag}_cfl_last": cfl_last, f"{tag}_utau_lo": np.sqrt(S.nu * abs(dU[0])),
                 f"{tag}_utau_hi": np.sqrt(S.nu * abs(dU[-1]))})

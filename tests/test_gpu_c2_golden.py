@@ -2,10 +2,16 @@
 
 The oracle takes about 45 minutes for this run, so its result is stored:
 tests/golden/make_c2_golden.py runs only the oracle and keeps 8192 seeded
-mode-point samples of v, omega2, chi, u1, u3, omega1, omega3 plus the full
-mean profiles.  Here the GPU path runs the same 20 steps, in the launch
-configuration the benchmark times, and is compared on those samples:
-e(X) = ||X_gpu[s] - X_oracle[s]|| / ||X_oracle[s]||.
+mode-point samples of v, omega2, chi, u1, u3, omega1, omega3, whole
+wall-normal pencils of 24 modes from the lowest to the highest retained
+wavenumbers, the full mean profiles, the mean pressure gradient and the step
+diagnostics (CFL number entering the last sub-step, u_tau at both walls).
+Here the GPU path runs the same 20 steps, in the launch configuration the
+benchmark times, and is compared on those values:
+  - e(X) = ||X_gpu[s] - X_oracle[s]|| / ||X_oracle[s]|| over the samples;
+  - element-wise, max |X_gpu[s] - X_oracle[s]| / max |X_oracle[s]|;
+  - per mode, the relative error of each stored pencil whose energy is above
+    1e-6 of the most energetic one's.
 """
 import os
 
@@ -18,13 +24,18 @@ torch = pytest.importorskip("torch")
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_20steps.npz")
 FIELDS = ("v", "omega2", "chi", "u1", "u3", "omega1", "omega3")
+VORT = ("omega1", "omega2", "omega3", "chi")
 
-# float64: 1e-11 per field, chi (wall values from the influence-matrix
-# cancellation) 1e-10.  Mixed: 1e-5 on the velocities; the vorticities and
-# chi, one derivative further from the products, get 1e-4.
-TOL64 = dict(v=1e-11, omega2=1e-11, chi=1e-10, u1=1e-11, u3=1e-11, omega1=1e-11, omega3=1e-11,
-             U1=1e-11, U3=1e-11)
-TOLMX = dict(v=1e-5, omega2=1e-4, chi=1e-4, u1=1e-5, u3=1e-5, omega1=1e-4, omega3=1e-4, U1=1e-5, U3=1e-5)
+# float64: 1e-11 per field; mixed: 1e-5 per field (FP32 transforms and
+# products, FP64 solves).  chi's wall rows (the influence-matrix
+# coefficients) amplify rounding, as in the 64 x 65 x 64 run: element-wise
+# 5x the bound inside, 50x at the walls.  Per mode: float32 products carry
+# errors of ~1e-7 of the largest mode into every mode, so the per-mode bound
+# of the mixed path is 1e-3 (velocities) and 3e-2 (vorticities, chi); the
+# float64 path 1e-9.  Step diagnostics: 1e-12 float64 (mean pressure
+# gradient 1e-9), 1e-6 mixed (1e-4 for the pressure gradient).
+TOL = {"fp64": dict(field=1e-11, mode=1e-9, vmode=1e-9, diag=1e-12, f=1e-9),
+       "mixed": dict(field=1e-5, mode=1e-3, vmode=3e-2, diag=1e-6, f=1e-4)}
 
 
 def rel(a, b):
@@ -41,7 +52,15 @@ def _run(precision, g):
         info = ch.step(float(g["dt"]), int(g["nsteps"]), info=True)
         f = ch.get_fields(*FIELDS, "u1mean", "u3mean")
         idx = (torch.from_numpy(g["iy"]), torch.from_numpy(g["ikx"]), torch.from_numpy(g["ikz"]))
-        out = {k: f[k].cpu()[idx].numpy() if f[k].dim() == 3 else f[k].cpu().numpy() for k in f}
+        pk = (torch.from_numpy(g["pen_kx"]), torch.from_numpy(g["pen_kz"]))
+        out = {}
+        for k, t in f.items():
+            t = t.cpu()
+            if t.dim() == 3:
+                out[k] = t[idx].numpy()
+                out["pen_" + k] = t[:, pk[0], pk[1]].numpy()
+            else:
+                out[k] = t.numpy()
         out["U1"], out["U3"] = out.pop("u1mean"), out.pop("u3mean")
         return out, info
     finally:
@@ -53,9 +72,37 @@ def _run(precision, g):
 def test_c2_twenty_steps_against_oracle_samples(precision):
     g = np.load(GOLDEN)
     out, info = _run(precision, g)
-    tol = TOL64 if precision == "fp64" else TOLMX
-    errs = {k: rel(out[k], g[k]) for k in tol}
-    print(precision, {k: f"{e:.2e}" for k, e in errs.items()}, "f", info["f_mean"], float(g["f"]))
-    for k, e in errs.items():
-        assert e <= tol[k], (k, e)
-    assert abs(info["f_mean"] - float(g["f"])) <= (1e-9 if precision == "fp64" else 1e-4) * abs(float(g["f"]))
+    tol = TOL[precision]
+    t = tol["field"]
+    wall = (g["iy"] == 0) | (g["iy"] == int(g["U1"].shape[0]) - 1)
+    for k in FIELDS:
+        got, ref = out[k], g[k]
+        e2 = rel(got, ref)
+        scale = np.abs(ref).max()
+        if k == "chi":
+            em = np.abs(got[~wall] - ref[~wall]).max() / scale
+            ew = np.abs(got[wall] - ref[wall]).max() / scale
+            line = f"{precision} {k}: L2 {e2:.2e} max interior {em:.2e} walls {ew:.2e}"
+            assert em < 5 * t and ew < 50 * t, (k, em, ew)
+        else:
+            em = np.abs(got - ref).max() / scale
+            line = f"{precision} {k}: L2 {e2:.2e} max {em:.2e}"
+            assert em < t, (k, em)
+        pen, pref = out["pen_" + k], g["pen_" + k]
+        e = np.sum(np.abs(pref) ** 2, axis=0)
+        per = {(int(g["pen_kx"][j]), int(g["pen_kz"][j])): float(np.linalg.norm(pen[:, j] - pref[:, j]) / np.sqrt(e[j]))
+               for j in range(pref.shape[1]) if e[j] > 1e-6 * e.max()}
+        worst = max(per, key=per.get)
+        line += f", {len(per)} pencils, worst mode {per[worst]:.2e} at {worst}"
+        print(line)
+        assert e2 < t, (k, e2)
+        assert per[worst] < tol["vmode" if k in VORT else "mode"], (k, worst, per[worst])
+    for k in ("U1", "U3"):
+        err = np.abs(out[k] - g[k]).max() / max(np.abs(g[k]).max(), 1.0)
+        print(f"{precision} {k}: max {err:.2e}")
+        assert err < t, (k, err)
+    for k, gk in (("cfl_max", "cfl_last"), ("utau_lo", "utau_lo"), ("utau_hi", "utau_hi")):
+        e = abs(info[k] / float(g[gk]) - 1)
+        print(f"{precision} {k}: {info[k]:.12e} oracle {float(g[gk]):.12e} rel {e:.2e}")
+        assert e < tol["diag"], (k, e)
+    assert abs(info["f_mean"] / float(g["f"]) - 1) < tol["f"]
