@@ -33,9 +33,12 @@ VORT = ("omega1", "omega2", "omega3", "chi")
 # errors of ~1e-7 of the largest mode into every mode, so the per-mode bound
 # of the mixed path is 1e-3 (velocities) and 3e-2 (vorticities, chi); the
 # float64 path 1e-9.  Step diagnostics: 1e-12 float64 (mean pressure
-# gradient 1e-9), 1e-6 mixed (1e-4 for the pressure gradient).
-TOL = {"fp64": dict(field=1e-11, mode=1e-9, vmode=1e-9, diag=1e-12, f=1e-9),
-       "mixed": dict(field=1e-5, mode=1e-3, vmode=3e-2, diag=1e-6, f=1e-4)}
+# gradient 1e-9), 1e-6 mixed (1e-4 for the pressure gradient); u_tau comes
+# from the wall derivative of U1, whose compact row weights sum to 3.5e4
+# against dU1/dy = 30 on this mesh, so errors of 1e-14 in U1 may reach 1e-11
+# in u_tau: its float64 bound is 1e-11.
+TOL = {"fp64": dict(field=1e-11, mode=1e-9, vmode=1e-9, diag=1e-12, utau=1e-11, f=1e-9),
+       "mixed": dict(field=1e-5, mode=1e-3, vmode=3e-2, diag=1e-6, utau=1e-6, f=1e-4)}
 
 
 def rel(a, b):
@@ -104,5 +107,5 @@ def test_c2_twenty_steps_against_oracle_samples(precision):
     for k, gk in (("cfl_max", "cfl_last"), ("utau_lo", "utau_lo"), ("utau_hi", "utau_hi")):
         e = abs(info[k] / float(g[gk]) - 1)
         print(f"{precision} {k}: {info[k]:.12e} oracle {float(g[gk]):.12e} rel {e:.2e}")
-        assert e < tol["diag"], (k, e)
+        assert e < tol["utau" if k.startswith("utau") else "diag"], (k, e)
     assert abs(info["f_mean"] / float(g["f"]) - 1) < tol["f"]
