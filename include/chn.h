@@ -248,6 +248,21 @@ chn_status chn_filtered_pressure(chn_ctx *ctx, int32_t kcx, int32_t kcz, const d
  * Works on every context; the only compute call of a planes_only context. */
 chn_status chn_plane_products(chn_ctx *ctx, const void *const *d_in, void *const *d_out);
 
+/* For callers that cannot allocate device memory at the time of the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): chn_plane_products with the transform intermediate held in a
+ * static device array of the library (64 MiB per GPU, reserved when the
+ * library is loaded and held until the process ends) instead of the
+ * context's workspace; the planes go through it in chunks of as many planes
+ * as it holds.  Same arguments, layouts, results and errors as
+ * chn_plane_products, plus CHN_EUNSUPPORTED when one plane of the
+ * intermediate (6 * 3n3/2 * n1/2 complex values of the context's transform
+ * precision) exceeds 64 MiB.  The call allocates nothing and creates no
+ * events (chn_timing_enable does not apply to it).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (from different
+ * streams or threads) race and give wrong results. */
+chn_status chn_plane_products_static(chn_ctx *ctx, const void *const *d_in, void *const *d_out);
+
 /* Copies the context's n2 wall-normal nodes (the configured mesh, or the
  * default one) to the HOST array y. */
 chn_status chn_get_mesh(chn_ctx *ctx, double *y);

@@ -74,6 +74,7 @@ def lib():
         L.chn_get_mesh.argtypes = [P, P]
         L.chn_get_plan.argtypes = [P, C.POINTER(Plan)]
         L.chn_plane_products.argtypes = [P, C.POINTER(P), C.POINTER(P)]
+        L.chn_plane_products_static.argtypes = [P, C.POINTER(P), C.POINTER(P)]
         L.chn_set_plan.argtypes = [P, C.POINTER(Plan)]
         L.chn_autotune.argtypes = [P, C.c_int32, C.POINTER(Plan)]
         L.chn_timing_enable.argtypes = [P, C.c_int32]
@@ -99,6 +100,7 @@ def lib():
                      "chn_get_operators", "chn_get_mesh",
                      "chn_timing_enable", "chn_timing_read", "chn_ens_create", "chn_ens_destroy", "chn_ens_step",
                      "chn_get_plan", "chn_set_plan", "chn_autotune", "chn_plane_products",
+                     "chn_plane_products_static",
                      "chn_optimise_mesh", "chn_ens_set_state"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -238,6 +240,21 @@ class Channel:
         a = (C.c_void_p * 6)(*[None if f is None else f.data_ptr() for f in fields])
         b = (C.c_void_p * 3)(*[t.data_ptr() for t in out])
         self._check(self.L.chn_plane_products(self.ctx, a, b), "chn_plane_products")
+        return out
+
+    def plane_products_static(self, fields, out):
+        """chn_plane_products_static: as plane_products, with the transform
+        intermediate in the library's static device array; `out` must be given
+        (three tensors as plane_products returns), so that nothing is allocated."""
+        dt = torch.complex64 if self.precision == MIXED else torch.complex128
+        for f in list(fields) + list(out):
+            if f is not None and (f.dtype != dt or not f.is_contiguous() or f.device != self.device
+                                  or tuple(f.shape) != (self.n2, self.n1h, self.n3)):
+                raise ChnError(f"plane_products_static needs contiguous {dt} [{self.n2}, {self.n1h}, {self.n3}] "
+                               f"on {self.device}")
+        a = (C.c_void_p * 6)(*[None if f is None else f.data_ptr() for f in fields])
+        b = (C.c_void_p * 3)(*[t.data_ptr() for t in out])
+        self._check(self.L.chn_plane_products_static(self.ctx, a, b), "chn_plane_products_static")
         return out
 
     def filter_and_stress(self, kcx, kcz, q1, q3, with_tau=True):

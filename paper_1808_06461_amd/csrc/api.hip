@@ -3,6 +3,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -311,16 +312,19 @@ bool plan_fits(const chn_ctx* x, int xrows, int zK, int ych) {
 }
 template <typename T> int z_lines(const chn_ctx* x) { return x->zK; }
 
-// guard: the context's instability guard inside the time step, else nullptr
+// guard: the context's instability guard inside the time step, else nullptr;
+// inter: the transform intermediate (nullptr: the context's own)
 template <typename T, typename TO>
 void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* const* out, chn::ZinvArgs<T>& za,
-                chn::XpassArgs<T>& xa, chn::ZfwdArgs<T, TO>& fa, unsigned* guard = nullptr) {
+                chn::XpassArgs<T>& xa, chn::ZfwdArgs<T, TO>& fa, unsigned* guard = nullptr,
+                void* inter = nullptr) {
   using C = typename Ty<T>::c;
+  if (!inter) inter = x->inter;
   const int K = z_lines<T>(x);
   za = {};
   for (int f = 0; f < 6; ++f) za.in[f] = reinterpret_cast<const C*>(in[f]);
   if (!omega2_given) za.in[4] = nullptr;
-  za.out = reinterpret_cast<C*>(x->inter);
+  za.out = reinterpret_cast<C*>(inter);
   za.tw = reinterpret_cast<const C*>(x->tw3);
   za.plan = x->plan3;
   za.d = x->dims;
@@ -333,7 +337,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   za.fixed = x->ffix;
   za.guard = guard;
   xa = {};
-  xa.buf = reinterpret_cast<C*>(x->inter);
+  xa.buf = reinterpret_cast<C*>(inter);
   xa.tw = reinterpret_cast<const C*>(x->tw1);
   xa.plan = x->plan1;
   xa.d = x->dims;
@@ -349,7 +353,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   xa.fixed = x->ffix;
   xa.guard = guard;
   fa = {};
-  fa.buf = reinterpret_cast<const C*>(x->inter);
+  fa.buf = reinterpret_cast<const C*>(inter);
   for (int f = 0; f < 3; ++f) fa.out[f] = reinterpret_cast<typename Ty<TO>::c*>(out[f]);
   fa.tw = reinterpret_cast<const C*>(x->tw3);
   fa.plan = x->plan3;
@@ -363,17 +367,19 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
 }
 
 // plane phase: ph (6 slots) -> H (3 slots) through the intermediate
+// inter, chunk: an intermediate other than the context's, holding chunk planes
 template <typename T, typename TO>
 chn_status plane_phase(chn_ctx* x, const void* const* in, bool omega2_given, void* const* out,
-                       unsigned* guard = nullptr) {
+                       unsigned* guard = nullptr, void* inter = nullptr, int chunk = 0) {
   chn::ZinvArgs<T> za;
   chn::XpassArgs<T> xa;
   chn::ZfwdArgs<T, TO> fa;
-  plane_args<T, TO>(x, in, omega2_given, out, za, xa, fa, guard);
+  plane_args<T, TO>(x, in, omega2_given, out, za, xa, fa, guard, inter);
+  const int ych = chunk > 0 ? chunk : x->ychunk;
   // chunks of planes: the intermediate holds the chunk from its plane 0
-  for (int y0 = 0; y0 < x->n2; y0 += x->ychunk) {
+  for (int y0 = 0; y0 < x->n2; y0 += ych) {
     za.y0 = xa.y0 = fa.y0 = y0;
-    za.ny = xa.ny = fa.ny = std::min(x->ychunk, x->n2 - y0);
+    za.ny = xa.ny = fa.ny = std::min(ych, x->n2 - y0);
     HIPCHK(x, timed(x, CHN_K_ZINV, [&] { return chn::launch_zinv<T>(za, x->stream); }));
     HIPCHK(x, timed(x, CHN_K_XPASS, [&] { return chn::launch_xpass<T>(xa, x->stream); }));
     HIPCHK(x, timed(x, CHN_K_ZFWD, [&] { return chn::launch_zfwd<T, TO>(fa, x->stream); }));
@@ -519,6 +525,33 @@ template <typename T> chn_status divergence(chn_ctx* x, unsigned long long* maxb
 
 chn_status check(chn_ctx* x);
 chn_status need_fields(chn_ctx* x);
+
+// ---------------------------------------------------------------- static scratch
+// The transform intermediate of chn_plane_products_static: a file-scope
+// device array, one per GPU the library runs on, held until the process
+// ends.  In host code its name is only a stand-in: its device address comes
+// from hipGetSymbolAddress, taken once per device (with that device
+// current) and kept in g_scratch_ptr; every launch uses that address.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+chn_status static_scratch(chn_ctx* x, void** out) {
+  int dev = -1;
+  HIPCHK(x, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(x, CHN_EUNSUPPORTED, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(x, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(x, CHN_EDEVICE, "hipGetSymbolAddress returned no address for the static scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CHN_OK;
+}
 
 // The filter stage transforms in float64 on both paths.  tau_ij is a small
 // difference of F(u_i u_j) and F(u_i) F(u_j) (about 1e-2 to 1e-3 of either
@@ -1286,6 +1319,37 @@ chn_status chn_plane_products(chn_ctx* x, const void* const* d_in, void* const* 
   for (int f = 0; f < 3; ++f) out[f] = d_out[f];
   const bool om2 = d_in[4] != nullptr;
   return x->mixed ? plane_phase<float, float>(x, in, om2, out) : plane_phase<double, double>(x, in, om2, out);
+}
+
+chn_status chn_plane_products_static(chn_ctx* x, const void* const* d_in, void* const* d_out) {
+  if (chn_status s = check(x)) return s;
+  if (!d_in || !d_out) return fail(x, CHN_EINVAL, "NULL field array");
+  for (int f = 0; f < 6; ++f)
+    if (!d_in[f] && f != 4) return fail(x, CHN_EINVAL, "NULL input field");
+  for (int f = 0; f < 3; ++f)
+    if (!d_out[f]) return fail(x, CHN_EINVAL, "NULL output field");
+  // one plane of the intermediate: six z-padded fields of n1/2 lines
+  const size_t plane = (size_t)6 * x->p3 * x->n1h * (x->mixed ? 8 : 16);
+  if (plane > kStaticScratchBytes)
+    return fail(x, CHN_EUNSUPPORTED, "one plane of the transform intermediate (" + std::to_string(plane) +
+                                         " bytes) exceeds the static scratch of " +
+                                         std::to_string(kStaticScratchBytes) + " bytes");
+  void* scr = nullptr;
+  if (chn_status s = static_scratch(x, &scr)) return s;
+  const int chunk = (int)std::min<size_t>((size_t)x->n2, kStaticScratchBytes / plane);
+  const void* in[6];
+  void* out[3];
+  for (int f = 0; f < 6; ++f) in[f] = d_in[f];
+  for (int f = 0; f < 3; ++f) out[f] = d_out[f];
+  const bool om2 = d_in[4] != nullptr;
+  // no timing events either: their creation is left to the allocating entry points
+  const bool timing = x->timing, rec = x->phase_rec;
+  x->timing = x->phase_rec = false;
+  const chn_status st = x->mixed ? plane_phase<float, float>(x, in, om2, out, nullptr, scr, chunk)
+                                 : plane_phase<double, double>(x, in, om2, out, nullptr, scr, chunk);
+  x->timing = timing;
+  x->phase_rec = rec;
+  return st;
 }
 
 chn_status chn_filter_and_stress(chn_ctx* x, int32_t kcx, int32_t kcz, int32_t q1, int32_t q3, double* d_ubar,
