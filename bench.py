@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-points x RK3 steps/sec, mixed-prec vs FP64 GPU at stated rel. error"
 UNIT = "grid-points*RK3-steps/s"
 HBM_PEAK_GBS = 8000.0
-FIXED_PLAN = None  # (x_rows, z_lines, y_chunk[, fixed_radix]) from --plan; None: autotune
+FIXED_PLAN = None  # (x_rows, z_lines, y_chunk[, fixed_radix[, z_pipeline]]) from --plan; None: autotune
 
 
 def algorithmic_bytes(kind, n1, n2, n3, elem):
@@ -384,7 +384,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the per-phase timing of the Re_tau 5300 share")
     ap.add_argument("--no-c5", action="store_true", help="skip the timing of the low-storage stage")
     ap.add_argument("--no-meshopt", action="store_true", help="skip the near-wall mesh optimisation leg")
-    ap.add_argument("--plan", default=None, metavar="XROWS,ZLINES,YCHUNK[,FIXED]",
+    ap.add_argument("--plan", default=None, metavar="XROWS,ZLINES,YCHUNK[,FIXED[,ZPIPE]]",
                     help="fixed plane-phase schedule instead of the autotuner (for profiling one schedule)")
     ap.add_argument("--source-hash", default=None, metavar="KIND",
                     help="print the source hash a traffic summary of this kernel kind must carry, then exit")
@@ -431,6 +431,7 @@ def main():
         print(f"[bench] {args.only} only: {args.warmup} warmup + {args.steps} timed RK3 steps", file=sys.stderr)
         ms, _, kern, _ = run_path(case, v, om, U1, U3, y, args.only, args.steps, args.warmup)
         plan = kern.pop("_plan")
+        kern.pop("_instrumented_ms")
         print(json.dumps({"precision": args.only, "ms_per_step": ms / args.steps, "plane_schedule": plan,
                           "value": G * args.steps / (ms / 1e3), "kernels_ms": {k: t / max(n, 1) for k, (t, n) in kern.items()}}))
         return

@@ -383,6 +383,11 @@ typedef struct {
   int32_t y_chunk;      /* planes per launch of the three plane kernels */
   int32_t fixed_radix;  /* 1: transforms whose length has a compile-time radix
                            schedule (576 points) use it; 0: the runtime plan */
+  int32_t z_pipeline;   /* 1: the z passes issue the next field's loads before
+                           transforming the current one (and the z inverse forms
+                           omega2 from the u1, u3 values it loaded), where a
+                           field of z_lines lines fits their staging registers;
+                           0: one field at a time */
 } chn_plan;
 
 /* Current schedule (chn_create picks 2 rows when they fit, 16 lines capped

@@ -33,7 +33,10 @@ class Config(C.Structure):
 
 class Plan(C.Structure):
     _fields_ = [("x_rows", C.c_int32), ("z_lines", C.c_int32), ("y_chunk", C.c_int32),
-                ("fixed_radix", C.c_int32)]
+                ("fixed_radix", C.c_int32), ("z_pipeline", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class StepInfo(C.Structure):
@@ -297,16 +300,17 @@ class Channel:
     def plan(self):
         p = Plan()
         self._check(self.L.chn_get_plan(self.ctx, C.byref(p)), "chn_get_plan")
-        return {"x_rows": p.x_rows, "z_lines": p.z_lines, "y_chunk": p.y_chunk, "fixed_radix": p.fixed_radix}
+        return p.as_dict()
 
-    def set_plan(self, x_rows, z_lines, y_chunk=None, fixed_radix=0):
-        p = Plan(int(x_rows), int(z_lines), int(self.n2 if y_chunk is None else y_chunk), int(fixed_radix))
+    def set_plan(self, x_rows, z_lines, y_chunk=None, fixed_radix=0, z_pipeline=0):
+        p = Plan(int(x_rows), int(z_lines), int(self.n2 if y_chunk is None else y_chunk), int(fixed_radix),
+                 int(z_pipeline))
         self._check(self.L.chn_set_plan(self.ctx, C.byref(p)), "chn_set_plan")
 
     def autotune(self, reps=3):
         p = Plan()
         self._check(self.L.chn_autotune(self.ctx, int(reps), C.byref(p)), "chn_autotune")
-        return {"x_rows": p.x_rows, "z_lines": p.z_lines, "y_chunk": p.y_chunk, "fixed_radix": p.fixed_radix}
+        return p.as_dict()
 
     def operators(self):
         import numpy as np

@@ -105,6 +105,7 @@ struct chn_ctx {
   int zK = 1;           // lines per z-pass workgroup
   int ychunk = 1;       // planes per plane-phase launch
   int ffix = 0;         // compile-time radix schedules where available
+  int zpipe = 0;        // pipelined z passes (next field's loads during this field's transform)
   int ychunk_max = 1;   // planes the intermediate holds
   bool planes_only = false;
   // per-kernel timing (chn_timing_enable): events bracketing every launch
@@ -335,6 +336,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   za.y0 = 0;
   za.ny = x->n2;
   za.fixed = x->ffix;
+  za.pipe = x->zpipe;
   za.guard = guard;
   xa = {};
   xa.buf = reinterpret_cast<C*>(inter);
@@ -364,6 +366,7 @@ void plane_args(chn_ctx* x, const void* const* in, bool omega2_given, void* cons
   fa.y0 = 0;
   fa.ny = x->n2;
   fa.fixed = x->ffix;
+  fa.pipe = x->zpipe;
 }
 
 // plane phase: ph (6 slots) -> H (3 slots) through the intermediate
@@ -1449,18 +1452,20 @@ chn_status chn_get_plan(chn_ctx* x, chn_plan* plan) {
   plan->z_lines = x->zK;
   plan->y_chunk = x->ychunk;
   plan->fixed_radix = x->ffix;
+  plan->z_pipeline = x->zpipe;
   return CHN_OK;
 }
 
 chn_status chn_set_plan(chn_ctx* x, const chn_plan* plan) {
   if (chn_status s = check(x)) return s;
   if (!plan || !plan_fits(x, plan->x_rows, plan->z_lines, plan->y_chunk) ||
-      (plan->fixed_radix != 0 && plan->fixed_radix != 1))
+      (plan->fixed_radix != 0 && plan->fixed_radix != 1) || (plan->z_pipeline != 0 && plan->z_pipeline != 1))
     return fail(x, CHN_EINVAL, "schedule does not fit this grid or the device's LDS");
   x->xrows = plan->x_rows;
   x->zK = plan->z_lines;
   x->ychunk = plan->y_chunk;
   x->ffix = plan->fixed_radix;
+  x->zpipe = plan->z_pipeline;
   return CHN_OK;
 }
 
@@ -1468,7 +1473,7 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
   if (chn_status s = check(x)) return s;
   if (x->planes_only) return fail(x, CHN_EUNSUPPORTED, "autotune needs the context's own field buffers (not planes_only)");
   if (reps < 1) reps = 3;
-  struct Cand { int xr, K, ych, fx; };
+  struct Cand { int xr, K, ych, fx, zp; };
   std::vector<Cand> cand;
   const int kmax = z_lines_max(x);
   // planes per launch: the largest, and even splits of the planes into 2..12 launches
@@ -1479,14 +1484,19 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
   }
   const bool has_fixed = chn::plan_is_576(x->plan1) || chn::plan_is_576(x->plan3) || chn::plan_is_9216(x->plan3) ||
                          chn::plan_is_12288(x->plan1);
-  for (int fx = 0; fx <= (has_fixed ? 1 : 0); ++fx)
-    for (int xr : {8, 4, 2, 1})
-      for (int K : {1, 2, 4, 8, 12, 16, kmax})
-        for (int c : chunks)
-          if (plan_fits(x, xr, K, c) && std::none_of(cand.begin(), cand.end(), [&](const Cand& q) {
-                return q.xr == xr && q.K == K && q.ych == c && q.fx == fx;
-              }))
-            cand.push_back({xr, K, c, fx});
+  // the pipelined z passes engage where a field of K lines fits their staging
+  // registers (8 values per thread inverse, 12 forward, 256 threads)
+  auto pipe_engages = [&](int K) { return K * x->n3 <= 8 * 256 || K * x->p3 <= 12 * 256; };
+  for (int zp = 0; zp <= 1; ++zp)
+    for (int fx = 0; fx <= (has_fixed ? 1 : 0); ++fx)
+      for (int xr : {8, 4, 2, 1})
+        for (int K : {1, 2, 4, 8, 12, 16, kmax})
+          for (int c : chunks)
+            if (plan_fits(x, xr, K, c) && (zp == 0 || pipe_engages(K)) &&
+                std::none_of(cand.begin(), cand.end(), [&](const Cand& q) {
+                  return q.xr == xr && q.K == K && q.ych == c && q.fx == fx && q.zp == zp;
+                }))
+              cand.push_back({xr, K, c, fx, zp});
   if (cand.empty()) return fail(x, CHN_EINVAL, "no schedule fits");
   hipEvent_t a = nullptr, b = nullptr;
   HIPCHK(x, hipEventCreate(&a));
@@ -1504,6 +1514,7 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
     x->zK = c.K;
     x->ychunk = c.ych;
     x->ffix = c.fx;
+    x->zpipe = c.zp;
     auto run = [&]() { return x->mixed ? plane_phase<float, float>(x, x->ph, false, x->H)
                                        : plane_phase<double, double>(x, x->ph, false, x->H); };
     if ((st = run()) != CHN_OK) break;
@@ -1527,12 +1538,14 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
   x->zK = pick.K;
   x->ychunk = pick.ych;
   x->ffix = pick.fx;
+  x->zpipe = pick.zp;
   if (st != CHN_OK) return st;
   if (chosen) {
     chosen->x_rows = pick.xr;
     chosen->z_lines = pick.K;
     chosen->y_chunk = pick.ych;
     chosen->fixed_radix = pick.fx;
+    chosen->z_pipeline = pick.zp;
   }
   return CHN_OK;
 }

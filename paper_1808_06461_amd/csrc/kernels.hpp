@@ -25,6 +25,8 @@ template <typename T> struct ZinvArgs {
   int fixed;           // nonzero: compile-time radix schedule where one exists for the plan
   unsigned* guard;     // instability guard (common.hpp) whose CFL word the launch
                        // with y0 == 0 resets; nullptr outside the time step
+  int pipe;            // nonzero: the next field's loads overlap this field's transform
+                       // (256-thread launches whose field fits the staging registers)
 };
 
 template <typename T> struct XpassArgs {
@@ -55,6 +57,7 @@ template <typename T, typename TO> struct ZfwdArgs {
   double scale;        // 1 / (p1 p3)
   int y0, ny;          // buf holds planes y0 .. y0 + ny - 1 (from its plane 0); out is global
   int fixed;           // nonzero: compile-time radix schedule where one exists for the plan
+  int pipe;            // nonzero: the next field's loads overlap this field's transform
 };
 
 template <typename T> hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st);

@@ -25,7 +25,14 @@ static constexpr double kTwoPi = 6.283185307179586476925286766559;
 // plane_lds_stride(p) = p + p / 8 + 1.
 constexpr bool kPad = true;
 
-template <typename T, int MAXV, int FN = 0>
+// Values of one field staged per thread by the pipelined z passes: the next
+// field's loads are issued before the current field's transform, so their
+// latency hides behind it.  Fields with more values per thread than this take
+// the unpipelined loop.
+constexpr int kZinvStage = 8;
+constexpr int kZfwdStage = 12;
+
+template <typename T, int MAXV, int FN = 0, bool PIPE = false>
 __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
@@ -40,6 +47,69 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
   const unsigned mnp = qmagic(npad), mn3 = qmagic(n3), mnk = qmagic(nk);
   const double tpx = kTwoPi / a.d.lx, tpz = kTwoPi / a.d.lz;
   const c2<T> zero = mk<T>(T(0), T(0));
+  // the first launch of a sub-step's plane phase starts the CFL maximum
+  if (a.guard && a.y0 == 0 && bx == 0 && by == 0 && threadIdx.x == 0) a.guard[0] = 0u;
+  const int nt = blockDim.x, tot = K * n3;
+  if (PIPE && tot <= kZinvStage * nt) {
+    // Pipelined: field f's values sit in registers (st) while field f - 1 is
+    // transformed.  omega2 = i b u1 - i a u3, when not given, is accumulated
+    // in ws from the u1 and u3 values already loaded, so it costs no loads.
+    const bool form_w = a.in[4] == nullptr && a.nfields == 6;
+    int order[6], loads[6], nl = 0;
+    for (int i = 0; i < a.nfields; ++i) order[i] = i;
+    if (form_w) {
+      const int o[6] = {0, 2, 4, 1, 3, 5};
+      for (int i = 0; i < 6; ++i) order[i] = o[i];
+    }
+    for (int i = 0; i < a.nfields; ++i)
+      if (!(form_w && order[i] == 4)) loads[nl++] = order[i];
+    c2<T> st[kZinvStage], ws[kZinvStage];
+    auto fetch = [&](int f) {
+#pragma unroll
+      for (int q = 0; q < kZinvStage; ++q) {
+        const int e = threadIdx.x + q * nt;
+        const int l = (int)qdiv(e, n3, mn3), s = e - l * n3;
+        st[q] = zero;
+        if (e < tot && l < nk && s != half && !(a.zero_mean && kx0 + l == 0 && s == 0))
+          st[q] = a.in[f][((size_t)y * n1h + kx0 + l) * n3 + s];
+      }
+    };
+    fetch(loads[0]);
+    int next = 1;
+    for (int i = 0; i < a.nfields; ++i) {
+      const int f = order[i];
+      for (int e = threadIdx.x; e < K * npad; e += nt) {
+        const int l = (int)qdiv(e, npad, mnp);
+        lds[l * LS + lx<kPad>(half + (e - l * npad))] = zero;
+      }
+#pragma unroll
+      for (int q = 0; q < kZinvStage; ++q) {
+        const int e = threadIdx.x + q * nt;
+        const int l = (int)qdiv(e, n3, mn3), s = e - l * n3;
+        if (e >= tot || s == half) continue;
+        c2<T> v = st[q];
+        if (form_w) {
+          const int kz = s < half ? s : s - n3;
+          const T ka = T(tpx * (kx0 + l)), kb = T(tpz * kz);
+          if (f == 0) ws[q] = mk<T>(-kb * v.y, kb * v.x);                    // i b u1
+          if (f == 2) ws[q] = mk<T>(ws[q].x + ka * v.y, ws[q].y - ka * v.x);  // - i a u3
+          if (f == 4) v = ws[q];
+        }
+        lds[l * LS + lx<kPad>(s < half ? s : p3 - (n3 - s))] = v;
+      }
+      // the next loaded field's values, in flight during this transform
+      if (!(form_w && f == 4) && next < nl) fetch(loads[next++]);
+      __syncthreads();
+      fft_lines<T, MAXV, FN, kPad>(lds, LS, K, a.plan, a.tw, +1);
+      c2<T>* out = a.out + ((size_t)(by * a.nslot + f) * p3) * n1h + kx0;
+      for (int e = threadIdx.x; e < nk * p3; e += nt) {
+        const int z = (int)qdiv(e, nk, mnk), l = e - z * nk;
+        out[(size_t)z * n1h + l] = lds[l * LS + lx<kPad>(z)];
+      }
+      __syncthreads();
+    }
+    return;
+  }
   auto value = [&](int f, int l, int s) -> c2<T> {
     c2<T> v = zero;
     if (l < nk && !(a.zero_mean && kx0 + l == 0 && s == 0)) {
@@ -57,8 +127,6 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
     }
     return v;
   };
-  // the first launch of a sub-step's plane phase starts the CFL maximum
-  if (a.guard && a.y0 == 0 && bx == 0 && by == 0 && threadIdx.x == 0) a.guard[0] = 0u;
   for (int f = 0; f < a.nfields; ++f) {
     for (int e = threadIdx.x; e < K * npad; e += blockDim.x) {
       const int l = (int)qdiv(e, npad, mnp);
@@ -307,7 +375,7 @@ __device__ __forceinline__ void xrow_body(const XpassArgs<T>& a, int z, int y) {
   forward(1, r1);
 }
 
-template <typename T, typename TO, int MAXV, int FN = 0>
+template <typename T, typename TO, int MAXV, int FN = 0, bool PIPE = false>
 __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smem_raw);
@@ -319,6 +387,49 @@ __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int 
   const unsigned mK = qmagic(K), mn3 = qmagic(n3);  // exact multiply-high divisions
   const T scale = T(a.scale);
   const c2<T> zero = mk<T>(T(0), T(0));
+  const int nt = blockDim.x, tot = K * p3;
+  auto store = [&](int f) {
+    c2<TO>* out = a.out[f] + ((size_t)(a.y0 + y) * n1h + kx0) * n3;
+    for (int e = threadIdx.x; e < nk * n3; e += nt) {
+      const int l = (int)qdiv(e, n3, mn3), s = e - l * n3;
+      c2<TO> v = mk<TO>(TO(0), TO(0));
+      if (s != half) {
+        const c2<T> w = lds[l * LS + lx<kPad>(s < half ? s : p3 - (n3 - s))];
+        v = mk<TO>(TO(w.x * scale), TO(w.y * scale));
+      }
+      out[(size_t)l * n3 + s] = v;
+    }
+  };
+  if (PIPE && tot <= kZfwdStage * nt) {
+    // Pipelined: the next field's transposed lines are loaded into registers
+    // while this one is transformed.
+    c2<T> st[kZfwdStage];
+    auto fetch = [&](int f) {
+      const c2<T>* in = a.buf + ((size_t)(y * 6 + f) * p3) * n1h + kx0;
+#pragma unroll
+      for (int q = 0; q < kZfwdStage; ++q) {
+        const int e = threadIdx.x + q * nt;
+        const int z = (int)qdiv(e, K, mK), l = e - z * K;
+        st[q] = (e < tot && l < nk) ? in[(size_t)z * n1h + l] : zero;
+      }
+    };
+    fetch(0);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+      for (int q = 0; q < kZfwdStage; ++q) {
+        const int e = threadIdx.x + q * nt;
+        const int z = (int)qdiv(e, K, mK), l = e - z * K;
+        if (e < tot) lds[l * LS + lx<kPad>(z)] = st[q];
+      }
+      if (f < 2) fetch(f + 1);
+      __syncthreads();
+      fft_lines<T, MAXV, FN, kPad>(lds, LS, K, a.plan, a.tw, -1);
+      store(f);
+      __syncthreads();
+    }
+    return;
+  }
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const c2<T>* in = a.buf + ((size_t)(y * 6 + f) * p3) * n1h + kx0;
@@ -328,16 +439,7 @@ __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int 
     }
     __syncthreads();
     fft_lines<T, MAXV, FN, kPad>(lds, LS, K, a.plan, a.tw, -1);
-    c2<TO>* out = a.out[f] + ((size_t)(a.y0 + y) * n1h + kx0) * n3;
-    for (int e = threadIdx.x; e < nk * n3; e += blockDim.x) {
-      const int l = (int)qdiv(e, n3, mn3), s = e - l * n3;
-      c2<TO> v = mk<TO>(TO(0), TO(0));
-      if (s != half) {
-        const c2<T> w = lds[l * LS + lx<kPad>(s < half ? s : p3 - (n3 - s))];
-        v = mk<TO>(TO(w.x * scale), TO(w.y * scale));
-      }
-      out[(size_t)l * n3 + s] = v;
-    }
+    store(f);
     __syncthreads();
   }
 }
@@ -353,19 +455,19 @@ __device__ __forceinline__ int2 z_tile() {
   const int t = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, n);
   return make_int2(t % gridDim.x, t / gridDim.x);
 }
-template <typename T, int MAXV, int FN, int NT = 256>
+template <typename T, int MAXV, int FN, int NT = 256, bool PIPE = false>
 __global__ void __launch_bounds__(NT) k_zinv(ZinvArgs<T> a) {
   const int2 t = z_tile();
-  zinv_body<T, MAXV, FN>(a, t.x, t.y);
+  zinv_body<T, MAXV, FN, PIPE>(a, t.x, t.y);
 }
 template <typename T, int MAXV, int FN, int RZ>
 __global__ void __launch_bounds__(256) k_xpass(XpassArgs<T> a) { xpass_body<T, MAXV, FN, RZ>(a, blockIdx.x, blockIdx.y); }
 template <typename T, int NT, int QX, int MAXV, int FN = 0>
 __global__ void __launch_bounds__(NT) k_xrow(XpassArgs<T> a) { xrow_body<T, NT, QX, MAXV, FN>(a, blockIdx.x, blockIdx.y); }
-template <typename T, typename TO, int MAXV, int FN, int NT = 256>
+template <typename T, typename TO, int MAXV, int FN, int NT = 256, bool PIPE = false>
 __global__ void __launch_bounds__(NT) k_zfwd(ZfwdArgs<T, TO> a) {
   const int2 t = z_tile();
-  zfwd_body<T, TO, MAXV, FN>(a, t.x, t.y);
+  zfwd_body<T, TO, MAXV, FN, PIPE>(a, t.x, t.y);
 }
 
 template <typename T, int MAXV>
@@ -442,8 +544,14 @@ hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st) {
     return hipGetLastError();
   }
   const int m = pick_staging<T>(a.plan, a.K, 256);
-  if (a.fixed && plan_is_576(a.plan)) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 576>), grid, dim3(256), sh, st, a));
-  else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 0>), grid, dim3(256), sh, st, a));
+  const bool fx = a.fixed && plan_is_576(a.plan);
+  if (a.pipe) {
+    if (fx) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 576, 256, true>), grid, dim3(256), sh, st, a));
+    else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 0, 256, true>), grid, dim3(256), sh, st, a));
+  } else {
+    if (fx) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 576>), grid, dim3(256), sh, st, a));
+    else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 0>), grid, dim3(256), sh, st, a));
+  }
   return hipGetLastError();
 }
 
@@ -510,8 +618,14 @@ hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st) {
     return hipGetLastError();
   }
   const int m = pick_staging<T>(a.plan, a.K, 256);
-  if (a.fixed && plan_is_576(a.plan)) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 576>), grid, dim3(256), sh, st, a));
-  else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 0>), grid, dim3(256), sh, st, a));
+  const bool fx = a.fixed && plan_is_576(a.plan);
+  if (a.pipe) {
+    if (fx) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 576, 256, true>), grid, dim3(256), sh, st, a));
+    else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 0, 256, true>), grid, dim3(256), sh, st, a));
+  } else {
+    if (fx) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 576>), grid, dim3(256), sh, st, a));
+    else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zfwd<T, TO, MV, 0>), grid, dim3(256), sh, st, a));
+  }
   return hipGetLastError();
 }
 

@@ -70,18 +70,20 @@ def test_every_schedule_matches_oracle(name, precision):
                 break
         assert kmax >= 1
         tried = set()
-        for fixed in (0, 1):
-            for x_rows in (8, 4, 2, 1):
-                for k in sorted({1, 2, 3, kmax}):
-                    if k > kmax:
-                        continue
-                    try:
-                        ch.set_plan(x_rows, k, None, fixed)
-                    except ChnError:  # more rows than the staging registers or LDS hold
-                        assert x_rows > 2, (x_rows, k)
-                        continue
-                    tried.add(x_rows)
-                    _check(ch, fields, ref, TOL[precision], f"{precision} rows={x_rows} lines={k} fixed={fixed}")
+        for pipe in (0, 1):
+            for fixed in (0, 1):
+                for x_rows in (8, 4, 2, 1):
+                    for k in sorted({1, 2, 3, kmax}):
+                        if k > kmax:
+                            continue
+                        try:
+                            ch.set_plan(x_rows, k, None, fixed, pipe)
+                        except ChnError:  # more rows than the staging registers or LDS hold
+                            assert x_rows > 2, (x_rows, k)
+                            continue
+                        tried.add(x_rows)
+                        _check(ch, fields, ref, TOL[precision],
+                               f"{precision} rows={x_rows} lines={k} fixed={fixed} pipeline={pipe}")
         assert {1, 2} <= tried
         ch.set_plan(2, 1, max(1, case.n2 // 3))  # planes in chunks
         _check(ch, fields, ref, TOL[precision], f"{precision} chunked planes")
