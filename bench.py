@@ -309,17 +309,31 @@ def c5_run(reps=5, precision="mixed"):
     # algorithmic bytes: the three velocity coefficient fields in (float32
     # complex on the mixed path), F(u_i) and F(u_i u_j) out (complex128 on the
     # retained set), tau_ij out (float64 on the q grid); nominal flops: the
-    # inverse transforms of u_i to the 3/2 grid and the forward transforms of
-    # the six products (2.5 n log2 n each), the tau grid's transforms ignored
+    # inverse transforms of u_i and the forward transforms of the six
+    # products (2.5 n log2 n each) on the grid the stage uses, the smallest
+    # 2,3-smooth f > 2 h + kc per direction (h the highest stored
+    # wavenumber), the tau grid's transforms ignored
     NP = c.n2 * (c.n1 // 2) * c.n3
     R = (kcx + 1) * (2 * kcz + 1)
     alg = 3 * NP * (8 if precision == "mixed" else 16) + 9 * c.n2 * R * 16 + 6 * c.n2 * q1 * q3 * 8
     import math
-    n = (3 * c.n1 // 2) * (3 * c.n3 // 2)
+
+    def grid(h, kc):
+        n = 2 * h + kc + 1
+        while True:
+            m = n
+            for p in (2, 3):
+                while m % p == 0:
+                    m //= p
+            if m == 1:
+                return n
+            n += 1
+    f1, f3 = grid(c.n1 // 2 - 1, kcx), grid(c.n3 // 2 - 1, kcz)
+    n = f1 * f3
     fl = 9 * c.n2 * 2.5 * n * math.log2(n)
     roof = {"bound": "hbm", "achieved": round(alg / (ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_bytes": alg,
-            "nominal_flop": fl, "TFLOPs": round(fl / (ms / 1e3) / 1e12, 2)}
+            "nominal_flop": fl, "TFLOPs": round(fl / (ms / 1e3) / 1e12, 2), "product_grid": [f1, f3]}
     return {"workload": f"low-storage stage, {c.n1}x{c.n2}x{c.n3}, kc=({kcx},{kcz}), q=({q1},{q3})",
             "precision": precision, "ms_median": round(ms, 3), "ms_min": round(ms_min, 3),
             "roofline": roof,

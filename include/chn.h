@@ -187,22 +187,35 @@ chn_status chn_nonlinear(chn_ctx *ctx, const double *const *d_in, double *const 
  * retained set K = {0 <= kx <= kcx, |kz| <= kcz} (kcx < n1/2, kcz < n3/2):
  *   d_ubar  [3][n2][kcx+1][2kcz+1] complex: F(u_i) for i = 1, 2, 3,
  *   d_uubar [6][n2][kcx+1][2kcz+1] complex: F(u_i u_j), pairs 11,12,13,22,23,33,
- *           products formed on the 3/2 padded grid,
+ *           the products formed on an f1 x f3 grid of each plane with
+ *           f1 > n1 - 2 + kcx, f3 > n3 - 2 + kcz (2,3-smooth, at most the
+ *           3/2 padded grid), on which every retained product mode is exact,
  *   d_tau   [6][n2][q3][q1] float64: tau_ij = F(u_i u_j) - F(u_i) F(u_j)
  *           evaluated on the uniform q1 x q3 grid of each plane,
  * kz in FFT slot order (0..kcz, then -kcz..-1).  q1 > 2 kcx, q3 > 2 kcz,
- * both even and factoring into 2s and 3s.  d_tau may be NULL. */
+ * both even and factoring into 2s and 3s.  d_tau may be NULL.  Outputs are
+ * complex float64 / float64 DEVICE arrays owned by the caller.  The inputs
+ * are the velocity coefficients the time step holds in the context's
+ * transform precision (CHN_MIXED: float32, with float32 inverse transforms);
+ * the products, forward transforms, mean terms and stresses are float64 on
+ * both precisions.  The state, the time step's phase fields and its
+ * factor tables are left unchanged.  CHN_EINVAL for a cut-off or q grid
+ * outside these ranges or a NULL output; CHN_EUNSUPPORTED where the
+ * workspace cannot hold the retained products or the q grid. */
 chn_status chn_filter_and_stress(chn_ctx *ctx, int32_t kcx, int32_t kcz, int32_t q1, int32_t q3,
                                  double *d_ubar, double *d_uubar, double *d_tau);
 
 /* Filtered enstrophy of Section 3.1 (the tenth variable of the database):
  * F(omega_i omega_i), the sharp cut-off (0 <= kx <= kcx, |kz| <= kcz) of
- * omega_1^2 + omega_2^2 + omega_3^2 formed on the 3n1/2 x 3n3/2 grid of
- * every plane from the vorticity of the current state (omega1, omega3 by
- * continuity and compact D1, the mean vorticity D1 U3, -D1 U1 included).
- * d_out: DEVICE, complex float64 [n2][kcx+1][2kcz+1], kz in slot order as
- * for chn_filter_and_stress; owned by the caller.  Float64 transforms and
- * products on both precisions.  CHN_EINVAL for a cut-off outside
+ * omega_1^2 + omega_2^2 + omega_3^2 formed on the f1 x f3 grid of
+ * chn_filter_and_stress from the vorticity of the current state (omega1,
+ * omega3 by continuity and compact D1, the mean vorticity D1 U3, -D1 U1
+ * included).  d_out: DEVICE, complex float64 [n2][kcx+1][2kcz+1], kz in
+ * slot order as for chn_filter_and_stress; owned by the caller.  The
+ * vorticity coefficients in the context's transform precision (CHN_MIXED:
+ * float32 omega1, omega3 of the time step and omega2 rounded to float32,
+ * float32 inverse transforms); the sum of squares, forward transforms and
+ * mean terms in float64.  CHN_EINVAL for a cut-off outside
  * 0 <= kcx < n1/2, 0 <= kcz < n3/2 or a NULL pointer; CHN_ESTATE before
  * chn_set_state; CHN_EUNSUPPORTED on a planes_only context or where the
  * workspace cannot hold the retained products.  Uses the scratch of

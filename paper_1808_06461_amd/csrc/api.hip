@@ -91,6 +91,9 @@ struct chn_ctx {
   void *tw1 = nullptr, *tw3 = nullptr;
   double2 *tw1d = nullptr, *tw3d = nullptr, *twq = nullptr;  // float64 tables (filter stage)
   std::vector<double> twq_host;
+  double2* twf = nullptr;  // filter-grid tables (filter stage), for the sizes twf_n1, twf_n3
+  std::vector<double> twf_host;
+  int twf_n1 = 0, twf_n3 = 0;
   FftPlan plan1{}, plan3{};
   double *mean_scr = nullptr, *mean_out = nullptr, *info_dev = nullptr;
   unsigned* guard = nullptr;  // instability guard, four words (common.hpp)
@@ -171,6 +174,7 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
   void* tw1d = cv.take(16 * (size_t)p1);
   void* tw3d = cv.take(16 * (size_t)p3);
   void* twq = cv.take(16 * (size_t)kMaxQ * 2);
+  void* twf = cv.take(16 * (size_t)kMaxQ * 2);
   double* mean_scr = D(3 * (size_t)n2 * 5 + 4 * (size_t)n2);
   double* mean_out = D(8);
   double* info = D(8);
@@ -202,6 +206,7 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
     x->tw1d = reinterpret_cast<double2*>(tw1d);
     x->tw3d = reinterpret_cast<double2*>(tw3d);
     x->twq = reinterpret_cast<double2*>(twq);
+    x->twf = reinterpret_cast<double2*>(twf);
     x->mean_scr = mean_scr; x->mean_out = mean_out; x->info_dev = info;
     x->guard = guard;
   }
@@ -565,15 +570,26 @@ chn_status static_scratch(chn_ctx* x, void** out) {
 // With d_ens the same transforms run on the vorticity (omega1, omega2,
 // omega3) instead of the velocity, and only the trace F(omega_i omega_i), the
 // filtered enstrophy, is written (q1, q3, d_ubar, d_uubar, d_tau unused).
+// Smallest 2,3-smooth size above 2 h + kc (h = highest stored wavenumber of
+// the direction, kc = cut-off), at most p: a grid on which the retained modes
+// of every product are exact.
+int filter_grid(int h, int kc, int p) {
+  for (int n = 2 * h + kc + 1; n < p; ++n)
+    if (smooth23(n)) return n;
+  return p;
+}
+
+// The low-storage stage (filter + products + stresses, or the filtered
+// enstrophy when d_ens is given) from the phase-precision fields of the
+// state.  Buffers: the z-inverse output in the plane intermediate, the x
+// output in S[0..2], pp in the H buffers, the q-grid intermediate in the
+// plane intermediate.  The state, the phase fields and the factor tables
+// are left as they are.
 chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_ubar, double* d_uubar,
                         double* d_tau, double* d_ens = nullptr) {
-  using C = double2;
+  using CT = double2;
   const bool ens = d_ens != nullptr;
-  const int n2 = x->n2, n1h = x->n1h, n3 = x->n3, p1 = x->p1, p3 = x->p3;
-  const size_t te = sizeof(C);
-  // slots of the intermediate per plane: float64 data in a float32-sized buffer on the mixed path
-  const int nslot = x->mixed ? 3 : 6;
-  const size_t plane_bytes = (size_t)(x->mixed ? 6 * 8 : 6 * 16) * p3 * n1h;
+  const int n2 = x->n2, n1h = x->n1h, n3 = x->n3;
   if (!ens && (!d_ubar || !d_uubar)) return fail(x, CHN_EINVAL, "NULL output pointer");
   if (kcx < 0 || kcz < 0 || kcx >= n1h || kcz >= n3 / 2) return fail(x, CHN_EINVAL, "need 0 <= kcx < n1/2, 0 <= kcz < n3/2");
   if (!ens && (q1 <= 2 * kcx || q3 <= 2 * kcz || (q1 % 2) || (q3 % 2) || !smooth23(q1) || !smooth23(q3) ||
@@ -581,16 +597,17 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
     return fail(x, CHN_EINVAL, "q1, q3 must be even, 2,3-smooth, <= 4096 and exceed 2 kcx, 2 kcz");
   const int kc1 = kcx + 1, nz = 2 * kcz + 1;
   const size_t NP = (size_t)n2 * x->M;
-  // buffer reuse: x-filter output in the free slots 3..5 of each plane of the
-  // intermediate (float64 contexts) or in S[0..2] (mixed), pp in the H
-  // buffers, the q-grid intermediate in the intermediate
-  const size_t hbytes = 3 * NP * (x->mixed ? 8 : 16);
-  if (!x->mixed && (size_t)6 * p3 * kc1 * 16 > (size_t)3 * p3 * n1h * te) return fail(x, CHN_EUNSUPPORTED, "kcx too large for the workspace");
-  if (x->mixed && (size_t)6 * n2 * p3 * kc1 * 16 > 3 * 16 * NP) return fail(x, CHN_EUNSUPPORTED, "kcx too large for the workspace");
-  if ((size_t)6 * n2 * kc1 * nz * 16 > hbytes) return fail(x, CHN_EUNSUPPORTED, "cut-off too large for the workspace");
+  const int f1 = filter_grid(n1h - 1, kcx, x->p1), f3 = filter_grid(n3 / 2 - 1, kcz, x->p3);
+  const int nout = ens ? 1 : 6;
+  if (f1 > 12 * 256 || f3 > kMaxQ) return fail(x, CHN_EUNSUPPORTED, "plane too large for the filter x-pass");
+  if ((size_t)3 * n2 * f3 * n1h * sizeof(CT) > x->inter_bytes)
+    return fail(x, CHN_EUNSUPPORTED, "filter grid too large for the workspace");
+  // S[0..2] are consecutive allocations, so their span holds 3 * 16 NP bytes
+  if ((size_t)nout * n2 * f3 * kc1 * 16 > 3 * 16 * NP) return fail(x, CHN_EUNSUPPORTED, "kcx too large for the workspace");
+  if (!ens && (size_t)6 * n2 * kc1 * nz * 16 > 3 * NP * (x->mixed ? 8 : 16))
+    return fail(x, CHN_EUNSUPPORTED, "cut-off too large for the workspace");
   if (!ens && (size_t)9 * n2 * q3 * kc1 * 16 > x->inter_bytes) return fail(x, CHN_EUNSUPPORTED, "q grid too large for the workspace");
-  if (p1 > 12 * 256) return fail(x, CHN_EUNSUPPORTED, "3*n1/2 too large for the filter x-pass");
-  const size_t lds_x = (size_t)(p1 + 1) * 16;  // one line at a time
+  const size_t lds_x = (size_t)(f1 + 1) * 16;  // one float64 line
   const size_t lds_t = (size_t)5 * (q1 + 1) * 16;
   auto lines = [&](int len, int cap) {
     int K = 24 * 256 / len;
@@ -600,12 +617,28 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
     if (K > cap) K = cap;
     return K < 1 ? 1 : K;
   };
-  const int Kf = lines(p3, kc1), Kq = ens ? 1 : lines(q3, kc1);
-  if (lds_x > (size_t)x->lds_max || lds_t > (size_t)x->lds_max || (size_t)(p3 + 1) * 16 > (size_t)x->lds_max ||
-      2 * p1 > 24 * 256 || p1 > 24 * 256 || p3 > 24 * 256 || 5 * q1 > 24 * 256 ||
-      q3 > 24 * 256)
+  const int Kf = lines(f3, kc1), Kq = ens ? 1 : lines(q3, kc1);
+  if (lds_x > (size_t)x->lds_max || (size_t)(f3 + 1) * 16 > (size_t)x->lds_max || f3 > 24 * 256 ||
+      (!ens && (lds_t > (size_t)x->lds_max || 5 * q1 > 24 * 256 || q3 > 24 * 256)))
     return fail(x, CHN_EUNSUPPORTED, "plane too large for the filter kernels' LDS tiles on this device");
-  // q-grid FFT tables
+  // FFT tables of the filter grid and of the q grid (float64)
+  FftPlan pf1{}, pf3{};
+  {
+    std::vector<double> t1, t3;
+    if (!chn::host::fft_plan(f1, &pf1, &t1) || !chn::host::fft_plan(f3, &pf3, &t3))
+      return fail(x, CHN_EINVAL, "filter grid not supported");
+    if (x->twf_n1 != f1 || x->twf_n3 != f3) {
+      std::vector<double>& h = x->twf_host;  // [f1 | f3], kMaxQ entries each
+      h.assign((size_t)4 * kMaxQ, 0.0);
+      std::copy(t1.begin(), t1.end(), h.begin());
+      std::copy(t3.begin(), t3.end(), h.begin() + 2 * kMaxQ);
+      HIPCHK(x, hipMemcpyAsync(x->twf, h.data(), h.size() * 8, hipMemcpyHostToDevice, x->stream));
+      x->twf_n1 = f1;
+      x->twf_n3 = f3;
+    }
+  }
+  const double2* twf1 = x->twf;
+  const double2* twf3 = x->twf + kMaxQ;
   FftPlan pq1{}, pq3{};
   if (!ens) {
     std::vector<double> t1, t3;
@@ -618,90 +651,107 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   }
   const double2* twq1 = x->twq;
   const double2* twq3 = x->twq + kMaxQ;
-  // 1. float64 spectra of u1, u2, u3, omega1, omega3 (omega2 is the state);
-  //    mixed: the velocities rounded to float32 in place (the stored data of
-  //    that path; the enstrophy is formed from the float64 vorticity)
-  double* su[5] = {x->S[3], x->S[4], x->S[5], x->S[6], x->S[7]};
-  x->htab_dt = 0.0;  // overwrites the factor tables of sub-steps 1 and 2
-  if (chn_status st = recover<double>(x, su, ens)) return st;  // the stresses need the velocities only
-  double* fin[3] = {x->S[3], x->S[4], x->S[5]};
-  if (ens) {
-    fin[0] = x->S[6];
-    fin[1] = x->om2;
-    fin[2] = x->S[7];
-  }
-  if (x->mixed && !ens) {
-    // the plane intermediate (9 n2 M float64 or more) is free until step 2;
-    // the phase fields stay valid for the next sub-step
-    for (int f = 0; f < 3; ++f) {
-      float* tmp = reinterpret_cast<float*>(x->inter);
-      HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_convert_d2f(x->S[3 + f], tmp, 2 * NP, x->stream); }));
-      HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_convert_f2d(tmp, x->S[3 + f], 2 * NP, x->stream); }));
+  // 1. the phase fields of the state: u1, u2, u3, omega1, omega3 (current
+  //    after a step; recovered for a new state), float32 on the mixed path;
+  //    omega2 is the float64 state itself
+  void* po[5];
+  if (x->mixed) {
+    float* pf[5];
+    phase_ptrs<float>(x, pf);
+    if (!x->phase_valid) {
+      if (chn_status st = recover<float>(x, pf)) return st;
+      x->phase_valid = true;
     }
+    for (int f = 0; f < 5; ++f) po[f] = pf[f];
+  } else {
+    double* pd[5];
+    phase_ptrs<double>(x, pd);
+    if (!x->phase_valid) {
+      if (chn_status st = recover<double>(x, pd)) return st;
+      x->phase_valid = true;
+    }
+    for (int f = 0; f < 5; ++f) po[f] = pd[f];
   }
-  // 2. z inverse of the fluctuations
+  chn::FieldsIn fin{};
+  const unsigned all32 = x->mixed ? 7u : 0u;
+  if (ens) {
+    fin.u[0] = po[3];
+    fin.u[1] = x->om2;
+    fin.u[2] = po[4];
+    fin.f32 = all32 & 5u;
+  } else {
+    for (int f = 0; f < 3; ++f) fin.u[f] = po[f];
+    fin.f32 = all32;
+  }
+  // 2. z inverse of the fluctuations onto f3 points
+  chn::PlaneDims fd = x->dims;
+  fd.p1 = f1;
+  fd.p3 = f3;
   chn::ZinvArgs<double> za{};
-  for (int f = 0; f < 3; ++f) za.in[f] = reinterpret_cast<const C*>(fin[f]);
-  za.out = reinterpret_cast<C*>(x->inter);
-  za.tw = x->tw3d;
-  za.plan = x->plan3;
-  za.d = x->dims;
-  za.lstride = plane_lds_stride(p3);
+  for (int f = 0; f < 3; ++f) za.in[f] = reinterpret_cast<const CT*>(fin.u[f]);
+  za.in_f32 = fin.f32;
+  za.out = reinterpret_cast<CT*>(x->inter);
+  za.tw = twf3;
+  za.plan = pf3;
+  za.d = fd;
+  za.lstride = plane_lds_stride(f3);
   // lines per workgroup: at most what leaves room for three workgroups per CU
-  za.K = std::max(1, std::min(lines(p3, n1h), (int)((size_t)x->lds_max / 3 / ((size_t)za.lstride * 16))));
+  za.K = std::max(1, std::min(lines(f3, n1h), (int)((size_t)x->lds_max / 3 / ((size_t)za.lstride * sizeof(CT)))));
   za.nfields = 3;
-  za.nslot = nslot;
+  za.nslot = 3;
   za.zero_mean = 1;
   za.y0 = 0;
   za.ny = n2;
-  while (za.K > 1 && (size_t)za.K * za.lstride * 16 > (size_t)x->lds_max) --za.K;
-  if ((size_t)za.K * za.lstride * 16 > (size_t)x->lds_max) return fail(x, CHN_EUNSUPPORTED, "z lines exceed LDS");
+  za.pipe = 1;
+  while (za.K > 1 && (size_t)za.K * za.lstride * sizeof(CT) > (size_t)x->lds_max) --za.K;
+  if ((size_t)za.K * za.lstride * sizeof(CT) > (size_t)x->lds_max) return fail(x, CHN_EUNSUPPORTED, "z lines exceed LDS");
   HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_zinv<double>(za, x->stream); }));
-  // 3. products and float64 forward in x
+  // 3. inverse in x, products, float64 forward in x
   chn::XfilterArgs<double> xa{};
-  xa.buf = reinterpret_cast<const C*>(x->inter);
-  xa.nslot = nslot;
-  if (x->mixed) {
-    xa.out = reinterpret_cast<double2*>(x->S[0]);
-    xa.plane_stride = (size_t)6 * p3 * kc1;
-  } else {
-    xa.out = reinterpret_cast<double2*>(reinterpret_cast<char*>(x->inter) + (size_t)3 * p3 * n1h * te);
-    xa.plane_stride = plane_bytes / 16;
-  }
-  xa.tw = x->tw1d;
-  xa.plan = x->plan1;
-  xa.tw_d = x->tw1d;
-  xa.plan_d = x->plan1;
-  xa.d = x->dims;
-  xa.lst = p1 + 1;
-  xa.lsd = p1 + 1;
+  xa.buf = za.out;
+  xa.out = reinterpret_cast<double2*>(x->S[0]);
+  xa.plane_stride = (size_t)nout * f3 * kc1;
+  xa.tw = twf1;
+  xa.plan = pf1;
+  xa.tw_d = twf1;
+  xa.n1h = n1h;
+  xa.n2 = n2;
+  xa.f1 = f1;
+  xa.f3 = f3;
+  xa.lst = f1 + 1;
+  xa.lsd = f1 + 1;
   xa.kcx = kcx;
+  xa.trace = ens ? 1 : 0;
   HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_xfilter<double>(xa, lds_x, x->stream); }));
   // 4. float64 forward in z, retained set, mean terms
   chn::ZfilterArgs fa{};
   fa.xout = xa.out;
   fa.plane_stride = xa.plane_stride;
-  for (int f = 0; f < 3; ++f) fa.u[f] = fin[f];
+  fa.u = fin;
   fa.pp = reinterpret_cast<double2*>(x->H[0]);
   fa.uubar = ens ? nullptr : reinterpret_cast<double2*>(d_uubar);
   fa.ubar = ens ? nullptr : reinterpret_cast<double2*>(d_ubar);
   fa.trace = ens ? reinterpret_cast<double2*>(d_ens) : nullptr;
-  fa.tw = x->tw3d;
-  fa.plan = x->plan3;
-  fa.d = x->dims;
+  fa.trace_only = ens ? 1 : 0;
+  fa.tw = twf3;
+  fa.plan = pf3;
+  fa.n1h = n1h;
+  fa.n2 = n2;
+  fa.n3 = n3;
+  fa.f3 = f3;
   fa.kcx = kcx;
   fa.kcz = kcz;
   fa.K = Kf;
-  fa.lstride = p3 + 1;
-  fa.scale = 1.0 / ((double)p1 * p3);
+  fa.lstride = f3 + 1;
+  fa.scale = 1.0 / ((double)f1 * f3);
   HIPCHK(x, timed(x, CHN_K_FILTER, [&] {
-    return chn::launch_zfilter(fa, (size_t)Kf * (p3 + 1) * 16, x->stream);
+    return chn::launch_zfilter(fa, (size_t)Kf * (f3 + 1) * 16, x->stream);
   }));
   if (ens || !d_tau) return CHN_OK;
   // 5. q grid: inverse in z, then in x with tau = pp - ub ub
   chn::ZinvQArgs qa{};
   qa.pp = fa.pp;
-  for (int f = 0; f < 3; ++f) qa.u[f] = x->S[3 + f];
+  qa.u = fin;
   qa.out = reinterpret_cast<double2*>(x->inter);
   qa.tw = twq3;
   qa.plan = pq3;

@@ -27,6 +27,8 @@ template <typename T> struct ZinvArgs {
                        // with y0 == 0 resets; nullptr outside the time step
   int pipe;            // nonzero: the next field's loads overlap this field's transform
                        // (256-thread launches whose field fits the staging registers)
+  unsigned in_f32;     // bit f set: in[f] points to float32 coefficients, widened on
+                       // load (float64 transforms of float32 data; 0 for float32 transforms)
 };
 
 template <typename T> struct XpassArgs {
@@ -68,38 +70,49 @@ int xrow_threads(int p1, int bytes_per_value);  // 0: too long
 template <typename T, typename TO> hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st);
 
 // ---------------------------------------------------------------- filter stage
+// The products are formed on an f1 x f3 grid with f > 2 h + kc (h = highest
+// stored wavenumber of the direction, kc the cut-off): every product mode
+// that aliases onto a retained one lies beyond 2 h, so the retained modes are
+// exact on that grid (the 3/2 grid of the time step is one such grid).
 template <typename T> struct XfilterArgs {
-  const c2<T>* buf;      // [n2][nslot][p3][n1h], slots 0..2 = u1, u2, u3 after the z inverse
-  int nslot;
-  double2* out;          // per plane y at out + y * plane_stride: [6][p3][kcx+1]
+  const c2<T>* buf;      // [n2][3][f3][n1h]: the three fields after the z inverse (float64 in use)
+  double2* out;          // per plane y at out + y * plane_stride: [6][f3][kcx+1] (trace: [1][f3][kcx+1])
   size_t plane_stride;   // in double2 elements
-  const c2<T>* tw;       // p1 plan, context precision
+  const c2<T>* tw;       // f1 plan twiddles, phase precision (inverse)
   FftPlan plan;
-  const double2* tw_d;   // p1 plan, float64
-  FftPlan plan_d;
-  PlaneDims d;
-  int lst, lsd;          // LDS line strides (context-precision and float64 lines)
+  const double2* tw_d;   // f1 plan twiddles, float64 (forward)
+  int n1h, n2, f1, f3;
+  int lst, lsd;          // LDS line strides (phase-precision and float64 lines)
   int kcx;
+  int trace;             // nonzero: one product, the sum of the three squares
+};
+
+// The three fields' coefficients, spectral [n2][n1h][n3]: complex float64, or
+// complex float32 where bit i of `f32` is set.
+struct FieldsIn {
+  const void* u[3];
+  unsigned f32;
 };
 
 struct ZfilterArgs {
   const double2* xout;   // output of k_xfilter
   size_t plane_stride;
-  const double* u[3];    // float64 spectral u1, u2, u3 (full mode set)
+  FieldsIn u;            // the three fields (full mode set)
   double2* pp;           // [6][n2][kcx+1][2kcz+1] F(u'_i u'_j)
   double2* uubar;        // [6][n2][kcx+1][2kcz+1] F(u_i u_j), or nullptr
   double2* ubar;         // [3][n2][kcx+1][2kcz+1] F(u_i), or nullptr
-  double2* trace;        // [n2][kcx+1][2kcz+1] F(u_i u_i) (sum over i), or nullptr
-  const double2* tw;     // p3 plan, float64
+  double2* trace;        // trace mode: [n2][kcx+1][2kcz+1] F(u_i u_i) (sum over i)
+  const double2* tw;     // f3 plan, float64
   FftPlan plan;
-  PlaneDims d;
+  int n1h, n2, n3, f3;
   int kcx, kcz, K, lstride;
-  double scale;          // 1 / (p1 p3)
+  double scale;          // 1 / (f1 f3)
+  int trace_only;        // nonzero: xout holds the trace of the fluctuation squares
 };
 
 struct ZinvQArgs {
   const double2* pp;
-  const double* u[3];
+  FieldsIn u;
   double2* out;          // [n2][9][q3][kcx+1]
   const double2* tw;     // q3 plan
   FftPlan plan;

@@ -32,6 +32,17 @@ constexpr bool kPad = true;
 constexpr int kZinvStage = 8;
 constexpr int kZfwdStage = 12;
 
+// Input coefficient idx of field f; float32 data widened where in_f32 says so.
+template <typename T> __device__ __forceinline__ c2<T> ldin(const ZinvArgs<T>& a, int f, size_t idx) {
+  if constexpr (sizeof(T) == 8) {
+    if ((a.in_f32 >> f) & 1u) {
+      const float2 v = reinterpret_cast<const float2*>(a.in[f])[idx];
+      return mk<T>((T)v.x, (T)v.y);
+    }
+  }
+  return a.in[f][idx];
+}
+
 template <typename T, int MAXV, int FN = 0, bool PIPE = false>
 __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) {
   extern __shared__ unsigned char smem_raw[];
@@ -71,7 +82,7 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
         const int l = (int)qdiv(e, n3, mn3), s = e - l * n3;
         st[q] = zero;
         if (e < tot && l < nk && s != half && !(a.zero_mean && kx0 + l == 0 && s == 0))
-          st[q] = a.in[f][((size_t)y * n1h + kx0 + l) * n3 + s];
+          st[q] = ldin(a, f, ((size_t)y * n1h + kx0 + l) * n3 + s);
       }
     };
     fetch(loads[0]);
@@ -118,11 +129,11 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
         // omega2 = i (b u1 - a u3)
         const int kz = s < half ? s : s - n3;
         const T ka = T(tpx * (kx0 + l)), kb = T(tpz * kz);
-        const c2<T> u1 = a.in[0][idx], u3 = a.in[2][idx];
+        const c2<T> u1 = ldin(a, 0, idx), u3 = ldin(a, 2, idx);
         const c2<T> t = mk<T>(kb * u1.x - ka * u3.x, kb * u1.y - ka * u3.y);
         v = mk<T>(-t.y, t.x);
       } else {
-        v = a.in[f][idx];
+        v = ldin(a, f, idx);
       }
     }
     return v;

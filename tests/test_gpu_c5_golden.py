@@ -6,9 +6,10 @@ samples of F(u_i), F(u_i u_j) and tau_ij on the planes y_3, y_96 and y_192;
 the GPU computes every plane with the launch configuration of the full stage
 and is compared there: e(X) = ||X_gpu[s] - X_oracle[s]|| / ||X_oracle[s]||
 per component.  Bounds: float64 as for the small cases (F(u_i) 1e-13,
-F(u_i u_j) 1e-12, tau 1e-10); mixed 1e-5 on F(u_i u_j) and tau.  The
-filtered enstrophy F(omega_i omega_i) (float64 from the float64 vorticity on
-both paths) is compared on its own seeded samples and its (0,0) mode: 1e-12.
+F(u_i u_j) 1e-12, tau 1e-10); mixed (float32 coefficients and inverse
+transforms, float64 products and forward sums) 1e-5 on F(u_i u_j) and tau.
+The filtered enstrophy F(omega_i omega_i) is compared on its own seeded
+samples and its (0,0) mode: 1e-12 (float64), 1e-5 (mixed).
 """
 import os
 
@@ -67,6 +68,7 @@ def test_c5_filter_against_oracle_samples(field, precision):
             e_ens = rel(got, g[f"y{p}_ens"])
             e_00 = abs(complex(ens[p, 0, 0].item()) - complex(g[f"y{p}_ens00"])) / abs(complex(g[f"y{p}_ens00"]))
             print(f"[c5] {precision} y{p}: enstrophy {e_ens:.2e}, mode (0,0) {e_00:.2e}", flush=True)
-            assert e_ens <= 1e-12 and e_00 <= 1e-12, (p, e_ens, e_00)
+            t_ens = 1e-12 if precision == "fp64" else 1e-5
+            assert e_ens <= t_ens and e_00 <= t_ens, (p, e_ens, e_00)
     finally:
         ch.close()

@@ -17,7 +17,10 @@
   squared fluctuation computed pointwise from a direct synthesis (no FFT);
 * the filter equals the physical-space convolution with the sharp cut-off
   kernel (inclusive cut-off, no FFT), and it commutes with the compact
-  wall-normal D1 and D2 (it acts on x and z only).
+  wall-normal D1 and D2 (it acts on x and z only);
+* the retained modes of a product are exact on any grid with f > 2 h + kc
+  per direction (h the highest stored wavenumber), the reading behind the
+  smaller product grid of the library, and not on f = 2 h + kc.
 """
 import numpy as np
 import pytest
@@ -216,3 +219,34 @@ def test_filter_commutes_with_the_wall_normal_derivative():
         lhs = lowstorage.truncate(d(S, uh), 3, 2)
         rhs = d(S, lowstorage.truncate(uh, 3, 2))
         np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-13 * np.abs(lhs).max())
+
+
+@pytest.mark.parametrize("kcx,kcz", [(2, 2), (5, 3)])
+def test_retained_product_modes_exact_above_2h_plus_kc(kcx, kcz):
+    """Products formed on an f1 x f3 grid with the oracle's transforms (no
+    padding rule): equal to the brute-force convolution on the retained set
+    when f1 > 2 h1 + kcx and f3 > 2 h3 + kcz, aliased one point below."""
+    rng = np.random.default_rng(11)
+    a, b = _field(rng), _field(rng)
+    h1, h3 = N1 // 2 - 1, N3 // 2 - 1
+    slots = lowstorage.kc_slots(N3, kcz)
+    kzs = [s if s < N3 // 2 else s - N3 for s in slots]
+
+    def retained(f1, f3):
+        fa, fb = fourier.to_physical(a, f1, f3), fourier.to_physical(b, f1, f3)
+        # forward transform onto the full stored set of the f1 x f3 grid
+        F = np.fft.rfft2(fa * fb) / (f1 * f3)
+        return np.array([[[F[y, kz % f3, kx] for kz in kzs] for kx in range(kcx + 1)] for y in range(N2)])
+
+    ref = np.zeros((N2, kcx + 1, len(kzs)), complex)
+    for y in range(N2):
+        prod = brute.product_modes(brute.full_modes(a[y]), brute.full_modes(b[y]))
+        for kx in range(kcx + 1):
+            for c, kz in enumerate(kzs):
+                ref[y, kx, c] = prod.get((kx, kz), 0)
+    scale = np.abs(ref).max()
+    f1, f3 = 2 * h1 + kcx + 1, 2 * h3 + kcz + 1
+    assert np.abs(retained(f1, f3) - ref).max() < 1e-13 * scale
+    assert np.abs(retained(f1 + 3, f3 + 2) - ref).max() < 1e-13 * scale
+    assert np.abs(retained(f1 - 1, f3) - ref).max() > 1e-3 * scale
+    assert np.abs(retained(f1, f3 - 1) - ref).max() > 1e-3 * scale
