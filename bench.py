@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-points x RK3 steps/sec, mixed-prec vs FP64 GPU at stated rel. error"
 UNIT = "grid-points*RK3-steps/s"
 HBM_PEAK_GBS = 8000.0
-FIXED_PLAN = None  # (x_rows, z_lines, y_chunk[, fixed_radix[, z_pipeline]]) from --plan; None: autotune
+FIXED_PLAN = None  # (x_rows, z_lines, y_chunk[, fixed_radix[, z_pipeline[, radix_set]]]) from --plan; None: autotune
 
 
 def algorithmic_bytes(kind, n1, n2, n3, elem):
@@ -199,6 +199,20 @@ def c3_run(reps=3):
     synth.c3_fill_slab(fields, (), cfg=c["cfg"])
     fields[4] = None  # omega2 formed in the z pass, as in the RK3 sub-step
     out = [torch.empty((P, n1 // 2, n3), dtype=torch.complex64, device="cuda") for _ in range(3)]
+    # the slab's schedule: the default one under each radix set (a planes_only
+    # context has no buffers of its own for chn_autotune), the fastest kept
+    base = ch.plan()
+    by_set = {}
+    for rs in range(4):
+        ch.set_plan(base["x_rows"], base["z_lines"], base["y_chunk"], base["fixed_radix"], base["z_pipeline"], rs)
+        ch.plane_products(fields, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.plane_products(fields, out)
+        torch.cuda.synchronize()
+        by_set[rs] = round((time.perf_counter() - t0) * 1e3, 2)
+    best = min(by_set, key=by_set.get)
+    ch.set_plan(base["x_rows"], base["z_lines"], base["y_chunk"], base["fixed_radix"], base["z_pipeline"], best)
     ch.plane_products(fields, out)
     ch.timing(True)
     for _ in range(reps):
@@ -206,7 +220,7 @@ def c3_run(reps=3):
     kern = ch.timing_read()
     ch.timing(False)
     planes = {"shape": f"{P} planes x {n1} x {n3} modes ({3 * n1 // 2} x {3 * n3 // 2} padded)",
-              "plan": ch.plan()}
+              "plan": ch.plan(), "ms_by_radix_set": by_set}
     tot = 0.0
     for k in ("zinv", "xpass", "zfwd"):
         t, n = kern[k]
@@ -398,7 +412,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the per-phase timing of the Re_tau 5300 share")
     ap.add_argument("--no-c5", action="store_true", help="skip the timing of the low-storage stage")
     ap.add_argument("--no-meshopt", action="store_true", help="skip the near-wall mesh optimisation leg")
-    ap.add_argument("--plan", default=None, metavar="XROWS,ZLINES,YCHUNK[,FIXED[,ZPIPE]]",
+    ap.add_argument("--plan", default=None, metavar="XROWS,ZLINES,YCHUNK[,FIXED[,ZPIPE[,RADIXSET]]]",
                     help="fixed plane-phase schedule instead of the autotuner (for profiling one schedule)")
     ap.add_argument("--source-hash", default=None, metavar="KIND",
                     help="print the source hash a traffic summary of this kernel kind must carry, then exit")

@@ -401,11 +401,18 @@ typedef struct {
                            omega2 from the u1, u3 values it loaded), where a
                            field of z_lines lines fits their staging registers;
                            0: one field at a time */
+  int32_t radix_set;    /* bit 0 for the x transforms, bit 1 for the z
+                           transforms: 0 = Stockham passes of radix 8, then 4,
+                           2, 3; 1 = the fewest passes with radices up to 16
+                           (6, 9, 12 and 16 computed in registers: 576 points
+                           in 3 passes instead of 4, 1296 in 3 instead of 6).
+                           fixed_radix applies to 576-point lines in either
+                           set (8, 8, 3, 3 or 9, 8, 8) */
 } chn_plan;
 
 /* Current schedule (chn_create picks 2 rows when they fit, 16 lines capped
- * by registers and LDS, plane_chunk or all planes, and the runtime radix
- * plan). */
+ * by registers and LDS, plane_chunk or all planes, and radix set 0 with its
+ * compile-time schedules). */
 chn_status chn_get_plan(chn_ctx *ctx, chn_plan *plan);
 
 /* Sets the schedule; CHN_EINVAL (context unchanged) if it does not fit the
@@ -414,9 +421,17 @@ chn_status chn_get_plan(chn_ctx *ctx, chn_plan *plan);
 chn_status chn_set_plan(chn_ctx *ctx, const chn_plan *plan);
 
 /* Autotuner: times the plane phase (reps repetitions after one warm-up) for
- * every schedule that fits, keeps the fastest and writes it to *chosen
- * (may be NULL).  Only scratch buffers are written; the state is
- * untouched.  Synchronises. */
+ * every schedule that fits with the classic radices, then with the
+ * composite radix sets at the chosen planes per launch, keeps the fastest
+ * and writes it to *chosen (may be NULL).  Only scratch buffers are
+ * written; the state is untouched.  Synchronises.  The choice is kept in a
+ * cache file, one JSON object per line keyed by the device architecture,
+ * n1 x n2 x n3, the precision and the planes per launch the context
+ * allows; a later call for the same key applies the cached schedule
+ * without timing.  The file is
+ * $CHN_TUNE_CACHE, else $XDG_CACHE_HOME/chn_tune.jsonl, else
+ * $HOME/.cache/chn_tune.jsonl; CHN_TUNE_CACHE set to an empty string turns
+ * the cache off.  An unreadable or unwritable file only disables caching. */
 chn_status chn_autotune(chn_ctx *ctx, int32_t reps, chn_plan *chosen);
 
 /* Message of the last failing call on ctx (or of the last failing

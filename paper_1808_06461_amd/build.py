@@ -8,14 +8,20 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchn.so")
-HIP_SOURCES = ["api.hip", "plane.hip", "pencil.hip", "lowstorage.hip"]
+HIP_SOURCES = ["api.hip", "plane.hip", "plane_zinv_f.hip", "plane_zinv_d.hip", "plane_xpass_f.hip",
+               "plane_xpass_d.hip", "plane_zfwd_f.hip", "plane_zfwd_d.hip", "plane_batch.hip", "pencil.hip",
+               "lowstorage.hip"]
 HOST_SOURCES = ["coeffs.cpp", "meshopt.cpp"]
 ARCH = os.environ.get("CHN_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
+# -ffp-contract=on: products are fused into FMAs within a source expression
+# only, never across statements, so a kernel body gives the same bits in every
+# kernel that inlines it (an ensemble's batched launches and a single
+# context's launches agree bit for bit)
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+          "-munsafe-fp-atomics", "-ffp-contract=on"]
 
 
 def _run(cmd):

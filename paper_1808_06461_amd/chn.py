@@ -33,7 +33,7 @@ class Config(C.Structure):
 
 class Plan(C.Structure):
     _fields_ = [("x_rows", C.c_int32), ("z_lines", C.c_int32), ("y_chunk", C.c_int32),
-                ("fixed_radix", C.c_int32), ("z_pipeline", C.c_int32)]
+                ("fixed_radix", C.c_int32), ("z_pipeline", C.c_int32), ("radix_set", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -302,9 +302,9 @@ class Channel:
         self._check(self.L.chn_get_plan(self.ctx, C.byref(p)), "chn_get_plan")
         return p.as_dict()
 
-    def set_plan(self, x_rows, z_lines, y_chunk=None, fixed_radix=0, z_pipeline=0):
+    def set_plan(self, x_rows, z_lines, y_chunk=None, fixed_radix=0, z_pipeline=0, radix_set=0):
         p = Plan(int(x_rows), int(z_lines), int(self.n2 if y_chunk is None else y_chunk), int(fixed_radix),
-                 int(z_pipeline))
+                 int(z_pipeline), int(radix_set))
         self._check(self.L.chn_set_plan(self.ctx, C.byref(p)), "chn_set_plan")
 
     def autotune(self, reps=3):

@@ -1,6 +1,7 @@
 // C ABI of the channel RK3 hot path: context, workspace layout, sub-step driver.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -91,9 +92,9 @@ struct chn_ctx {
   void *tw1 = nullptr, *tw3 = nullptr;
   double2 *tw1d = nullptr, *tw3d = nullptr, *twq = nullptr;  // float64 tables (filter stage)
   std::vector<double> twq_host;
-  double2* twf = nullptr;  // filter-grid tables (filter stage), for the sizes twf_n1, twf_n3
+  double2* twf = nullptr;  // filter-grid tables (filter stage) of the plans twf_p1, twf_p3
   std::vector<double> twf_host;
-  int twf_n1 = 0, twf_n3 = 0;
+  FftPlan twf_p1{}, twf_p3{};
   FftPlan plan1{}, plan3{};
   double *mean_scr = nullptr, *mean_out = nullptr, *info_dev = nullptr;
   unsigned* guard = nullptr;  // instability guard, four words (common.hpp)
@@ -109,6 +110,7 @@ struct chn_ctx {
   int ychunk = 1;       // planes per plane-phase launch
   int ffix = 0;         // compile-time radix schedules where available
   int zpipe = 0;        // pipelined z passes (next field's loads during this field's transform)
+  int radix = 0;        // radix sets: bit 0 composite radices for plan1 (x), bit 1 for plan3 (z)
   int ychunk_max = 1;   // planes the intermediate holds
   bool planes_only = false;
   // per-kernel timing (chn_timing_enable): events bracketing every launch
@@ -309,12 +311,39 @@ void default_plan(chn_ctx* x) {
 bool plan_fits(const chn_ctx* x, int xrows, int zK, int ych) {
   const int cb = x->mixed ? 8 : 16;
   if (ych < 1 || ych > x->ychunk_max) return false;
-  if (zK < 1 || zK > z_lines_max(x)) return false;
+  if (zK < 1 || zK > z_lines_max(x) || chn::z_staging(x->plan3, zK, cb) == 0) return false;
   if (xrows == 2 || xrows == 4 || xrows == 8)
     return chn::staging_for(x->plan1, 3 * xrows, cb) > 0 &&
            (size_t)3 * xrows * plane_lds_stride(x->p1) * cb <= (size_t)x->lds_max;
-  if (xrows == 1) return chn::xrow_threads(x->p1, cb) > 0 && (size_t)x->p1 * cb <= (size_t)x->lds_max;
+  if (xrows == 1) return chn::xrow_fits(x->plan1, cb) && (size_t)x->p1 * cb <= (size_t)x->lds_max;
   return false;
+}
+
+// Rebuild plan1, plan3 and their twiddle tables for the radix sets rs
+// (bit 0: x transforms composite, bit 1: z transforms composite).
+chn_status set_radix(chn_ctx* x, int rs) {
+  if (rs == x->radix) return CHN_OK;
+  FftPlan p1{}, p3{};
+  std::vector<double> t1, t3;
+  const int r1 = (rs & 1) ? chn::host::kRadixComposite : chn::host::kRadixClassic;
+  const int r3 = (rs & 2) ? chn::host::kRadixComposite : chn::host::kRadixClassic;
+  if (!chn::host::fft_plan(x->p1, &p1, &t1, r1) || !chn::host::fft_plan(x->p3, &p3, &t3, r3))
+    return fail(x, CHN_EINVAL, "FFT length not supported by this radix set");
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  if (x->mixed) {
+    std::vector<float> g1(t1.begin(), t1.end()), g3(t3.begin(), t3.end());
+    HIPCHK(x, hipMemcpy(x->tw1, g1.data(), g1.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(x, hipMemcpy(x->tw3, g3.data(), g3.size() * 4, hipMemcpyHostToDevice));
+  } else {
+    HIPCHK(x, hipMemcpy(x->tw1, t1.data(), t1.size() * 8, hipMemcpyHostToDevice));
+    HIPCHK(x, hipMemcpy(x->tw3, t3.data(), t3.size() * 8, hipMemcpyHostToDevice));
+  }
+  HIPCHK(x, hipMemcpy(x->tw1d, t1.data(), t1.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(x, hipMemcpy(x->tw3d, t3.data(), t3.size() * 8, hipMemcpyHostToDevice));
+  x->plan1 = p1;
+  x->plan3 = p3;
+  x->radix = rs;
+  return CHN_OK;
 }
 template <typename T> int z_lines(const chn_ctx* x) { return x->zK; }
 
@@ -621,20 +650,33 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   if (lds_x > (size_t)x->lds_max || (size_t)(f3 + 1) * 16 > (size_t)x->lds_max || f3 > 24 * 256 ||
       (!ens && (lds_t > (size_t)x->lds_max || 5 * q1 > 24 * 256 || q3 > 24 * 256)))
     return fail(x, CHN_EUNSUPPORTED, "plane too large for the filter kernels' LDS tiles on this device");
-  // FFT tables of the filter grid and of the q grid (float64)
+  // z-inverse lines per workgroup: at most what leaves room for three workgroups per CU
+  const int zls = plane_lds_stride(f3);
+  int zK = std::max(1, std::min(lines(f3, n1h), (int)((size_t)x->lds_max / 3 / ((size_t)zls * sizeof(CT)))));
+  while (zK > 1 && (size_t)zK * zls * sizeof(CT) > (size_t)x->lds_max) --zK;
+  if ((size_t)zK * zls * sizeof(CT) > (size_t)x->lds_max) return fail(x, CHN_EUNSUPPORTED, "z lines exceed LDS");
+  // FFT plans (float64 tables): the composite radix set where every launch's
+  // staging holds it, else the classic one
+  auto make_plan = [&](int n, FftPlan* pl, std::vector<double>* t, auto fits) {
+    if (chn::host::fft_plan(n, pl, t, chn::host::kRadixComposite) && fits(*pl)) return true;
+    return chn::host::fft_plan(n, pl, t, chn::host::kRadixClassic) && fits(*pl);
+  };
   FftPlan pf1{}, pf3{};
   {
     std::vector<double> t1, t3;
-    if (!chn::host::fft_plan(f1, &pf1, &t1) || !chn::host::fft_plan(f3, &pf3, &t3))
-      return fail(x, CHN_EINVAL, "filter grid not supported");
-    if (x->twf_n1 != f1 || x->twf_n3 != f3) {
+    if (!make_plan(f1, &pf1, &t1, [&](const FftPlan& p) { return chn::staging_fits(p, 1, 256, 16); }) ||
+        !make_plan(f3, &pf3, &t3, [&](const FftPlan& p) {
+          return chn::z_staging(p, zK, 16) > 0 && chn::staging_fits(p, Kf, 256, 24);
+        }))
+      return fail(x, CHN_EUNSUPPORTED, "filter grid not supported by the transform kernels");
+    if (std::memcmp(&x->twf_p1, &pf1, sizeof pf1) != 0 || std::memcmp(&x->twf_p3, &pf3, sizeof pf3) != 0) {
       std::vector<double>& h = x->twf_host;  // [f1 | f3], kMaxQ entries each
       h.assign((size_t)4 * kMaxQ, 0.0);
       std::copy(t1.begin(), t1.end(), h.begin());
       std::copy(t3.begin(), t3.end(), h.begin() + 2 * kMaxQ);
       HIPCHK(x, hipMemcpyAsync(x->twf, h.data(), h.size() * 8, hipMemcpyHostToDevice, x->stream));
-      x->twf_n1 = f1;
-      x->twf_n3 = f3;
+      x->twf_p1 = pf1;
+      x->twf_p3 = pf3;
     }
   }
   const double2* twf1 = x->twf;
@@ -642,7 +684,8 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   FftPlan pq1{}, pq3{};
   if (!ens) {
     std::vector<double> t1, t3;
-    if (!chn::host::fft_plan(q1, &pq1, &t1) || !chn::host::fft_plan(q3, &pq3, &t3))
+    if (!make_plan(q1, &pq1, &t1, [&](const FftPlan& p) { return chn::staging_fits(p, 5, 256, 24); }) ||
+        !make_plan(q3, &pq3, &t3, [&](const FftPlan& p) { return chn::staging_fits(p, Kq, 256, 24); }))
       return fail(x, CHN_EINVAL, "q grid not supported");
     x->twq_host.assign(t1.begin(), t1.end());
     x->twq_host.resize(2 * kMaxQ, 0.0);
@@ -694,17 +737,14 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   za.tw = twf3;
   za.plan = pf3;
   za.d = fd;
-  za.lstride = plane_lds_stride(f3);
-  // lines per workgroup: at most what leaves room for three workgroups per CU
-  za.K = std::max(1, std::min(lines(f3, n1h), (int)((size_t)x->lds_max / 3 / ((size_t)za.lstride * sizeof(CT)))));
+  za.lstride = zls;
+  za.K = zK;
   za.nfields = 3;
   za.nslot = 3;
   za.zero_mean = 1;
   za.y0 = 0;
   za.ny = n2;
   za.pipe = 1;
-  while (za.K > 1 && (size_t)za.K * za.lstride * sizeof(CT) > (size_t)x->lds_max) --za.K;
-  if ((size_t)za.K * za.lstride * sizeof(CT) > (size_t)x->lds_max) return fail(x, CHN_EUNSUPPORTED, "z lines exceed LDS");
   HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_zinv<double>(za, x->stream); }));
   // 3. inverse in x, products, float64 forward in x
   chn::XfilterArgs<double> xa{};
@@ -858,6 +898,12 @@ bool ens_layout(int n, const chn_config* cfgs, EnsLayout* L) {
 
 template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
   const int n = e->n;
+  // the batched kernels take the classic radix passes (chn_create's default)
+  for (const chn_ctx* c : e->ctx)
+    if (chn::plan_is_composite(c->plan1) || chn::plan_is_composite(c->plan3)) {
+      e->err = "ensemble channels need the classic radix set";
+      return CHN_EUNSUPPORTED;
+    }
   // larger channels first: a static longest-processing-time order
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
@@ -1503,14 +1549,21 @@ chn_status chn_get_plan(chn_ctx* x, chn_plan* plan) {
   plan->y_chunk = x->ychunk;
   plan->fixed_radix = x->ffix;
   plan->z_pipeline = x->zpipe;
+  plan->radix_set = x->radix;
   return CHN_OK;
 }
 
 chn_status chn_set_plan(chn_ctx* x, const chn_plan* plan) {
   if (chn_status s = check(x)) return s;
-  if (!plan || !plan_fits(x, plan->x_rows, plan->z_lines, plan->y_chunk) ||
-      (plan->fixed_radix != 0 && plan->fixed_radix != 1) || (plan->z_pipeline != 0 && plan->z_pipeline != 1))
+  if (!plan || (plan->fixed_radix != 0 && plan->fixed_radix != 1) || (plan->z_pipeline != 0 && plan->z_pipeline != 1) ||
+      plan->radix_set < 0 || plan->radix_set > 3)
+    return fail(x, CHN_EINVAL, "schedule fields out of range");
+  const int old = x->radix;
+  if (chn_status s = set_radix(x, plan->radix_set)) return s;
+  if (!plan_fits(x, plan->x_rows, plan->z_lines, plan->y_chunk)) {
+    if (chn_status s = set_radix(x, old)) return s;
     return fail(x, CHN_EINVAL, "schedule does not fit this grid or the device's LDS");
+  }
   x->xrows = plan->x_rows;
   x->zK = plan->z_lines;
   x->ychunk = plan->y_chunk;
@@ -1519,35 +1572,105 @@ chn_status chn_set_plan(chn_ctx* x, const chn_plan* plan) {
   return CHN_OK;
 }
 
+namespace {
+// Autotuner cache: one JSON object per line, {"key": "...", "plan": [x_rows,
+// z_lines, y_chunk, fixed_radix, z_pipeline, radix_set]}; the last line of a
+// key wins.
+std::string tune_path() {
+  if (const char* e = std::getenv("CHN_TUNE_CACHE")) return e;
+  if (const char* d = std::getenv("XDG_CACHE_HOME"); d && *d) return std::string(d) + "/chn_tune.jsonl";
+  if (const char* h = std::getenv("HOME"); h && *h) return std::string(h) + "/.cache/chn_tune.jsonl";
+  return "";
+}
+std::string tune_key(const chn_ctx* x) {
+  int dev = 0;
+  hipDeviceProp_t pr{};
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&pr, dev) == hipSuccess) arch = pr.gcnArchName;
+  return arch + "/" + std::to_string(x->n1) + "x" + std::to_string(x->n2) + "x" + std::to_string(x->n3) + "/" +
+         (x->mixed ? "mixed" : "fp64") + "/planes" + std::to_string(x->ychunk_max);
+}
+bool tune_lookup(const std::string& path, const std::string& key, chn_plan* p) {
+  if (path.empty()) return false;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  const std::string tag = "\"key\": \"" + key + "\"";
+  char line[1024];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    const char* k = std::strstr(line, tag.c_str());
+    const char* q = std::strstr(line, "\"plan\": [");
+    if (!k || !q) continue;
+    chn_plan t{};
+    if (std::sscanf(q + 9, "%d , %d , %d , %d , %d , %d", &t.x_rows, &t.z_lines, &t.y_chunk, &t.fixed_radix,
+                    &t.z_pipeline, &t.radix_set) == 6) {
+      *p = t;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+void tune_store(const std::string& path, const std::string& key, const chn_plan& p) {
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%s\", \"plan\": [%d, %d, %d, %d, %d, %d]}\n", key.c_str(), p.x_rows, p.z_lines,
+               p.y_chunk, p.fixed_radix, p.z_pipeline, p.radix_set);
+  std::fclose(f);
+}
+}  // namespace
+
 chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
   if (chn_status s = check(x)) return s;
   if (x->planes_only) return fail(x, CHN_EUNSUPPORTED, "autotune needs the context's own field buffers (not planes_only)");
   if (reps < 1) reps = 3;
-  struct Cand { int xr, K, ych, fx, zp; };
+  const std::string path = tune_path(), key = tune_key(x);
+  {
+    chn_plan c{};
+    if (tune_lookup(path, key, &c)) {
+      chn_plan prev{};
+      chn_get_plan(x, &prev);
+      if (chn_set_plan(x, &c) == CHN_OK) {
+        if (chosen) *chosen = c;
+        return CHN_OK;
+      }
+      x->err.clear();  // a stale entry: tune again
+      if (chn_status s = chn_set_plan(x, &prev)) return s;
+    }
+  }
+  struct Cand { int xr, K, ych, fx, zp, rs; };
   std::vector<Cand> cand;
-  const int kmax = z_lines_max(x);
   // planes per launch: the largest, and even splits of the planes into 2..12 launches
   std::vector<int> chunks;
   for (int parts : {1, 2, 4, 8, 12}) {
     const int c = std::min(x->ychunk_max, (x->n2 + parts - 1) / parts);
     if (c >= 1 && std::find(chunks.begin(), chunks.end(), c) == chunks.end()) chunks.push_back(c);
   }
-  const bool has_fixed = chn::plan_is_576(x->plan1) || chn::plan_is_576(x->plan3) || chn::plan_is_9216(x->plan3) ||
-                         chn::plan_is_12288(x->plan1);
   // the pipelined z passes engage where a field of K lines fits their staging
   // registers (8 values per thread inverse, 12 forward, 256 threads)
   auto pipe_engages = [&](int K) { return K * x->n3 <= 8 * 256 || K * x->p3 <= 12 * 256; };
-  for (int zp = 0; zp <= 1; ++zp)
-    for (int fx = 0; fx <= (has_fixed ? 1 : 0); ++fx)
-      for (int xr : {8, 4, 2, 1})
-        for (int K : {1, 2, 4, 8, 12, 16, kmax})
-          for (int c : chunks)
-            if (plan_fits(x, xr, K, c) && (zp == 0 || pipe_engages(K)) &&
-                std::none_of(cand.begin(), cand.end(), [&](const Cand& q) {
-                  return q.xr == xr && q.K == K && q.ych == c && q.fx == fx && q.zp == zp;
-                }))
-              cand.push_back({xr, K, c, fx, zp});
-  if (cand.empty()) return fail(x, CHN_EINVAL, "no schedule fits");
+  // candidates of radix sets rs over the planes per launch in ychs
+  auto add = [&](int rs, const std::vector<int>& ychs) {
+    if (set_radix(x, rs) != CHN_OK) {
+      x->err.clear();
+      return;
+    }
+    const int kmax = z_lines_max(x);
+    const bool has_fixed = chn::plan_is_576(x->plan1) || chn::plan_is_576(x->plan3) || chn::plan_is_576c(x->plan1) ||
+                           chn::plan_is_576c(x->plan3) || chn::plan_is_9216(x->plan3) || chn::plan_is_12288(x->plan1);
+    for (int zp = 0; zp <= 1; ++zp)
+      for (int fx = 0; fx <= (has_fixed ? 1 : 0); ++fx)
+        for (int xr : {8, 4, 2, 1})
+          for (int K : {1, 2, 4, 8, 12, 16, kmax})
+            for (int c : ychs)
+              if (plan_fits(x, xr, K, c) && (zp == 0 || pipe_engages(K)) &&
+                  std::none_of(cand.begin(), cand.end(), [&](const Cand& q) {
+                    return q.xr == xr && q.K == K && q.ych == c && q.fx == fx && q.zp == zp && q.rs == rs;
+                  }))
+                cand.push_back({xr, K, c, fx, zp, rs});
+  };
+  const int rs0 = x->radix;
   hipEvent_t a = nullptr, b = nullptr;
   HIPCHK(x, hipEventCreate(&a));
   if (hipEventCreate(&b) != hipSuccess) {
@@ -1557,46 +1680,60 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
   const bool timing = x->timing;
   x->timing = false;
   float best = 0.0f;
-  Cand pick = cand[0];
+  Cand pick{};
   chn_status st = CHN_OK;
-  for (const auto& c : cand) {
-    x->xrows = c.xr;
-    x->zK = c.K;
-    x->ychunk = c.ych;
-    x->ffix = c.fx;
-    x->zpipe = c.zp;
-    auto run = [&]() { return x->mixed ? plane_phase<float, float>(x, x->ph, false, x->H)
-                                       : plane_phase<double, double>(x, x->ph, false, x->H); };
-    if ((st = run()) != CHN_OK) break;
-    hipError_t e = hipEventRecord(a, x->stream);
-    for (int r = 0; r < reps && st == CHN_OK && e == hipSuccess; ++r) st = run();
-    if (e == hipSuccess) e = hipEventRecord(b, x->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(b);
-    float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-    if (st == CHN_OK && e != hipSuccess) st = fail(x, CHN_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
-    if (st != CHN_OK) break;
-    if (best == 0.0f || ms < best) {
-      best = ms;
-      pick = c;
+  auto time_all = [&]() {
+    for (const auto& c : cand) {
+      if ((st = set_radix(x, c.rs)) != CHN_OK) return;
+      x->xrows = c.xr;
+      x->zK = c.K;
+      x->ychunk = c.ych;
+      x->ffix = c.fx;
+      x->zpipe = c.zp;
+      auto run = [&]() { return x->mixed ? plane_phase<float, float>(x, x->ph, false, x->H)
+                                         : plane_phase<double, double>(x, x->ph, false, x->H); };
+      if ((st = run()) != CHN_OK) return;
+      hipError_t e = hipEventRecord(a, x->stream);
+      for (int r = 0; r < reps && st == CHN_OK && e == hipSuccess; ++r) st = run();
+      if (e == hipSuccess) e = hipEventRecord(b, x->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (st == CHN_OK && e != hipSuccess) st = fail(x, CHN_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+      if (st != CHN_OK) return;
+      if (best == 0.0f || ms < best) {
+        best = ms;
+        pick = c;
+      }
     }
+  };
+  // stage 1: the classic radices over every schedule; stage 2: the other
+  // radix sets at the planes per launch stage 1 chose
+  add(0, chunks);
+  time_all();
+  if (st == CHN_OK && best > 0.0f) {
+    cand.clear();
+    for (int rs = 1; rs <= 3; ++rs) add(rs, std::vector<int>{pick.ych});
+    time_all();
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   x->timing = timing;
+  if (st == CHN_OK && best == 0.0f) st = fail(x, CHN_EINVAL, "no schedule fits");
+  if (st != CHN_OK) {
+    (void)set_radix(x, rs0);
+    return st;
+  }
+  if ((st = set_radix(x, pick.rs)) != CHN_OK) return st;
   x->xrows = pick.xr;
   x->zK = pick.K;
   x->ychunk = pick.ych;
   x->ffix = pick.fx;
   x->zpipe = pick.zp;
-  if (st != CHN_OK) return st;
-  if (chosen) {
-    chosen->x_rows = pick.xr;
-    chosen->z_lines = pick.K;
-    chosen->y_chunk = pick.ych;
-    chosen->fixed_radix = pick.fx;
-    chosen->z_pipeline = pick.zp;
-  }
+  chn_plan out{};
+  chn_get_plan(x, &out);
+  tune_store(path, key, out);
+  if (chosen) *chosen = out;
   return CHN_OK;
 }
 

@@ -199,19 +199,56 @@ bool wall_rows(int n, const double* A1, const double* B1, double* clo, double* c
   return true;
 }
 
-bool fft_plan(int n, FftPlan* pl, std::vector<double>* tw) {
+namespace {
+// Fewest passes over the radices {16, 12, 9, 8, 6, 4, 3, 2}, ties to the
+// smallest largest radix (lighter butterflies), passes in non-increasing
+// radix order.  Depth-first over non-increasing sequences.
+struct RadixSearch {
+  int best_np = 1 << 30, best_max = 1 << 30;
+  int best[kMaxPass] = {}, cur[kMaxPass] = {};
+  void run(int m, int np, int maxr) {
+    static const int rads[8] = {16, 12, 9, 8, 6, 4, 3, 2};
+    if (m == 1) {
+      const int mx = np ? cur[0] : 1;
+      if (np < best_np || (np == best_np && mx < best_max)) {
+        best_np = np;
+        best_max = mx;
+        for (int p = 0; p < np; ++p) best[p] = cur[p];
+      }
+      return;
+    }
+    if (np + 1 > best_np || np >= kMaxPass) return;
+    for (int r : rads)
+      if (r <= maxr && m % r == 0) {
+        cur[np] = r;
+        run(m / r, np + 1, r);
+      }
+  }
+};
+}  // namespace
+
+bool fft_plan(int n, FftPlan* pl, std::vector<double>* tw, int radices) {
   std::memset(pl, 0, sizeof(*pl));
   pl->n = n;
   int m = n, np = 0;
-  const int rads[4] = {8, 4, 2, 3};
-  for (int ri = 0; ri < 4; ++ri) {
-    while (m % rads[ri] == 0) {
-      if (np >= kMaxPass) return false;
-      pl->radix[np++] = rads[ri];
-      m /= rads[ri];
+  if (radices == kRadixComposite) {
+    if (n < 1) return false;
+    RadixSearch rs;
+    rs.run(n, 0, 16);
+    if (rs.best_np > kMaxPass) return false;
+    np = rs.best_np;
+    for (int p = 0; p < np; ++p) pl->radix[p] = rs.best[p];
+  } else {
+    const int rads[4] = {8, 4, 2, 3};
+    for (int ri = 0; ri < 4; ++ri) {
+      while (m % rads[ri] == 0) {
+        if (np >= kMaxPass) return false;
+        pl->radix[np++] = rads[ri];
+        m /= rads[ri];
+      }
     }
+    if (m != 1) return false;
   }
-  if (m != 1) return false;
   pl->npass = np;
   tw->clear();
   int Ns = 1;

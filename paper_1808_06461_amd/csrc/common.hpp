@@ -40,10 +40,22 @@ template <typename T> __device__ __forceinline__ T nanmax(T a, T b) { return (b 
 //   [3] unused.
 constexpr unsigned kGuardNonFinite = 0x7f800000u;  // bits of +inf
 
+// Plans with a composite radix (6, 9, 12, 16): their kernels take the
+// runtime passes that include those radices.
+__host__ __device__ inline bool plan_is_composite(const FftPlan& pl) {
+  for (int p = 0; p < pl.npass; ++p)
+    if (pl.radix[p] != 2 && pl.radix[p] != 3 && pl.radix[p] != 4 && pl.radix[p] != 8) return true;
+  return false;
+}
+
 // Plans with a compile-time radix schedule (FN template argument of the plane kernels).
 __host__ __device__ inline bool plan_is_576(const FftPlan& pl) {
   return pl.n == 576 && pl.npass == 4 && pl.radix[0] == 8 && pl.radix[1] == 8 && pl.radix[2] == 3 &&
          pl.radix[3] == 3;
+}
+// 576 points in the composite radix set: 9, 8, 8.
+__host__ __device__ inline bool plan_is_576c(const FftPlan& pl) {
+  return pl.n == 576 && pl.npass == 3 && pl.radix[0] == 9 && pl.radix[1] == 8 && pl.radix[2] == 8;
 }
 // The long lines of the 8192 x 6144 planes: 9216 points (radices 8, 8, 8, 2,
 // 3, 3) and 12288 points (8, 8, 8, 8, 3), compile-time schedules like 576.

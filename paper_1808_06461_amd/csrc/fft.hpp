@@ -54,11 +54,97 @@ template <typename T> __device__ __forceinline__ void dft8(c2<T>* v, int sgn) {
   v[3] = cadd<T>(e3, o3); v[7] = csub<T>(e3, o3);
 }
 
+// (cos, sin)(2 pi m / R) at compile time: the angle is reduced to the
+// nearest multiple q pi / 2 (exact integer arithmetic) plus |rho| <= pi / 4,
+// whose Taylor series converges to double rounding in a dozen terms; the
+// quadrant rotates the result exactly (so multiples of pi / 2 give 0, +-1).
+struct Cis {
+  double c, s;
+};
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+constexpr Cis cis_const(int m, int R) {
+  m %= R;
+  if (m < 0) m += R;
+  const int q = (8 * m + R) / (2 * R);  // nearest integer to 4 m / R
+  const double rho = (kPiD / 2) * (double)(4 * m - q * R) / (double)R;
+  double c = 1.0, s = rho, tc = 1.0, ts = rho;
+  for (int k = 1; k < 12; ++k) {
+    tc *= -rho * rho / (double)((2 * k - 1) * (2 * k));
+    ts *= -rho * rho / (double)((2 * k) * (2 * k + 1));
+    c += tc;
+    s += ts;
+  }
+  switch (q & 3) {
+    case 0: return Cis{c, s};
+    case 1: return Cis{-s, c};
+    case 2: return Cis{-c, -s};
+    default: return Cis{s, -c};
+  }
+}
+
+template <typename T, int R> __device__ __forceinline__ void dft(c2<T>* v, int sgn);
+
+// v * exp(sgn 2 pi i m / R), m and R known at compile time: multiples of a
+// quarter turn are exact swaps and negations, the rest one complex product.
+template <typename T, int M, int R> __device__ __forceinline__ c2<T> rot(c2<T> v, int sgn) {
+  constexpr int m = M % R;
+  if constexpr (m == 0) {
+    return v;
+  } else if constexpr ((4 * m) % R == 0) {
+    constexpr int q = 4 * m / R;  // quarter turns: 1, 2, 3
+    if constexpr (q == 2) return mk<T>(-v.x, -v.y);
+    else if constexpr (q == 1) return cmuli<T>(v, sgn);
+    else return cmuli<T>(v, -sgn);
+  } else {
+    constexpr Cis w = cis_const(m, R);
+    const T c = T(w.c), s = T(w.s) * T(sgn);
+    return mk<T>(v.x * c - v.y * s, v.x * s + v.y * c);
+  }
+}
+
+// Radix R = R1 R2 in registers (Cooley-Tukey with n = R2 n1 + n2, k = k1 +
+// R1 k2): R2 DFTs of length R1, the twiddles exp(sgn 2 pi i n2 k1 / R), R1
+// DFTs of length R2, outputs in natural order.
+template <typename T, int R1, int R2, int N2, int K1 = 0>
+__device__ __forceinline__ void comp_twiddle(const c2<T>* t, c2<T>* w, int sgn) {
+  w[N2 * R1 + K1] = rot<T, N2 * K1, R1 * R2>(t[K1], sgn);
+  if constexpr (K1 + 1 < R1) comp_twiddle<T, R1, R2, N2, K1 + 1>(t, w, sgn);
+}
+template <typename T, int R1, int R2, int N2 = 0>
+__device__ __forceinline__ void comp_stage1(const c2<T>* v, c2<T>* w, int sgn) {
+  c2<T> t[R1];
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) t[n1] = v[R2 * n1 + N2];
+  dft<T, R1>(t, sgn);
+  comp_twiddle<T, R1, R2, N2>(t, w, sgn);
+  if constexpr (N2 + 1 < R2) comp_stage1<T, R1, R2, N2 + 1>(v, w, sgn);
+}
+template <typename T, int R1, int R2> __device__ __forceinline__ void dft_comp(c2<T>* v, int sgn) {
+  c2<T> w[R1 * R2];
+  comp_stage1<T, R1, R2>(v, w, sgn);
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    c2<T> t[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) t[n2] = w[n2 * R1 + k1];
+    dft<T, R2>(t, sgn);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+  }
+}
+
+// Radices of the Stockham passes: 2, 3, 4, 8 directly; 6, 9, 12, 16 as
+// compositions held in registers (one LDS round trip for the whole radix).
 template <typename T, int R> __device__ __forceinline__ void dft(c2<T>* v, int sgn) {
   if constexpr (R == 2) dft2<T>(v);
   else if constexpr (R == 3) dft3<T>(v, sgn);
   else if constexpr (R == 4) dft4<T>(v[0], v[1], v[2], v[3], sgn);
-  else dft8<T>(v, sgn);
+  else if constexpr (R == 8) dft8<T>(v, sgn);
+  else if constexpr (R == 6) dft_comp<T, 2, 3>(v, sgn);
+  else if constexpr (R == 9) dft_comp<T, 3, 3>(v, sgn);
+  else if constexpr (R == 12) dft_comp<T, 4, 3>(v, sgn);
+  else if constexpr (R == 16) dft_comp<T, 4, 4>(v, sgn);
+  else static_assert(R == 2, "unsupported radix");
 }
 
 // x / d as a multiply-high with m = ceil(2^32 / d) (m = 0 for d = 1): exact
@@ -183,8 +269,17 @@ __device__ __forceinline__ void stockham_pass_c(c2<T>* lds, int lstride, int nli
   __syncthreads();
 }
 
+// FN value of a runtime plan that may hold the composite radices 6, 9, 12,
+// 16 (FN = 0: radices 2, 3, 4, 8 only, which keeps the register allocation of
+// those kernels to the classic passes).
+constexpr int kFnComposite = 1;
+// FN of the compile-time schedule of 576-point lines in the composite radix
+// set (9, 8, 8); FN = 576 is the classic one (8, 8, 3, 3).
+constexpr int kFn576Composite = 10576;
+
 // Full transform of nlines lines of length pl.n.  MAXV = complex values
-// staged per thread (a multiple of 24); requires nlines * pl.n <= MAXV * blockDim.x.
+// staged per thread; every pass must hold nlines * pl.n / R butterflies in
+// (MAXV / R) * blockDim.x (the host checks this with the plan).
 template <typename T, int MAXV, int FN = 0, bool PAD = false>
 __device__ __forceinline__ void fft_lines(c2<T>* lds, int lstride, int nlines, const FftPlan& pl,
                           const c2<T>* __restrict__ tw, int sgn) {
@@ -194,6 +289,14 @@ __device__ __forceinline__ void fft_lines(c2<T>* lds, int lstride, int nlines, c
     stockham_pass_c<T, 8, MAXV / 8, 576, 8, PAD>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
     stockham_pass_c<T, 3, MAXV / 3, 576, 64, PAD>(lds, lstride, nlines, tw + pl.twoff[2], sgn);
     stockham_pass_c<T, 3, MAXV / 3, 576, 192, PAD>(lds, lstride, nlines, tw + pl.twoff[3], sgn);
+    return;
+  } else if constexpr (FN == kFn576Composite) {  // 576 in three passes: radices 9, 8, 8
+    // (the host never stages this plan in fewer than 9 values per thread)
+    if constexpr (MAXV >= 9) {
+      stockham_pass_c<T, 9, MAXV / 9, 576, 1, PAD>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
+      stockham_pass_c<T, 8, MAXV / 8, 576, 9, PAD>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
+      stockham_pass_c<T, 8, MAXV / 8, 576, 72, PAD>(lds, lstride, nlines, tw + pl.twoff[2], sgn);
+    }
     return;
   } else if constexpr (FN == 9216) {  // 3/2 x 6144: radices 8, 8, 8, 2, 3, 3
     stockham_pass_c<T, 8, MAXV / 8, 9216, 1, PAD>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
@@ -216,11 +319,31 @@ __device__ __forceinline__ void fft_lines(c2<T>* lds, int lstride, int nlines, c
     const c2<T>* twp = tw + pl.twoff[p];
     const int R = pl.radix[p];
     const unsigned mb = qmagic((unsigned)(pl.n / R)), mk = qmagic((unsigned)Ns);
+    if constexpr (FN == kFnComposite) {
+      // composite radices only where the staging holds one butterfly (the
+      // host's staging check never plans them otherwise)
+      switch (R) {
+        case 16:
+          if constexpr (MAXV >= 16) stockham_pass<T, 16, MAXV / 16, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn);
+          break;
+        case 12:
+          if constexpr (MAXV >= 12) stockham_pass<T, 12, MAXV / 12, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn);
+          break;
+        case 9:
+          if constexpr (MAXV >= 9) stockham_pass<T, 9, MAXV / 9, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn);
+          break;
+        case 6:
+          if constexpr (MAXV >= 6) stockham_pass<T, 6, MAXV / 6, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn);
+          break;
+        default: break;
+      }
+    }
     switch (R) {
       case 8: stockham_pass<T, 8, MAXV / 8, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
       case 4: stockham_pass<T, 4, MAXV / 4, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
       case 3: stockham_pass<T, 3, MAXV / 3, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
-      default: stockham_pass<T, 2, MAXV / 2, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
+      case 2: stockham_pass<T, 2, MAXV / 2, PAD>(lds, lstride, nlines, pl.n, Ns, mb, mk, twp, sgn); break;
+      default: break;
     }
     Ns *= R;
   }

@@ -24,7 +24,12 @@ bool compact_bands(int n2, const double* y, int p, double* A, double* B);
 void quadrature(int n2, const double* y, double* w);
 bool band_lu(int n, const double* band, int dir, double* L, double* U);
 bool wall_rows(int n, const double* A1, const double* B1, double* clo, double* chi);
-bool fft_plan(int n, FftPlan* pl, std::vector<double>* tw);
+// Stockham plan of a length-n transform and its twiddle table.  Radix sets:
+// kRadixClassic takes 8s, then 4, 2, 3 (at most radix 8 per pass);
+// kRadixComposite the fewest passes over radices up to 16 (6, 9, 12, 16 are
+// computed in registers), so each element makes fewer LDS round trips.
+constexpr int kRadixClassic = 0, kRadixComposite = 1;
+bool fft_plan(int n, FftPlan* pl, std::vector<double>* tw, int radices = kRadixClassic);
 // 1-norm condition number ||A||_1 ||A^-1||_1 of a [n][7] band (inf if singular)
 double band_cond1(int n, const double* A);
 // cond_1 of A1 and of A2 with its end rows replaced by Dirichlet rows (the

@@ -67,6 +67,12 @@ template <typename T> hipError_t launch_xpass(const XpassArgs<T>& a, hipStream_t
 // x-pass kernel choice for rows of p1 points of bytes_per_value-byte complex values
 bool xpass_two_rows(int p1, int bytes_per_value);
 int xrow_threads(int p1, int bytes_per_value);  // 0: too long
+// Staging checks of the transforms: whether nlines lines of the plan over nt
+// threads fit m staged values per thread in every pass; the staging a z pass
+// of K lines would use (0: none fits); whether the long-row x pass fits.
+bool staging_fits(const FftPlan& pl, int nlines, int nt, int m);
+int z_staging(const FftPlan& pl, int K, int bytes_per_value);
+bool xrow_fits(const FftPlan& pl, int bytes_per_value);
 template <typename T, typename TO> hipError_t launch_zfwd(const ZfwdArgs<T, TO>& a, hipStream_t st);
 
 // ---------------------------------------------------------------- filter stage

@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
       }
     }
     __syncthreads();
-    fft_lines<T, 16>(lt, a.lst, 1, a.plan, a.tw, +1);
+    fft_lines<T, 16, kFnComposite>(lt, a.lst, 1, a.plan, a.tw, +1);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int x = threadIdx.x + q * blockDim.x;
@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
       if (x < f1) ld[x] = make_double2(u * u + v * v + w * w, 0.0);
     }
     __syncthreads();
-    fft_lines<double, 16>(ld, a.lsd, 1, a.plan, a.tw_d, -1);
+    fft_lines<double, 16, kFnComposite>(ld, a.lsd, 1, a.plan, a.tw_d, -1);
     for (int k = threadIdx.x; k < kc1; k += blockDim.x) out[k] = ld[k];
     return;
   }
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
         ld[x] = make_double2((double)ph[ia][q] * (double)ph[ja][q], (double)ph[ib][q] * (double)ph[jb][q]);
     }
     __syncthreads();
-    fft_lines<double, 16>(ld, a.lsd, 1, a.plan, a.tw_d, -1);
+    fft_lines<double, 16, kFnComposite>(ld, a.lsd, 1, a.plan, a.tw_d, -1);
     // pairs of the line: 0 (11) and 3 (22); 1 (12) and 2 (13); 4 (23) and 5 (33)
     const int pa = l == 0 ? 0 : (l == 1 ? 1 : 4);
     const int pb = l == 0 ? 3 : (l == 1 ? 2 : 5);
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(256) k_zfilter(ZfilterArgs a) {
       lds[l * LS + z] = l < nk ? src[(size_t)z * kc1 + l] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    fft_lines<double, 24>(lds, LS, K, a.plan, a.tw, -1);
+    fft_lines<double, 24, kFnComposite>(lds, LS, K, a.plan, a.tw, -1);
     for (int e = threadIdx.x; e < nk * nz; e += blockDim.x) {
       const int l = e / nz, s = e - l * nz;
       const int kz = s <= a.kcz ? s : s - nz;
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(256) k_zinv_q(ZinvQArgs a) {
       lds[l * LS + (kz >= 0 ? kz : q3 + kz)] = v;
     }
     __syncthreads();
-    fft_lines<double, 24>(lds, LS, K, a.plan, a.tw, +1);
+    fft_lines<double, 24, kFnComposite>(lds, LS, K, a.plan, a.tw, +1);
     double2* out = a.out + ((size_t)(y * 9 + f) * q3) * kc1 + kx0;
     for (int e = threadIdx.x; e < nk * q3; e += blockDim.x) {
       const int z = e / nk, l = e - z * nk;
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(256) k_xtau(XtauArgs a) {
     }
   }
   __syncthreads();
-  fft_lines<double, 24>(lds, LS, 5, a.plan, a.tw, +1);
+  fft_lines<double, 24, kFnComposite>(lds, LS, 5, a.plan, a.tw, +1);
   for (int x = threadIdx.x; x < q1; x += blockDim.x) {
     double f[10];
 #pragma unroll
@@ -325,6 +325,7 @@ hipError_t launch_xfilter(const XfilterArgs<T>& a, size_t lds_bytes, hipStream_t
   // hold every radix pass (radix 8: 2 butterflies, 4: 4, 3: 5, 2: 8 per thread);
   // physical values per thread: the fewest of 3, 6, 9, 12 that cover f1
   const dim3 grid(a.f3, a.n2);
+  if (!staging_fits(a.plan, 1, 256, 16)) return hipErrorInvalidValue;
   if (a.f1 <= 3 * 256) hipLaunchKernelGGL((k_xfilter<T, 3>), grid, dim3(256), lds_bytes, st, a);
   else if (a.f1 <= 6 * 256) hipLaunchKernelGGL((k_xfilter<T, 6>), grid, dim3(256), lds_bytes, st, a);
   else if (a.f1 <= 9 * 256) hipLaunchKernelGGL((k_xfilter<T, 9>), grid, dim3(256), lds_bytes, st, a);
@@ -333,14 +334,17 @@ hipError_t launch_xfilter(const XfilterArgs<T>& a, size_t lds_bytes, hipStream_t
   return hipGetLastError();
 }
 hipError_t launch_zfilter(const ZfilterArgs& a, size_t lds_bytes, hipStream_t st) {
+  if (!staging_fits(a.plan, a.K, 256, 24)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_zfilter, dim3((a.kcx + 1 + a.K - 1) / a.K, a.n2), dim3(256), lds_bytes, st, a);
   return hipGetLastError();
 }
 hipError_t launch_zinv_q(const ZinvQArgs& a, size_t lds_bytes, hipStream_t st) {
+  if (!staging_fits(a.plan, a.K, 256, 24)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_zinv_q, dim3((a.kcx + 1 + a.K - 1) / a.K, a.n2), dim3(256), lds_bytes, st, a);
   return hipGetLastError();
 }
 hipError_t launch_xtau(const XtauArgs& a, size_t lds_bytes, hipStream_t st) {
+  if (!staging_fits(a.plan, 5, 256, 24)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_xtau, dim3(a.q3, a.n2), dim3(256), lds_bytes, st, a);
   return hipGetLastError();
 }

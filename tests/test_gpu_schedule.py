@@ -3,10 +3,17 @@
 Every schedule must give the oracle's non-linear term to the same bounds as
 the default one (float64 1e-13, mixed 2e-6 relative per component): the
 x pass with 8, 4, 2 or one row per workgroup, z-pass workgroups of one line up to the
-largest that fits, planes in chunks, and the runtime or compile-time radix
-schedule (576-point lines).  The autotuner must pick a schedule that fits and leave
-results within those bounds.
+largest that fits, planes in chunks, the runtime or compile-time radix
+schedule (576-point lines), and the radix sets of the x and z transforms
+(passes of radix 8, 4, 2, 3, or the fewest passes with the composite
+radices 6, 9, 12, 16).  The
+autotuner must pick a schedule that fits and leave results within those
+bounds; its cache file must be written, and a cached schedule reused
+without timing.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -70,21 +77,23 @@ def test_every_schedule_matches_oracle(name, precision):
                 break
         assert kmax >= 1
         tried = set()
-        for pipe in (0, 1):
-            for fixed in (0, 1):
-                for x_rows in (8, 4, 2, 1):
-                    for k in sorted({1, 2, 3, kmax}):
-                        if k > kmax:
-                            continue
-                        try:
-                            ch.set_plan(x_rows, k, None, fixed, pipe)
-                        except ChnError:  # more rows than the staging registers or LDS hold
-                            assert x_rows > 2, (x_rows, k)
-                            continue
-                        tried.add(x_rows)
-                        _check(ch, fields, ref, TOL[precision],
-                               f"{precision} rows={x_rows} lines={k} fixed={fixed} pipeline={pipe}")
-        assert {1, 2} <= tried
+        for radix in (0, 1, 2, 3):
+            for pipe in (0, 1):
+                for fixed in (0, 1):
+                    for x_rows in (8, 4, 2, 1):
+                        for k in sorted({1, 2, 3, kmax}):
+                            if k > kmax:
+                                continue
+                            try:
+                                ch.set_plan(x_rows, k, None, fixed, pipe, radix)
+                            except ChnError:  # more rows or lines than the staging registers or LDS hold
+                                assert x_rows > 2 or radix > 0, (x_rows, k, radix)
+                                continue
+                            tried.add((radix, x_rows))
+                            _check(ch, fields, ref, TOL[precision],
+                                   f"{precision} radix set {radix} rows={x_rows} lines={k} fixed={fixed} "
+                                   f"pipeline={pipe}")
+        assert {(0, 1), (0, 2), (1, 2), (2, 2), (3, 2)} <= tried, tried
         ch.set_plan(2, 1, max(1, case.n2 // 3))  # planes in chunks
         _check(ch, fields, ref, TOL[precision], f"{precision} chunked planes")
         with pytest.raises(ChnError):
@@ -97,8 +106,9 @@ def test_every_schedule_matches_oracle(name, precision):
 
 @gpu
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_autotune_picks_a_fitting_schedule(precision):
+def test_autotune_picks_a_fitting_schedule(precision, tmp_path, monkeypatch):
     from paper_1808_06461_amd import Channel
+    monkeypatch.setenv("CHN_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
     case = CASES["wide"]
     y, fields, ref = _oracle(case)
     ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, precision=precision, y=y)
@@ -115,3 +125,47 @@ def test_autotune_picks_a_fitting_schedule(precision):
         _check(ch, fields, ref, TOL[precision], f"{precision} autotuned")
     finally:
         ch.close()
+
+
+@gpu
+def test_autotune_cache_is_reused(tmp_path, monkeypatch):
+    """A cached schedule for the context's key is applied without timing (the
+    last entry of a key wins), still matches the oracle, and an empty
+    CHN_TUNE_CACHE writes no file."""
+    from paper_1808_06461_amd import Channel
+    case = CASES["wide"]
+    y, fields, ref = _oracle(case)
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("CHN_TUNE_CACHE", str(path))
+    ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, precision="mixed", y=y)
+    try:
+        p = ch.autotune(reps=1)
+    finally:
+        ch.close()
+    rows = [json.loads(line) for line in path.read_text().splitlines()]
+    assert len(rows) == 1 and rows[0]["plan"] == [p[k] for k in ("x_rows", "z_lines", "y_chunk", "fixed_radix",
+                                                                 "z_pipeline", "radix_set")]
+    key = rows[0]["key"]
+    assert "/96x17x48/mixed/" in key, key
+    # a different schedule under the same key, appended: the later entry wins
+    other = [1, 1, case.n2, 0, 0, 3 - p["radix_set"]]
+    with open(path, "a") as f:
+        f.write(json.dumps({"key": key, "plan": other}) + "\n")
+    ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, precision="mixed", y=y)
+    try:
+        q = ch.autotune(reps=1)
+        assert [q[k] for k in ("x_rows", "z_lines", "y_chunk", "fixed_radix", "z_pipeline", "radix_set")] == other
+        assert ch.plan() == q
+        _check(ch, fields, ref, TOL["mixed"], "cached schedule")
+    finally:
+        ch.close()
+    assert len(path.read_text().splitlines()) == 2  # reused, nothing appended
+    off = tmp_path / "off"
+    monkeypatch.setenv("CHN_TUNE_CACHE", "")
+    monkeypatch.setenv("HOME", str(off))
+    ch = Channel(case.n1, case.n2, case.n3, case.lx, case.lz, case.re_b, precision="mixed", y=y)
+    try:
+        ch.autotune(reps=1)
+    finally:
+        ch.close()
+    assert not off.exists()
