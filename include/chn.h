@@ -153,8 +153,18 @@ chn_status chn_set_state(chn_ctx *ctx, const double *d_v, const double *d_omega2
  * failing sub-step: for sub-step 0 that is the start of the failing step;
  * for sub-steps 1 and 2 it is the state between two sub-steps of that step
  * (no copy of the state is kept per step).  If info is not NULL it is
- * filled for the last step. */
+ * filled for the last step.  Steps whose per-dt tables and phase fields are
+ * already current (all but the first after chn_set_state, a change of dt,
+ * or a call that reuses their scratch) are replayed from a HIP graph of one
+ * step, captured once per dt and schedule (kernel launches only; the graph
+ * runs on the context's stream, the capture on a stream of the context's
+ * own).  Replayed and launched steps give the same bits. */
 chn_status chn_step_rk3(chn_ctx *ctx, double dt, int32_t nsteps, chn_step_info *info);
+
+/* enable = 0: chn_step_rk3 launches every sub-step's kernels itself (no
+ * graph); 1 (the default): steady steps are replayed from the captured
+ * graph.  Frees the graph when disabled. */
+chn_status chn_step_graph_enable(chn_ctx *ctx, int32_t enable);
 
 /* Field selectors for chn_get_fields. */
 enum {

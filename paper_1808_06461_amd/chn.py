@@ -67,6 +67,7 @@ def lib():
         L.chn_destroy.argtypes = [P]
         L.chn_set_state.argtypes = [P, P, P, P, P]
         L.chn_step_rk3.argtypes = [P, C.c_double, C.c_int32, C.POINTER(StepInfo)]
+        L.chn_step_graph_enable.argtypes = [P, C.c_int32]
         L.chn_get_fields.argtypes = [P, C.c_uint32, C.POINTER(P)]
         L.chn_nonlinear.argtypes = [P, C.POINTER(P), C.POINTER(P)]
         L.chn_filter_and_stress.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P]
@@ -190,6 +191,10 @@ class Channel:
         self._keep = [self._dev(v, torch.complex128), self._dev(omega2, torch.complex128),
                       self._dev(u1mean, torch.float64), self._dev(u3mean, torch.float64)]
         self._check(self.L.chn_set_state(self.ctx, *[_ptr(t) for t in self._keep]), "chn_set_state")
+
+    def step_graph(self, enable=True):
+        """Replay steady steps from a captured graph (default) or launch every kernel."""
+        self._check(self.L.chn_step_graph_enable(self.ctx, 1 if enable else 0), "chn_step_graph_enable")
 
     def step(self, dt, nsteps=1, info=False):
         si = StepInfo()

@@ -120,7 +120,23 @@ struct chn_ctx {
   std::vector<Timed> phase_timed;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
+  // one RK3 step (three sub-steps) captured as a graph and replayed, for
+  // the time step and schedule of graph_key
+  bool use_graph = true;
+  hipStream_t cap = nullptr;  // capture stream (the caller's may be the null stream)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<double> graph_key;
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    graph_key.clear();
+  }
   ~chn_ctx() {
+    drop_graph();
+    if (cap) (void)hipStreamDestroy(cap);
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
 };
@@ -1269,6 +1285,48 @@ chn_status chn_set_state(chn_ctx* x, const double* d_v, const double* d_om2, con
   return CHN_OK;
 }
 
+namespace {
+chn_status step_eager(chn_ctx* x, double dt) {
+  for (int s = 0; s < 3; ++s)
+    if (chn_status st = x->mixed ? substep<float>(x, s, dt) : substep<double>(x, s, dt)) return st;
+  return CHN_OK;
+}
+
+// The graph of one step for dt and the current schedule, captured on the
+// context's capture stream (kernel launches only: the tables of dt and the
+// phase fields are current, so the step makes no other call).
+chn_status step_graph(chn_ctx* x, double dt) {
+  const std::vector<double> key = {dt, (double)x->xrows, (double)x->zK, (double)x->ychunk, (double)x->ffix,
+                                   (double)x->zpipe, (double)x->radix};
+  if (x->gexec && x->graph_key == key) return CHN_OK;
+  x->drop_graph();
+  if (!x->cap) HIPCHK(x, hipStreamCreate(&x->cap));
+  hipStream_t user = x->stream;
+  x->stream = x->cap;
+  hipError_t e = hipStreamBeginCapture(x->cap, hipStreamCaptureModeThreadLocal);
+  chn_status st = e == hipSuccess ? step_eager(x, dt) : CHN_OK;
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(x->cap, &g) : e;
+  x->stream = user;
+  if (st != CHN_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e2 != hipSuccess) return fail(x, CHN_EDEVICE, std::string("capturing the step: ") + hipGetErrorString(e2));
+  x->graph = g;
+  HIPCHK(x, hipGraphInstantiate(&x->gexec, g, nullptr, nullptr, 0));
+  x->graph_key = key;
+  return CHN_OK;
+}
+}  // namespace
+
+chn_status chn_step_graph_enable(chn_ctx* x, int32_t enable) {
+  if (chn_status s = check(x)) return s;
+  x->use_graph = enable != 0;
+  if (!x->use_graph) x->drop_graph();
+  return CHN_OK;
+}
+
 chn_status chn_step_rk3(chn_ctx* x, double dt, int32_t nsteps, chn_step_info* info) {
   if (chn_status s = check(x)) return s;
   if (chn_status s = need_fields(x)) return s;
@@ -1277,17 +1335,26 @@ chn_status chn_step_rk3(chn_ctx* x, double dt, int32_t nsteps, chn_step_info* in
   // the guard's CFL word, fail code and step count start from zero
   HIPCHK(x, hipMemsetAsync(x->guard, 0, 4 * sizeof(unsigned), x->stream));
   const size_t pool_mark = x->pool_used;
+  // steps replayed from the graph: those after the tables of dt and the
+  // phase fields are current, before the last step when info asks for its
+  // per-phase times; never while per-kernel events are recorded
+  const bool graph_ok = x->use_graph && !x->timing;
   for (int k = 0; k < nsteps; ++k) {
-    if (info && k == nsteps - 1) {  // per-phase times of the last step
+    const bool last_rec = info && k == nsteps - 1;
+    if (last_rec) {  // per-phase times of the last step
       x->phase_rec = true;
       x->phase_timed.clear();
     }
-    for (int s = 0; s < 3; ++s) {
-      const chn_status st = x->mixed ? substep<float>(x, s, dt) : substep<double>(x, s, dt);
-      if (st != CHN_OK) {
-        x->phase_rec = false;
-        return st;
-      }
+    chn_status st = CHN_OK;
+    if (graph_ok && !last_rec && x->phase_valid && x->htab_dt == dt) {
+      st = step_graph(x, dt);
+      if (st == CHN_OK) HIPCHK(x, hipGraphLaunch(x->gexec, x->stream));
+    } else {
+      st = step_eager(x, dt);
+    }
+    if (st != CHN_OK) {
+      x->phase_rec = false;
+      return st;
     }
   }
   x->phase_rec = false;
