@@ -71,10 +71,10 @@ def nominal_flops_per_substep(n1, n2, n3):
 # rocprofv3 counters (profiles/traffic_<kind>_channel_384x193x384.md) is used
 # only while these files are unchanged since the measurement.
 KERNEL_SOURCES = {
-    "advance": ["pencil.hip", "kernels.hpp", "common.hpp"],
-    "zinv": ["plane.hip", "fft.hpp", "kernels.hpp", "common.hpp"],
-    "xpass": ["plane.hip", "fft.hpp", "kernels.hpp", "common.hpp"],
-    "zfwd": ["plane.hip", "fft.hpp", "kernels.hpp", "common.hpp"],
+    "advance": ["pencil.hip", "kernels.hpp", "common.hpp", "host.hpp"],
+    "zinv": ["plane.hpp", "plane_zinv_f.hip", "fft.hpp", "kernels.hpp", "common.hpp", "host.hpp"],
+    "xpass": ["plane.hpp", "plane_xpass_f.hip", "fft.hpp", "kernels.hpp", "common.hpp", "host.hpp"],
+    "zfwd": ["plane.hpp", "plane_zfwd_f.hip", "fft.hpp", "kernels.hpp", "common.hpp", "host.hpp"],
 }
 
 

@@ -94,7 +94,7 @@ struct chn_ctx {
   std::vector<double> twq_host;
   double2* twf = nullptr;  // filter-grid tables (filter stage) of the plans twf_p1, twf_p3
   std::vector<double> twf_host;
-  FftPlan twf_p1{}, twf_p3{};
+  FftPlan twf_p1{}, twf_p3{}, twf_pz{};
   FftPlan plan1{}, plan3{};
   double *mean_scr = nullptr, *mean_out = nullptr, *info_dev = nullptr;
   unsigned* guard = nullptr;  // instability guard, four words (common.hpp)
@@ -192,7 +192,7 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
   void* tw1d = cv.take(16 * (size_t)p1);
   void* tw3d = cv.take(16 * (size_t)p3);
   void* twq = cv.take(16 * (size_t)kMaxQ * 2);
-  void* twf = cv.take(16 * (size_t)kMaxQ * 2);
+  void* twf = cv.take(16 * (size_t)kMaxQ * 3);
   double* mean_scr = D(3 * (size_t)n2 * 5 + 4 * (size_t)n2);
   double* mean_out = D(8);
   double* info = D(8);
@@ -662,14 +662,16 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
     if (K > cap) K = cap;
     return K < 1 ? 1 : K;
   };
-  const int Kf = lines(f3, kc1), Kq = ens ? 1 : lines(q3, kc1);
+  int Kf = lines(f3, kc1);
+  const int Kq = ens ? 1 : lines(q3, kc1);
   if (lds_x > (size_t)x->lds_max || (size_t)(f3 + 1) * 16 > (size_t)x->lds_max || f3 > 24 * 256 ||
       (!ens && (lds_t > (size_t)x->lds_max || 5 * q1 > 24 * 256 || q3 > 24 * 256)))
     return fail(x, CHN_EUNSUPPORTED, "plane too large for the filter kernels' LDS tiles on this device");
-  // z-inverse lines per workgroup: at most what leaves room for three workgroups per CU
+  // z inverse: one line per workgroup, one field at a time (float64 lines:
+  // the fewest registers give the most waves; measured on 1536x385x1152,
+  // 20 -> 15 ms against two lines with the pipelined loads)
   const int zls = plane_lds_stride(f3);
-  int zK = std::max(1, std::min(lines(f3, n1h), (int)((size_t)x->lds_max / 3 / ((size_t)zls * sizeof(CT)))));
-  while (zK > 1 && (size_t)zK * zls * sizeof(CT) > (size_t)x->lds_max) --zK;
+  const int zK = 1;
   if ((size_t)zK * zls * sizeof(CT) > (size_t)x->lds_max) return fail(x, CHN_EUNSUPPORTED, "z lines exceed LDS");
   // FFT plans (float64 tables): the composite radix set where every launch's
   // staging holds it, else the classic one
@@ -677,26 +679,41 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
     if (chn::host::fft_plan(n, pl, t, chn::host::kRadixComposite) && fits(*pl)) return true;
     return chn::host::fft_plan(n, pl, t, chn::host::kRadixClassic) && fits(*pl);
   };
-  FftPlan pf1{}, pf3{};
+  FftPlan pf1{}, pf3{}, pz3{};
   {
     std::vector<double> t1, t3;
+    // the z forward takes the most lines per workgroup (at most Kf) the plan's staging holds
+    const int kf_max = Kf;
+    auto z_fits = [&](const FftPlan& p) {
+      if (chn::z_staging(p, zK, 16) == 0) return false;
+      for (Kf = kf_max; Kf >= 1; --Kf)
+        if (chn::staging_fits(p, Kf, 256, 24)) return true;
+      return false;
+    };
+    // the float64 z inverse keeps the classic radices where they fit: its
+    // composite form needs staging registers that cost occupancy
+    std::vector<double> tz;
     if (!make_plan(f1, &pf1, &t1, [&](const FftPlan& p) { return chn::staging_fits(p, 1, 256, 16); }) ||
-        !make_plan(f3, &pf3, &t3, [&](const FftPlan& p) {
-          return chn::z_staging(p, zK, 16) > 0 && chn::staging_fits(p, Kf, 256, 24);
-        }))
+        !make_plan(f3, &pf3, &t3, z_fits) ||
+        !((chn::host::fft_plan(f3, &pz3, &tz, chn::host::kRadixClassic) && chn::z_staging(pz3, zK, 16) > 0) ||
+          (chn::host::fft_plan(f3, &pz3, &tz, chn::host::kRadixComposite) && chn::z_staging(pz3, zK, 16) > 0)))
       return fail(x, CHN_EUNSUPPORTED, "filter grid not supported by the transform kernels");
-    if (std::memcmp(&x->twf_p1, &pf1, sizeof pf1) != 0 || std::memcmp(&x->twf_p3, &pf3, sizeof pf3) != 0) {
-      std::vector<double>& h = x->twf_host;  // [f1 | f3], kMaxQ entries each
-      h.assign((size_t)4 * kMaxQ, 0.0);
+    if (std::memcmp(&x->twf_p1, &pf1, sizeof pf1) != 0 || std::memcmp(&x->twf_p3, &pf3, sizeof pf3) != 0 ||
+        std::memcmp(&x->twf_pz, &pz3, sizeof pz3) != 0) {
+      std::vector<double>& h = x->twf_host;  // [f1 | f3 z forward | f3 z inverse], kMaxQ entries each
+      h.assign((size_t)6 * kMaxQ, 0.0);
       std::copy(t1.begin(), t1.end(), h.begin());
       std::copy(t3.begin(), t3.end(), h.begin() + 2 * kMaxQ);
+      std::copy(tz.begin(), tz.end(), h.begin() + 4 * kMaxQ);
       HIPCHK(x, hipMemcpyAsync(x->twf, h.data(), h.size() * 8, hipMemcpyHostToDevice, x->stream));
       x->twf_p1 = pf1;
       x->twf_p3 = pf3;
+      x->twf_pz = pz3;
     }
   }
   const double2* twf1 = x->twf;
   const double2* twf3 = x->twf + kMaxQ;
+  const double2* twz3 = x->twf + 2 * kMaxQ;
   FftPlan pq1{}, pq3{};
   if (!ens) {
     std::vector<double> t1, t3;
@@ -750,8 +767,8 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   for (int f = 0; f < 3; ++f) za.in[f] = reinterpret_cast<const CT*>(fin.u[f]);
   za.in_f32 = fin.f32;
   za.out = reinterpret_cast<CT*>(x->inter);
-  za.tw = twf3;
-  za.plan = pf3;
+  za.tw = twz3;
+  za.plan = pz3;
   za.d = fd;
   za.lstride = zls;
   za.K = zK;
@@ -760,7 +777,7 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   za.zero_mean = 1;
   za.y0 = 0;
   za.ny = n2;
-  za.pipe = 1;
+  za.pipe = 0;
   HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_zinv<double>(za, x->stream); }));
   // 3. inverse in x, products, float64 forward in x
   chn::XfilterArgs<double> xa{};
