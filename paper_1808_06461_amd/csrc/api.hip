@@ -111,6 +111,7 @@ struct chn_ctx {
   int ffix = 0;         // compile-time radix schedules where available
   int zpipe = 0;        // pipelined z passes (next field's loads during this field's transform)
   int radix = 0;        // radix sets: bit 0 composite radices for plan1 (x), bit 1 for plan3 (z)
+  bool in_ensemble = false;  // a channel of an ensemble: its batched kernels take the classic radices
   int ychunk_max = 1;   // planes the intermediate holds
   bool planes_only = false;
   // per-kernel timing (chn_timing_enable): events bracketing every launch
@@ -339,6 +340,7 @@ bool plan_fits(const chn_ctx* x, int xrows, int zK, int ych) {
 // (bit 0: x transforms composite, bit 1: z transforms composite).
 chn_status set_radix(chn_ctx* x, int rs) {
   if (rs == x->radix) return CHN_OK;
+  if (x->in_ensemble) return fail(x, CHN_EUNSUPPORTED, "the channels of an ensemble keep the classic radix set");
   FftPlan p1{}, p3{};
   std::vector<double> t1, t3;
   const int r1 = (rs & 1) ? chn::host::kRadixComposite : chn::host::kRadixClassic;
@@ -1872,6 +1874,7 @@ chn_status chn_ens_create(int32_t n, const chn_config* cfgs, void* d_ws, size_t 
       delete e;
       return s;
     }
+    c->in_ensemble = true;
     e->ctx.push_back(c);
   }
   if (hipStreamCreate(&e->own) != hipSuccess || hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming) != hipSuccess ||

@@ -137,3 +137,28 @@ def test_ens_set_state_index_checked():
         assert b"out of range" in ens.L.chn_ens_last_error(ens.ens)
     finally:
         ens.close()
+
+
+@gpu
+def test_ensemble_channels_keep_the_classic_radix_set():
+    """An ensemble's batched kernels take the classic radix passes: a composite
+    radix set on one of its channels is refused (CHN_EUNSUPPORTED) and the
+    autotuner keeps set 0 there; the ensemble still steps as before."""
+    from paper_1808_06461_amd import ChnError
+    from paper_1808_06461_amd.chn import Ensemble
+    c = SPECS[0]
+    v, om, U1, U3, y = synth.turbulent_field(c)
+    ens = Ensemble([_spec(c, y)], precision="mixed")
+    try:
+        ch = ens.channels[0]
+        ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+        p = ch.plan()
+        with pytest.raises(ChnError, match="CHN_EUNSUPPORTED"):
+            ch.set_plan(p["x_rows"], p["z_lines"], p["y_chunk"], p["fixed_radix"], p["z_pipeline"], 3)
+        assert ch.plan() == p
+        assert ch.autotune(reps=1)["radix_set"] == 0
+        ens.step([c.dt], 2)
+        f = ch.get_fields("v")["v"].cpu().numpy()
+        assert np.isfinite(f).all()
+    finally:
+        ens.close()
