@@ -427,9 +427,10 @@ chn_status chn_get_plan(chn_ctx *ctx, chn_plan *plan);
 
 /* Sets the schedule; CHN_EINVAL (context unchanged) if it does not fit the
  * grid or the device's LDS.  Channels of an ensemble keep the schedule
- * their batched tables were built with, and a radix set other than 0 on one
- * of them is CHN_EUNSUPPORTED (their batched kernels take the classic
- * radices; the autotuner then keeps set 0). */
+ * their batched tables were built with (chn_ens_create gives a channel the
+ * composite radices in a direction where they take fewer passes), and a
+ * different radix set on one of them is CHN_EUNSUPPORTED (the autotuner then
+ * keeps the channel's set). */
 chn_status chn_set_plan(chn_ctx *ctx, const chn_plan *plan);
 
 /* Autotuner: times the plane phase (reps repetitions after one warm-up) for

@@ -111,7 +111,7 @@ struct chn_ctx {
   int ffix = 0;         // compile-time radix schedules where available
   int zpipe = 0;        // pipelined z passes (next field's loads during this field's transform)
   int radix = 0;        // radix sets: bit 0 composite radices for plan1 (x), bit 1 for plan3 (z)
-  bool in_ensemble = false;  // a channel of an ensemble: its batched kernels take the classic radices
+  bool in_ensemble = false;  // a channel of an ensemble: keeps the radix sets its batched tables were built with
   int ychunk_max = 1;   // planes the intermediate holds
   bool planes_only = false;
   // per-kernel timing (chn_timing_enable): events bracketing every launch
@@ -340,7 +340,7 @@ bool plan_fits(const chn_ctx* x, int xrows, int zK, int ych) {
 // (bit 0: x transforms composite, bit 1: z transforms composite).
 chn_status set_radix(chn_ctx* x, int rs) {
   if (rs == x->radix) return CHN_OK;
-  if (x->in_ensemble) return fail(x, CHN_EUNSUPPORTED, "the channels of an ensemble keep the classic radix set");
+  if (x->in_ensemble) return fail(x, CHN_EUNSUPPORTED, "the channels of an ensemble keep the radix sets of their batched tables");
   FftPlan p1{}, p3{};
   std::vector<double> t1, t3;
   const int r1 = (rs & 1) ? chn::host::kRadixComposite : chn::host::kRadixClassic;
@@ -878,6 +878,7 @@ struct chn_ens {
   size_t lds_z = 0, lds_x = 0;
   int mz = 0, mx = 0;  // transform staging of the batched z and x passes
   int rz = 2;          // rows per batched x-pass workgroup
+  int comp = 0;        // some channel's plans hold composite radices
   std::vector<char> h_adv;    // host copy of the advance blocks (dt dependent)
   std::vector<double> last_dt;
   hipGraph_t graph = nullptr;
@@ -933,12 +934,25 @@ bool ens_layout(int n, const chn_config* cfgs, EnsLayout* L) {
 
 template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
   const int n = e->n;
-  // the batched kernels take the classic radix passes (chn_create's default)
-  for (const chn_ctx* c : e->ctx)
-    if (chn::plan_is_composite(c->plan1) || chn::plan_is_composite(c->plan3)) {
-      e->err = "ensemble channels need the classic radix set";
-      return CHN_EUNSUPPORTED;
+  // composite radices in a direction where they take fewer passes (the
+  // channels' short lines: 48 = 8 x 6, 72 = 9 x 8, 96 = 12 x 8)
+  e->comp = 0;
+  for (chn_ctx* c : e->ctx) {
+    int rs = 0;
+    for (int d = 0; d < 2; ++d) {
+      FftPlan pc{}, pk{};
+      std::vector<double> t;
+      const int n = d == 0 ? c->p1 : c->p3;
+      if (chn::host::fft_plan(n, &pc, &t, chn::host::kRadixComposite) &&
+          chn::host::fft_plan(n, &pk, &t, chn::host::kRadixClassic) && pc.npass < pk.npass)
+        rs |= 1 << d;
     }
+    if (rs && set_radix(c, rs) != CHN_OK) {
+      e->err = "channel radix set: " + c->err;
+      return CHN_EDEVICE;
+    }
+    if (rs) e->comp = 1;
+  }
   // larger channels first: a static longest-processing-time order
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
@@ -1098,6 +1112,7 @@ template <typename T> chn_status ens_step(chn_ens* e, const double* dt, int nste
   bp.mz = e->mz;
   bp.mx = e->mx;
   bp.rz = e->rz;
+  bp.comp = e->comp;
   const auto* adv = reinterpret_cast<const chn::AdvanceArgs<T, T>*>(e->d_adv);
   auto one_step = [&]() -> hipError_t {
     for (int s = 0; s < 3; ++s) {
@@ -1793,11 +1808,13 @@ chn_status chn_autotune(chn_ctx* x, int32_t reps, chn_plan* chosen) {
       }
     }
   };
-  // stage 1: the classic radices over every schedule; stage 2: the other
-  // radix sets at the planes per launch stage 1 chose
-  add(0, chunks);
+  // stage 1: the classic radices (an ensemble's channel: its own sets) over
+  // every schedule; stage 2: the other radix sets at the planes per launch
+  // stage 1 chose
+  const int rs1 = x->in_ensemble ? x->radix : 0;
+  add(rs1, chunks);
   time_all();
-  if (st == CHN_OK && best > 0.0f) {
+  if (st == CHN_OK && best > 0.0f && !x->in_ensemble) {
     cand.clear();
     for (int rs = 1; rs <= 3; ++rs) add(rs, std::vector<int>{pick.ych});
     time_all();
@@ -1874,7 +1891,6 @@ chn_status chn_ens_create(int32_t n, const chn_config* cfgs, void* d_ws, size_t 
       delete e;
       return s;
     }
-    c->in_ensemble = true;
     e->ctx.push_back(c);
   }
   if (hipStreamCreate(&e->own) != hipSuccess || hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -1888,6 +1904,7 @@ chn_status chn_ens_create(int32_t n, const chn_config* cfgs, void* d_ws, size_t 
     delete e;
     return s;
   }
+  for (chn_ctx* c : e->ctx) c->in_ensemble = true;
   *out = e;
   return CHN_OK;
 }

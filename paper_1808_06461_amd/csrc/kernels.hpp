@@ -302,6 +302,7 @@ template <typename T> struct BatchPlan {
   size_t lds_z, lds_x;
   int mz, mx;       // transform staging (complex values per thread) of the z and x passes
   int rz;           // rows per x-pass workgroup
+  int comp;         // nonzero: some channel's plans hold composite radices
 };
 // Smallest staging size that holds every pass of nlines lines over 256 threads
 // (bytes_per_value: 8 for complex float, 16 for complex double); 0 if none.

@@ -203,6 +203,72 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
   __syncthreads();
   fft_lines<T, MAXV, FN, kPad>(lds, LS, 3 * RZ, a.plan, a.tw, +1);
   // --- products, row sums and CFL
+  const T idx_ = T(a.inv_dx), idy = T(a.inv_dy[yg]), idz = T(a.inv_dz);
+  // (the compile-time 576-point schedules never take the short-row branch)
+  constexpr bool kLong = FN == 576 || FN == kFn576Composite;
+  if (!kLong && p1 < 256) {
+    // Short rows: one wave per row (rows dealt to the waves in turn), lane l
+    // summing x = l, l + 64, ... in order, then a wave reduction: every
+    // thread is busy and the order of the sums depends on the row length
+    // only (the same bits for any rows per workgroup).  The products stay in
+    // registers until every input line has been read.
+    constexpr int RW = (RZ + 3) / 4, PL = 4;  // rows per wave (four waves), points per lane
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T hv[RW][PL][3];
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const int row = wid + 4 * j;
+      double t1 = 0.0, t3 = 0.0;
+      T c = T(0);
+#pragma unroll
+      for (int q = 0; q < PL; ++q) {
+        const int x = lane + 64 * q;
+        hv[j][q][0] = hv[j][q][1] = hv[j][q][2] = T(0);
+        if (row < RZ && x < p1) {
+          const int px = lx<kPad>(x);
+          const c2<T> Z0 = lds[(3 * row + 0) * LS + px];
+          const c2<T> Z1 = lds[(3 * row + 1) * LS + px];
+          const c2<T> Z2 = lds[(3 * row + 2) * LS + px];
+          const T u1 = Z0.x, u2 = Z0.y, u3 = Z1.x, o1 = Z1.y, o2 = Z2.x, o3 = Z2.y;
+          hv[j][q][0] = u2 * o3 - u3 * o2;
+          hv[j][q][1] = u3 * o1 - u1 * o3;
+          hv[j][q][2] = u1 * o2 - u2 * o1;
+          t1 += (double)hv[j][q][0];
+          t3 += (double)hv[j][q][2];
+          c = nanmax(c, fabs(u1) * idx_ + fabs(u2) * idy + fabs(u3) * idz);
+        }
+      }
+      double tc = (double)c;
+      for (int off = 32; off > 0; off >>= 1) {
+        t1 += __shfl_xor(t1, off);
+        t3 += __shfl_xor(t3, off);
+        tc = nanmax(tc, __shfl_xor(tc, off));
+      }
+      if (lane == 0 && row < RZ && z0 + row < p3) {
+        const size_t o = (size_t)yg * p3 + z0 + row;
+        a.rowsum[o] = t1;
+        a.rowsum[(size_t)a.d.n2 * p3 + o] = t3;
+        a.rowcfl[o] = tc;
+        if (a.guard) atomicMax(a.guard, __float_as_uint(fabsf((float)tc)) | (tc != tc ? kGuardNonFinite : 0u));
+      }
+    }
+    __syncthreads();
+    // line row <- H1 + i H2 of the row; line RZ + row / 2 <- H3 of rows 2j (real) and 2j + 1 (imaginary)
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const int row = wid + 4 * j;
+#pragma unroll
+      for (int q = 0; q < PL; ++q) {
+        const int x = lane + 64 * q;
+        if (row < RZ && x < p1) {
+          const int px = lx<kPad>(x);
+          lds[row * LS + px] = mk<T>(hv[j][q][0], hv[j][q][1]);
+          reinterpret_cast<T*>(&lds[(RZ + row / 2) * LS + px])[row & 1] = hv[j][q][2];
+        }
+      }
+    }
+    __syncthreads();
+  } else {
   double s1[RZ], s3[RZ];
   T cf[RZ];  // CFL numbers in the transform precision (they only report)
 #pragma unroll
@@ -210,7 +276,6 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
     s1[row] = s3[row] = 0.0;
     cf[row] = T(0);
   }
-  const T idx_ = T(a.inv_dx), idy = T(a.inv_dy[yg]), idz = T(a.inv_dz);
   for (int x = threadIdx.x; x < p1; x += blockDim.x) {
     const int px = lx<kPad>(x);
     T h3[RZ];
@@ -261,6 +326,7 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
     a.rowsum[(size_t)a.d.n2 * p3 + o] = t3;
     a.rowcfl[o] = tc;
     if (a.guard) atomicMax(a.guard, __float_as_uint(fabsf((float)tc)) | (tc != tc ? kGuardNonFinite : 0u));
+  }
   }
   fft_lines<T, MAXV, FN, kPad>(lds, LS, RZ + RZ / 2, a.plan, a.tw, -1);
   // --- unpack two real spectra per line, truncate, store in place over fields 0..2
@@ -484,20 +550,20 @@ __global__ void __launch_bounds__(NT) k_zfwd(ZfwdArgs<T, TO> a) {
   zfwd_body<T, TO, MAXV, FN, PIPE>(a, t.x, t.y);
 }
 
-template <typename T, int MAXV>
+template <typename T, int MAXV, int FN = 0>
 __global__ void __launch_bounds__(256) k_zinv_batch(const ZinvArgs<T>* __restrict__ d, const int4* __restrict__ w) {
   const int4 q = w[blockIdx.x];
-  zinv_body<T, MAXV>(d[q.x], q.y, q.z);
+  zinv_body<T, MAXV, FN>(d[q.x], q.y, q.z);
 }
-template <typename T, int MAXV, int RZ>
+template <typename T, int MAXV, int RZ, int FN = 0>
 __global__ void __launch_bounds__(256) k_xpass_batch(const XpassArgs<T>* __restrict__ d, const int4* __restrict__ w) {
   const int4 q = w[blockIdx.x];
-  xpass_body<T, MAXV, 0, RZ>(d[q.x], q.y, q.z);
+  xpass_body<T, MAXV, FN, RZ>(d[q.x], q.y, q.z);
 }
-template <typename T, int MAXV>
+template <typename T, int MAXV, int FN = 0>
 __global__ void __launch_bounds__(256) k_zfwd_batch(const ZfwdArgs<T, T>* __restrict__ d, const int4* __restrict__ w) {
   const int4 q = w[blockIdx.x];
-  zfwd_body<T, T, MAXV>(d[q.x], q.y, q.z);
+  zfwd_body<T, T, MAXV, FN>(d[q.x], q.y, q.z);
 }
 
 // ---------------------------------------------------------------- launchers

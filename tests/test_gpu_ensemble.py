@@ -26,6 +26,12 @@ def _spec(c, y):
     return dict(n1=c.n1, n2=c.n2, n3=c.n3, lx=c.lx, lz=c.lz, re_b=c.re_b, mass_flux=c.mass_flux, y=y)
 
 
+def _same_radix(single, channel):
+    """The single context takes the radix sets the ensemble gave the channel."""
+    p, q = single.plan(), channel.plan()
+    single.set_plan(p["x_rows"], p["z_lines"], p["y_chunk"], p["fixed_radix"], p["z_pipeline"], q["radix_set"])
+
+
 @gpu
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_ensemble_matches_single_contexts(precision):
@@ -39,6 +45,7 @@ def test_ensemble_matches_single_contexts(precision):
     for k, (c, (v, om, U1, U3, y)) in enumerate(zip(SPECS, fields)):
         got = {n: t.cpu().numpy() for n, t in ens.channels[k].get_fields("v", "omega2", "chi", "u1mean").items()}
         single = Channel(c.n1, c.n2, c.n3, c.lx, c.lz, c.re_b, precision=precision, y=y)
+        _same_radix(single, ens.channels[k])
         single.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
         single.step(c.dt, 2)
         ref = {n: t.cpu().numpy() for n, t in single.get_fields("v", "omega2", "chi", "u1mean").items()}
@@ -105,6 +112,7 @@ def test_c4_ensemble_fifty_steps():
         c = cases[k]
         v, om, U1, U3, y = fields[k]
         single = Channel(c.n1, c.n2, c.n3, c.lx, c.lz, c.re_b, y=y)
+        _same_radix(single, ens.channels[k])
         single.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
         single.step(dts[k], 50)
         ref = single.get_fields("v", "omega2")
@@ -140,23 +148,25 @@ def test_ens_set_state_index_checked():
 
 
 @gpu
-def test_ensemble_channels_keep_the_classic_radix_set():
-    """An ensemble's batched kernels take the classic radix passes: a composite
-    radix set on one of its channels is refused (CHN_EUNSUPPORTED) and the
-    autotuner keeps set 0 there; the ensemble still steps as before."""
+def test_ensemble_channels_keep_their_radix_sets():
+    """chn_ens_create gives a channel the composite radices where they take
+    fewer passes (48 = 8 x 6, 72 = 9 x 8, 96 = 12 x 8); the batched tables are
+    built with them, so another radix set on a channel is refused
+    (CHN_EUNSUPPORTED) and the autotuner keeps the channel's set."""
     from paper_1808_06461_amd import ChnError
     from paper_1808_06461_amd.chn import Ensemble
-    c = SPECS[0]
+    c = SPECS[4]  # 48 x 25 x 16: x lines of 72 points, z lines of 24
     v, om, U1, U3, y = synth.turbulent_field(c)
     ens = Ensemble([_spec(c, y)], precision="mixed")
     try:
         ch = ens.channels[0]
         ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
         p = ch.plan()
+        assert p["radix_set"] & 1, p  # 72 = 9 x 8 (two passes) against 8, 3, 3
         with pytest.raises(ChnError, match="CHN_EUNSUPPORTED"):
-            ch.set_plan(p["x_rows"], p["z_lines"], p["y_chunk"], p["fixed_radix"], p["z_pipeline"], 3)
+            ch.set_plan(p["x_rows"], p["z_lines"], p["y_chunk"], p["fixed_radix"], p["z_pipeline"], 0)
         assert ch.plan() == p
-        assert ch.autotune(reps=1)["radix_set"] == 0
+        assert ch.autotune(reps=1)["radix_set"] == p["radix_set"]
         ens.step([c.dt], 2)
         f = ch.get_fields("v")["v"].cpu().numpy()
         assert np.isfinite(f).all()

@@ -118,7 +118,7 @@ def test_autotune_picks_a_fitting_schedule(precision, tmp_path, monkeypatch):
         before = {k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "chi").items()}
         p = ch.autotune(reps=2)
         print(precision, "autotune ->", p)
-        assert p == ch.plan() and p["x_rows"] in (1, 2) and p["z_lines"] >= 1
+        assert p == ch.plan() and p["x_rows"] in (1, 2, 4, 8) and p["z_lines"] >= 1
         after = {k: t.cpu().numpy() for k, t in ch.get_fields("v", "omega2", "chi").items()}
         for k in before:  # the state is untouched
             assert np.array_equal(before[k], after[k]), k
