@@ -13,6 +13,11 @@ template <> struct V2<double> { using type = double2; };
 template <typename T> using c2 = typename V2<T>::type;
 
 template <typename T> __device__ __forceinline__ c2<T> mk(T x, T y) { c2<T> r; r.x = x; r.y = y; return r; }
+// v where c holds, else zero: selected per component (a select of the whole
+// pair can be lowered through a stack copy of both candidates)
+template <typename T> __device__ __forceinline__ c2<T> keep_if(bool c, c2<T> v) {
+  return mk<T>(c ? v.x : T(0), c ? v.y : T(0));
+}
 template <typename T> __device__ __forceinline__ c2<T> cadd(c2<T> a, c2<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
 template <typename T> __device__ __forceinline__ c2<T> csub(c2<T> a, c2<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
 template <typename T> __device__ __forceinline__ c2<T> cmul(c2<T> a, c2<T> b) {

@@ -50,15 +50,27 @@ __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
   for (int l = 0; l < 2; ++l) {
     for (int e = threadIdx.x; e < f1; e += blockDim.x) lt[e] = zero;
     __syncthreads();
-    for (int k = threadIdx.x; k < n1h; k += blockDim.x) {
-      const size_t base = ((size_t)(y * 3 + 2 * l) * f3 + z) * n1h + k;
-      const c2<T> X = a.buf[base];
-      const c2<T> Y = l == 0 ? a.buf[base + (size_t)f3 * n1h] : zero;
-      if (k == 0) {
-        lt[0] = mk<T>(X.x, Y.x);
-      } else {
-        lt[k] = mk<T>(X.x - Y.y, X.y + Y.x);
-        lt[f1 - k] = mk<T>(X.x + Y.y, Y.x - X.y);
+    // kG coefficients per thread loaded together (clamped addresses), then
+    // written to LDS
+    constexpr int kG = 4;
+    for (int k0 = threadIdx.x; k0 < n1h; k0 += kG * blockDim.x) {
+      c2<T> X[kG], Y[kG];
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        const int k = k0 + u * blockDim.x;
+        const size_t base = ((size_t)(y * 3 + 2 * l) * f3 + z) * n1h + (k < n1h ? k : 0);
+        X[u] = a.buf[base];
+        Y[u] = l == 0 ? a.buf[base + (size_t)f3 * n1h] : zero;
+      }
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        const int k = k0 + u * blockDim.x;
+        if (k == 0) {
+          lt[0] = mk<T>(X[u].x, Y[u].x);
+        } else if (k < n1h) {
+          lt[k] = mk<T>(X[u].x - Y[u].y, X[u].y + Y[u].x);
+          lt[f1 - k] = mk<T>(X[u].x + Y[u].y, Y[u].x - X[u].y);
+        }
       }
     }
     __syncthreads();
@@ -66,7 +78,7 @@ __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int x = threadIdx.x + q * blockDim.x;
-      const c2<T> v = x < f1 ? lt[x] : zero;
+      const c2<T> v = keep_if<T>(x < f1, lt[x < f1 ? x : 0]);
       if (l == 0) {
         ph[0][q] = v.x;
         ph[1][q] = v.y;

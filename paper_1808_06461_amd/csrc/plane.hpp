@@ -34,6 +34,10 @@ constexpr bool kPad = true;
 // the unpipelined loop.
 constexpr int kZinvStage = 8;
 constexpr int kZfwdStage = 12;
+// Loads per thread issued together by the unpipelined element loops (the
+// x pass's coefficient loads, the z passes' fields): a group's values are
+// all in flight before the first is written to LDS.
+constexpr int kGroup = 6;
 
 // Input coefficient idx of field f; float32 data widened where in_f32 says so.
 template <typename T> __device__ __forceinline__ c2<T> ldin(const ZinvArgs<T>& a, int f, size_t idx) {
@@ -124,32 +128,47 @@ __device__ __forceinline__ void zinv_body(const ZinvArgs<T>& a, int bx, int by) 
     }
     return;
   }
-  auto value = [&](int f, int l, int s) -> c2<T> {
-    c2<T> v = zero;
-    if (l < nk && !(a.zero_mean && kx0 + l == 0 && s == 0)) {
-      const size_t idx = ((size_t)y * n1h + kx0 + l) * n3 + s;
-      if (f == 4 && a.in[4] == nullptr) {
-        // omega2 = i (b u1 - a u3)
-        const int kz = s < half ? s : s - n3;
-        const T ka = T(tpx * (kx0 + l)), kb = T(tpz * kz);
-        const c2<T> u1 = ldin(a, 0, idx), u3 = ldin(a, 2, idx);
-        const c2<T> t = mk<T>(kb * u1.x - ka * u3.x, kb * u1.y - ka * u3.y);
-        v = mk<T>(-t.y, t.x);
-      } else {
-        v = ldin(a, f, idx);
-      }
-    }
-    return v;
-  };
+
   for (int f = 0; f < a.nfields; ++f) {
     for (int e = threadIdx.x; e < K * npad; e += blockDim.x) {
       const int l = (int)qdiv(e, npad, mnp);
       lds[l * LS + lx<kPad>(half + (e - l * npad))] = zero;
     }
-    for (int e = threadIdx.x; e < K * n3; e += blockDim.x) {
-      const int l = (int)qdiv(e, n3, mn3), s = e - l * n3;
-      if (s == half) continue;
-      lds[l * LS + lx<kPad>(s < half ? s : p3 - (n3 - s))] = value(f, l, s);
+    // kGroup values per thread loaded together (addresses clamped in
+    // bounds, values masked after), then written to LDS
+    const bool wform = f == 4 && a.in[4] == nullptr;
+    const int tot = K * n3;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += kGroup * (int)blockDim.x) {
+      c2<T> A[kGroup], B[kGroup];
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
+        const int e = e0 + u * blockDim.x;
+        const int l = (int)qdiv(e, n3, mn3), s = e - l * n3;
+        const bool ok = e < tot && l < nk && s != half && !(a.zero_mean && kx0 + l == 0 && s == 0);
+        const size_t idx = ok ? ((size_t)y * n1h + kx0 + l) * n3 + s : 0;
+        if (wform) {
+          A[u] = ldin(a, 0, idx);
+          B[u] = ldin(a, 2, idx);
+        } else {
+          A[u] = ldin(a, f, idx);
+          B[u] = zero;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
+        const int e = e0 + u * blockDim.x;
+        const int l = (int)qdiv(e, n3, mn3), s = e - l * n3;
+        const bool keep = l < nk && !(a.zero_mean && kx0 + l == 0 && s == 0);
+        c2<T> v = keep_if<T>(keep, A[u]);
+        if (wform) {  // omega2 = i (b u1 - a u3)
+          const int kz = s < half ? s : s - n3;
+          const T ka = T(tpx * (kx0 + l)), kb = T(tpz * kz);
+          const c2<T> u1 = v, u3 = keep_if<T>(keep, B[u]);
+          const c2<T> t = mk<T>(kb * u1.x - ka * u3.x, kb * u1.y - ka * u3.y);
+          v = mk<T>(-t.y, t.x);
+        }
+        if (e < tot && s != half) lds[l * LS + lx<kPad>(s < half ? s : p3 - (n3 - s))] = v;
+      }
     }
     __syncthreads();
     fft_lines<T, MAXV, FN, kPad>(lds, LS, K, a.plan, a.tw, +1);
@@ -183,21 +202,33 @@ __device__ __forceinline__ void xpass_body(const XpassArgs<T>& a, int bx, int by
     const int l = (int)qdiv(e, npad, mnp);
     lds[l * LS + lx<kPad>(n1h + (e - l * npad))] = zero;
   }
-  for (int e = threadIdx.x; e < 3 * RZ * n1h; e += blockDim.x) {
-    const int l = (int)qdiv(e, n1h, mnh), k = e - l * n1h;
-    const int row = l / 3, pr = l - row * 3;
-    c2<T> X = zero, Y = zero;
-    if (z0 + row < p3) {
-      const size_t base = ((size_t)(y * 6 + 2 * pr) * p3 + z0 + row) * n1h + k;
-      X = a.buf[base];
-      Y = a.buf[base + (size_t)p3 * n1h];
+  // coefficients fetched kGroup per thread at a time, every load of a group
+  // in flight together (addresses clamped in bounds, values masked after)
+  const int tot = 3 * RZ * n1h, nt = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += kGroup * nt) {
+    c2<T> X[kGroup], Y[kGroup];
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const int e = e0 + u * nt;
+      const int l = (int)qdiv(e, n1h, mnh), k = e - l * n1h;
+      const int row = l / 3, pr = l - row * 3;
+      const bool ok = e < tot && z0 + row < p3;
+      const size_t base = ok ? ((size_t)(y * 6 + 2 * pr) * p3 + z0 + row) * n1h + k : 0;
+      X[u] = a.buf[base];
+      Y[u] = a.buf[base + (size_t)p3 * n1h];
     }
-    c2<T>* line = lds + l * LS;
-    if (k == 0) {
-      line[0] = mk<T>(X.x, Y.x);
-    } else {
-      line[lx<kPad>(k)] = mk<T>(X.x - Y.y, X.y + Y.x);
-      line[lx<kPad>(p1 - k)] = mk<T>(X.x + Y.y, Y.x - X.y);
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const int e = e0 + u * nt;
+      const int l = (int)qdiv(e, n1h, mnh), k = e - l * n1h;
+      const c2<T> Xu = keep_if<T>(z0 + l / 3 < p3, X[u]), Yu = keep_if<T>(z0 + l / 3 < p3, Y[u]);
+      c2<T>* line = lds + l * LS;
+      if (e < tot && k == 0) {
+        line[0] = mk<T>(Xu.x, Yu.x);
+      } else if (e < tot) {
+        line[lx<kPad>(k)] = mk<T>(Xu.x - Yu.y, Xu.y + Yu.x);
+        line[lx<kPad>(p1 - k)] = mk<T>(Xu.x + Yu.y, Yu.x - Xu.y);
+      }
     }
   }
   __syncthreads();
@@ -380,7 +411,7 @@ __device__ __forceinline__ void xrow_body(const XpassArgs<T>& a, int z, int y) {
 #pragma unroll
     for (int q = 0; q < QX; ++q) {
       const int x = threadIdx.x + q * NT;
-      r[q] = x < p1 ? line[x] : zero;
+      r[q] = keep_if<T>(x < p1, line[x < p1 ? x : 0]);
     }
     __syncthreads();
   };
@@ -490,7 +521,8 @@ __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int 
       for (int q = 0; q < kZfwdStage; ++q) {
         const int e = threadIdx.x + q * nt;
         const int z = (int)qdiv(e, K, mK), l = e - z * K;
-        st[q] = (e < tot && l < nk) ? in[(size_t)z * n1h + l] : zero;
+        const bool ok = e < tot && l < nk;
+        st[q] = keep_if<T>(ok, in[ok ? (size_t)z * n1h + l : 0]);
       }
     };
     fetch(0);
@@ -513,9 +545,20 @@ __device__ __forceinline__ void zfwd_body(const ZfwdArgs<T, TO>& a, int bx, int 
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const c2<T>* in = a.buf + ((size_t)(y * 6 + f) * p3) * n1h + kx0;
-    for (int e = threadIdx.x; e < K * p3; e += blockDim.x) {
-      const int z = (int)qdiv(e, K, mK), l = e - z * K;
-      lds[l * LS + lx<kPad>(z)] = l < nk ? in[(size_t)z * n1h + l] : zero;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += kGroup * nt) {
+      c2<T> v[kGroup];
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
+        const int e = e0 + u * nt;
+        const int z = (int)qdiv(e, K, mK), l = e - z * K;
+        v[u] = in[e < tot && l < nk ? (size_t)z * n1h + l : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
+        const int e = e0 + u * nt;
+        const int z = (int)qdiv(e, K, mK), l = e - z * K;
+        if (e < tot) lds[l * LS + lx<kPad>(z)] = keep_if<T>(l < nk, v[u]);
+      }
     }
     __syncthreads();
     fft_lines<T, MAXV, FN, kPad>(lds, LS, K, a.plan, a.tw, -1);
