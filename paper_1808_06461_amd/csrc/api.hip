@@ -863,8 +863,8 @@ chn_status check(chn_ctx* x) {
 struct chn_ens {
   int n = 0;
   bool mixed = false;
-  hipStream_t user = nullptr, own = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipStream_t user = nullptr, own = nullptr, own2 = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_lag = nullptr, ev_join = nullptr;
   std::vector<chn_ctx*> ctx;
   std::string err;
   // device tables
@@ -875,6 +875,11 @@ struct chn_ens {
   unsigned* d_guard = nullptr;  // [n][4] instability guards of the channels
   int4 *d_wz = nullptr, *d_wx = nullptr, *d_wa = nullptr;
   int nz = 0, nx = 0, na = 0;
+  // two groups of channels (work-list items of group 0 first): the step
+  // graph runs them on two branches, group 1 one plane phase behind, so one
+  // group's pencil phase overlaps the other's plane phase
+  int gz[2] = {0, 0}, gx[2] = {0, 0}, ga[2] = {0, 0};
+  bool lag = true;  // group 1 starts after group 0's first plane phase
   size_t lds_z = 0, lds_x = 0;
   int mz = 0, mx = 0;  // transform staging of the batched z and x passes
   int rz = 2;          // rows per batched x-pass workgroup
@@ -889,7 +894,10 @@ struct chn_ens {
     for (chn_ctx* c : ctx) delete c;
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
+    if (ev_lag) (void)hipEventDestroy(ev_lag);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     if (own) (void)hipStreamDestroy(own);
+    if (own2) (void)hipStreamDestroy(own2);
   }
 };
 
@@ -1010,16 +1018,40 @@ template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
     e->lds_z = std::max(e->lds_z, (size_t)za[i].K * za[i].lstride * cb);
     e->lds_x = std::max(e->lds_x, (size_t)3 * e->rz * xa[i].lstride * cb);
   }
-  for (int c : order) {
-    chn_ctx* x = e->ctx[c];
-    const int nbz = (x->n1h + za[c].K - 1) / za[c].K;
-    for (int y = 0; y < x->n2; ++y)
-      for (int b = 0; b < nbz; ++b) wz.push_back(make_int4(c, b, y, 0));
-    for (int y = 0; y < x->n2; ++y)
-      for (int b = 0; b < (x->p3 + e->rz - 1) / e->rz; ++b) wx.push_back(make_int4(c, b, y, 0));
-    const int nb = chn::advance_blocks(x->M);
-    wa.push_back(make_int4(c, 0, 0, 1));  // mean-mode workgroup
-    for (int b = 0; b < nb; ++b) wa.push_back(make_int4(c, b, 0, 0));
+  // Two groups of channels.  The pencil phase of a channel takes as long as
+  // its n2-row chains, whatever the number of channels beside it, so when
+  // the wall-normal sizes differ, group 0 holds the channels with the
+  // longest lines and both groups start together: the other group's shorter
+  // pencil phases and plane phases fill the time.  With one n2 for all,
+  // channels are dealt to the groups in turn and group 1 starts one plane
+  // phase later, so each group's pencil phase runs beside the other's plane
+  // phase.
+  int n2max = 0, n2min = 1 << 30;
+  for (chn_ctx* c : e->ctx) {
+    n2max = std::max(n2max, c->n2);
+    n2min = std::min(n2min, c->n2);
+  }
+  e->lag = n2max == n2min;
+  std::vector<int> grp(n);
+  for (int k = 0; k < n; ++k) grp[order[k]] = e->lag ? k % 2 : (e->ctx[order[k]]->n2 == n2max ? 0 : 1);
+  for (int g = 0; g < 2; ++g) {
+    const size_t z0 = wz.size(), x0 = wx.size(), a0 = wa.size();
+    for (int k = 0; k < n; ++k) {
+      const int c = order[k];
+      if (grp[c] != g) continue;
+      chn_ctx* x = e->ctx[c];
+      const int nbz = (x->n1h + za[c].K - 1) / za[c].K;
+      for (int y = 0; y < x->n2; ++y)
+        for (int b = 0; b < nbz; ++b) wz.push_back(make_int4(c, b, y, 0));
+      for (int y = 0; y < x->n2; ++y)
+        for (int b = 0; b < (x->p3 + e->rz - 1) / e->rz; ++b) wx.push_back(make_int4(c, b, y, 0));
+      const int nb = chn::advance_blocks(x->M);
+      wa.push_back(make_int4(c, 0, 0, 1));  // mean-mode workgroup
+      for (int b = 0; b < nb; ++b) wa.push_back(make_int4(c, b, 0, 0));
+    }
+    e->gz[g] = (int)(wz.size() - z0);
+    e->gx[g] = (int)(wx.size() - x0);
+    e->ga[g] = (int)(wa.size() - a0);
   }
   e->d_zinv = take(sizeof(za[0]) * n);
   e->d_xpass = take(sizeof(xa[0]) * n);
@@ -1114,13 +1146,37 @@ template <typename T> chn_status ens_step(chn_ens* e, const double* dt, int nste
   bp.rz = e->rz;
   bp.comp = e->comp;
   const auto* adv = reinterpret_cast<const chn::AdvanceArgs<T, T>*>(e->d_adv);
+  // group g's work lists: a contiguous range of each list
+  chn::BatchPlan<T> bg[2] = {bp, bp};
+  bg[0].nz = e->gz[0];
+  bg[0].nx = e->gx[0];
+  bg[1].wz = e->d_wz + e->gz[0];
+  bg[1].wx = e->d_wx + e->gx[0];
+  bg[1].nz = e->gz[1];
+  bg[1].nx = e->gx[1];
+  const int4* wag[2] = {e->d_wa, e->d_wa + e->ga[0]};
+  // One RK3 step: group 0 on the ensemble's stream, group 1 on a second
+  // branch (from the start, or after group 0's first plane phase).
   auto one_step = [&]() -> hipError_t {
-    for (int s = 0; s < 3; ++s) {
-      hipError_t r = chn::launch_plane_batch<T>(bp, e->own);
-      if (r == hipSuccess) r = chn::launch_advance_batch<T>(adv + s * n, e->d_wa, e->na, e->own);
-      if (r != hipSuccess) return r;
+    hipError_t r = hipSuccess;
+    const bool two = e->gz[1] > 0;
+    if (two && !e->lag) {
+      r = hipEventRecord(e->ev_lag, e->own);
+      if (r == hipSuccess) r = hipStreamWaitEvent(e->own2, e->ev_lag, 0);
     }
-    return hipSuccess;
+    for (int s = 0; s < 3 && r == hipSuccess; ++s) {
+      r = chn::launch_plane_batch<T>(bg[0], e->own);
+      if (r == hipSuccess && s == 0 && two && e->lag) r = hipEventRecord(e->ev_lag, e->own);
+      if (r == hipSuccess && s == 0 && two && e->lag) r = hipStreamWaitEvent(e->own2, e->ev_lag, 0);
+      if (r == hipSuccess) r = chn::launch_advance_batch<T>(adv + s * n, wag[0], e->ga[0], e->own);
+    }
+    for (int s = 0; s < 3 && r == hipSuccess && two; ++s) {
+      r = chn::launch_plane_batch<T>(bg[1], e->own2);
+      if (r == hipSuccess) r = chn::launch_advance_batch<T>(adv + s * n, wag[1], e->ga[1], e->own2);
+    }
+    if (r == hipSuccess && two) r = hipEventRecord(e->ev_join, e->own2);
+    if (r == hipSuccess && two) r = hipStreamWaitEvent(e->own, e->ev_join, 0);
+    return r;
   };
   if (!e->exec) {  // capture one RK3 step of the whole ensemble once
     ENSCHK(e, hipStreamBeginCapture(e->own, hipStreamCaptureModeThreadLocal));
@@ -1893,8 +1949,11 @@ chn_status chn_ens_create(int32_t n, const chn_config* cfgs, void* d_ws, size_t 
     }
     e->ctx.push_back(c);
   }
-  if (hipStreamCreate(&e->own) != hipSuccess || hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming) != hipSuccess) {
+  if (hipStreamCreate(&e->own) != hipSuccess || hipStreamCreate(&e->own2) != hipSuccess ||
+      hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&e->ev_lag, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&e->ev_join, hipEventDisableTiming) != hipSuccess) {
     delete e;
     return fail(nullptr, CHN_EDEVICE, "creating the ensemble stream/events");
   }
