@@ -58,6 +58,35 @@ def test_ensemble_matches_single_contexts(precision):
 
 
 @gpu
+def test_ensemble_one_wall_normal_size_matches_single_contexts():
+    """Channels of one n2 run on two graph branches with the second group one
+    plane phase behind; every channel still steps exactly as alone."""
+    from paper_1808_06461_amd import Channel
+    from paper_1808_06461_amd.chn import Ensemble
+    specs = [synth.Case(n1=16, n2=33, n3=16, lx=2 * np.pi, lz=np.pi, re_b=2800.0, dt=0.004, amp=0.1, kmax=5, cfg=51),
+             synth.Case(n1=24, n2=33, n3=12, lx=np.pi, lz=np.pi / 2, re_b=1500.0, dt=0.003, amp=0.1, cfg=52),
+             synth.Case(n1=32, n2=33, n3=24, lx=np.pi, lz=np.pi / 2, re_b=2000.0, dt=0.002, amp=0.1, cfg=53)]
+    fields = [synth.turbulent_field(c) for c in specs]
+    ens = Ensemble([_spec(c, f[4]) for c, f in zip(specs, fields)], precision="mixed")
+    for ch, (v, om, U1, U3, y) in zip(ens.channels, fields):
+        ch.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    ens.step([c.dt for c in specs], 3)
+    for k, (c, (v, om, U1, U3, y)) in enumerate(zip(specs, fields)):
+        got = {n: t.cpu().numpy() for n, t in ens.channels[k].get_fields("v", "omega2", "chi", "u1mean").items()}
+        single = Channel(c.n1, c.n2, c.n3, c.lx, c.lz, c.re_b, precision="mixed", y=y)
+        _same_radix(single, ens.channels[k])
+        single.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+        single.step(c.dt, 3)
+        ref = {n: t.cpu().numpy() for n, t in single.get_fields("v", "omega2", "chi", "u1mean").items()}
+        single.close()
+        for n in ref:
+            e = rel(got[n], ref[n])
+            print(f"one-n2 channel {k} {n}: {e:.2e}")
+            assert e < 1e-14, (k, n, e)
+    ens.close()
+
+
+@gpu
 def test_ensemble_channel_matches_oracle():
     from paper_1808_06461_amd.chn import Ensemble
     fields = [synth.turbulent_field(c) for c in SPECS]
