@@ -36,7 +36,7 @@ __device__ __constant__ int kPairJ[6] = {0, 1, 2, 1, 2, 2};
 // kcx kept.  Trace mode: one product, u1^2 + u2^2 + u3^2, one forward line.
 // One line in LDS at a time (the physical values stay in registers), so
 // several workgroups share a CU.
-template <typename T, int NQ>
+template <typename T, int NQ, int FN = kFnComposite>
 __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   c2<T>* lt = reinterpret_cast<c2<T>*>(smem_raw);      // one phase-precision line
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
       }
     }
     __syncthreads();
-    fft_lines<T, 16, kFnComposite>(lt, a.lst, 1, a.plan, a.tw, +1);
+    fft_lines<T, 16, FN>(lt, a.lst, 1, a.plan, a.tw, +1);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int x = threadIdx.x + q * blockDim.x;
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
       if (x < f1) ld[x] = make_double2(u * u + v * v + w * w, 0.0);
     }
     __syncthreads();
-    fft_lines<double, 16, kFnComposite>(ld, a.lsd, 1, a.plan, a.tw_d, -1);
+    fft_lines<double, 16, FN>(ld, a.lsd, 1, a.plan, a.tw_d, -1);
     for (int k = threadIdx.x; k < kc1; k += blockDim.x) out[k] = ld[k];
     return;
   }
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256) k_xfilter(XfilterArgs<T> a) {
         ld[x] = make_double2((double)ph[ia][q] * (double)ph[ja][q], (double)ph[ib][q] * (double)ph[jb][q]);
     }
     __syncthreads();
-    fft_lines<double, 16, kFnComposite>(ld, a.lsd, 1, a.plan, a.tw_d, -1);
+    fft_lines<double, 16, FN>(ld, a.lsd, 1, a.plan, a.tw_d, -1);
     // pairs of the line: 0 (11) and 3 (22); 1 (12) and 2 (13); 4 (23) and 5 (33)
     const int pa = l == 0 ? 0 : (l == 1 ? 1 : 4);
     const int pb = l == 0 ? 3 : (l == 1 ? 2 : 5);
@@ -340,6 +340,8 @@ hipError_t launch_xfilter(const XfilterArgs<T>& a, size_t lds_bytes, hipStream_t
   if (!staging_fits(a.plan, 1, 256, 16)) return hipErrorInvalidValue;
   if (a.f1 <= 3 * 256) hipLaunchKernelGGL((k_xfilter<T, 3>), grid, dim3(256), lds_bytes, st, a);
   else if (a.f1 <= 6 * 256) hipLaunchKernelGGL((k_xfilter<T, 6>), grid, dim3(256), lds_bytes, st, a);
+  else if (a.f1 <= 9 * 256 && plan_is_1728c(a.plan))  // compile-time 12, 12, 12
+    hipLaunchKernelGGL((k_xfilter<T, 9, kFn1728Composite>), grid, dim3(256), lds_bytes, st, a);
   else if (a.f1 <= 9 * 256) hipLaunchKernelGGL((k_xfilter<T, 9>), grid, dim3(256), lds_bytes, st, a);
   else if (a.f1 <= 12 * 256) hipLaunchKernelGGL((k_xfilter<T, 12>), grid, dim3(256), lds_bytes, st, a);
   else return hipErrorInvalidValue;
