@@ -172,8 +172,11 @@ size_t layout(const chn_config* c, char* base, chn_ctx* x) {
   for (int f = 0; f < 3; ++f) H[f] = cv.take(te * NPb);
   const size_t ib = te * 6 * (size_t)ych * p3 * n1h;
   void* inter = cv.take(ib);
+  // (the pencil kernel keeps its scratch rows per wave: every lane of its
+  // last workgroup, up to 256 beyond M, has its own column)
+  const size_t SB = po ? 0 : CB + 16 * (size_t)n2 * 256;
   double* S[8];
-  for (int k = 0; k < 8; ++k) S[k] = reinterpret_cast<double*>(cv.take(CB));
+  for (int k = 0; k < 8; ++k) S[k] = reinterpret_cast<double*>(cv.take(SB));
   double* SU[8];
   for (int k = 0; k < 8; ++k) SU[k] = D(NPb);
   double* junk = D(po ? 0 : 2 * M);

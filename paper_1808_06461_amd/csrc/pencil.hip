@@ -600,6 +600,13 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
   double* S0r = a.S[0];
   double* S1r = a.S[1];
   double* S2r = a.S[2];
+  double* S5r = a.S[5];
+  // The scratch rows are stored per wave ([wave][n2][64 lanes], 1 KB per row
+  // of a wave), so each wave walks one contiguous region of n2 KB per array
+  // instead of striding across the whole mode plane from row to row.
+  const size_t wv = (size_t)bx * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const unsigned so = 16u * (threadIdx.x & 63u);
+  auto SR = [&](double* p, int i) { return p + 2 * ((size_t)wv * n + i) * 64; };
 
   // ---- S1 (down): G = i(a H1 + b H3), eliminate A1 (dG) = B1 G (look-ahead 3)
   {
@@ -624,7 +631,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
         [&](int t, B& b) {
           w[6] = (t + 3 < n) ? gval(b) : zz();
           const dv2 yi = elim3z(dot7z(B1 + t * 7, w), L1d + t * 3, yb);
-          if (L.act) stz(ZR(S0r, t), zo, yi);
+          if (L.act) stz(SR(S0r, t), so, yi);
           shift3(yb, yi);
           push_back(w, zz());
         });
@@ -655,7 +662,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
         n + 3,
         [&](int t, B& b) {  // rows clamped; the step uses them only inside the line
           const int i = max(n - 1 - t, 0), r = min(max(n + 2 - t, 0), n - 1);
-          b.s0 = ldz(ZR(S0r, i), zo);
+          b.s0 = ldz(SR(S0r, i), so);
           b.h1 = ldr(ZR(a.H[0], i), ho);
           b.h2 = ldr(ZR(a.H[1], i), ho);
           b.h3 = ldr(ZR(a.H[2], i), ho);
@@ -705,8 +712,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             }
             const double u0 = 1.0 / m7[3];
             if (L.act) {
-              stz(ZR(a.S[1], r), zo, rc);
-              stz(ZR(a.S[2], r), zo, ro);
+              stz(SR(S1r, r), so, rc);
+              stz(SR(S2r, r), so, ro);
             }
             push_u(uh, u0, m7[2], m7[1], m7[0]);
             shift3(ycb, rc);
@@ -746,8 +753,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           i = min(i, n - 1);
 #pragma unroll
           for (int k = 0; k < 4; ++k) b.u[k] = ldn(QR(a.SU[k], i), qo);
-          b.s1 = ldz(ZR(a.S[1], i), zo);
-          b.s2 = ldz(ZR(a.S[2], i), zo);
+          b.s1 = ldz(SR(S1r, i), so);
+          b.s2 = ldz(SR(S2r, i), so);
           b.hc = ldz(Q2R(a.hc, i), qo2);
         },
         [&](int i, B& b) {
@@ -776,7 +783,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
 #pragma unroll
             for (int d = 3; d >= 1; --d) rv -= lm[3 - d] * yvb[3 - d];
             const double u0 = 1.0 / p7[3];
-            if (L.act) stz(ZR(a.S[5], r), zo, rv);
+            if (L.act) stz(SR(S5r, r), so, rv);
             push_u(uh, u0, p7[4], p7[5], p7[6]);
             shift3(yvb, rv);
           }
@@ -796,7 +803,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           const int r = max(n - 1 - t, 0);
 #pragma unroll
           for (int k = 0; k < 4; ++k) b.u[k] = ldn(QR(a.SU[4 + k], r), qo);
-          b.s5 = ldz(ZR(a.S[5], r), zo);
+          b.s5 = ldz(SR(S5r, r), so);
         },
         [&](int t, B& b) {
           const int i = n - 1 - t;
@@ -811,7 +818,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
           const int r = i + 3;
           if (r <= n - 1) {
             const dv2 yr = elim3z(dot7z(B1 + r * 7, wv), L1u + r * 3, yb);
-            if (L.act) stz(ZR(S0r, r), zo, yr);
+            if (L.act) stz(SR(S0r, r), so, yr);
             shift3(yb, yr);
           }
         });
@@ -829,7 +836,7 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
         n + 3,
         [&](int i, B& b) {
           i = min(i, n - 1);
-          b.s0 = ldz(ZR(S0r, i), zo);
+          b.s0 = ldz(SR(S0r, i), so);
           b.om = ldz(ZR(a.om2, i), zo);
         },
         [&](int i, B& b) {
@@ -856,8 +863,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
             const dv2 y1 = elim3z(dot7z(bb, w1), l, y1b);
             const dv2 y3 = elim3z(dot7z(bb, w3), l, y3b);
             if (L.act) {
-              stz(ZR(S1r, r), zo, y1);
-              stz(ZR(S2r, r), zo, y3);
+              stz(SR(S1r, r), so, y1);
+              stz(SR(S2r, r), so, y3);
             }
             shift3(y1b, y1);
             shift3(y3b, y3);
@@ -874,8 +881,8 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
         n,
         [&](int t, B& b) {
           const int r = max(n - 1 - t, 0);
-          b.s1 = ldz(ZR(S1r, r), zo);
-          b.s2 = ldz(ZR(S2r, r), zo);
+          b.s1 = ldz(SR(S1r, r), so);
+          b.s2 = ldz(SR(S2r, r), so);
           b.v = ldz(ZR(a.v, r), zo);
         },
         [&](int t, B& b) {
