@@ -884,6 +884,7 @@ struct chn_ens {
   // group's pencil phase overlaps the other's plane phase
   int gz[2] = {0, 0}, gx[2] = {0, 0}, ga[2] = {0, 0};
   bool lag = true;  // group 1 starts after group 0's first plane phase
+  int n2max = 0;     // largest wall-normal size (LDS tables of the pencil kernel)
   size_t lds_z = 0, lds_x = 0;
   int mz = 0, mx = 0;  // transform staging of the batched z and x passes
   int rz = 2;          // rows per batched x-pass workgroup
@@ -1036,6 +1037,7 @@ template <typename T> chn_status ens_build(chn_ens* e, char* tables) {
     n2min = std::min(n2min, c->n2);
   }
   e->lag = n2max == n2min;
+  e->n2max = n2max;
   std::vector<int> grp(n);
   for (int k = 0; k < n; ++k) grp[order[k]] = e->lag ? k % 2 : (e->ctx[order[k]]->n2 == n2max ? 0 : 1);
   for (int g = 0; g < 2; ++g) {
@@ -1172,11 +1174,11 @@ template <typename T> chn_status ens_step(chn_ens* e, const double* dt, int nste
       r = chn::launch_plane_batch<T>(bg[0], e->own);
       if (r == hipSuccess && s == 0 && two && e->lag) r = hipEventRecord(e->ev_lag, e->own);
       if (r == hipSuccess && s == 0 && two && e->lag) r = hipStreamWaitEvent(e->own2, e->ev_lag, 0);
-      if (r == hipSuccess) r = chn::launch_advance_batch<T>(adv + s * n, wag[0], e->ga[0], e->own);
+      if (r == hipSuccess) r = chn::launch_advance_batch<T>(adv + s * n, wag[0], e->ga[0], e->n2max, e->own);
     }
     for (int s = 0; s < 3 && r == hipSuccess && two; ++s) {
       r = chn::launch_plane_batch<T>(bg[1], e->own2);
-      if (r == hipSuccess) r = chn::launch_advance_batch<T>(adv + s * n, wag[1], e->ga[1], e->own2);
+      if (r == hipSuccess) r = chn::launch_advance_batch<T>(adv + s * n, wag[1], e->ga[1], e->n2max, e->own2);
     }
     if (r == hipSuccess && two) r = hipEventRecord(e->ev_join, e->own2);
     if (r == hipSuccess && two) r = hipStreamWaitEvent(e->own, e->ev_join, 0);

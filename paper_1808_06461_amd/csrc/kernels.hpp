@@ -309,7 +309,7 @@ template <typename T> struct BatchPlan {
 int staging_for(const FftPlan& pl, int nlines, int bytes_per_value);
 template <typename T> hipError_t launch_plane_batch(const BatchPlan<T>& b, hipStream_t st);
 template <typename T>
-hipError_t launch_advance_batch(const AdvanceArgs<T, T>* d, const int4* w, int nblocks, hipStream_t st);
+hipError_t launch_advance_batch(const AdvanceArgs<T, T>* d, const int4* w, int nblocks, int n2max, hipStream_t st);
 
 // workgroups of k_advance for M modes per plane (the mean workgroup not counted)
 int advance_blocks(int M);

@@ -900,9 +900,51 @@ __device__ __forceinline__ void advance_body(const AdvanceArgs<TH, TP>& a, int b
   }
 }
 
+// The mesh's operator rows (B1, A2, B2 and the A1 factors L1d, U1d, L1u,
+// U1u: 35 values per row) staged in LDS once per workgroup.  Every sweep
+// step reads one or two rows of several of them, wave-uniform; from LDS they
+// return in about a hundred cycles, where the scalar cache, missing to L2 on
+// each new row, made every step wait on a chain of scalar loads.
+constexpr int kTableRow = 35;
+__device__ __forceinline__ void stage_table(double* dst, const double* __restrict__ src, int cnt) {
+  constexpr int G = 6;  // loads per thread in flight together
+  for (int e0 = threadIdx.x; e0 < cnt; e0 += G * (int)blockDim.x) {
+    double v[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int e = e0 + u * blockDim.x;
+      v[u] = src[e < cnt ? e : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e < cnt) dst[e] = v[u];
+    }
+  }
+}
+template <typename TH, typename TP>
+__device__ __forceinline__ void advance_lds(const AdvanceArgs<TH, TP>& a, int bx, const double* __restrict__ B1,
+                                            const double* __restrict__ A2, const double* __restrict__ B2,
+                                            const double* __restrict__ L1d, const double* __restrict__ U1d,
+                                            const double* __restrict__ L1u, const double* __restrict__ U1u) {
+  extern __shared__ double tbl[];
+  const int n = a.g.n2;
+  double* t = tbl;
+  stage_table(t, B1, 7 * n);
+  stage_table(t + 7 * n, A2, 7 * n);
+  stage_table(t + 14 * n, B2, 7 * n);
+  stage_table(t + 21 * n, L1d, 3 * n);
+  stage_table(t + 24 * n, U1d, 4 * n);
+  stage_table(t + 28 * n, L1u, 3 * n);
+  stage_table(t + 31 * n, U1u, 4 * n);
+  __syncthreads();
+  advance_body(a, bx, t, t + 7 * n, t + 14 * n, t + 21 * n, t + 24 * n, t + 28 * n, t + 31 * n);
+}
+
 // Workgroups of 128 pairs (256 modes); at most 256 VGPRs (two waves per
 // SIMD): the 384 x 384 mode plane gives 289 workgroups, resident in one round.
-template <typename TH, typename TP>
+// LT: operator rows from LDS (meshes whose tables fit), else from the scalar cache.
+template <typename TH, typename TP, bool LT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
     k_advance(AdvanceArgs<TH, TP> a, const double* __restrict__ B1, const double* __restrict__ A2,
               const double* __restrict__ B2, const double* __restrict__ L1d, const double* __restrict__ U1d,
@@ -911,11 +953,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     mean_block(a);
     return;
   }
-  advance_body(a, blockIdx.x, B1, A2, B2, L1d, U1d, L1u, U1u);
+  if constexpr (LT) advance_lds(a, blockIdx.x, B1, A2, B2, L1d, U1d, L1u, U1u);
+  else advance_body(a, blockIdx.x, B1, A2, B2, L1d, U1d, L1u, U1u);
 }
 
 // Batched over contexts: work item (context, block, -, mean flag).
-template <typename TH, typename TP>
+template <typename TH, typename TP, bool LT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_advance_batch(const AdvanceArgs<TH, TP>* __restrict__ d,
                                                        const int4* __restrict__ w) {
   const int4 q = w[blockIdx.x];
@@ -925,7 +968,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     return;
   }
   const PencilGeom& g = a.g;
-  advance_body(a, q.y, g.B1, g.A2, g.B2, g.L1d, g.U1d, g.L1u, g.U1u);
+  if constexpr (LT) advance_lds(a, q.y, g.B1, g.A2, g.B2, g.L1d, g.U1d, g.L1u, g.U1u);
+  else advance_body(a, q.y, g.B1, g.A2, g.B2, g.L1d, g.U1d, g.L1u, g.U1u);
 }
 
 // ---------------------------------------------------------------- homogeneous solutions
@@ -1527,9 +1571,21 @@ hipError_t launch_homog(const HomogArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Operator rows in LDS on the mixed path up to this many bytes per workgroup
+// (two workgroups per CU keep their tables; 193 rows take 54 KB), else from
+// the scalar cache.  Measured on 384x193x384: mixed 2.12 -> 2.03 ms per
+// launch; float64 2.24 -> 2.40 ms (the rows then occupy vector registers the
+// float64 sweeps need), so the float64 path keeps the scalar cache.
+constexpr size_t kTableLdsMax = 64 << 10;
+size_t advance_table_bytes(int n2) { return (size_t)kTableRow * n2 * sizeof(double); }
 template <typename TH, typename TP> hipError_t launch_advance(const AdvanceArgs<TH, TP>& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_advance<TH, TP>), dim3(advance_blocks(a.g.M) + 1), dim3(256), 0, st, a, a.g.B1, a.g.A2,
-                     a.g.B2, a.g.L1d, a.g.U1d, a.g.L1u, a.g.U1u);
+  const size_t tb = advance_table_bytes(a.g.n2);
+  if (sizeof(TP) == 4 && tb <= kTableLdsMax)
+    hipLaunchKernelGGL((k_advance<TH, TP, true>), dim3(advance_blocks(a.g.M) + 1), dim3(256), tb, st, a, a.g.B1,
+                       a.g.A2, a.g.B2, a.g.L1d, a.g.U1d, a.g.L1u, a.g.U1u);
+  else
+    hipLaunchKernelGGL((k_advance<TH, TP, false>), dim3(advance_blocks(a.g.M) + 1), dim3(256), 0, st, a, a.g.B1,
+                       a.g.A2, a.g.B2, a.g.L1d, a.g.U1d, a.g.L1u, a.g.U1u);
   return hipGetLastError();
 }
 hipError_t launch_pressure(const PressureArgs& a, hipStream_t st) {
@@ -1565,12 +1621,15 @@ hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_
 template hipError_t launch_recover<double>(const RecoverArgs<double>&, hipStream_t);
 template hipError_t launch_recover<float>(const RecoverArgs<float>&, hipStream_t);
 template <typename T>
-hipError_t launch_advance_batch(const AdvanceArgs<T, T>* d, const int4* w, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_advance_batch<T, T>), dim3(nblocks), dim3(256), 0, st, d, w);
+hipError_t launch_advance_batch(const AdvanceArgs<T, T>* d, const int4* w, int nblocks, int n2max, hipStream_t st) {
+  const size_t tb = advance_table_bytes(n2max);
+  if (sizeof(T) == 4 && tb <= kTableLdsMax)
+    hipLaunchKernelGGL((k_advance_batch<T, T, true>), dim3(nblocks), dim3(256), tb, st, d, w);
+  else hipLaunchKernelGGL((k_advance_batch<T, T, false>), dim3(nblocks), dim3(256), 0, st, d, w);
   return hipGetLastError();
 }
-template hipError_t launch_advance_batch<double>(const AdvanceArgs<double, double>*, const int4*, int, hipStream_t);
-template hipError_t launch_advance_batch<float>(const AdvanceArgs<float, float>*, const int4*, int, hipStream_t);
+template hipError_t launch_advance_batch<double>(const AdvanceArgs<double, double>*, const int4*, int, int, hipStream_t);
+template hipError_t launch_advance_batch<float>(const AdvanceArgs<float, float>*, const int4*, int, int, hipStream_t);
 
 template hipError_t launch_advance<double, double>(const AdvanceArgs<double, double>&, hipStream_t);
 template hipError_t launch_advance<float, float>(const AdvanceArgs<float, float>&, hipStream_t);
