@@ -332,13 +332,18 @@ chn_status chn_optimise_mesh(const double *y_ref, int n2, int m, double kstar, d
 
 /* ---------------------------------------------------------------- ensembles
  * An ensemble advances n independent channels of uneven sizes together:
- * every phase of the RK3 sub-step is one batched launch over all channels
+ * every phase of the RK3 sub-step is one batched launch per channel group
  * (a work list of (channel, block) items, larger channels first, and one
  * argument block per channel in device memory), and one RK3 step of the
- * whole ensemble is a captured HIP graph replayed nsteps times.  All
- * configurations must share the precision and the stream.  The ensemble
- * runs on a private stream ordered after and before the configured stream
- * by events.  Same conventions as single contexts (caller-owned workspace). */
+ * whole ensemble is a captured HIP graph replayed nsteps times.  The graph
+ * has two branches, one per group: the channels with the most wall-normal
+ * nodes, and the rest (with one n2 for all: channels dealt in turn, the
+ * second branch starting one plane phase later), so one group's pencil
+ * phase overlaps the other's plane phase; each channel's results are those
+ * of a single context with the same radix sets.  All configurations must
+ * share the precision and the stream.  The ensemble runs on two private
+ * streams ordered after and before the configured stream by events.  Same
+ * conventions as single contexts (caller-owned workspace). */
 typedef struct chn_ens chn_ens;
 
 /* Workspace bytes for n channels (0 if any configuration is invalid). */
