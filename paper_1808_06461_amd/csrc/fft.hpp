@@ -273,6 +273,10 @@ __device__ __forceinline__ void stockham_pass_c(c2<T>* lds, int lstride, int nli
 // 16 (FN = 0: radices 2, 3, 4, 8 only, which keeps the register allocation of
 // those kernels to the classic passes).
 constexpr int kFnComposite = 1;
+// FN of the batched kernels of ensembles: the short composite lines of
+// minimal channels (48 = 8 x 6, 72 = 9 x 8, 96 = 12 x 8) take compile-time
+// schedules, any other plan the runtime composite passes.
+constexpr int kFnShort = 2;
 // FN of the compile-time schedule of 576-point lines in the composite radix
 // set (9, 8, 8); FN = 576 is the classic one (8, 8, 3, 3).
 constexpr int kFn576Composite = 10576;
@@ -315,6 +319,26 @@ __device__ __forceinline__ void fft_lines(c2<T>* lds, int lstride, int nlines, c
       stockham_pass_c<T, 12, MAXV / 12, 1728, 12, PAD>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
       stockham_pass_c<T, 12, MAXV / 12, 1728, 144, PAD>(lds, lstride, nlines, tw + pl.twoff[2], sgn);
     }
+    return;
+  } else if constexpr (FN == kFnShort) {
+    if constexpr (MAXV >= 12) {
+      if (pl.npass == 2 && pl.n == 48 && pl.radix[0] == 8 && pl.radix[1] == 6) {
+        stockham_pass_c<T, 8, MAXV / 8, 48, 1, PAD>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
+        stockham_pass_c<T, 6, MAXV / 6, 48, 8, PAD>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
+        return;
+      }
+      if (pl.npass == 2 && pl.n == 72 && pl.radix[0] == 9 && pl.radix[1] == 8) {
+        stockham_pass_c<T, 9, MAXV / 9, 72, 1, PAD>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
+        stockham_pass_c<T, 8, MAXV / 8, 72, 9, PAD>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
+        return;
+      }
+      if (pl.npass == 2 && pl.n == 96 && pl.radix[0] == 12 && pl.radix[1] == 8) {
+        stockham_pass_c<T, 12, MAXV / 12, 96, 1, PAD>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
+        stockham_pass_c<T, 8, MAXV / 8, 96, 12, PAD>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
+        return;
+      }
+    }
+    fft_lines<T, MAXV, kFnComposite, PAD>(lds, lstride, nlines, pl, tw, sgn);
     return;
   } else if constexpr (FN == 9216) {  // 3/2 x 6144: radices 8, 8, 8, 2, 3, 3
     stockham_pass_c<T, 8, MAXV / 8, 9216, 1, PAD>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
