@@ -783,7 +783,6 @@ chn_status filter_stage(chn_ctx* x, int kcx, int kcz, int q1, int q3, double* d_
   za.y0 = 0;
   za.ny = n2;
   za.pipe = 0;
-  za.fixed = 1;  // compile-time schedules where the plan has one
   HIPCHK(x, timed(x, CHN_K_FILTER, [&] { return chn::launch_zinv<double>(za, x->stream); }));
   // 3. inverse in x, products, float64 forward in x
   chn::XfilterArgs<double> xa{};

@@ -78,13 +78,8 @@ __host__ __device__ inline bool plan_is_12288(const FftPlan& pl) {
   const int r[5] = {8, 8, 8, 8, 3};
   return plan_has(pl, 12288, 5, r);
 }
-// The product grid of the 1536 x 385 x 1152 low-storage stage: 1296-point z
-// lines in the classic set (8, 2, 3, 3, 3, 3) and 1728-point x lines in the
-// composite set (12, 12, 12).
-__host__ __device__ inline bool plan_is_1296(const FftPlan& pl) {
-  const int r[6] = {8, 2, 3, 3, 3, 3};
-  return plan_has(pl, 1296, 6, r);
-}
+// The product grid of the 1536 x 385 x 1152 low-storage stage: 1728-point x
+// lines in the composite set (12, 12, 12).
 __host__ __device__ inline bool plan_is_1728c(const FftPlan& pl) {
   const int r[3] = {12, 12, 12};
   return plan_has(pl, 1728, 3, r);

@@ -280,8 +280,7 @@ constexpr int kFnShort = 2;
 // FN of the compile-time schedule of 576-point lines in the composite radix
 // set (9, 8, 8); FN = 576 is the classic one (8, 8, 3, 3).
 constexpr int kFn576Composite = 10576;
-// FN of the 1728-point schedule in the composite set (12, 12, 12); FN = 1296
-// is the classic 1296-point one (8, 2, 3, 3, 3, 3).
+// FN of the 1728-point schedule in the composite set (12, 12, 12).
 constexpr int kFn1728Composite = 11728;
 
 // Full transform of nlines lines of length pl.n.  MAXV = complex values
@@ -304,14 +303,6 @@ __device__ __forceinline__ void fft_lines(c2<T>* lds, int lstride, int nlines, c
       stockham_pass_c<T, 8, MAXV / 8, 576, 9, PAD>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
       stockham_pass_c<T, 8, MAXV / 8, 576, 72, PAD>(lds, lstride, nlines, tw + pl.twoff[2], sgn);
     }
-    return;
-  } else if constexpr (FN == 1296) {  // the low-storage product grid in z: 8, 2, 3, 3, 3, 3
-    stockham_pass_c<T, 8, MAXV / 8, 1296, 1, PAD>(lds, lstride, nlines, tw + pl.twoff[0], sgn);
-    stockham_pass_c<T, 2, MAXV / 2, 1296, 8, PAD>(lds, lstride, nlines, tw + pl.twoff[1], sgn);
-    stockham_pass_c<T, 3, MAXV / 3, 1296, 16, PAD>(lds, lstride, nlines, tw + pl.twoff[2], sgn);
-    stockham_pass_c<T, 3, MAXV / 3, 1296, 48, PAD>(lds, lstride, nlines, tw + pl.twoff[3], sgn);
-    stockham_pass_c<T, 3, MAXV / 3, 1296, 144, PAD>(lds, lstride, nlines, tw + pl.twoff[4], sgn);
-    stockham_pass_c<T, 3, MAXV / 3, 1296, 432, PAD>(lds, lstride, nlines, tw + pl.twoff[5], sgn);
     return;
   } else if constexpr (FN == kFn1728Composite) {  // the low-storage product grid in x: 12, 12, 12
     if constexpr (MAXV >= 12) {

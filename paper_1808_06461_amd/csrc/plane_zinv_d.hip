@@ -27,7 +27,6 @@ hipError_t launch_zinv(const ZinvArgs<T>& a, hipStream_t st) {
     else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 0, 256, true>), grid, dim3(256), sh, st, a));
   } else {
     if (fx) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 576>), grid, dim3(256), sh, st, a));
-    else if (a.fixed && plan_is_1296(a.plan)) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 1296>), grid, dim3(256), sh, st, a));
     else if (fc) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, kFn576Composite>), grid, dim3(256), sh, st, a));
     else if (cp) CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, kFnComposite>), grid, dim3(256), sh, st, a));
     else CHN_STAGED(T, m, hipLaunchKernelGGL((k_zinv<T, MV, 0>), grid, dim3(256), sh, st, a));
