@@ -87,6 +87,30 @@ def test_ensemble_one_wall_normal_size_matches_single_contexts():
 
 
 @gpu
+def test_ensemble_of_one_channel_matches_single_context():
+    """One channel: a graph of one branch."""
+    from paper_1808_06461_amd import Channel
+    from paper_1808_06461_amd.chn import Ensemble
+    c = SPECS[0]
+    v, om, U1, U3, y = synth.turbulent_field(c)
+    ens = Ensemble([_spec(c, y)], precision="mixed")
+    ens.channels[0].set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    ens.step([c.dt], 2)
+    got = {n: t.cpu().numpy() for n, t in ens.channels[0].get_fields("v", "omega2", "chi", "u1mean").items()}
+    single = Channel(c.n1, c.n2, c.n3, c.lx, c.lz, c.re_b, precision="mixed", y=y)
+    _same_radix(single, ens.channels[0])
+    single.set_state(torch.from_numpy(v), torch.from_numpy(om), torch.from_numpy(U1), torch.from_numpy(U3))
+    single.step(c.dt, 2)
+    ref = {n: t.cpu().numpy() for n, t in single.get_fields("v", "omega2", "chi", "u1mean").items()}
+    single.close()
+    ens.close()
+    for n in ref:
+        e = rel(got[n], ref[n])
+        print(f"one channel {n}: {e:.2e}")
+        assert e < 1e-14, (n, e)
+
+
+@gpu
 def test_ensemble_channel_matches_oracle():
     from paper_1808_06461_amd.chn import Ensemble
     fields = [synth.turbulent_field(c) for c in SPECS]
