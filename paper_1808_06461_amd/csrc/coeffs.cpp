@@ -231,10 +231,10 @@ bool fft_plan(int n, FftPlan* pl, std::vector<double>* tw, int radices) {
   std::memset(pl, 0, sizeof(*pl));
   pl->n = n;
   int m = n, np = 0;
-  if (radices == kRadixComposite) {
+  if (radices == kRadixComposite || radices == kRadixUpTo6) {
     if (n < 1) return false;
     RadixSearch rs;
-    rs.run(n, 0, 16);
+    rs.run(n, 0, radices == kRadixUpTo6 ? 6 : 16);
     if (rs.best_np > kMaxPass) return false;
     np = rs.best_np;
     for (int p = 0; p < np; ++p) pl->radix[p] = rs.best[p];

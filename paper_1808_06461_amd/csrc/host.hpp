@@ -28,7 +28,9 @@ bool wall_rows(int n, const double* A1, const double* B1, double* clo, double* c
 // kRadixClassic takes 8s, then 4, 2, 3 (at most radix 8 per pass);
 // kRadixComposite the fewest passes over radices up to 16 (6, 9, 12, 16 are
 // computed in registers), so each element makes fewer LDS round trips.
-constexpr int kRadixClassic = 0, kRadixComposite = 1;
+// kRadixUpTo6 the fewest passes over radices up to 6 (one radix-6 butterfly
+// stages six values per thread, fewer than the classic radix-8 passes need).
+constexpr int kRadixClassic = 0, kRadixComposite = 1, kRadixUpTo6 = 2;
 bool fft_plan(int n, FftPlan* pl, std::vector<double>* tw, int radices = kRadixClassic);
 // 1-norm condition number ||A||_1 ||A^-1||_1 of a [n][7] band (inf if singular)
 double band_cond1(int n, const double* A);
